@@ -1,0 +1,194 @@
+/*
+ * stencil.h -- C ABI of the MI355X (gfx950) outer-product stencil library.
+ *
+ * The library computes Jacobi time steps of 2D/3D star and box stencils of
+ * order (radius) r.  The problem statement follows "Stencil Matrixization"
+ * (arXiv 2310.16298):
+ *   - two arrays A (time t) and B (time t+1) that swap roles every step
+ *     (Section 2.2);
+ *   - a (2r+1)^d gather coefficient tensor C^g (Section 3.2, Eq. (1)-(2)),
+ *     B[x] = sum_o C^g[o + r] * A[x + o];
+ *   - stencils classified by dimension, shape (star/box) and order
+ *     (Section 1; star = box with the off-axis weights zero, Section 3.3);
+ *   - C-style storage, rightmost index contiguous (Section 4.1 footnote).
+ *
+ * Two computation paths sit behind one plan:
+ *   GATHER   -- the plain gather-form vector kernel of Eq. (1) (baseline);
+ *   MFMA*    -- the scatter-mode outer-product form of Eq. (3)-(12): each
+ *               coefficient line (Eq. (9)) becomes a banded operand tile, and
+ *               the rank-1 updates of Eq. (12) are issued as matrix-core
+ *               (MFMA) products band x input-tile into an output tile held in
+ *               registers (Section 3.2-3.3, Section 4, Algorithm 1).
+ *
+ * Conventions for every entry point:
+ *   - Every function returns a stencil_status_t; no C++ exception crosses
+ *     the ABI.  Negative values are errors.
+ *   - Grid buffers are device pointers owned by the caller: contiguous,
+ *     unpadded, C order, dims slowest to fastest, element type = plan dtype.
+ *   - Streams are hipStream_t handles passed as void*; NULL means the
+ *     default (null) stream of the current device.
+ *   - Entry points that take a stream only enqueue work on it: they neither
+ *     synchronise nor allocate, so they can be captured into a HIP graph.
+ *     Kernel faults surface at the caller's next synchronisation.
+ *   - A plan belongs to the device that was current when it was created and
+ *     must be used with that device current.  A plan is immutable after
+ *     creation; concurrent applies of one plan on different streams are safe
+ *     as long as their buffers do not overlap.
+ */
+#ifndef PAPER_2310_16298_STENCIL_H
+#define PAPER_2310_16298_STENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STENCIL_OK = 0,
+  STENCIL_EINVAL = -1,       /* bad argument: null pointer, ndim, radius, dims, star with off-axis weight, non-finite coefficient */
+  STENCIL_EUNSUPPORTED = -2, /* valid request whose combination is not built (e.g. split precision on FP64 grids) */
+  STENCIL_ENOMEM = -3,       /* device or host allocation failed */
+  STENCIL_EHIP = -4,         /* a HIP runtime call or kernel launch failed */
+  STENCIL_EALIAS = -5,       /* input and output buffers are the same */
+  STENCIL_EINTERNAL = -6     /* unexpected internal error */
+} stencil_status_t;
+
+typedef enum { STENCIL_STAR = 0, STENCIL_BOX = 1 } stencil_shape_t;
+
+/* Boundary rule (the paper states none):
+ *   ZERO     -- every grid point is updated; values outside the grid read as 0;
+ *   PERIODIC -- indices wrap modulo each extent. */
+typedef enum { STENCIL_BC_ZERO = 0, STENCIL_BC_PERIODIC = 1 } stencil_boundary_t;
+
+/* Element type of the grids (and of the arithmetic for GATHER/MFMA). */
+typedef enum { STENCIL_F32 = 0, STENCIL_F64 = 1 } stencil_dtype_t;
+
+typedef enum {
+  STENCIL_PATH_AUTO = 0,        /* library picks (see stencil_plan_info) */
+  STENCIL_PATH_GATHER = 1,      /* gather-form vector kernel, Eq. (1) */
+  STENCIL_PATH_MFMA = 2,        /* outer-product form on MFMA in the grid dtype (FP32 or FP64) */
+  STENCIL_PATH_MFMA_BF16X3 = 3, /* outer-product form, BF16 hi/lo split operands (3 products), FP32 accumulate; F32 grids */
+  STENCIL_PATH_MFMA_F16X3 = 4   /* outer-product form, FP16 hi/lo split operands (3 products), FP32 accumulate; F32 grids */
+} stencil_path_t;
+
+/* Coefficient line cover for star stencils (Tables 1 and 2).
+ *   PARALLEL   -- lines along one axis only (2D: CLS(*,j); 3D: CLS(i,*,k), i=r or k=r);
+ *   ORTHOGONAL -- one line per axis through the centre (2D only here);
+ *   HYBRID     -- 3D: CLS(i,*,r) for all i plus CLS(r,r,*).
+ * Box stencils always use PARALLEL. */
+typedef enum {
+  STENCIL_LINES_AUTO = 0,
+  STENCIL_LINES_PARALLEL = 1,
+  STENCIL_LINES_ORTHOGONAL = 2,
+  STENCIL_LINES_HYBRID = 3
+} stencil_lines_t;
+
+typedef struct {
+  int32_t ndim;         /* 2 or 3 (1D stencils have no outer-product form, Section 3.1) */
+  int32_t radius;       /* order r, 1..4 */
+  int64_t dims[3];      /* extents, slowest to fastest; dims[2] ignored when ndim == 2 */
+  int32_t shape;        /* stencil_shape_t */
+  int32_t boundary;     /* stencil_boundary_t */
+  int32_t dtype;        /* stencil_dtype_t */
+  int32_t path;         /* stencil_path_t */
+  int32_t lines;        /* stencil_lines_t */
+  int32_t reserved;     /* must be 0 */
+  const double* coeffs; /* host pointer to (2r+1)^ndim gather coefficients C^g,
+                           C order, index o + r for offset o; copied by the call.
+                           For an F32 plan they are rounded to float first. */
+} stencil_desc_t;
+
+typedef struct {
+  int32_t path;          /* resolved stencil_path_t */
+  int32_t lines;         /* resolved stencil_lines_t */
+  int32_t ndim, radius, shape, boundary, dtype;
+  int32_t taps;          /* nonzero-capable taps: (2r+1)^d box, 2rd+1 star (Section 3.4) */
+  int32_t tile_rows;     /* output tile of one workgroup: rows (2D) or j-rows (3D) */
+  int32_t tile_cols;     /* ... contiguous columns */
+  int32_t block_n;       /* edge n of one MFMA output block (16); 0 for GATHER */
+  int32_t mfma_lines;    /* coefficient lines issued on the matrix cores */
+  int32_t valu_lines;    /* single-weight lines issued as vector FMAs */
+  int32_t k_rows;        /* rank-1 updates per n x n block as issued, incl. MFMA K padding */
+  int64_t rank1_per_block;       /* outer products per n x n block of the cover, Section 3.4 / Tables 1-2 */
+  double useful_flops_per_point; /* 2 * taps */
+  double executed_flops_per_point; /* flops the matrix+vector units execute per output point */
+  int32_t bytes_per_point;       /* algorithmic HBM bytes per point-step: read + write of one element */
+  int32_t reserved;
+} stencil_plan_info_t;
+
+typedef struct stencil_plan_s* stencil_plan_t;
+
+/* Version string of the library (static storage). */
+const char* stencil_version(void);
+
+/* Human-readable text for a status (static storage; never NULL). */
+const char* stencil_status_string(stencil_status_t s);
+
+/* Host-only: validate a descriptor without touching any device.
+ * Returns STENCIL_OK, STENCIL_EINVAL or STENCIL_EUNSUPPORTED. */
+stencil_status_t stencil_desc_check(const stencil_desc_t* desc);
+
+/* Host-only: resolve the plan choices (path, line cover, tile, operation
+ * counts) that stencil_plan would make, without touching any device. */
+stencil_status_t stencil_plan_describe(const stencil_desc_t* desc, stencil_plan_info_t* info);
+
+/* Host-only: the banded coefficient operand of one 2D coefficient line for an
+ * output block of edge n (Section 3.2, Eq. (9)-(12); Section 3.3, Eq. (14)).
+ *   axis 0 (a line along i, CLS(*, index) in the paper's naming, index = the
+ *     C^g column; Eq. (9)): out is n x (n+2r), row-major;
+ *     out[p*(n+2r) + x] = weight with which input row x of the block's
+ *     halo'd input (row 0 = block row 0 minus r) reaches output row p;
+ *     that is C^g[x-p][index] when 0 <= x-p <= 2r, else 0.  The input segment
+ *     multiplied by it is shifted by index - r columns from the output.
+ *   axis 1 (a line along j, CLS(index, *); Eq. (14)): out is (n+2r) x n;
+ *     out[y*n + q] = C^g[index][y-q] when 0 <= y-q <= 2r, else 0: the weight
+ *     with which input column y of the halo'd block reaches output column q,
+ *     the input rows being shifted by index - r from the output.
+ * coeffs: host (2r+1)x(2r+1) C^g, C order.  out: host, caller-allocated.
+ * Returns STENCIL_EINVAL for null pointers, radius outside 1..4, n < 1 or
+ * axis outside {0, 1}. */
+stencil_status_t stencil_line_band(const double* coeffs, int32_t radius, int32_t n, int32_t axis,
+                                   int32_t index, double* out);
+
+/* Create a plan on the current device: validates the descriptor, builds the
+ * line cover and the banded operand fragments in MFMA lane order, and copies
+ * them to the device (the only allocation the library makes).  The caller
+ * may free desc->coeffs afterwards.  On error *out is set to NULL. */
+stencil_status_t stencil_plan(const stencil_desc_t* desc, stencil_plan_t* out);
+
+/* Report the resolved choices and operation counts of a plan. */
+stencil_status_t stencil_plan_info(stencil_plan_t plan, stencil_plan_info_t* info);
+
+/* Release a plan and its device memory.  NULL is accepted.  The caller must
+ * ensure no enqueued work still uses the plan (e.g. synchronise first). */
+stencil_status_t stencil_plan_destroy(stencil_plan_t plan);
+
+/* One Jacobi step out = S(in) on `stream` (Section 2.2).  in and out are
+ * device buffers of the plan's dims and dtype and must not overlap
+ * (in == out returns STENCIL_EALIAS). */
+stencil_status_t stencil_apply(stencil_plan_t plan, const void* in, void* out, void* stream);
+
+/* `steps` Jacobi steps with two buffers used alternately: step t reads
+ * buf[t % 2] and writes buf[(t+1) % 2], starting from the state in buf0.
+ * *result_index (may be NULL) receives steps % 2, the buffer holding the
+ * final state.  steps == 0 enqueues nothing.  Negative steps: EINVAL. */
+stencil_status_t stencil_run_steps(stencil_plan_t plan, void* buf0, void* buf1, int64_t steps,
+                                   void* stream, int32_t* result_index);
+
+/* Error norms of a state against a reference, for the drift check of
+ * mixed-precision runs.  a: device array of n elements of a_dtype
+ * (stencil_dtype_t); ref: device FP64 array of n elements.  out: device
+ * array of 3 doubles, overwritten with
+ *   out[0] = sum (a - ref)^2,  out[1] = sum ref^2,  out[2] = max |a - ref|.
+ * Enqueued on `stream`; the sums are accumulated with atomics, so their last
+ * bits may vary between calls. */
+stencil_status_t stencil_error_norms(const void* a, int32_t a_dtype, const double* ref, int64_t n,
+                                     double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_2310_16298_STENCIL_H */

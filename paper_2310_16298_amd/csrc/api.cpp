@@ -1,0 +1,210 @@
+// The extern "C" entry points declared in include/stencil.h.
+#include <cstring>
+#include <new>
+
+#include "plan.hpp"
+
+using namespace stencil;
+
+struct stencil_plan_s {
+  Resolved rs;
+  int device = -1;
+  void* d_frag = nullptr;
+  void* d_coef = nullptr;
+  size_t grid_bytes = 0;
+};
+
+namespace {
+
+void free_plan(stencil_plan_s* p) {
+  if (!p) return;
+  if (p->d_frag) (void)hipFree(p->d_frag);
+  if (p->d_coef) (void)hipFree(p->d_coef);
+  delete p;
+}
+
+bool overlaps(const void* a, const void* b, size_t n) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + n && y < x + n;
+}
+
+stencil_status_t check_device(const stencil_plan_s* p) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return STENCIL_EHIP;
+  return dev == p->device ? STENCIL_OK : STENCIL_EINVAL;
+}
+
+stencil_status_t launch_one(const stencil_plan_s* p, const void* in, void* out, hipStream_t s) {
+  KArgs a = p->rs.args;
+  a.in = in;
+  a.out = out;
+  return p->rs.launch(a, p->rs.grid, s) == hipSuccess ? STENCIL_OK : STENCIL_EHIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* stencil_version(void) { return "paper_2310_16298_amd 0.1.0 (gfx950)"; }
+
+const char* stencil_status_string(stencil_status_t s) {
+  switch (s) {
+    case STENCIL_OK: return "ok";
+    case STENCIL_EINVAL: return "invalid argument";
+    case STENCIL_EUNSUPPORTED: return "unsupported combination";
+    case STENCIL_ENOMEM: return "out of memory";
+    case STENCIL_EHIP: return "HIP runtime error";
+    case STENCIL_EALIAS: return "input and output buffers overlap";
+    case STENCIL_EINTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+stencil_status_t stencil_desc_check(const stencil_desc_t* desc) {
+  try {
+    Resolved rs;
+    return (stencil_status_t)resolve_plan(desc, &rs, false);
+  } catch (...) {
+    return STENCIL_EINTERNAL;
+  }
+}
+
+stencil_status_t stencil_plan_describe(const stencil_desc_t* desc, stencil_plan_info_t* info) {
+  if (!info) return STENCIL_EINVAL;
+  try {
+    Resolved rs;
+    const int st = resolve_plan(desc, &rs, true);
+    if (st != STENCIL_OK) return (stencil_status_t)st;
+    *info = rs.info;
+    return STENCIL_OK;
+  } catch (...) {
+    return STENCIL_EINTERNAL;
+  }
+}
+
+stencil_status_t stencil_line_band(const double* coeffs, int32_t radius, int32_t n, int32_t axis,
+                                   int32_t index, double* out) {
+  if (!coeffs || !out || radius < 1 || radius > 4 || n < 1 || n > 4096 || (axis != 0 && axis != 1) ||
+      index < 0 || index > 2 * radius)
+    return STENCIL_EINVAL;
+  const int K = n + 2 * radius;
+  if (axis == 0) {
+    for (int p = 0; p < n; ++p)
+      for (int x = 0; x < K; ++x) out[(size_t)p * K + x] = band_value(coeffs, radius, n, 0, index, p, x);
+  } else {
+    for (int y = 0; y < K; ++y)
+      for (int q = 0; q < n; ++q) out[(size_t)y * n + q] = band_value(coeffs, radius, n, 1, index, y, q);
+  }
+  return STENCIL_OK;
+}
+
+stencil_status_t stencil_plan(const stencil_desc_t* desc, stencil_plan_t* out) {
+  if (!out) return STENCIL_EINVAL;
+  *out = nullptr;
+  stencil_plan_s* p = nullptr;
+  try {
+    p = new (std::nothrow) stencil_plan_s();
+    if (!p) return STENCIL_ENOMEM;
+    const int st = resolve_plan(desc, &p->rs, true);
+    if (st != STENCIL_OK) {
+      free_plan(p);
+      return (stencil_status_t)st;
+    }
+    if (hipGetDevice(&p->device) != hipSuccess) {
+      free_plan(p);
+      return STENCIL_EHIP;
+    }
+    int64_t npts = 1;
+    for (int k = 0; k < desc->ndim; ++k) npts *= desc->dims[k];
+    p->grid_bytes = (size_t)npts * (desc->dtype == STENCIL_F64 ? 8 : 4);
+    const size_t fb = p->rs.frag.size(), cb = p->rs.coef.size();
+    if (fb) {
+      if (hipMalloc(&p->d_frag, fb) != hipSuccess) {
+        free_plan(p);
+        return STENCIL_ENOMEM;
+      }
+      if (hipMemcpy(p->d_frag, p->rs.frag.data(), fb, hipMemcpyHostToDevice) != hipSuccess) {
+        free_plan(p);
+        return STENCIL_EHIP;
+      }
+    }
+    if (hipMalloc(&p->d_coef, cb) != hipSuccess) {
+      free_plan(p);
+      return STENCIL_ENOMEM;
+    }
+    if (hipMemcpy(p->d_coef, p->rs.coef.data(), cb, hipMemcpyHostToDevice) != hipSuccess) {
+      free_plan(p);
+      return STENCIL_EHIP;
+    }
+    p->rs.args.frag = p->d_frag;
+    p->rs.args.coef = p->d_coef;
+    *out = p;
+    return STENCIL_OK;
+  } catch (const std::bad_alloc&) {
+    free_plan(p);
+    return STENCIL_ENOMEM;
+  } catch (...) {
+    free_plan(p);
+    return STENCIL_EINTERNAL;
+  }
+}
+
+stencil_status_t stencil_plan_info(stencil_plan_t plan, stencil_plan_info_t* info) {
+  if (!plan || !info) return STENCIL_EINVAL;
+  *info = plan->rs.info;
+  return STENCIL_OK;
+}
+
+stencil_status_t stencil_plan_destroy(stencil_plan_t plan) {
+  try {
+    free_plan(plan);
+    return STENCIL_OK;
+  } catch (...) {
+    return STENCIL_EINTERNAL;
+  }
+}
+
+stencil_status_t stencil_apply(stencil_plan_t plan, const void* in, void* out, void* stream) {
+  if (!plan || !in || !out) return STENCIL_EINVAL;
+  if (overlaps(in, out, plan->grid_bytes)) return STENCIL_EALIAS;
+  try {
+    const stencil_status_t d = check_device(plan);
+    if (d != STENCIL_OK) return d;
+    return launch_one(plan, in, out, (hipStream_t)stream);
+  } catch (...) {
+    return STENCIL_EINTERNAL;
+  }
+}
+
+stencil_status_t stencil_run_steps(stencil_plan_t plan, void* buf0, void* buf1, int64_t steps,
+                                   void* stream, int32_t* result_index) {
+  if (!plan || !buf0 || !buf1 || steps < 0) return STENCIL_EINVAL;
+  if (overlaps(buf0, buf1, plan->grid_bytes)) return STENCIL_EALIAS;
+  try {
+    const stencil_status_t d = check_device(plan);
+    if (d != STENCIL_OK) return d;
+    void* buf[2] = {buf0, buf1};
+    for (int64_t t = 0; t < steps; ++t) {
+      const stencil_status_t st = launch_one(plan, buf[t & 1], buf[(t + 1) & 1], (hipStream_t)stream);
+      if (st != STENCIL_OK) return st;
+    }
+    if (result_index) *result_index = (int32_t)(steps & 1);
+    return STENCIL_OK;
+  } catch (...) {
+    return STENCIL_EINTERNAL;
+  }
+}
+
+stencil_status_t stencil_error_norms(const void* a, int32_t a_dtype, const double* ref, int64_t n,
+                                     double* out, void* stream) {
+  if (!a || !ref || !out || n < 0 || (a_dtype != STENCIL_F32 && a_dtype != STENCIL_F64))
+    return STENCIL_EINVAL;
+  try {
+    return launch_error_norms(a, a_dtype, ref, n, out, (hipStream_t)stream) == hipSuccess ? STENCIL_OK
+                                                                                          : STENCIL_EHIP;
+  } catch (...) {
+    return STENCIL_EINTERNAL;
+  }
+}
+
+}  // extern "C"

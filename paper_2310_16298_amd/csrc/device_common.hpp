@@ -1,0 +1,142 @@
+// Device-side building blocks shared by the stencil kernels (gfx950).
+//
+// Grids are C order with the rightmost index contiguous (2D: (i, j);
+// 3D: (i, j, k)).  A 2D tile is staged into LDS as a halo'd "window": the
+// output tile's rows and columns extended by r on every side.  Window row 0
+// is output row (tile row 0 - r); window column y is stored at LDS column
+// COL0 + y, with COL0 chosen so the tile body (window column r) starts on a
+// 16-byte boundary.  The boundary rule is applied here, once, so the compute
+// loops run without predicates: ZERO reads 0 outside the grid, PERIODIC wraps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stencil {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// Arguments common to every kernel.  Passed by value (kernarg segment).
+struct KArgs {
+  const void* in;       // input grid (device)
+  void* out;            // output grid (device)
+  const void* frag;     // packed MFMA operand fragments (device, plan-owned)
+  const void* coef;     // dense C^g in the arithmetic dtype (device, plan-owned)
+  int64_t d0, d1, d2;   // extents; d2 == 1 for 2D
+  int32_t periodic;     // 1 = wrap, 0 = zero halo
+  int32_t tiles0;       // tiles along the first tiled axis
+  int32_t tiles1;       // tiles along the second tiled axis
+  int32_t chunk;        // 3D: planes (i) per workgroup
+  int32_t nchunks;      // 3D: number of i-chunks
+  float out_scale;      // split-precision paths: exact power-of-two rescale of the result
+  float lo_scale;       // split-precision paths: weight of the cross-term accumulator
+};
+
+__host__ __device__ constexpr int round_up(int v, int m) { return (v + m - 1) / m * m; }
+__host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
+__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// Index of global coordinate g under the boundary rule, or -1 for a zero-halo
+// point outside [0, n).  The modulo branch is taken only at grid faces.
+__device__ __forceinline__ int64_t map_index(int64_t g, int64_t n, bool periodic) {
+  if (g >= 0 && g < n) return g;
+  if (!periodic) return -1;
+  int64_t m = g % n;
+  return m < 0 ? m + n : m;
+}
+
+// Column offset in LDS that puts window column R on a 16-byte boundary.
+template <typename T, int R>
+__host__ __device__ constexpr int lds_col0() {
+  return round_up(R, 16 / (int)sizeof(T)) - R;
+}
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef float4 type; };
+template <> struct Vec16<double> { typedef double2 type; };
+
+// Stage a ROWS x (BODY + 2R) window of a 2D slice into LDS.
+//   src          : the 2D slice (rows x cols = M x N), C order
+//   r0           : global row of window row 0
+//   c0           : global column of the tile body (window column R); c0 % VEC == 0
+//   lds[row * PITCH + COL0 + y] receives window element (row, y).
+// All NT threads of the block must call it.
+template <typename T, int R, int ROWS, int BODY, int PITCH, int NT>
+__device__ __forceinline__ void stage_window(T* __restrict__ lds, const T* __restrict__ src,
+                                             int64_t M, int64_t N, int64_t r0, int64_t c0,
+                                             bool periodic) {
+  constexpr int COL0 = lds_col0<T, R>();
+  constexpr int VEC = 16 / (int)sizeof(T);
+  constexpr int NV = BODY / VEC;
+  constexpr int WCOLS = BODY + 2 * R;
+  static_assert(BODY % VEC == 0, "tile body must be a whole number of 16-byte vectors");
+  typedef typename Vec16<T>::type V;
+  const int tid = threadIdx.x;
+  const bool fast = (c0 + BODY <= N) && (N % VEC == 0) && ((reinterpret_cast<uintptr_t>(src) & 15) == 0);
+  if (fast) {
+    for (int idx = tid; idx < ROWS * NV; idx += NT) {
+      const int row = idx / NV;
+      const int v = idx - row * NV;
+      const int64_t g = map_index(r0 + row, M, periodic);
+      V val;
+      if (g >= 0) {
+        val = *reinterpret_cast<const V*>(src + g * N + c0 + v * VEC);
+      } else {
+        val = V{};
+      }
+      T* dst = lds + row * PITCH + COL0 + R + v * VEC;
+      if constexpr (PITCH % VEC == 0) {
+        *reinterpret_cast<V*>(dst) = val;
+      } else {
+        const T* pv = reinterpret_cast<const T*>(&val);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) dst[e] = pv[e];
+      }
+    }
+    for (int idx = tid; idx < ROWS * 2 * R; idx += NT) {
+      const int row = idx / (2 * R);
+      const int h = idx - row * (2 * R);
+      const int64_t gc = (h < R) ? (c0 - R + h) : (c0 + BODY + (h - R));
+      const int y = (h < R) ? h : (BODY + h);
+      const int64_t g = map_index(r0 + row, M, periodic);
+      const int64_t c = map_index(gc, N, periodic);
+      lds[row * PITCH + COL0 + y] = (g >= 0 && c >= 0) ? src[g * N + c] : T(0);
+    }
+  } else {
+    for (int idx = tid; idx < ROWS * WCOLS; idx += NT) {
+      const int row = idx / WCOLS;
+      const int y = idx - row * WCOLS;
+      const int64_t g = map_index(r0 + row, M, periodic);
+      const int64_t c = map_index(c0 - R + y, N, periodic);
+      lds[row * PITCH + COL0 + y] = (g >= 0 && c >= 0) ? src[g * N + c] : T(0);
+    }
+  }
+}
+
+// Fill a rectangular LDS region with zeros (used once per block for the
+// padding rows/columns that MFMA K-padding reads but the window never covers).
+template <typename T, int NT>
+__device__ __forceinline__ void zero_region(T* lds, int rows, int cols, int pitch, int row0, int col0) {
+  for (int idx = threadIdx.x; idx < rows * cols; idx += NT) {
+    const int rr = idx / cols;
+    const int cc = idx - rr * cols;
+    lds[(row0 + rr) * pitch + col0 + cc] = T(0);
+  }
+}
+
+// XCD-aware tile order: workgroups are dispatched round-robin over the 8
+// XCDs; give each XCD a contiguous range of tiles so that tiles sharing halo
+// rows also share an L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  constexpr int NXCD = 8;
+  const int per = nblocks / NXCD;
+  const int full = per * NXCD;
+  if (bid >= full) return bid;
+  return (bid % NXCD) * per + bid / NXCD;
+}
+
+}  // namespace stencil

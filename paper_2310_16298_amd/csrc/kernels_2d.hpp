@@ -1,0 +1,214 @@
+// 2D stencil kernels: the gather-form baseline and the outer-product form on
+// MFMA in the grid dtype (FP32 or FP64).
+//
+// Both stage a 64x64 output tile plus an r-wide halo in LDS (one workgroup of
+// four waves per tile) and differ only in how the sum is formed.
+#pragma once
+
+#include "device_common.hpp"
+#include "mfma_traits.hpp"
+
+namespace stencil {
+
+enum Variant2D { VAR_BOX = 0, VAR_STAR_PARALLEL = 1, VAR_STAR_ORTHO = 2 };
+
+constexpr int kTile2D = 64;   // output tile edge of one workgroup
+constexpr int kThreads = 256; // four waves
+
+// LDS pitch (elements) with a bank-friendly residue.
+template <typename T, bool ROWREAD>
+__host__ __device__ constexpr int pick_pitch(int cols) {
+  // FP32: 16 lanes read 16 consecutive words of one row and the next 16 lanes
+  // the next row, so rows offset by half the banks avoid conflicts; when
+  // lanes also walk down a column (row-line reads), an odd residue spreads them.
+  constexpr int mod = sizeof(T) == 4 ? 32 : 16;
+  constexpr int res = sizeof(T) == 4 ? (ROWREAD ? 17 : 16) : (ROWREAD ? 9 : 8);
+  int p = cols;
+  while (p % mod != res) ++p;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Gather-form baseline (Section 3.2, Eq. (1)): each thread owns a 16-row strip
+// of one column and slides a register window down the LDS tile; coefficient
+// reads are wave-uniform (scalar loads).  Box: all (2r+1)^2 taps; star: the
+// on-axis taps only.
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool BOX>
+__global__ __launch_bounds__(kThreads) void gather2d_kernel(KArgs a) {
+  constexpr int TM = kTile2D, TN = kTile2D, W = 2 * R + 1;
+  constexpr int WROWS = TM + 2 * R;
+  constexpr int COL0 = lds_col0<T, R>();
+  constexpr int PITCH = pick_pitch<T, false>(COL0 + TN + 2 * R);
+  constexpr int STRIP = 16;
+  __shared__ __attribute__((aligned(16))) T lds[WROWS * PITCH];
+
+  const int64_t M = a.d0, N = a.d1;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tj = tile % a.tiles1, ti = tile / a.tiles1;
+  const int64_t i0 = (int64_t)ti * TM, j0 = (int64_t)tj * TN;
+  stage_window<T, R, WROWS, TN, PITCH, kThreads>(lds, (const T*)a.in, M, N, i0 - R, j0, a.periodic != 0);
+  __syncthreads();
+
+  const T* __restrict__ c = (const T*)a.coef;
+  const int q = threadIdx.x & 63;       // column within the tile
+  const int s = threadIdx.x >> 6;       // strip: rows 16 s .. 16 s + 15
+  T acc[STRIP];
+#pragma unroll
+  for (int p = 0; p < STRIP; ++p) acc[p] = T(0);
+  const T* base = lds + (STRIP * s) * PITCH + COL0 + q;
+#pragma unroll
+  for (int x = 0; x < STRIP + 2 * R; ++x) {
+    T h[W];
+#pragma unroll
+    for (int b = 0; b < W; ++b) h[b] = base[x * PITCH + b];
+#pragma unroll
+    for (int p = 0; p < STRIP; ++p) {
+      const int aa = x - p;  // coefficient row: input row x reaches output row p through C^g[x-p][.]
+      if (aa < 0 || aa > 2 * R) continue;
+#pragma unroll
+      for (int b = 0; b < W; ++b) {
+        if (!BOX && aa != R && b != R) continue;
+        acc[p] += c[aa * W + b] * h[b];
+      }
+    }
+  }
+  T* out = (T*)a.out;
+  const int64_t gj = j0 + q;
+#pragma unroll
+  for (int p = 0; p < STRIP; ++p) {
+    const int64_t gi = i0 + STRIP * s + p;
+    if (gi < M && gj < N) out[gi * N + gj] = acc[p];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Outer-product form on MFMA (Section 3.2, Eq. (7)-(12); Section 3.3 for star
+// stencils; Table 1 for the line options).
+//
+// Each wave owns a 16-row x 64-column strip of the tile = four 16x16 output
+// blocks held in MFMA accumulators.  A coefficient line along i (C^g column b)
+// is the band T_b[p][x] = C^g[x-p][b] (the zero-padded vectors of Eq. (9)-
+// (11)); the rank-1 updates of Eq. (12) for that line are
+//      D[p][q] += sum_x T_b[p][x] * H[x][q + b]
+// with H the halo'd input window: MFMA A operand = band (kept in VGPRs for
+// the whole kernel), B operand = one LDS row segment per K row, read with an
+// immediate offset.  One band fragment feeds the four blocks of the strip.
+//
+// VAR_BOX:           2r+1 lines along i (all columns of C^g).
+// VAR_STAR_PARALLEL: the centre line b = r on MFMA; the 2r single-weight lines
+//                    are scalar-times-vector updates, done as vector FMAs.
+// VAR_STAR_ORTHO:    the centre line along i on MFMA, plus the line along j
+//                    (C^g row r, centre excluded) in the transposed form
+//                    D[p][q] += sum_y H[p + r][y] * S[y][q], S[y][q] = C^g[r][y-q]
+//                    (Eq. (14)): the input column segment is the A operand.
+// K is padded to a multiple of 4 per line; padded rows carry zero weights.
+// ---------------------------------------------------------------------------
+template <typename T, int R, int VAR>
+struct Mfma2DShape {
+  static constexpr int KL = round_up(16 + 2 * R, 4);   // K rows per line incl. padding
+  static constexpr int CPL = KL / 4;                    // MFMA chunks per line
+  static constexpr int NLC = VAR == VAR_BOX ? 2 * R + 1 : 1;
+  static constexpr int NLR = VAR == VAR_STAR_ORTHO ? 1 : 0;
+  static constexpr int NCH = (NLC + NLR) * CPL;         // band fragments per lane
+  static constexpr int TM = kTile2D, TN = kTile2D;
+  static constexpr int WROWS = TM + 2 * R;
+  static constexpr int LROWS = TM - 16 + KL;            // rows touched by padded K reads
+  static constexpr int COL0 = lds_col0<T, R>();
+  static constexpr int WEND = COL0 + TN + 2 * R;        // one past the window's last column
+  static constexpr int REND = COL0 + (TN - 16) + KL;    // one past the row-line reads' last column
+  static constexpr int LCOLS = cmax(WEND, NLR ? REND : 0);
+  static constexpr int PITCH = pick_pitch<T, VAR == VAR_STAR_ORTHO>(LCOLS);
+};
+
+template <typename T, int R, int VAR>
+__global__ __launch_bounds__(kThreads) void mfma2d_kernel(KArgs a) {
+  typedef Mfma16<T> MM;
+  typedef typename MM::acc_t acc_t;
+  typedef Mfma2DShape<T, R, VAR> S;
+  __shared__ __attribute__((aligned(16))) T lds[S::LROWS * S::PITCH];
+
+  const int64_t M = a.d0, N = a.d1;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 4, q = lane & 15;
+  const int tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tj = tile % a.tiles1, ti = tile / a.tiles1;
+  const int64_t i0 = (int64_t)ti * S::TM, j0 = (int64_t)tj * S::TN;
+
+  // Band fragments for this lane (packed by the plan in lane order).
+  const T* __restrict__ frag = (const T*)a.frag;
+  T af[S::NCH];
+#pragma unroll
+  for (int c = 0; c < S::NCH; ++c) af[c] = frag[c * 64 + lane];
+
+  if constexpr (S::LROWS > S::WROWS)
+    zero_region<T, kThreads>(lds, S::LROWS - S::WROWS, S::PITCH, S::PITCH, S::WROWS, 0);
+  if constexpr (S::LCOLS > S::WEND)
+    zero_region<T, kThreads>(lds, S::WROWS, S::LCOLS - S::WEND, S::PITCH, 0, S::WEND);
+  stage_window<T, R, S::WROWS, S::TN, S::PITCH, kThreads>(lds, (const T*)a.in, M, N, i0 - R, j0,
+                                                          a.periodic != 0);
+  __syncthreads();
+
+  acc_t acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = acc_t{};
+
+  // Lines along i: B operand row x = 4 cc + g of the wave's window rows.
+  const T* colbase = lds + (16 * w + g) * S::PITCH + S::COL0 + q;
+#pragma unroll
+  for (int li = 0; li < S::NLC; ++li) {
+    const int b = VAR == VAR_BOX ? li : R;
+#pragma unroll
+    for (int cc = 0; cc < S::CPL; ++cc) {
+      const T av = af[li * S::CPL + cc];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const T bv = colbase[(4 * cc) * S::PITCH + 16 * t + b];
+        acc[t] = MM::mma(av, bv, acc[t]);
+      }
+    }
+  }
+  if constexpr (VAR == VAR_STAR_ORTHO) {
+    // Line along j: A operand = input column segment H[r + p][y], y = 4 cc + g.
+    const T* rowbase = lds + (16 * w + R + q) * S::PITCH + S::COL0 + g;
+#pragma unroll
+    for (int cc = 0; cc < S::CPL; ++cc) {
+      const T sv = af[S::NLC * S::CPL + cc];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const T hv = rowbase[16 * t + 4 * cc];
+        acc[t] = MM::mma(hv, sv, acc[t]);
+      }
+    }
+  }
+  if constexpr (VAR == VAR_STAR_PARALLEL) {
+    // Single-weight lines b != r: D[p][q] += C^g[r][b] * H[p + r][q + b].
+    const T* __restrict__ c = (const T*)a.coef;
+    const int col = MM::col(lane);
+#pragma unroll
+    for (int b = 0; b <= 2 * R; ++b) {
+      if (b == R) continue;
+      const T wgt = c[R * (2 * R + 1) + b];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T* rp = lds + (16 * w + R + MM::row(lane, v)) * S::PITCH + S::COL0 + col + b;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t][v] += wgt * rp[16 * t];
+      }
+    }
+  }
+
+  T* out = (T*)a.out;
+  const int64_t gj = j0 + MM::col(lane);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t gi = i0 + 16 * w + MM::row(lane, v);
+    if (gi >= M) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (gj + 16 * t < N) out[gi * N + gj + 16 * t] = acc[t][v];
+    }
+  }
+}
+
+}  // namespace stencil

@@ -1,0 +1,311 @@
+// Host-side plan construction.
+//
+// A coefficient line (Section 3.2, "coefficient line summation", Eq. (9)) is
+// turned into a banded operand: for an output block of edge n and a line
+// along i holding C^g column b, T_b[p][x] = C^g[x - p][b] for 0 <= x - p <= 2r
+// (zero elsewhere), x indexing the n + 2r rows of the halo'd input.  These
+// are exactly the zero-padded coefficient vectors of Eq. (10)-(11): column x
+// of T_b is the vector that multiplies input row x.  Eq. (12) as printed pairs
+// the C^o column j with the input segment starting at column j; reading Eq. (1)
+// and Eq. (3)-(5) together, the segment shifted by j - r from the output must
+// carry C^g column j (C^s column 2r - j), which is what is built here (the two
+// agree for stencils symmetric in j, the case of the paper's examples).
+#include "plan.hpp"
+
+#include <cmath>
+#include <cstring>
+
+#include "kernels_2d.hpp"
+
+namespace stencil {
+
+namespace {
+
+int dtype_size(int dtype) { return dtype == STENCIL_F64 ? 8 : 4; }
+
+bool on_axis(int ndim, int R, const int* idx) {
+  int nz = 0;
+  for (int d = 0; d < ndim; ++d)
+    if (idx[d] != R) ++nz;
+  return nz <= 1;
+}
+
+template <typename T>
+void put(std::vector<uint8_t>& buf, size_t index, T v) {
+  std::memcpy(buf.data() + index * sizeof(T), &v, sizeof(T));
+}
+
+// Round-to-nearest-even conversions to 16-bit formats, written out from the
+// IEEE-754 encodings (binary32 -> bfloat16 / binary16).
+uint16_t to_bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+float from_bf16_bits(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+uint16_t to_f16_bits(float f) {
+  _Float16 h = (_Float16)f;  // host conversion rounds to nearest even
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+float from_f16_bits(uint16_t b) {
+  _Float16 h;
+  std::memcpy(&h, &b, 2);
+  return (float)h;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+double band_value(const double* cg2d, int R, int n, int axis, int index, int i, int j) {
+  const int W = 2 * R + 1;
+  if (axis == 0) {  // T_index[p = i][x = j]
+    const int p = i, x = j, a = x - p;
+    if (x < 0 || x >= n + 2 * R || p < 0 || p >= n || a < 0 || a > 2 * R) return 0.0;
+    return cg2d[a * W + index];
+  }
+  // S_index[y = i][q = j]
+  const int y = i, q = j, b = y - q;
+  if (y < 0 || y >= n + 2 * R || q < 0 || q >= n || b < 0 || b > 2 * R) return 0.0;
+  return cg2d[index * W + b];
+}
+
+static int validate(const stencil_desc_t* d) {
+  if (!d || !d->coeffs) return STENCIL_EINVAL;
+  if (d->ndim != 2 && d->ndim != 3) return STENCIL_EINVAL;
+  if (d->radius < 1 || d->radius > 4) return STENCIL_EINVAL;
+  if (d->shape != STENCIL_STAR && d->shape != STENCIL_BOX) return STENCIL_EINVAL;
+  if (d->boundary != STENCIL_BC_ZERO && d->boundary != STENCIL_BC_PERIODIC) return STENCIL_EINVAL;
+  if (d->dtype != STENCIL_F32 && d->dtype != STENCIL_F64) return STENCIL_EINVAL;
+  if (d->path < STENCIL_PATH_AUTO || d->path > STENCIL_PATH_MFMA_F16X3) return STENCIL_EINVAL;
+  if (d->lines < STENCIL_LINES_AUTO || d->lines > STENCIL_LINES_HYBRID) return STENCIL_EINVAL;
+  if (d->reserved != 0) return STENCIL_EINVAL;
+  int64_t total = 1;
+  for (int k = 0; k < d->ndim; ++k) {
+    if (d->dims[k] < 1 || d->dims[k] > (int64_t(1) << 31) - 1) return STENCIL_EINVAL;
+    total *= d->dims[k];
+    if (total > (int64_t(1) << 40)) return STENCIL_EINVAL;
+  }
+  const int R = d->radius, W = 2 * R + 1;
+  const int ncoef = d->ndim == 2 ? W * W : W * W * W;
+  for (int t = 0; t < ncoef; ++t) {
+    const double c = d->coeffs[t];
+    if (!std::isfinite(c)) return STENCIL_EINVAL;
+    if (d->shape == STENCIL_STAR && c != 0.0) {
+      int idx[3] = {t / W % W, t % W, 0};
+      if (d->ndim == 3) {
+        idx[0] = t / (W * W);
+        idx[1] = t / W % W;
+        idx[2] = t % W;
+      }
+      if (!on_axis(d->ndim, R, idx)) return STENCIL_EINVAL;
+    }
+  }
+  const bool split = d->path == STENCIL_PATH_MFMA_BF16X3 || d->path == STENCIL_PATH_MFMA_F16X3;
+  if (split && d->dtype != STENCIL_F32) return STENCIL_EUNSUPPORTED;
+  if (d->shape == STENCIL_BOX && d->lines != STENCIL_LINES_AUTO && d->lines != STENCIL_LINES_PARALLEL)
+    return STENCIL_EUNSUPPORTED;
+  if (d->shape == STENCIL_STAR && d->ndim == 2 && d->lines == STENCIL_LINES_HYBRID)
+    return STENCIL_EUNSUPPORTED;
+  if (d->shape == STENCIL_STAR && d->ndim == 3 && d->lines == STENCIL_LINES_ORTHOGONAL)
+    return STENCIL_EUNSUPPORTED;  // needs a second output block shape (Table 2); not built
+  return STENCIL_OK;
+}
+
+// ----------------------------------------------------------------- 2D packing
+
+static void pack_mfma2d(Resolved* rs, int R, int var, int dtype) {
+  const int n = 16;
+  const int KL = round_up(16 + 2 * R, 4), CPL = KL / 4;
+  const int NLC = var == VAR_BOX ? 2 * R + 1 : 1;
+  const int NLR = var == VAR_STAR_ORTHO ? 1 : 0;
+  const int NCH = (NLC + NLR) * CPL;
+  const int es = dtype_size(dtype);
+  rs->frag.assign((size_t)NCH * 64 * es, 0);
+  const double* cg = rs->cg.data();
+  for (int c = 0; c < NCH; ++c) {
+    for (int lane = 0; lane < 64; ++lane) {
+      double v;
+      if (c < NLC * CPL) {
+        const int li = c / CPL, cc = c % CPL;
+        const int b = var == VAR_BOX ? li : R;
+        // A operand: lane holds T_b[p = lane % 16][x = 4 cc + lane / 16]
+        v = band_value(cg, R, n, 0, b, lane % 16, 4 * cc + lane / 16);
+      } else {
+        const int cc = c - NLC * CPL;
+        // B operand: lane holds S[y = 4 cc + lane / 16][q = lane % 16], centre excluded
+        const int y = 4 * cc + lane / 16, q = lane % 16;
+        v = (y - q == R) ? 0.0 : band_value(cg, R, n, 1, R, y, q);
+      }
+      if (es == 8)
+        put<double>(rs->frag, (size_t)c * 64 + lane, v);
+      else
+        put<float>(rs->frag, (size_t)c * 64 + lane, (float)v);
+    }
+  }
+  rs->info.mfma_lines = NLC + NLR;
+  rs->info.valu_lines = var == VAR_STAR_PARALLEL ? 2 * R : 0;
+  rs->info.k_rows = NCH * 4;
+}
+
+// Split-precision 2D: lines along j (C^g rows a = 0..2r), transposed form
+// D[p][q] += sum_y H[p + a][y] * S_a[y][q]; one 16x16x32 MFMA per line and
+// part, K = 32 >= 16 + 2r.  B operand: lane l, element e holds
+// S_a[8 (l / 16) + e][l % 16], stored as hi and lo 16-bit parts.
+static void pack_split2d(Resolved* rs, int R, int kind) {
+  const int n = 16, NL = 2 * R + 1;
+  rs->frag.assign((size_t)NL * 2 * 64 * 8 * 2, 0);
+  const double* cg = rs->cg.data();
+  double cmax = 0.0;
+  for (double c : rs->cg) cmax = std::fmax(cmax, std::fabs(c));
+  float cscale = 1.0f, lscale = 1.0f;
+  if (kind == 1) {  // FP16: scale the coefficients into the upper normal range; lo parts carry 2^11
+    int e = 0;
+    if (cmax > 0.0) e = 14 - (int)std::floor(std::log2(cmax));
+    cscale = std::ldexp(1.0f, e);
+    lscale = std::ldexp(1.0f, 11);
+  }
+  for (int a = 0; a < NL; ++a) {
+    for (int lane = 0; lane < 64; ++lane) {
+      for (int e = 0; e < 8; ++e) {
+        const int y = 8 * (lane / 16) + e, q = lane % 16;
+        const float c = (float)band_value(cg, R, n, 1, a, y, q) * cscale;
+        uint16_t hi, lo;
+        if (kind == 0) {
+          hi = to_bf16_bits(c);
+          lo = to_bf16_bits(c - from_bf16_bits(hi));
+        } else {
+          hi = to_f16_bits(c);
+          lo = to_f16_bits((c - from_f16_bits(hi)) * lscale);
+        }
+        put<uint16_t>(rs->frag, ((size_t)(a * 2 + 0) * 64 + lane) * 8 + e, hi);
+        put<uint16_t>(rs->frag, ((size_t)(a * 2 + 1) * 64 + lane) * 8 + e, lo);
+      }
+    }
+  }
+  rs->out_scale = 1.0f / cscale;
+  rs->lo_scale = 1.0f / lscale;
+  rs->info.mfma_lines = NL;
+  rs->info.valu_lines = 0;
+  rs->info.k_rows = NL * 32;
+}
+
+int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
+  const int st = validate(desc);
+  if (st != STENCIL_OK) return st;
+  const stencil_desc_t& d = *desc;
+  const int R = d.radius, W = 2 * R + 1, nd = d.ndim;
+  const int ncoef = nd == 2 ? W * W : W * W * W;
+  rs->cg.resize(ncoef);
+  for (int t = 0; t < ncoef; ++t)
+    rs->cg[t] = d.dtype == STENCIL_F32 ? (double)(float)d.coeffs[t] : d.coeffs[t];
+
+  stencil_plan_info_t& in = rs->info;
+  std::memset(&in, 0, sizeof(in));
+  in.ndim = nd;
+  in.radius = R;
+  in.shape = d.shape;
+  in.boundary = d.boundary;
+  in.dtype = d.dtype;
+  const bool box = d.shape == STENCIL_BOX;
+  in.taps = box ? (nd == 2 ? W * W : W * W * W) : 2 * R * nd + 1;
+  in.useful_flops_per_point = 2.0 * in.taps;
+  in.bytes_per_point = 2 * dtype_size(d.dtype);
+  const int n = 16;
+
+  int path = d.path;
+  if (path == STENCIL_PATH_AUTO) path = STENCIL_PATH_MFMA;
+  int lines = d.lines;
+  if (box) {
+    lines = STENCIL_LINES_PARALLEL;
+  } else if (lines == STENCIL_LINES_AUTO) {
+    if (nd == 2) lines = R == 1 ? STENCIL_LINES_PARALLEL : STENCIL_LINES_ORTHOGONAL;
+    else lines = STENCIL_LINES_HYBRID;
+  }
+
+  KArgs& a = rs->args;
+  std::memset(&a, 0, sizeof(a));
+  a.d0 = d.dims[0];
+  a.d1 = d.dims[1];
+  a.d2 = nd == 3 ? d.dims[2] : 1;
+  a.periodic = d.boundary == STENCIL_BC_PERIODIC ? 1 : 0;
+  a.out_scale = 1.0f;
+  a.lo_scale = 1.0f;
+
+  // Dense coefficients in the arithmetic dtype (gather kernels, vector lines).
+  rs->coef.assign((size_t)ncoef * dtype_size(d.dtype), 0);
+  for (int t = 0; t < ncoef; ++t) {
+    if (d.dtype == STENCIL_F64) put<double>(rs->coef, t, rs->cg[t]);
+    else put<float>(rs->coef, t, (float)rs->cg[t]);
+  }
+
+  if (nd == 2) {
+    const int64_t t0 = ceil_div(d.dims[0], kTile2D), t1 = ceil_div(d.dims[1], kTile2D);
+    if (t0 * t1 > (int64_t(1) << 31) - 1) return STENCIL_EUNSUPPORTED;
+    a.tiles0 = (int32_t)t0;
+    a.tiles1 = (int32_t)t1;
+    rs->grid = dim3((unsigned)(t0 * t1));
+    in.tile_rows = kTile2D;
+    in.tile_cols = kTile2D;
+    if (path == STENCIL_PATH_GATHER) {
+      rs->family = FAM_GATHER2D;
+      rs->launch = find_gather2d(d.dtype, R, box);
+      in.executed_flops_per_point = 2.0 * in.taps;
+      lines = STENCIL_LINES_AUTO;
+    } else if (path == STENCIL_PATH_MFMA) {
+      rs->family = FAM_MFMA2D;
+      rs->variant = box ? VAR_BOX : (lines == STENCIL_LINES_PARALLEL ? VAR_STAR_PARALLEL : VAR_STAR_ORTHO);
+      rs->launch = find_mfma2d(d.dtype, R, rs->variant);
+      if (pack) pack_mfma2d(rs, R, rs->variant, d.dtype);
+      else {
+        const int KL = round_up(16 + 2 * R, 4);
+        const int nl = rs->variant == VAR_BOX ? W : (rs->variant == VAR_STAR_ORTHO ? 2 : 1);
+        in.mfma_lines = nl;
+        in.valu_lines = rs->variant == VAR_STAR_PARALLEL ? 2 * R : 0;
+        in.k_rows = nl * KL;
+      }
+      in.block_n = n;
+      in.executed_flops_per_point = 2.0 * in.k_rows + 2.0 * in.valu_lines;
+      if (rs->variant == VAR_BOX) in.rank1_per_block = (int64_t)W * (2 * R + n);
+      else if (rs->variant == VAR_STAR_PARALLEL) in.rank1_per_block = (2 * R + n) + (int64_t)2 * R * n;
+      else in.rank1_per_block = 2 * (2 * R + n);
+    } else {
+      // Split precision: lines along j, star handled as a box with zero weights.
+      rs->family = FAM_SPLIT2D;
+      rs->split16 = path == STENCIL_PATH_MFMA_F16X3 ? 1 : 0;
+      rs->launch = find_split2d(rs->split16, R, 0);
+      lines = STENCIL_LINES_PARALLEL;
+      if (pack) pack_split2d(rs, R, rs->split16);
+      else {
+        in.mfma_lines = W;
+        in.k_rows = W * 32;
+      }
+      if (rs->split16 == 1 && !pack) {
+        // scales are only known after packing; describe() does not need them
+      }
+      a.out_scale = rs->out_scale;
+      a.lo_scale = rs->lo_scale;
+      in.block_n = n;
+      in.executed_flops_per_point = 3.0 * 2.0 * in.k_rows;
+      in.rank1_per_block = (int64_t)W * (2 * R + n);
+    }
+  } else {
+    return STENCIL_EUNSUPPORTED;  // 3D families are added below as they are built
+  }
+  in.path = path;
+  in.lines = lines;
+  if (!rs->launch) return STENCIL_EUNSUPPORTED;
+  return STENCIL_OK;
+}
+
+}  // namespace stencil

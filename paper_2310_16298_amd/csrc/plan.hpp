@@ -1,0 +1,61 @@
+// Host-side plan: descriptor validation, coefficient line cover, banded
+// operand construction and MFMA fragment packing, kernel selection.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/stencil.h"
+#include "device_common.hpp"
+
+namespace stencil {
+
+typedef hipError_t (*LaunchFn)(const KArgs& args, dim3 grid, hipStream_t stream);
+
+// Kernel families.
+enum Family {
+  FAM_GATHER2D = 0,
+  FAM_MFMA2D = 1,      // outer-product form, grid dtype (f32/f64)
+  FAM_SPLIT2D = 2,     // outer-product form, bf16/f16 hi/lo split operands
+  FAM_GATHER3D = 3,
+  FAM_MFMA3D_STAR = 4, // hybrid cover, Algorithm 1 plane order
+  FAM_MFMA3D_BOX = 5,
+  FAM_SPLIT3D_STAR = 6,
+  FAM_SPLIT3D_BOX = 7
+};
+
+// Everything the plan resolves on the host.
+struct Resolved {
+  stencil_plan_info_t info{};
+  int family = 0;
+  int variant = 0;          // kernel-specific (line option)
+  int split16 = 0;          // 0 = bf16, 1 = f16 (split families)
+  std::vector<double> cg;   // C^g after rounding to the grid dtype
+  std::vector<uint8_t> frag;  // packed operand fragments (bytes)
+  std::vector<uint8_t> coef;  // dense C^g in the arithmetic dtype (bytes)
+  float out_scale = 1.0f, lo_scale = 1.0f;
+  KArgs args{};             // everything but in/out
+  dim3 grid;
+  LaunchFn launch = nullptr;
+};
+
+// Validate + resolve + pack (no device calls).  Returns a stencil status.
+int resolve_plan(const stencil_desc_t* desc, Resolved* out, bool pack);
+
+// Banded operand of a 2D coefficient line (see stencil_line_band).
+double band_value(const double* cg2d, int R, int n, int axis, int index, int i, int j);
+
+// Kernel lookups, one per family (defined next to the kernels).
+LaunchFn find_gather2d(int dtype, int R, bool box);
+LaunchFn find_mfma2d(int dtype, int R, int variant);
+LaunchFn find_split2d(int kind, int R, int variant);
+LaunchFn find_gather3d(int dtype, int R, bool box);
+LaunchFn find_mfma3d(int dtype, int R, bool box);
+LaunchFn find_split3d(int kind, int R, bool box);
+
+hipError_t launch_error_norms(const void* a, int a_dtype, const double* ref, int64_t n, double* out,
+                              hipStream_t s);
+
+}  // namespace stencil

@@ -1,0 +1,240 @@
+"""Thin ctypes binding of the C ABI in ``include/stencil.h``.
+
+Argument marshalling only: every step of the sweep runs in the HIP library.
+PyTorch provides device memory and streams (``tensor.data_ptr()`` and
+``torch.cuda.current_stream().cuda_stream``).  If ``libstencil.so`` is not
+built, loading raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstencil.so")
+
+# enums (mirror include/stencil.h)
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, EALIAS, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+STAR, BOX = 0, 1
+BC_ZERO, BC_PERIODIC = 0, 1
+F32, F64 = 0, 1
+PATH_AUTO, PATH_GATHER, PATH_MFMA, PATH_MFMA_BF16X3, PATH_MFMA_F16X3 = 0, 1, 2, 3, 4
+LINES_AUTO, LINES_PARALLEL, LINES_ORTHOGONAL, LINES_HYBRID = 0, 1, 2, 3
+
+PATH_NAMES = {PATH_AUTO: "auto", PATH_GATHER: "gather", PATH_MFMA: "mfma",
+              PATH_MFMA_BF16X3: "mfma_bf16x3", PATH_MFMA_F16X3: "mfma_f16x3"}
+
+
+class StencilError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32), ("radius", ctypes.c_int32), ("dims", ctypes.c_int64 * 3),
+        ("shape", ctypes.c_int32), ("boundary", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("path", ctypes.c_int32), ("lines", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("coeffs", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("path", ctypes.c_int32), ("lines", ctypes.c_int32),
+        ("ndim", ctypes.c_int32), ("radius", ctypes.c_int32), ("shape", ctypes.c_int32),
+        ("boundary", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("taps", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("tile_cols", ctypes.c_int32),
+        ("block_n", ctypes.c_int32), ("mfma_lines", ctypes.c_int32), ("valu_lines", ctypes.c_int32),
+        ("k_rows", ctypes.c_int32), ("rank1_per_block", ctypes.c_int64),
+        ("useful_flops_per_point", ctypes.c_double), ("executed_flops_per_point", ctypes.c_double),
+        ("bytes_per_point", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+EXPORTS = [
+    "stencil_version", "stencil_status_string", "stencil_desc_check", "stencil_plan_describe",
+    "stencil_line_band", "stencil_plan", "stencil_plan_info", "stencil_plan_destroy",
+    "stencil_apply", "stencil_run_steps", "stencil_error_norms",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libstencil.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2310_16298_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.stencil_version.restype = ctypes.c_char_p
+    lib.stencil_status_string.argtypes = [ctypes.c_int]
+    lib.stencil_status_string.restype = ctypes.c_char_p
+    lib.stencil_desc_check.argtypes = [ctypes.POINTER(Desc)]
+    lib.stencil_plan_describe.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(PlanInfo)]
+    lib.stencil_line_band.argtypes = [dp, i32, i32, i32, i32, dp]
+    lib.stencil_plan.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp)]
+    lib.stencil_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.stencil_plan_destroy.argtypes = [vp]
+    lib.stencil_apply.argtypes = [vp, vp, vp, vp]
+    lib.stencil_run_steps.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(i32)]
+    lib.stencil_error_norms.argtypes = [vp, i32, vp, i64, vp, vp]
+    for name in EXPORTS[2:]:
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load_library().stencil_status_string(int(status)).decode()
+
+
+def version() -> str:
+    return load_library().stencil_version().decode()
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise StencilError(status, where)
+
+
+def make_desc(dims: Sequence[int], radius: int, shape: int, coeffs, boundary: int = BC_ZERO,
+              dtype: int = F32, path: int = PATH_AUTO, lines: int = LINES_AUTO):
+    """Build a Desc; returns (desc, keepalive) -- keep the array alive while used."""
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    d = Desc()
+    d.ndim = len(dims)
+    d.radius = int(radius)
+    for k in range(3):
+        d.dims[k] = int(dims[k]) if k < len(dims) else 1
+    d.shape, d.boundary, d.dtype, d.path, d.lines, d.reserved = (
+        int(shape), int(boundary), int(dtype), int(path), int(lines), 0)
+    d.coeffs = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return d, c
+
+
+def desc_check(dims, radius, shape, coeffs, **kw) -> int:
+    d, keep = make_desc(dims, radius, shape, coeffs, **kw)
+    return load_library().stencil_desc_check(ctypes.byref(d))
+
+
+def describe(dims, radius, shape, coeffs, **kw) -> dict:
+    """Host-only: the plan choices and operation counts stencil_plan would make."""
+    d, keep = make_desc(dims, radius, shape, coeffs, **kw)
+    info = PlanInfo()
+    _check(load_library().stencil_plan_describe(ctypes.byref(d), ctypes.byref(info)), "stencil_plan_describe")
+    return info.as_dict()
+
+
+def line_band(coeffs, radius: int, n: int, axis: int, index: int) -> np.ndarray:
+    """Host-only: banded operand of one 2D coefficient line (see stencil.h)."""
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    k = n + 2 * radius
+    out = np.zeros((n, k) if axis == 0 else (k, n), dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(load_library().stencil_line_band(c.ctypes.data_as(dp), radius, n, axis, index,
+                                            out.ctypes.data_as(dp)), "stencil_line_band")
+    return out
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """A stencil plan on the current device.
+
+    ``Plan(dims, radius, shape, coeffs, boundary, dtype, path, lines)``; grids
+    are torch tensors on the plan's device, contiguous, of the plan's dims and
+    dtype (float32 / float64).
+    """
+
+    def __init__(self, dims, radius, shape, coeffs, boundary=BC_ZERO, dtype=F32,
+                 path=PATH_AUTO, lines=LINES_AUTO):
+        lib = load_library()
+        self.dims = tuple(int(v) for v in dims)
+        self.dtype = dtype
+        d, keep = make_desc(self.dims, radius, shape, coeffs, boundary=boundary, dtype=dtype,
+                            path=path, lines=lines)
+        h = ctypes.c_void_p()
+        _check(lib.stencil_plan(ctypes.byref(d), ctypes.byref(h)), "stencil_plan")
+        self._h = h
+        self._lib = lib
+        self.info = self._info()
+
+    def _info(self) -> dict:
+        info = PlanInfo()
+        _check(self._lib.stencil_plan_info(self._h, ctypes.byref(info)), "stencil_plan_info")
+        return info.as_dict()
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def _validate(self, *tensors):
+        torch = _torch()
+        want = torch.float64 if self.dtype == F64 else torch.float32
+        for t in tensors:
+            if not t.is_cuda:
+                raise ValueError("grid tensors must be on the GPU")
+            if t.dtype != want:
+                raise ValueError(f"grid dtype {t.dtype} != plan dtype {want}")
+            if not t.is_contiguous():
+                raise ValueError("grid tensors must be contiguous")
+            if tuple(t.shape) != self.dims:
+                raise ValueError(f"grid shape {tuple(t.shape)} != plan dims {self.dims}")
+
+    def apply(self, x, out, stream=None):
+        """One Jacobi step out = S(x), enqueued on ``stream``."""
+        self._validate(x, out)
+        _check(self._lib.stencil_apply(self._h, x.data_ptr(), out.data_ptr(), _stream_ptr(stream)),
+               "stencil_apply")
+        return out
+
+    def run_steps(self, x, tmp, steps: int, stream=None):
+        """``steps`` Jacobi steps ping-ponging between x and tmp; returns the
+        tensor that holds the final state."""
+        self._validate(x, tmp)
+        idx = ctypes.c_int32(0)
+        _check(self._lib.stencil_run_steps(self._h, x.data_ptr(), tmp.data_ptr(), int(steps),
+                                           _stream_ptr(stream), ctypes.byref(idx)), "stencil_run_steps")
+        return x if idx.value == 0 else tmp
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.stencil_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def error_norms(a, ref, stream=None):
+    """(sum (a-ref)^2, sum ref^2, max |a-ref|) computed on the GPU; ref float64."""
+    torch = _torch()
+    out = torch.empty(3, dtype=torch.float64, device=a.device)
+    dt = F64 if a.dtype == torch.float64 else F32
+    _check(load_library().stencil_error_norms(a.data_ptr(), dt, ref.data_ptr(), a.numel(), out.data_ptr(),
+                                              _stream_ptr(stream)), "stencil_error_norms")
+    return out

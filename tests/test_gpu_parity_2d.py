@@ -1,0 +1,157 @@
+"""GPU parity of the 2D paths against the CPU FP64 oracle (elementwise).
+
+Sizes span several 64x64 workgroup tiles with ragged tails in both axes;
+edge cases: extents below one tile and below the stencil width, integer data
+(bit-exact), pure shifts (orientation), and the run_steps contract."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_16298_amd import inputs
+from paper_2310_16298_amd import stencil as st
+
+from gpu_helpers import eff_coeffs, error_bound, run_gpu, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+FULL_PATHS = [(st.PATH_GATHER, st.F32), (st.PATH_GATHER, st.F64), (st.PATH_MFMA, st.F32), (st.PATH_MFMA, st.F64)]
+SPLIT_PATHS = [(st.PATH_MFMA_BF16X3, st.F32), (st.PATH_MFMA_F16X3, st.F32)]
+SHAPES = [(st.BOX, st.LINES_AUTO), (st.STAR, st.LINES_PARALLEL), (st.STAR, st.LINES_ORTHOGONAL)]
+
+
+def _case(dims, r, shape, lines, bc, dtype, path, steps, seed):
+    c = inputs.coefficients(2, r, shape, seed=seed, dtype=np.float64)
+    ce = eff_coeffs(c, dtype)
+    a0 = inputs.grid(dims, seed=seed + 1, dtype=np.float32 if dtype == st.F32 else np.float64)
+    want = oracle.run(a0, ce, r, shape, bc, steps)
+    got = run_gpu(a0, c, r, shape, bc, dtype, path, steps, lines=lines)
+    tol = error_bound(ce, 2, r, shape, dtype, path, steps, np.abs(a0).max())
+    err = np.abs(got - want).max()
+    assert err <= tol, f"max err {err:.3e} > bound {tol:.3e}"
+    return err
+
+
+@pytest.mark.parametrize("path,dtype", FULL_PATHS + SPLIT_PATHS)
+@pytest.mark.parametrize("shape,lines", SHAPES)
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("bc", [st.BC_ZERO, st.BC_PERIODIC])
+def test_random_ragged(path, dtype, shape, lines, r, bc):
+    if path in (st.PATH_MFMA_BF16X3, st.PATH_MFMA_F16X3) and lines == st.LINES_ORTHOGONAL:
+        lines = st.LINES_AUTO
+    _case((150, 203), r, shape, lines, bc, dtype, path, 3, seed=10 * r + bc)
+
+
+@pytest.mark.parametrize("path,dtype", FULL_PATHS + SPLIT_PATHS)
+@pytest.mark.parametrize("dims", [(1, 1), (1, 7), (5, 3), (3, 64), (64, 64), (65, 1), (9, 130)])
+@pytest.mark.parametrize("bc", [st.BC_ZERO, st.BC_PERIODIC])
+def test_small_and_degenerate_extents(path, dtype, dims, bc):
+    _case(dims, 4, st.BOX, st.LINES_AUTO, bc, dtype, path, 2, seed=7)
+    _case(dims, 2, st.STAR, st.LINES_AUTO, bc, dtype, path, 2, seed=8)
+
+
+def _int_steps(c, limit):
+    s = float(np.abs(c).sum())
+    t = 1
+    while 8 * s ** (t + 1) < limit and t < 4:
+        t += 1
+    return t
+
+
+@pytest.mark.parametrize("path,dtype", FULL_PATHS + SPLIT_PATHS)
+@pytest.mark.parametrize("shape", [st.BOX, st.STAR])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_integer_bit_exact(path, dtype, shape, r):
+    """Integer data and weights: the sum is exact in every path, so the result
+    is unique and must match bit for bit."""
+    c = inputs.int_coefficients(2, r, shape, seed=20 + r)
+    limit = 2.0 ** 16 if path in (st.PATH_MFMA_BF16X3, st.PATH_MFMA_F16X3) else 2.0 ** 24
+    if path == st.PATH_MFMA_F16X3:
+        limit = 6.0e4
+    steps = _int_steps(c, limit)
+    a0 = inputs.int_grid((97, 140), seed=30 + r, dtype=np.float32 if dtype == st.F32 else np.float64)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        want = oracle.run(a0, c, r, shape, bc, steps)
+        got = run_gpu(a0, c, r, shape, bc, dtype, path, steps)
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("path,dtype", FULL_PATHS + SPLIT_PATHS)
+@pytest.mark.parametrize("offset", [(-4, 4), (4, -4), (-3, 0), (0, 2), (1, -1), (0, 0)])
+def test_pure_shift_orientation(path, dtype, offset):
+    """A single unit weight at gather offset o gives B[x] = A[x + o] exactly
+    (an asymmetric stencil: a mirrored band would move the data the other way)."""
+    r = 4
+    c = inputs.shift_coefficients(2, r, offset)
+    shape = st.STAR if 0 in offset else st.BOX
+    if path in (st.PATH_MFMA_BF16X3, st.PATH_MFMA_F16X3):
+        # split operands represent x exactly only when x = hi + lo: use integers
+        a0 = inputs.int_grid((77, 91), seed=40, lo=-30000, hi=30000)
+    else:
+        a0 = inputs.grid((77, 91), seed=40, dtype=np.float32 if dtype == st.F32 else np.float64)
+    got = run_gpu(a0, c, r, shape, st.BC_PERIODIC, dtype, path, 1)
+    want = np.roll(a0.astype(np.float64), shift=(-offset[0], -offset[1]), axis=(0, 1))
+    assert np.array_equal(got, want)
+    gotz = run_gpu(a0, c, r, shape, st.BC_ZERO, dtype, path, 1)
+    assert np.array_equal(gotz, oracle.run(a0, c, r, shape, st.BC_ZERO, 1))
+
+
+@pytest.mark.parametrize("path", [st.PATH_GATHER, st.PATH_MFMA, st.PATH_MFMA_BF16X3])
+def test_run_steps_resume_is_bitwise(path):
+    """run_steps(k) then run_steps(T-k) equals run_steps(T): the grid is the
+    whole state, and the kernels are deterministic."""
+    torch = torch_cuda()
+    r = 2
+    c = inputs.coefficients(2, r, st.BOX, seed=50, dtype=np.float64)
+    a0 = inputs.grid((130, 129), seed=51)
+    plan = st.Plan(a0.shape, r, st.BOX, c, boundary=st.BC_PERIODIC, dtype=st.F32, path=path)
+    x = torch.from_numpy(a0).cuda()
+    full = plan.run_steps(x.clone(), torch.empty_like(x), 7).clone()
+    part = plan.run_steps(x.clone(), torch.empty_like(x), 3).clone()
+    rest = plan.run_steps(part, torch.empty_like(x), 4)
+    torch.cuda.synchronize()
+    assert torch.equal(full, rest)
+    one = x.clone()
+    for _ in range(7):
+        nxt = torch.empty_like(one)
+        plan.apply(one, nxt)
+        one = nxt
+    torch.cuda.synchronize()
+    assert torch.equal(full, one)
+
+
+def test_abi_errors_on_device():
+    torch = torch_cuda()
+    c = inputs.coefficients(2, 1, st.BOX, seed=60, dtype=np.float64)
+    plan = st.Plan((64, 64), 1, st.BOX, c, path=st.PATH_MFMA)
+    x = torch.zeros(64, 64, device="cuda")
+    lib = st.load_library()
+    s = torch.cuda.current_stream().cuda_stream
+    assert lib.stencil_apply(plan.handle, x.data_ptr(), x.data_ptr(), s) == st.EALIAS
+    assert lib.stencil_apply(plan.handle, x.data_ptr(), x.data_ptr() + 4, s) == st.EALIAS
+    y = torch.zeros_like(x)
+    assert lib.stencil_run_steps(plan.handle, x.data_ptr(), y.data_ptr(), -1, s, None) == st.EINVAL
+    x.fill_(3.0)
+    res = plan.run_steps(x, y, 0)
+    torch.cuda.synchronize()
+    assert res.data_ptr() == x.data_ptr() and float(res[0, 0]) == 3.0
+
+
+def test_auto_path_matches_oracle():
+    c = inputs.coefficients(2, 3, st.BOX, seed=70, dtype=np.float64)
+    ce = eff_coeffs(c, st.F32)
+    a0 = inputs.grid((200, 130), seed=71)
+    got = run_gpu(a0, c, 3, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_AUTO, 4)
+    want = oracle.run(a0, ce, 3, st.BOX, st.BC_PERIODIC, 4)
+    assert np.abs(got - want).max() <= error_bound(ce, 2, 3, st.BOX, st.F32, st.PATH_MFMA_BF16X3, 4, 1.0)
+
+
+def test_error_norms_kernel():
+    torch = torch_cuda()
+    a = torch.from_numpy(inputs.grid((300, 301), seed=80)).cuda()
+    ref = a.double() + 1e-3
+    ref[5, 7] += 0.5
+    out = st.error_norms(a, ref).cpu().numpy()
+    d = (a.double() - ref).cpu().numpy()
+    assert np.isclose(out[0], (d ** 2).sum(), rtol=1e-12)
+    assert np.isclose(out[1], (ref.cpu().numpy() ** 2).sum(), rtol=1e-12)
+    assert out[2] == np.abs(d).max()

@@ -1,0 +1,227 @@
+"""Host-side tests of the C-ABI library (no GPU needed): symbol exports,
+descriptor validation, the band builder against the paper's printed
+coefficient-line examples, and the plan's operation counts against the
+closed forms of Section 3.4 and Tables 1-2."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2310_16298_amd import inputs
+from paper_2310_16298_amd import stencil as st
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(st.LIB_PATH):
+        from paper_2310_16298_amd import build
+        build.build()
+    return st.load_library()
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "stencil.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stencil_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(names) == sorted(st.EXPORTS)
+
+
+def test_status_strings(lib):
+    for s in (st.OK, st.EINVAL, st.EUNSUPPORTED, st.ENOMEM, st.EHIP, st.EALIAS, st.EINTERNAL):
+        assert st.status_string(s) not in ("", "unknown status")
+    assert st.status_string(99) == "unknown status"
+    assert "gfx950" in st.version()
+
+
+def _box(nd, r):
+    return inputs.coefficients(nd, r, inputs.BOX, seed=1, dtype=np.float64)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dims=(16,), radius=1),                     # 1D has no outer-product form
+    dict(dims=(16, 16, 16, 16), radius=1),
+    dict(dims=(16, 16), radius=0),
+    dict(dims=(16, 16), radius=5),
+    dict(dims=(0, 16), radius=1),
+    dict(dims=(16, 16), radius=1, boundary=7),
+    dict(dims=(16, 16), radius=1, dtype=5),
+    dict(dims=(16, 16), radius=1, path=9),
+])
+def test_desc_check_rejects(lib, bad):
+    dims, r = bad.pop("dims"), bad.pop("radius")
+    nd = len(dims)
+    rr = max(r, 1)
+    c = np.ones((2 * rr + 1,) * max(nd, 1)) if nd in (2, 3) else np.ones(3)
+    if r != rr or nd not in (2, 3):
+        c = np.ones((3, 3))
+    d, keep = st.make_desc(dims, r, inputs.BOX, c, **bad)
+    if nd not in (2, 3):
+        d.ndim = nd
+    assert lib.stencil_desc_check(ctypes.byref(d)) == st.EINVAL
+
+
+def test_desc_check_star_off_axis_and_nonfinite(lib):
+    c = inputs.coefficients(2, 2, inputs.STAR, seed=2, dtype=np.float64)
+    assert st.desc_check((32, 32), 2, inputs.STAR, c) == st.OK
+    bad = c.copy()
+    bad[0, 0] = 0.5
+    assert st.desc_check((32, 32), 2, inputs.STAR, bad) == st.EINVAL
+    bad = c.copy()
+    bad[2, 2] = np.nan
+    assert st.desc_check((32, 32), 2, inputs.STAR, bad) == st.EINVAL
+    c3 = inputs.coefficients(3, 1, inputs.STAR, seed=3, dtype=np.float64)
+    bad3 = c3.copy()
+    bad3[0, 1, 0] = 1.0
+    assert st.desc_check((8, 8, 8), 1, inputs.STAR, bad3) == st.EINVAL
+
+
+def test_desc_check_unsupported(lib):
+    c = _box(2, 1)
+    assert st.desc_check((32, 32), 1, inputs.BOX, c, dtype=st.F64, path=st.PATH_MFMA_BF16X3) == st.EUNSUPPORTED
+    assert st.desc_check((32, 32), 1, inputs.BOX, c, lines=st.LINES_ORTHOGONAL) == st.EUNSUPPORTED
+    s = inputs.coefficients(2, 1, inputs.STAR, seed=4, dtype=np.float64)
+    assert st.desc_check((32, 32), 1, inputs.STAR, s, lines=st.LINES_HYBRID) == st.EUNSUPPORTED
+
+
+def test_null_arguments(lib):
+    assert lib.stencil_desc_check(None) == st.EINVAL
+    assert lib.stencil_plan(None, None) == st.EINVAL
+    assert lib.stencil_plan_info(None, None) == st.EINVAL
+    assert lib.stencil_apply(None, None, None, None) == st.EINVAL
+    assert lib.stencil_run_steps(None, None, None, 1, None, None) == st.EINVAL
+    assert lib.stencil_plan_destroy(None) == st.OK
+
+
+# ------------------------------------------------------------ band builder
+
+def _golden(name):
+    rows = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            rows.append(line.split())
+    return rows
+
+
+def _symbolic_cg():
+    """Prime-valued C^g so that a misplaced entry is visible."""
+    return np.array([[2., 3., 5.], [7., 11., 13.], [17., 19., 23.]])
+
+
+def _name_value(cg, name):
+    if name == "0":
+        return 0.0
+    assert name[0] == "C"
+    return cg[int(name[1]), int(name[2])]
+
+
+def test_band_reproduces_eq9(lib):
+    """CLS(*,1) with n = 3 (Eq. (9)): column x of the band is the coefficient
+    vector multiplying input row A[i-2+x][j]."""
+    cg = _symbolic_cg()
+    band = st.line_band(cg, 1, 3, 0, 1)
+    assert band.shape == (3, 5)
+    rows = _golden("eq9_cls_middle_column.txt")
+    assert len(rows) == 5
+    for x, row in enumerate(rows):
+        assert int(row[0]) == x - 2
+        want = [_name_value(cg, nm) for nm in row[1:]]
+        assert list(band[:, x]) == want
+
+
+def test_band_reproduces_eq14_row_line(lib):
+    """Row line CLS(1,*) (Eq. (14)): input column j reaches outputs j-1, j, j+1
+    with C12, C11, C10."""
+    cg = _symbolic_cg()
+    n = 4
+    band = st.line_band(cg, 1, n, 1, 1)  # (n+2) x n
+    rows = _golden("eq14_row_line.txt")
+    # input column y = q + 1 + d_in ... take the centre input column y = 1 + q0
+    for q0 in range(1, n - 1):
+        y = q0 + 1  # window column of input column j = output column q0
+        for dq, name in rows:
+            assert band[y, q0 + int(dq)] == _name_value(cg, name)
+
+
+def test_band_star_line_cover_eq13(lib):
+    """Eq. (13): the 2D 5-point scatter matrix has full middle row/column and
+    zero corners; the side column lines of a star therefore carry a single
+    weight each (scalar x vector updates)."""
+    rows = _golden("eq13_star5_scatter.txt")
+    cg = _symbolic_cg() * np.array([[0, 1, 0], [1, 1, 1], [0, 1, 0]])
+    # C^s = J C^g J read back from the printed matrix
+    for sr, row in enumerate(rows):
+        for sc, name in enumerate(row):
+            assert cg[2 - sr, 2 - sc] == _name_value(_symbolic_cg(), name)
+    for b in (0, 2):
+        band = st.line_band(cg, 1, 8, 0, b)
+        assert np.count_nonzero(band) == 8  # one diagonal: n scalar-vector updates
+    band = st.line_band(cg, 1, 8, 0, 1)
+    assert np.count_nonzero(band) == 3 * 8
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_band_is_eq1_consistent(lib, r):
+    """Summing band x shifted input over all lines reproduces Eq. (1) on an
+    interior block (orientation check with an asymmetric C^g)."""
+    rng = np.random.default_rng(r)
+    cg = rng.integers(-9, 10, (2 * r + 1, 2 * r + 1)).astype(np.float64)
+    n = 8
+    h = rng.integers(-9, 10, (n + 2 * r, n + 2 * r)).astype(np.float64)  # halo'd input window
+    got = np.zeros((n, n))
+    for b in range(2 * r + 1):
+        got += st.line_band(cg, r, n, 0, b) @ h[:, b:b + n]
+    want = np.zeros((n, n))
+    for p in range(n):
+        for q in range(n):
+            want[p, q] = sum(cg[a, b] * h[p + a, q + b] for a in range(2 * r + 1) for b in range(2 * r + 1))
+    assert np.array_equal(got, want)
+    got2 = np.zeros((n, n))
+    for a in range(2 * r + 1):
+        got2 += h[a:a + n, :] @ st.line_band(cg, r, n, 1, a)
+    assert np.array_equal(got2, want)
+
+
+def test_line_band_rejects(lib):
+    cg = _symbolic_cg()
+    with pytest.raises(st.StencilError):
+        st.line_band(cg, 1, 3, 2, 0)
+    with pytest.raises(st.StencilError):
+        st.line_band(cg, 1, 3, 0, 3)
+
+
+# -------------------------------------------------------- operation counts
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_counts_2d(lib, r):
+    n = 16
+    box = st.describe((64, 64), r, inputs.BOX, _box(2, r), path=st.PATH_MFMA)
+    assert box["taps"] == (2 * r + 1) ** 2
+    assert box["rank1_per_block"] == (2 * r + 1) * (2 * r + n)      # Section 3.4
+    assert box["mfma_lines"] == 2 * r + 1
+    assert box["k_rows"] >= box["rank1_per_block"]
+    s = inputs.coefficients(2, r, inputs.STAR, seed=5, dtype=np.float64)
+    par = st.describe((64, 64), r, inputs.STAR, s, path=st.PATH_MFMA, lines=st.LINES_PARALLEL)
+    assert par["rank1_per_block"] == (2 * r + n) + 2 * r * n        # Table 1, parallel
+    assert par["mfma_lines"] == 1 and par["valu_lines"] == 2 * r
+    orth = st.describe((64, 64), r, inputs.STAR, s, path=st.PATH_MFMA, lines=st.LINES_ORTHOGONAL)
+    assert orth["rank1_per_block"] == 2 * (2 * r + n)               # Table 1, orthogonal
+    assert orth["taps"] == 4 * r + 1
+    auto = st.describe((64, 64), r, inputs.STAR, s, path=st.PATH_MFMA)
+    assert auto["lines"] == (st.LINES_PARALLEL if r == 1 else st.LINES_ORTHOGONAL)
+    g = st.describe((64, 64), r, inputs.BOX, _box(2, r), path=st.PATH_GATHER)
+    assert g["executed_flops_per_point"] == 2 * (2 * r + 1) ** 2
+    assert g["bytes_per_point"] == 8
+    assert st.describe((64, 64), r, inputs.BOX, _box(2, r), dtype=st.F64, path=st.PATH_GATHER)["bytes_per_point"] == 16
