@@ -112,6 +112,7 @@ def load_traffic(kernel_key: str, src_hash: str):
 
 
 def main() -> int:
+    global RADII, JACOBI_STEPS
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed bench steps (one step = 4 solves x 100 Jacobi steps)")
@@ -119,6 +120,11 @@ def main() -> int:
     ap.add_argument("--headline", default="auto", choices=["auto", "mfma", "gather", "mfma_f16x3", "mfma_bf16x3"])
     ap.add_argument("--paths", default="gather,mfma,mfma_f16x3,mfma_bf16x3,auto")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--radii", default="1,2,3,4", help="orders to run (profiling runs use a subset)")
+    ap.add_argument("--jacobi-steps", type=int, default=JACOBI_STEPS,
+                    help="Jacobi steps per solve (profiling runs only; the benchmark uses 100)")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="first run N plain device copies of one grid (known bytes) for counter scaling")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU runs are not part of this build.",
@@ -139,10 +145,18 @@ def main() -> int:
     if args.headline not in paths:
         paths.append(args.headline)
 
+    RADII = tuple(int(v) for v in args.radii.split(","))
+    JACOBI_STEPS = args.jacobi_steps
     a0 = inputs.grid(DIMS, seed=INPUT_SEED, dtype=np.float32)
     coeffs = {r: inputs.coefficients(2, r, inputs.BOX, seed=COEF_SEED0 + r, dtype=np.float64) for r in RADII}
     a0_dev = torch.from_numpy(a0).cuda()
     stream = torch.cuda.Stream()
+    if args.calibrate_copy:
+        dst = torch.empty_like(a0_dev)
+        for _ in range(args.calibrate_copy):
+            dst.copy_(a0_dev)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration: {args.calibrate_copy} copies of {a0_dev.numel() * 4} bytes", file=sys.stderr)
     pts_per_solve = DIMS[0] * DIMS[1] * JACOBI_STEPS
 
     results = {}
@@ -163,7 +177,7 @@ def main() -> int:
     # one bench step = the four solves; per-step time = sum of the per-order medians
     step_times = [sum(head[r]["times"][k] for r in RADII) for k in range(args.steps)]
     ms_per_step = float(np.median(step_times))
-    value = 4 * pts_per_solve / (ms_per_step * 1e-3) / 1e9
+    value = len(RADII) * pts_per_solve / (ms_per_step * 1e-3) / 1e9
 
     # dominant kernel: the order with the largest share of the step
     r_dom = max(RADII, key=lambda r: head[r]["ms_per_solve"])

@@ -1,12 +1,14 @@
 // 2D stencil kernels: the gather-form baseline and the outer-product form on
 // MFMA in the grid dtype (FP32 or FP64).
 //
-// Both stage a 64x64 output tile plus an r-wide halo in LDS (one workgroup of
-// four waves per tile) and differ only in how the sum is formed.
+// Both walk a 64-column strip in blocks of 64 rows (four waves per
+// workgroup), stream the input rows through an LDS window with an r-wide
+// halo (stream2d.hpp), and differ only in how each block's sum is formed.
 #pragma once
 
 #include "device_common.hpp"
 #include "mfma_traits.hpp"
+#include "stream2d.hpp"
 
 namespace stencil {
 
@@ -36,49 +38,64 @@ __host__ __device__ constexpr int pick_pitch(int cols) {
 // ---------------------------------------------------------------------------
 template <typename T, int R, bool BOX>
 __global__ __launch_bounds__(kThreads) void gather2d_kernel(KArgs a) {
-  constexpr int TM = kTile2D, TN = kTile2D, W = 2 * R + 1;
-  constexpr int WROWS = TM + 2 * R;
+  constexpr int BM = kTile2D, TN = kTile2D, W = 2 * R + 1;
+  constexpr int WROWS = BM + 2 * R, WCOLS = TN + 2 * R;
   constexpr int COL0 = lds_col0<T, R>();
-  constexpr int PITCH = pick_pitch<T, false>(COL0 + TN + 2 * R);
+  constexpr int PITCH = pick_pitch<T, false>(COL0 + WCOLS);
   constexpr int STRIP = 16;
   __shared__ __attribute__((aligned(16))) T lds[WROWS * PITCH];
 
   const int64_t M = a.d0, N = a.d1;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int tj = tile % a.tiles1, ti = tile / a.tiles1;
-  const int64_t i0 = (int64_t)ti * TM, j0 = (int64_t)tj * TN;
-  stage_window<T, R, WROWS, TN, PITCH, kThreads>(lds, (const T*)a.in, M, N, i0 - R, j0, a.periodic != 0);
+  const bool periodic = a.periodic != 0;
+  const T* __restrict__ in = (const T*)a.in;
+  T* __restrict__ out = (T*)a.out;
+  const Strip2D sp = decode_strip(a, TN);
+  const bool fast = strip_fast(in, N, sp.j0, TN);
+  PlainWriter<T, R, PITCH> wr{lds};
+  stage_window<T, R, WROWS, TN, PITCH, kThreads>(lds, in, M, N, sp.i0 - R, sp.j0, periodic);
   __syncthreads();
 
   const T* __restrict__ c = (const T*)a.coef;
-  const int q = threadIdx.x & 63;       // column within the tile
-  const int s = threadIdx.x >> 6;       // strip: rows 16 s .. 16 s + 15
-  T acc[STRIP];
-#pragma unroll
-  for (int p = 0; p < STRIP; ++p) acc[p] = T(0);
+  const int q = threadIdx.x & 63;  // column within the strip
+  const int s = threadIdx.x >> 6;  // rows 16 s .. 16 s + 15 of each block
   const T* base = lds + (STRIP * s) * PITCH + COL0 + q;
+  RowPrefetch<T, R, BM, TN, kThreads> pf;
+  RowMover<T, R, WCOLS, kThreads> mv;
+  for (int64_t ib = sp.i0; ib < sp.i1; ib += BM) {
+    const bool more = ib + BM < sp.i1;
+    if (more) pf.fetch(in, M, N, ib + BM + R, sp.j0, periodic, fast);
+    T acc[STRIP];
 #pragma unroll
-  for (int x = 0; x < STRIP + 2 * R; ++x) {
-    T h[W];
+    for (int p = 0; p < STRIP; ++p) acc[p] = T(0);
 #pragma unroll
-    for (int b = 0; b < W; ++b) h[b] = base[x * PITCH + b];
+    for (int x = 0; x < STRIP + 2 * R; ++x) {
+      T h[W];
 #pragma unroll
-    for (int p = 0; p < STRIP; ++p) {
-      const int aa = x - p;  // coefficient row: input row x reaches output row p through C^g[x-p][.]
-      if (aa < 0 || aa > 2 * R) continue;
+      for (int b = 0; b < W; ++b) h[b] = base[x * PITCH + b];
 #pragma unroll
-      for (int b = 0; b < W; ++b) {
-        if (!BOX && aa != R && b != R) continue;
-        acc[p] += c[aa * W + b] * h[b];
+      for (int p = 0; p < STRIP; ++p) {
+        const int aa = x - p;  // input row x reaches output row p through C^g[x-p][.]
+        if (aa < 0 || aa > 2 * R) continue;
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+          if (!BOX && aa != R && b != R) continue;
+          acc[p] += c[aa * W + b] * h[b];
+        }
       }
     }
-  }
-  T* out = (T*)a.out;
-  const int64_t gj = j0 + q;
+    const int64_t gj = sp.j0 + q;
 #pragma unroll
-  for (int p = 0; p < STRIP; ++p) {
-    const int64_t gi = i0 + STRIP * s + p;
-    if (gi < M && gj < N) out[gi * N + gj] = acc[p];
+    for (int p = 0; p < STRIP; ++p) {
+      const int64_t gi = ib + STRIP * s + p;
+      if (gi < sp.i1 && gj < N) out[gi * N + gj] = acc[p];
+    }
+    if (more) mv.load([&](int rr, int cc) { return lds[(BM + rr) * PITCH + COL0 + cc]; });
+    __syncthreads();
+    if (more) {
+      mv.store([&](int rr, int cc, T v) { lds[rr * PITCH + COL0 + cc] = v; });
+      pf.commit(2 * R, wr);
+    }
+    __syncthreads();
   }
 }
 
@@ -126,88 +143,109 @@ __global__ __launch_bounds__(kThreads) void mfma2d_kernel(KArgs a) {
   typedef Mfma16<T> MM;
   typedef typename MM::acc_t acc_t;
   typedef Mfma2DShape<T, R, VAR> S;
+  constexpr int BM = S::TM, WCOLS = S::TN + 2 * R;
   __shared__ __attribute__((aligned(16))) T lds[S::LROWS * S::PITCH];
 
   const int64_t M = a.d0, N = a.d1;
+  const bool periodic = a.periodic != 0;
+  const T* __restrict__ in = (const T*)a.in;
+  T* __restrict__ out = (T*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, q = lane & 15;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int tj = tile % a.tiles1, ti = tile / a.tiles1;
-  const int64_t i0 = (int64_t)ti * S::TM, j0 = (int64_t)tj * S::TN;
+  const Strip2D sp = decode_strip(a, S::TN);
+  const bool fast = strip_fast(in, N, sp.j0, S::TN);
 
   // Band fragments for this lane (packed by the plan in lane order).
   const T* __restrict__ frag = (const T*)a.frag;
   T af[S::NCH];
 #pragma unroll
   for (int c = 0; c < S::NCH; ++c) af[c] = frag[c * 64 + lane];
+  T cw[2 * R + 1];  // parallel star: single-weight lines C^g[r][b]
+  if constexpr (VAR == VAR_STAR_PARALLEL) {
+    const T* __restrict__ c = (const T*)a.coef;
+#pragma unroll
+    for (int b = 0; b <= 2 * R; ++b) cw[b] = c[R * (2 * R + 1) + b];
+  }
 
   if constexpr (S::LROWS > S::WROWS)
     zero_region<T, kThreads>(lds, S::LROWS - S::WROWS, S::PITCH, S::PITCH, S::WROWS, 0);
   if constexpr (S::LCOLS > S::WEND)
     zero_region<T, kThreads>(lds, S::WROWS, S::LCOLS - S::WEND, S::PITCH, 0, S::WEND);
-  stage_window<T, R, S::WROWS, S::TN, S::PITCH, kThreads>(lds, (const T*)a.in, M, N, i0 - R, j0,
-                                                          a.periodic != 0);
+  stage_window<T, R, S::WROWS, S::TN, S::PITCH, kThreads>(lds, in, M, N, sp.i0 - R, sp.j0, periodic);
   __syncthreads();
 
-  acc_t acc[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = acc_t{};
-
+  PlainWriter<T, R, S::PITCH> wr{lds};
+  RowPrefetch<T, R, BM, S::TN, kThreads> pf;
+  RowMover<T, R, WCOLS, kThreads> mv;
   // Lines along i: B operand row x = 4 cc + g of the wave's window rows.
   const T* colbase = lds + (16 * w + g) * S::PITCH + S::COL0 + q;
+  const T* rowbase = lds + (16 * w + R + q) * S::PITCH + S::COL0 + g;
+  for (int64_t ib = sp.i0; ib < sp.i1; ib += BM) {
+    const bool more = ib + BM < sp.i1;
+    if (more) pf.fetch(in, M, N, ib + BM + R, sp.j0, periodic, fast);
+    acc_t acc[4];
 #pragma unroll
-  for (int li = 0; li < S::NLC; ++li) {
-    const int b = VAR == VAR_BOX ? li : R;
+    for (int t = 0; t < 4; ++t) acc[t] = acc_t{};
 #pragma unroll
-    for (int cc = 0; cc < S::CPL; ++cc) {
-      const T av = af[li * S::CPL + cc];
+    for (int li = 0; li < S::NLC; ++li) {
+      const int b = VAR == VAR_BOX ? li : R;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const T bv = colbase[(4 * cc) * S::PITCH + 16 * t + b];
-        acc[t] = MM::mma(av, bv, acc[t]);
+      for (int cc = 0; cc < S::CPL; ++cc) {
+        const T av = af[li * S::CPL + cc];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const T bv = colbase[(4 * cc) * S::PITCH + 16 * t + b];
+          acc[t] = MM::mma(av, bv, acc[t]);
+        }
       }
     }
-  }
-  if constexpr (VAR == VAR_STAR_ORTHO) {
-    // Line along j: A operand = input column segment H[r + p][y], y = 4 cc + g.
-    const T* rowbase = lds + (16 * w + R + q) * S::PITCH + S::COL0 + g;
+    if constexpr (VAR == VAR_STAR_ORTHO) {
+      // Line along j: A operand = input column segment H[r + p][y], y = 4 cc + g.
 #pragma unroll
-    for (int cc = 0; cc < S::CPL; ++cc) {
-      const T sv = af[S::NLC * S::CPL + cc];
+      for (int cc = 0; cc < S::CPL; ++cc) {
+        const T sv = af[S::NLC * S::CPL + cc];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const T hv = rowbase[16 * t + 4 * cc];
-        acc[t] = MM::mma(hv, sv, acc[t]);
+        for (int t = 0; t < 4; ++t) {
+          const T hv = rowbase[16 * t + 4 * cc];
+          acc[t] = MM::mma(hv, sv, acc[t]);
+        }
       }
     }
-  }
-  if constexpr (VAR == VAR_STAR_PARALLEL) {
-    // Single-weight lines b != r: D[p][q] += C^g[r][b] * H[p + r][q + b].
-    const T* __restrict__ c = (const T*)a.coef;
-    const int col = MM::col(lane);
-#pragma unroll
-    for (int b = 0; b <= 2 * R; ++b) {
-      if (b == R) continue;
-      const T wgt = c[R * (2 * R + 1) + b];
+    if constexpr (VAR == VAR_STAR_PARALLEL) {
+      // Single-weight lines b != r: D[p][q] += C^g[r][b] * H[p + r][q + b].
+      const int col = MM::col(lane);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const T* rp = lds + (16 * w + R + MM::row(lane, v)) * S::PITCH + S::COL0 + col + b;
+        const T* rp = lds + (16 * w + R + MM::row(lane, v)) * S::PITCH + S::COL0 + col;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t][v] += wgt * rp[16 * t];
+        for (int t = 0; t < 4; ++t) {
+          T sum = T(0);
+#pragma unroll
+          for (int b = 0; b <= 2 * R; ++b) {
+            if (b == R) continue;
+            sum += cw[b] * rp[16 * t + b];
+          }
+          acc[t][v] += sum;
+        }
       }
     }
-  }
-
-  T* out = (T*)a.out;
-  const int64_t gj = j0 + MM::col(lane);
+    const int64_t gj = sp.j0 + MM::col(lane);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int64_t gi = i0 + 16 * w + MM::row(lane, v);
-    if (gi >= M) continue;
+    for (int v = 0; v < 4; ++v) {
+      const int64_t gi = ib + 16 * w + MM::row(lane, v);
+      if (gi >= sp.i1) continue;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (gj + 16 * t < N) out[gi * N + gj + 16 * t] = acc[t][v];
+      for (int t = 0; t < 4; ++t) {
+        if (gj + 16 * t < N) out[gi * N + gj + 16 * t] = acc[t][v];
+      }
     }
+    if (more) mv.load([&](int rr, int cc) { return lds[(BM + rr) * S::PITCH + S::COL0 + cc]; });
+    __syncthreads();
+    if (more) {
+      mv.store([&](int rr, int cc, T v) { lds[rr * S::PITCH + S::COL0 + cc] = v; });
+      pf.commit(2 * R, wr);
+    }
+    __syncthreads();
   }
 }
 

@@ -1,0 +1,456 @@
+// 3D stencil kernels (grid (i, j, k), k contiguous).
+//
+// Plane order of Algorithm 1 (Section 4.4): a workgroup owns a TJ x TK tile
+// of the (j, k) plane and a chunk of CH output planes along i.  It walks the
+// input planes i = ib - r .. ib + CH + r - 1 once; each plane is staged into
+// LDS with its in-plane halo and scattered into the 2r+1 output planes it
+// reaches, whose accumulators form a ring in registers (the i-direction
+// unrolling of Section 4.2: an input element is loaded once and used by all
+// its neighbours along i).  When input plane i has been scattered, output
+// plane i - r is complete: it is stored and its ring slot reset.
+//
+// Ring slot of output plane o: (o - ib + 2r) mod (2r+1).  With the input
+// counter u = i - ib + r unrolled in groups of 2r+1 (u = G (2r+1) + uu), the
+// slot reached through coefficient plane a (o = i - a + r) is
+// (uu + 2r - a) mod (2r+1) and the completed plane sits in slot uu: all slot
+// indices are compile-time constants.
+#pragma once
+
+#include "device_common.hpp"
+#include "kernels_2d.hpp"
+#include "kernels_split2d.hpp"
+#include "mfma_traits.hpp"
+
+namespace stencil {
+
+constexpr int kTJ = 32;   // workgroup tile along j
+constexpr int kTK = 64;   // workgroup tile along k
+
+struct Chunk3D {
+  int64_t ib, iend, j0, k0;  // output planes [ib, iend), tile origin
+};
+
+__device__ __forceinline__ Chunk3D decode_chunk(const KArgs& a) {
+  const int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int per_plane = a.tiles0 * a.tiles1;
+  const int chunk = id / per_plane;
+  const int t = id - chunk * per_plane;
+  const int tj = t / a.tiles1, tk = t - tj * a.tiles1;
+  Chunk3D c;
+  c.ib = (int64_t)chunk * a.chunk;
+  c.iend = c.ib + a.chunk < a.d0 ? c.ib + a.chunk : a.d0;
+  c.j0 = (int64_t)tj * kTJ;
+  c.k0 = (int64_t)tk * kTK;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// Gather-form baseline (Eq. (1) in 3D).  Thread (s, q) owns k column q and
+// j rows 8 s .. 8 s + 7 of the tile.  Box: each input plane adds its
+// (2r+1)^2 in-plane taps to the 2r+1 output planes it reaches; star: the
+// centre plane adds the j and k arms, every plane adds its i-arm weight.
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool BOX>
+__global__ __launch_bounds__(kThreads) void gather3d_kernel(KArgs a) {
+  constexpr int W = 2 * R + 1, ROWS = 8;
+  constexpr int WROWS = kTJ + 2 * R;
+  constexpr int COL0 = lds_col0<T, R>();
+  constexpr int PITCH = pick_pitch<T, false>(COL0 + kTK + 2 * R);
+  __shared__ __attribute__((aligned(16))) T lds[WROWS * PITCH];
+
+  const Chunk3D ch = decode_chunk(a);
+  const int64_t Ni = a.d0, Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
+  const bool periodic = a.periodic != 0;
+  const T* __restrict__ in = (const T*)a.in;
+  T* __restrict__ out = (T*)a.out;
+  const T* __restrict__ c = (const T*)a.coef;
+  const int q = threadIdx.x & 63, s = threadIdx.x >> 6;
+
+  T ring[W][ROWS];
+#pragma unroll
+  for (int z = 0; z < W; ++z)
+#pragma unroll
+    for (int p = 0; p < ROWS; ++p) ring[z][p] = T(0);
+
+  const int nu = (int)(ch.iend - ch.ib) + 2 * R;
+  const T* base = lds + (ROWS * s) * PITCH + COL0 + q;
+  for (int ug = 0; ug < nu; ug += W) {
+#pragma unroll
+    for (int uu = 0; uu < W; ++uu) {
+      const int u = ug + uu;
+      if (u >= nu) break;
+      const int64_t gi = map_index(ch.ib - R + u, Ni, periodic);
+      __syncthreads();
+      if (gi >= 0) {
+        stage_window<T, R, WROWS, kTK, PITCH, kThreads>(lds, in + gi * plane, Nj, Nk, ch.j0 - R, ch.k0, periodic);
+        __syncthreads();
+        if constexpr (BOX) {
+#pragma unroll
+          for (int x = 0; x < ROWS + 2 * R; ++x) {
+            T h[W];
+#pragma unroll
+            for (int cc = 0; cc < W; ++cc) h[cc] = base[x * PITCH + cc];
+#pragma unroll
+            for (int ap = 0; ap < W; ++ap) {
+              const int slot = (uu + 2 * R - ap) % W;
+#pragma unroll
+              for (int p = 0; p < ROWS; ++p) {
+                const int bb = x - p;
+                if (bb < 0 || bb > 2 * R) continue;
+#pragma unroll
+                for (int cc = 0; cc < W; ++cc) ring[slot][p] += c[(ap * W + bb) * W + cc] * h[cc];
+              }
+            }
+          }
+        } else {
+          // centre plane (slot of output plane i): j arm (column k = q + r) and k arm (row j = p + r)
+#pragma unroll
+          for (int x = 0; x < ROWS + 2 * R; ++x) {
+            const T hv = base[x * PITCH + R];
+#pragma unroll
+            for (int p = 0; p < ROWS; ++p) {
+              const int bb = x - p;
+              if (bb < 0 || bb > 2 * R) continue;
+              ring[(uu + R) % W][p] += c[(R * W + bb) * W + R] * hv;
+            }
+          }
+#pragma unroll
+          for (int p = 0; p < ROWS; ++p) {
+            const T* rowp = base + (p + R) * PITCH;
+#pragma unroll
+            for (int cc = 0; cc < W; ++cc) {
+              if (cc == R) continue;
+              ring[(uu + R) % W][p] += c[(R * W + R) * W + cc] * rowp[cc];
+            }
+            // i arm: this plane reaches output plane i - ap + r with C^g[ap][r][r]
+            const T ctr = rowp[R];
+#pragma unroll
+            for (int ap = 0; ap < W; ++ap) {
+              if (ap == R) continue;
+              ring[(uu + 2 * R - ap) % W][p] += c[(ap * W + R) * W + R] * ctr;
+            }
+          }
+        }
+      }
+      // output plane ib + u - 2r is complete (slot uu)
+      const int64_t o = ch.ib + u - 2 * R;
+      if (u >= 2 * R) {
+        const int64_t gk = ch.k0 + q;
+#pragma unroll
+        for (int p = 0; p < ROWS; ++p) {
+          const int64_t gj = ch.j0 + ROWS * s + p;
+          if (gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = ring[uu][p];
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < ROWS; ++p) ring[uu][p] = T(0);
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Outer-product form on MFMA (FP32 / FP64).  Waves form a 2 x 2 grid over the
+// 32 x 64 tile; each wave owns two 16 x 16 blocks (16 j-rows x 32 k-columns)
+// in each of the 2r+1 ring slots.
+//
+// Box (3D box stencils, Section 3.3: the (2r+1)^2 lines CLS(a, *, c) along j):
+// input plane i adds, for every coefficient plane a and k-shift c, the band
+// T_{a,c}[p][x] = C^g[a][x - p][c] times the window rows shifted by c to output
+// plane i - a + r.  The band fragments of all lines stay in VGPRs.
+// Star (hybrid cover of Table 2): on the centre plane the line CLS(r, *, r)
+// along j (band, rows of the window as B operand) and CLS(r, r, *) along k
+// (window column segments as A operand, centre excluded); the lines CLS(a, *, r)
+// with a != r hold one weight each and are the vector FMAs of the i arm.
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool BOX>
+struct Mfma3DShape {
+  static constexpr int W = 2 * R + 1;
+  static constexpr int KL = round_up(16 + 2 * R, 4);
+  static constexpr int CPL = KL / 4;
+  static constexpr int NLINES = BOX ? W * W : 2;
+  static constexpr int NCH = NLINES * CPL;
+  static constexpr int WROWS = kTJ + 2 * R;
+  static constexpr int LROWS = (kTJ - 16) + KL;
+  static constexpr int COL0 = lds_col0<T, R>();
+  static constexpr int WEND = COL0 + kTK + 2 * R;
+  static constexpr int REND = COL0 + (kTK - 16) + KL;
+  static constexpr int LCOLS = cmax(WEND, BOX ? 0 : REND);
+  static constexpr int PITCH = pick_pitch<T, !BOX>(LCOLS);
+};
+
+template <typename T, int R, bool BOX>
+__global__ __launch_bounds__(kThreads) void mfma3d_kernel(KArgs a) {
+  typedef Mfma16<T> MM;
+  typedef typename MM::acc_t acc_t;
+  typedef Mfma3DShape<T, R, BOX> S;
+  constexpr int W = S::W;
+  __shared__ __attribute__((aligned(16))) T lds[S::LROWS * S::PITCH];
+
+  const Chunk3D ch = decode_chunk(a);
+  const int64_t Ni = a.d0, Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
+  const bool periodic = a.periodic != 0;
+  const T* __restrict__ in = (const T*)a.in;
+  T* __restrict__ out = (T*)a.out;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wj = w >> 1, wk = w & 1;
+  const int g = lane >> 4, q = lane & 15;
+
+  const T* __restrict__ frag = (const T*)a.frag;
+  T af[S::NCH];
+#pragma unroll
+  for (int cidx = 0; cidx < S::NCH; ++cidx) af[cidx] = frag[cidx * 64 + lane];
+  T ci[W];  // i-arm weights C^g[a][r][r] (star)
+  if constexpr (!BOX) {
+    const T* __restrict__ c = (const T*)a.coef;
+#pragma unroll
+    for (int ap = 0; ap < W; ++ap) ci[ap] = c[(ap * W + R) * W + R];
+  }
+
+  if constexpr (S::LROWS > S::WROWS)
+    zero_region<T, kThreads>(lds, S::LROWS - S::WROWS, S::PITCH, S::PITCH, S::WROWS, 0);
+  if constexpr (S::LCOLS > S::WEND)
+    zero_region<T, kThreads>(lds, S::WROWS, S::LCOLS - S::WEND, S::PITCH, 0, S::WEND);
+
+  acc_t ring[W][2];
+#pragma unroll
+  for (int z = 0; z < W; ++z) {
+    ring[z][0] = acc_t{};
+    ring[z][1] = acc_t{};
+  }
+  const T* colbase = lds + (16 * wj + g) * S::PITCH + S::COL0 + 32 * wk + q;
+  const T* rowbase = lds + (16 * wj + R + q) * S::PITCH + S::COL0 + 32 * wk + g;
+  const int nu = (int)(ch.iend - ch.ib) + 2 * R;
+  for (int ug = 0; ug < nu; ug += W) {
+#pragma unroll
+    for (int uu = 0; uu < W; ++uu) {
+      const int u = ug + uu;
+      if (u >= nu) break;
+      const int64_t gi = map_index(ch.ib - R + u, Ni, periodic);
+      __syncthreads();
+      if (gi >= 0) {
+        stage_window<T, R, S::WROWS, kTK, S::PITCH, kThreads>(lds, in + gi * plane, Nj, Nk, ch.j0 - R, ch.k0,
+                                                              periodic);
+        __syncthreads();
+        if constexpr (BOX) {
+#pragma unroll
+          for (int ap = 0; ap < W; ++ap) {
+            const int slot = (uu + 2 * R - ap) % W;
+#pragma unroll
+            for (int cs = 0; cs < W; ++cs) {
+#pragma unroll
+              for (int cc = 0; cc < S::CPL; ++cc) {
+                const T av = af[(ap * W + cs) * S::CPL + cc];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                  const T bv = colbase[(4 * cc) * S::PITCH + 16 * t + cs];
+                  ring[slot][t] = MM::mma(av, bv, ring[slot][t]);
+                }
+              }
+            }
+          }
+        } else {
+          const int slot = (uu + R) % W;
+#pragma unroll
+          for (int cc = 0; cc < S::CPL; ++cc) {
+            const T av = af[cc];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              const T bv = colbase[(4 * cc) * S::PITCH + 16 * t + R];
+              ring[slot][t] = MM::mma(av, bv, ring[slot][t]);
+            }
+          }
+#pragma unroll
+          for (int cc = 0; cc < S::CPL; ++cc) {
+            const T sv = af[S::CPL + cc];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              const T hv = rowbase[16 * t + 4 * cc];
+              ring[slot][t] = MM::mma(hv, sv, ring[slot][t]);
+            }
+          }
+          // i arm: lines CLS(a, *, r), a != r, one weight each
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const T* cp = lds + (16 * wj + R + MM::row(lane, v)) * S::PITCH + S::COL0 + 32 * wk + MM::col(lane) + R;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              const T ctr = cp[16 * t];
+#pragma unroll
+              for (int ap = 0; ap < W; ++ap) {
+                if (ap == R) continue;
+                ring[(uu + 2 * R - ap) % W][t][v] += ci[ap] * ctr;
+              }
+            }
+          }
+        }
+      }
+      const int64_t o = ch.ib + u - 2 * R;
+      if (u >= 2 * R) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t gj = ch.j0 + 16 * wj + MM::row(lane, v);
+          if (gj >= Nj) continue;
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const int64_t gk = ch.k0 + 32 * wk + 16 * t + MM::col(lane);
+            if (gk < Nk) out[o * plane + gj * Nk + gk] = ring[uu][t][v];
+          }
+        }
+      }
+      ring[uu][0] = acc_t{};
+      ring[uu][1] = acc_t{};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Outer-product form with 16-bit split operands (see kernels_split2d.hpp) in
+// the plane order of Algorithm 1.  Lines run along k: CLS(a, b, *) adds
+// D[p][q] += sum_y H[p + b][y] * S_{a,b}[y][q], S_{a,b}[y][q] = C^g[a][b][y - q],
+// to output plane i - a + r (window rows shifted by b as the A operand).
+// Box (27-point, r = 1): all (2r+1)^2 lines on MFMA.  Star: the k line
+// CLS(r, r, *) on MFMA; the other 4r lines hold one weight each and are vector
+// FMAs on an FP32 copy of the window (j arm on the centre plane, i arm into the
+// other ring slots), pre-multiplied by the plan's coefficient scale.
+// ---------------------------------------------------------------------------
+template <int R, bool BOX>
+struct Split3DShape {
+  static constexpr int W = 2 * R + 1;
+  static constexpr int NL = BOX ? W * W : 1;
+  static constexpr int WROWS = kTJ + 2 * R;
+  static constexpr int WEND = kTK + 2 * R;
+  static constexpr int P = 88;  // 16-bit pitch: multiple of 8, covers columns read by K = 32
+  static constexpr int COL0F = lds_col0<float, R>();
+  static constexpr int P32 = BOX ? 1 : pick_pitch<float, false>(COL0F + kTK + 2 * R);
+  static_assert((kTK - 32) + 16 + 32 <= P && WEND <= P, "pitch too small");
+};
+
+template <int KIND, int R, bool BOX>
+__global__ __launch_bounds__(kThreads) void split3d_kernel(KArgs a) {
+  typedef Split3DShape<R, BOX> S;
+  constexpr int W = S::W;
+  __shared__ __attribute__((aligned(16))) uint16_t lhi[S::WROWS * S::P];
+  __shared__ __attribute__((aligned(16))) uint16_t llo[S::WROWS * S::P];
+  __shared__ __attribute__((aligned(16))) float l32[BOX ? 4 : S::WROWS * S::P32];
+
+  const Chunk3D ch = decode_chunk(a);
+  const int64_t Ni = a.d0, Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
+  const bool periodic = a.periodic != 0;
+  const float* __restrict__ in = (const float*)a.in;
+  float* __restrict__ out = (float*)a.out;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wj = w >> 1, wk = w & 1;
+  const int g = lane >> 4, q = lane & 15;
+
+  const u16x8* __restrict__ frag = (const u16x8*)a.frag;
+  u16x8 bh[S::NL], bl[S::NL];
+#pragma unroll
+  for (int l = 0; l < S::NL; ++l) {
+    bh[l] = frag[(l * 2 + 0) * 64 + lane];
+    bl[l] = frag[(l * 2 + 1) * 64 + lane];
+  }
+  const float cscale = 1.0f / a.out_scale;  // exact power of two
+  float cj[W], ci[W];                        // star: j-arm and i-arm weights, scaled
+  if constexpr (!BOX) {
+    const float* __restrict__ c = (const float*)a.coef;
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+      cj[b] = c[(R * W + b) * W + R] * cscale;
+      ci[b] = c[(b * W + R) * W + R] * cscale;
+    }
+  }
+  zero_region<uint16_t, kThreads>(lhi, S::WROWS, S::P - S::WEND, S::P, 0, S::WEND);
+  zero_region<uint16_t, kThreads>(llo, S::WROWS, S::P - S::WEND, S::P, 0, S::WEND);
+  const float lo_mul = 1.0f / a.lo_scale;
+
+  floatx4 acc[W][2], acx[W][2];
+#pragma unroll
+  for (int z = 0; z < W; ++z)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      acc[z][t] = floatx4{0, 0, 0, 0};
+      acx[z][t] = floatx4{0, 0, 0, 0};
+    }
+  const int nu = (int)(ch.iend - ch.ib) + 2 * R;
+  for (int ug = 0; ug < nu; ug += W) {
+#pragma unroll
+    for (int uu = 0; uu < W; ++uu) {
+      const int u = ug + uu;
+      if (u >= nu) break;
+      const int64_t gi = map_index(ch.ib - R + u, Ni, periodic);
+      __syncthreads();
+      if (gi >= 0) {
+        stage_split<KIND, R, S::WROWS, kTK, S::P, kThreads>(lhi, llo, in + gi * plane, Nj, Nk, ch.j0 - R, ch.k0,
+                                                             periodic, lo_mul);
+        if constexpr (!BOX)
+          stage_window<float, R, S::WROWS, kTK, S::P32, kThreads>(l32, in + gi * plane, Nj, Nk, ch.j0 - R, ch.k0,
+                                                                  periodic);
+        __syncthreads();
+#pragma unroll
+        for (int ap = 0; ap < W; ++ap) {
+          if (!BOX && ap != R) continue;
+          const int slot = (uu + 2 * R - ap) % W;
+#pragma unroll
+          for (int b = 0; b < W; ++b) {
+            if (!BOX && b != R) continue;
+            const int l = BOX ? ap * W + b : 0;
+            const uint16_t* ph = lhi + (16 * wj + b + q) * S::P + 32 * wk + 8 * g;
+            const uint16_t* pl = llo + (16 * wj + b + q) * S::P + 32 * wk + 8 * g;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              const u16x8 ah = *reinterpret_cast<const u16x8*>(ph + 16 * t);
+              const u16x8 al = *reinterpret_cast<const u16x8*>(pl + 16 * t);
+              acc[slot][t] = Split16<KIND>::mma(ah, bh[l], acc[slot][t]);
+              acx[slot][t] = Split16<KIND>::mma(ah, bl[l], acx[slot][t]);
+              acx[slot][t] = Split16<KIND>::mma(al, bh[l], acx[slot][t]);
+            }
+          }
+        }
+        if constexpr (!BOX) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float* cp = l32 + (16 * wj + 4 * g + v) * S::P32 + S::COL0F + 32 * wk + q + R;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              float sj = 0.0f;
+#pragma unroll
+              for (int b = 0; b < W; ++b) {
+                if (b == R) continue;
+                sj += cj[b] * cp[b * S::P32 + 16 * t];
+              }
+              acc[(uu + R) % W][t][v] += sj;
+              const float ctr = cp[R * S::P32 + 16 * t];
+#pragma unroll
+              for (int ap = 0; ap < W; ++ap) {
+                if (ap == R) continue;
+                acc[(uu + 2 * R - ap) % W][t][v] += ci[ap] * ctr;
+              }
+            }
+          }
+        }
+      }
+      const int64_t o = ch.ib + u - 2 * R;
+      if (u >= 2 * R) {
+        const float ls = a.lo_scale, os = a.out_scale;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t gj = ch.j0 + 16 * wj + 4 * g + v;
+          if (gj >= Nj) continue;
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const int64_t gk = ch.k0 + 32 * wk + 16 * t + q;
+            if (gk < Nk) out[o * plane + gj * Nk + gk] = (acc[uu][t][v] + ls * acx[uu][t][v]) * os;
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        acc[uu][t] = floatx4{0, 0, 0, 0};
+        acx[uu][t] = floatx4{0, 0, 0, 0};
+      }
+    }
+  }
+}
+
+}  // namespace stencil

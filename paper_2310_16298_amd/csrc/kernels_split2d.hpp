@@ -19,6 +19,7 @@
 #pragma once
 
 #include "device_common.hpp"
+#include "stream2d.hpp"
 
 namespace stencil {
 
@@ -101,19 +102,37 @@ struct Split2DShape {
   static_assert(LCOLS <= P && WEND <= P, "pitch too small");
 };
 
+// Writer splitting FP32 window values into the hi/lo 16-bit LDS planes.
+template <int KIND, int P>
+struct SplitWriter {
+  uint16_t* hi;
+  uint16_t* lo;
+  float lo_mul;
+  __device__ __forceinline__ void put(int row, int y, float x) {
+    Split16<KIND>::split(x, lo_mul, hi[row * P + y], lo[row * P + y]);
+  }
+  __device__ __forceinline__ void put_vec(int row, int y, const float4& v) {
+    const float xs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) put(row, y + e, xs[e]);
+  }
+};
+
 template <int KIND, int R>
 __global__ __launch_bounds__(256) void split2d_kernel(KArgs a) {
   typedef Split2DShape<R> S;
-  constexpr int NL = 2 * R + 1;
+  constexpr int NL = 2 * R + 1, BM = S::TM;
   __shared__ __attribute__((aligned(16))) uint16_t lhi[S::WROWS * S::P];
   __shared__ __attribute__((aligned(16))) uint16_t llo[S::WROWS * S::P];
 
   const int64_t M = a.d0, N = a.d1;
+  const bool periodic = a.periodic != 0;
+  const float* __restrict__ in = (const float*)a.in;
+  float* __restrict__ out = (float*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, q = lane & 15;
-  const int tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int tj = tile % a.tiles1, ti = tile / a.tiles1;
-  const int64_t i0 = (int64_t)ti * S::TM, j0 = (int64_t)tj * S::TN;
+  const Strip2D sp = decode_strip(a, S::TN);
+  const bool fast = strip_fast(in, N, sp.j0, S::TN);
 
   // Band fragments S_a (hi, lo) for this lane: 16 bytes each.
   const u16x8* __restrict__ frag = (const u16x8*)a.frag;
@@ -127,41 +146,56 @@ __global__ __launch_bounds__(256) void split2d_kernel(KArgs a) {
   zero_region<uint16_t, 256>(lhi, S::WROWS, S::P - S::WEND, S::P, 0, S::WEND);
   zero_region<uint16_t, 256>(llo, S::WROWS, S::P - S::WEND, S::P, 0, S::WEND);
   const float lo_mul = 1.0f / a.lo_scale;
-  stage_split<KIND, R, S::WROWS, S::TN, S::P, 256>(lhi, llo, (const float*)a.in, M, N, i0 - R, j0,
-                                                   a.periodic != 0, lo_mul);
+  stage_split<KIND, R, S::WROWS, S::TN, S::P, 256>(lhi, llo, in, M, N, sp.i0 - R, sp.j0, periodic, lo_mul);
   __syncthreads();
 
-  floatx4 acc[4], acx[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    acc[t] = floatx4{0, 0, 0, 0};
-    acx[t] = floatx4{0, 0, 0, 0};
-  }
-#pragma unroll
-  for (int l = 0; l < NL; ++l) {
-    const uint16_t* ph = lhi + (16 * w + l + q) * S::P + 8 * g;
-    const uint16_t* pl = llo + (16 * w + l + q) * S::P + 8 * g;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const u16x8 ah = *reinterpret_cast<const u16x8*>(ph + 16 * t);
-      const u16x8 al = *reinterpret_cast<const u16x8*>(pl + 16 * t);
-      acc[t] = Split16<KIND>::mma(ah, bh[l], acc[t]);
-      acx[t] = Split16<KIND>::mma(ah, bl[l], acx[t]);
-      acx[t] = Split16<KIND>::mma(al, bh[l], acx[t]);
-    }
-  }
-
-  float* out = (float*)a.out;
+  SplitWriter<KIND, S::P> wr{lhi, llo, lo_mul};
+  RowPrefetch<float, R, BM, S::TN, 256> pf;
+  RowMover<uint16_t, R, S::WEND, 256> mvh, mvl;
   const float ls = a.lo_scale, os = a.out_scale;
-  const int64_t gj = j0 + q;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int64_t gi = i0 + 16 * w + 4 * g + v;
-    if (gi >= M) continue;
+  for (int64_t ib = sp.i0; ib < sp.i1; ib += BM) {
+    const bool more = ib + BM < sp.i1;
+    if (more) pf.fetch(in, M, N, ib + BM + R, sp.j0, periodic, fast);
+    floatx4 acc[4], acx[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      if (gj + 16 * t < N) out[gi * N + gj + 16 * t] = (acc[t][v] + ls * acx[t][v]) * os;
+      acc[t] = floatx4{0, 0, 0, 0};
+      acx[t] = floatx4{0, 0, 0, 0};
     }
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const uint16_t* ph = lhi + (16 * w + l + q) * S::P + 8 * g;
+      const uint16_t* pl = llo + (16 * w + l + q) * S::P + 8 * g;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const u16x8 ah = *reinterpret_cast<const u16x8*>(ph + 16 * t);
+        const u16x8 al = *reinterpret_cast<const u16x8*>(pl + 16 * t);
+        acc[t] = Split16<KIND>::mma(ah, bh[l], acc[t]);
+        acx[t] = Split16<KIND>::mma(ah, bl[l], acx[t]);
+        acx[t] = Split16<KIND>::mma(al, bh[l], acx[t]);
+      }
+    }
+    const int64_t gj = sp.j0 + q;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t gi = ib + 16 * w + 4 * g + v;
+      if (gi >= sp.i1) continue;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (gj + 16 * t < N) out[gi * N + gj + 16 * t] = (acc[t][v] + ls * acx[t][v]) * os;
+      }
+    }
+    if (more) {
+      mvh.load([&](int rr, int cc) { return lhi[(BM + rr) * S::P + cc]; });
+      mvl.load([&](int rr, int cc) { return llo[(BM + rr) * S::P + cc]; });
+    }
+    __syncthreads();
+    if (more) {
+      mvh.store([&](int rr, int cc, uint16_t v) { lhi[rr * S::P + cc] = v; });
+      mvl.store([&](int rr, int cc, uint16_t v) { llo[rr * S::P + cc] = v; });
+      pf.commit(2 * R, wr);
+    }
+    __syncthreads();
   }
 }
 

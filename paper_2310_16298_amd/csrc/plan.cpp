@@ -15,7 +15,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "kernels_2d.hpp"
+#include "kernels_3d.hpp"
 
 namespace stencil {
 
@@ -122,64 +122,63 @@ static int validate(const stencil_desc_t* d) {
   return STENCIL_OK;
 }
 
-// ----------------------------------------------------------------- 2D packing
+// ------------------------------------------------------------------ packing
+//
+// A line is given by its 2r+1 weights w[d], d = 0..2r.  A line along the
+// block's row axis ("column line", Eq. (9)-(12)) becomes the band
+// T[p][x] = w[x - p]; a line along the column axis ("row line", Eq. (14))
+// becomes S[y][q] = w[y - q]; x, y < n + 2r, zero elsewhere.
+typedef std::vector<double> Line;
 
-static void pack_mfma2d(Resolved* rs, int R, int var, int dtype) {
-  const int n = 16;
-  const int KL = round_up(16 + 2 * R, 4), CPL = KL / 4;
-  const int NLC = var == VAR_BOX ? 2 * R + 1 : 1;
-  const int NLR = var == VAR_STAR_ORTHO ? 1 : 0;
-  const int NCH = (NLC + NLR) * CPL;
+// FP32 / FP64 16x16x4 fragments.  Column lines are MFMA A operands (lane
+// holds T[p = lane % 16][x = 4 cc + lane / 16]); row lines are B operands
+// (lane holds S[y = 4 cc + lane / 16][q = lane % 16]).  Each line is padded to
+// KL = round_up(n + 2r, 4) K rows (CPL chunks of 4).
+static void pack_mfma(Resolved* rs, int R, int dtype, const std::vector<Line>& col,
+                      const std::vector<Line>& row) {
+  const int n = 16, K = n + 2 * R;
+  const int KL = round_up(K, 4), CPL = KL / 4;
+  const int NCH = (int)(col.size() + row.size()) * CPL;
   const int es = dtype_size(dtype);
   rs->frag.assign((size_t)NCH * 64 * es, 0);
-  const double* cg = rs->cg.data();
   for (int c = 0; c < NCH; ++c) {
+    const int li = c / CPL, cc = c % CPL;
     for (int lane = 0; lane < 64; ++lane) {
-      double v;
-      if (c < NLC * CPL) {
-        const int li = c / CPL, cc = c % CPL;
-        const int b = var == VAR_BOX ? li : R;
-        // A operand: lane holds T_b[p = lane % 16][x = 4 cc + lane / 16]
-        v = band_value(cg, R, n, 0, b, lane % 16, 4 * cc + lane / 16);
-      } else {
-        const int cc = c - NLC * CPL;
-        // B operand: lane holds S[y = 4 cc + lane / 16][q = lane % 16], centre excluded
-        const int y = 4 * cc + lane / 16, q = lane % 16;
-        v = (y - q == R) ? 0.0 : band_value(cg, R, n, 1, R, y, q);
-      }
+      const int a = lane % 16, k = 4 * cc + lane / 16;  // (p, x) or (q, y)
+      const int d = k - a;
+      const Line& w = li < (int)col.size() ? col[li] : row[li - col.size()];
+      const double v = (k < K && d >= 0 && d <= 2 * R) ? w[d] : 0.0;
       if (es == 8)
         put<double>(rs->frag, (size_t)c * 64 + lane, v);
       else
         put<float>(rs->frag, (size_t)c * 64 + lane, (float)v);
     }
   }
-  rs->info.mfma_lines = NLC + NLR;
-  rs->info.valu_lines = var == VAR_STAR_PARALLEL ? 2 * R : 0;
   rs->info.k_rows = NCH * 4;
 }
 
-// Split-precision 2D: lines along j (C^g rows a = 0..2r), transposed form
-// D[p][q] += sum_y H[p + a][y] * S_a[y][q]; one 16x16x32 MFMA per line and
-// part, K = 32 >= 16 + 2r.  B operand: lane l, element e holds
-// S_a[8 (l / 16) + e][l % 16], stored as hi and lo 16-bit parts.
-static void pack_split2d(Resolved* rs, int R, int kind) {
-  const int n = 16, NL = 2 * R + 1;
+// 16-bit split fragments for row lines on 16x16x32 (B operand: lane l,
+// element e holds S[y = 8 (l / 16) + e][q = l % 16]); hi and lo parts.  For
+// FP16 the coefficients are scaled by 2^e (max weight in [2^14, 2^15)) and the
+// lo parts by 2^11; out_scale / lo_scale undo both exactly.
+static void pack_split(Resolved* rs, int R, int kind, const std::vector<Line>& row) {
+  const int K = 16 + 2 * R;
+  const int NL = (int)row.size();
   rs->frag.assign((size_t)NL * 2 * 64 * 8 * 2, 0);
-  const double* cg = rs->cg.data();
   double cmax = 0.0;
   for (double c : rs->cg) cmax = std::fmax(cmax, std::fabs(c));
   float cscale = 1.0f, lscale = 1.0f;
-  if (kind == 1) {  // FP16: scale the coefficients into the upper normal range; lo parts carry 2^11
+  if (kind == 1) {
     int e = 0;
     if (cmax > 0.0) e = 14 - (int)std::floor(std::log2(cmax));
     cscale = std::ldexp(1.0f, e);
     lscale = std::ldexp(1.0f, 11);
   }
-  for (int a = 0; a < NL; ++a) {
+  for (int l = 0; l < NL; ++l) {
     for (int lane = 0; lane < 64; ++lane) {
       for (int e = 0; e < 8; ++e) {
-        const int y = 8 * (lane / 16) + e, q = lane % 16;
-        const float c = (float)band_value(cg, R, n, 1, a, y, q) * cscale;
+        const int y = 8 * (lane / 16) + e, q = lane % 16, d = y - q;
+        const float c = (float)((y < K && d >= 0 && d <= 2 * R) ? row[l][d] : 0.0) * cscale;
         uint16_t hi, lo;
         if (kind == 0) {
           hi = to_bf16_bits(c);
@@ -188,16 +187,45 @@ static void pack_split2d(Resolved* rs, int R, int kind) {
           hi = to_f16_bits(c);
           lo = to_f16_bits((c - from_f16_bits(hi)) * lscale);
         }
-        put<uint16_t>(rs->frag, ((size_t)(a * 2 + 0) * 64 + lane) * 8 + e, hi);
-        put<uint16_t>(rs->frag, ((size_t)(a * 2 + 1) * 64 + lane) * 8 + e, lo);
+        put<uint16_t>(rs->frag, ((size_t)(l * 2 + 0) * 64 + lane) * 8 + e, hi);
+        put<uint16_t>(rs->frag, ((size_t)(l * 2 + 1) * 64 + lane) * 8 + e, lo);
       }
     }
   }
   rs->out_scale = 1.0f / cscale;
   rs->lo_scale = 1.0f / lscale;
-  rs->info.mfma_lines = NL;
-  rs->info.valu_lines = 0;
   rs->info.k_rows = NL * 32;
+}
+
+// Weights of the line through C^g along one axis.  `fixed` gives the other
+// indices (entry for `axis` ignored).
+static Line line_of(const std::vector<double>& cg, int nd, int R, int axis, const int* fixed, bool drop_centre) {
+  const int W = 2 * R + 1;
+  Line w(W);
+  for (int d = 0; d < W; ++d) {
+    int idx[3] = {fixed[0], fixed[1], fixed[2]};
+    idx[axis] = d;
+    const size_t flat = nd == 2 ? (size_t)idx[0] * W + idx[1] : ((size_t)idx[0] * W + idx[1]) * W + idx[2];
+    w[d] = cg[flat];
+  }
+  if (drop_centre) w[R] = 0.0;
+  return w;
+}
+
+static void fill_2d_counts(Resolved* rs, int R, int variant, bool split) {
+  stencil_plan_info_t& in = rs->info;
+  const int n = 16, W = 2 * R + 1;
+  if (split) {
+    in.mfma_lines = W;
+    in.valu_lines = 0;
+    in.rank1_per_block = (int64_t)W * (2 * R + n);
+    return;
+  }
+  in.mfma_lines = variant == VAR_BOX ? W : (variant == VAR_STAR_ORTHO ? 2 : 1);
+  in.valu_lines = variant == VAR_STAR_PARALLEL ? 2 * R : 0;
+  if (variant == VAR_BOX) in.rank1_per_block = (int64_t)W * (2 * R + n);  // Section 3.4
+  else if (variant == VAR_STAR_PARALLEL) in.rank1_per_block = (2 * R + n) + (int64_t)2 * R * n;  // Table 1
+  else in.rank1_per_block = 2 * (2 * R + n);                                                      // Table 1
 }
 
 int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
@@ -209,6 +237,7 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   rs->cg.resize(ncoef);
   for (int t = 0; t < ncoef; ++t)
     rs->cg[t] = d.dtype == STENCIL_F32 ? (double)(float)d.coeffs[t] : d.coeffs[t];
+  const std::vector<double>& cg = rs->cg;
 
   stencil_plan_info_t& in = rs->info;
   std::memset(&in, 0, sizeof(in));
@@ -222,15 +251,21 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   in.useful_flops_per_point = 2.0 * in.taps;
   in.bytes_per_point = 2 * dtype_size(d.dtype);
   const int n = 16;
+  const int KL = round_up(16 + 2 * R, 4);
 
   int path = d.path;
-  if (path == STENCIL_PATH_AUTO) path = STENCIL_PATH_MFMA;
+  if (path == STENCIL_PATH_AUTO) {
+    path = STENCIL_PATH_MFMA;
+    if (nd == 3 && box && R > 2) path = STENCIL_PATH_GATHER;
+  }
+  const bool split = path == STENCIL_PATH_MFMA_BF16X3 || path == STENCIL_PATH_MFMA_F16X3;
+  rs->split16 = path == STENCIL_PATH_MFMA_F16X3 ? 1 : 0;
   int lines = d.lines;
   if (box) {
     lines = STENCIL_LINES_PARALLEL;
   } else if (lines == STENCIL_LINES_AUTO) {
     if (nd == 2) lines = R == 1 ? STENCIL_LINES_PARALLEL : STENCIL_LINES_ORTHOGONAL;
-    else lines = STENCIL_LINES_HYBRID;
+    else lines = split ? STENCIL_LINES_PARALLEL : STENCIL_LINES_HYBRID;
   }
 
   KArgs& a = rs->args;
@@ -245,16 +280,25 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   // Dense coefficients in the arithmetic dtype (gather kernels, vector lines).
   rs->coef.assign((size_t)ncoef * dtype_size(d.dtype), 0);
   for (int t = 0; t < ncoef; ++t) {
-    if (d.dtype == STENCIL_F64) put<double>(rs->coef, t, rs->cg[t]);
-    else put<float>(rs->coef, t, (float)rs->cg[t]);
+    if (d.dtype == STENCIL_F64) put<double>(rs->coef, t, cg[t]);
+    else put<float>(rs->coef, t, (float)cg[t]);
   }
 
   if (nd == 2) {
-    const int64_t t0 = ceil_div(d.dims[0], kTile2D), t1 = ceil_div(d.dims[1], kTile2D);
-    if (t0 * t1 > (int64_t(1) << 31) - 1) return STENCIL_EUNSUPPORTED;
-    a.tiles0 = (int32_t)t0;
-    a.tiles1 = (int32_t)t1;
-    rs->grid = dim3((unsigned)(t0 * t1));
+    // Column strips of kTile2D columns, each walked in chunks of `chunk` rows
+    // (a multiple of the 64-row block), sized for >= ~2048 workgroups.
+    const int64_t strips = ceil_div(d.dims[1], kTile2D);
+    int64_t chunk = d.dims[0] * strips / 2048;
+    chunk = ceil_div(chunk < kTile2D ? kTile2D : chunk, kTile2D) * kTile2D;
+    const int64_t mrows = ceil_div(d.dims[0], kTile2D) * kTile2D;
+    if (chunk > mrows) chunk = mrows;
+    const int64_t nchunks = ceil_div(d.dims[0], chunk);
+    if (strips * nchunks > (int64_t(1) << 31) - 1 || chunk > (int64_t(1) << 30)) return STENCIL_EUNSUPPORTED;
+    a.tiles0 = (int32_t)nchunks;
+    a.tiles1 = (int32_t)strips;
+    a.chunk = (int32_t)chunk;
+    a.nchunks = (int32_t)nchunks;
+    rs->grid = dim3((unsigned)(strips * nchunks));
     in.tile_rows = kTile2D;
     in.tile_cols = kTile2D;
     if (path == STENCIL_PATH_GATHER) {
@@ -266,41 +310,113 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       rs->family = FAM_MFMA2D;
       rs->variant = box ? VAR_BOX : (lines == STENCIL_LINES_PARALLEL ? VAR_STAR_PARALLEL : VAR_STAR_ORTHO);
       rs->launch = find_mfma2d(d.dtype, R, rs->variant);
-      if (pack) pack_mfma2d(rs, R, rs->variant, d.dtype);
-      else {
-        const int KL = round_up(16 + 2 * R, 4);
-        const int nl = rs->variant == VAR_BOX ? W : (rs->variant == VAR_STAR_ORTHO ? 2 : 1);
-        in.mfma_lines = nl;
-        in.valu_lines = rs->variant == VAR_STAR_PARALLEL ? 2 * R : 0;
-        in.k_rows = nl * KL;
+      std::vector<Line> col, row;
+      const int fixed_r[3] = {R, R, 0};
+      for (int b = 0; b < W; ++b) {
+        if (rs->variant != VAR_BOX && b != R) continue;
+        const int fx[3] = {0, b, 0};
+        col.push_back(line_of(cg, 2, R, 0, fx, false));  // C^g column b
       }
+      if (rs->variant == VAR_STAR_ORTHO) row.push_back(line_of(cg, 2, R, 1, fixed_r, true));  // C^g row r
+      fill_2d_counts(rs, R, rs->variant, false);
+      if (pack) pack_mfma(rs, R, d.dtype, col, row);
+      else in.k_rows = (int)(col.size() + row.size()) * KL;
       in.block_n = n;
       in.executed_flops_per_point = 2.0 * in.k_rows + 2.0 * in.valu_lines;
-      if (rs->variant == VAR_BOX) in.rank1_per_block = (int64_t)W * (2 * R + n);
-      else if (rs->variant == VAR_STAR_PARALLEL) in.rank1_per_block = (2 * R + n) + (int64_t)2 * R * n;
-      else in.rank1_per_block = 2 * (2 * R + n);
     } else {
-      // Split precision: lines along j, star handled as a box with zero weights.
+      // Split precision: lines along j (C^g rows), star as a box with zero weights.
       rs->family = FAM_SPLIT2D;
-      rs->split16 = path == STENCIL_PATH_MFMA_F16X3 ? 1 : 0;
       rs->launch = find_split2d(rs->split16, R, 0);
       lines = STENCIL_LINES_PARALLEL;
-      if (pack) pack_split2d(rs, R, rs->split16);
-      else {
-        in.mfma_lines = W;
-        in.k_rows = W * 32;
+      std::vector<Line> row;
+      for (int r0 = 0; r0 < W; ++r0) {
+        const int fx[3] = {r0, 0, 0};
+        row.push_back(line_of(cg, 2, R, 1, fx, false));
       }
-      if (rs->split16 == 1 && !pack) {
-        // scales are only known after packing; describe() does not need them
-      }
+      fill_2d_counts(rs, R, 0, true);
+      if (pack) pack_split(rs, R, rs->split16, row);
+      else in.k_rows = W * 32;
       a.out_scale = rs->out_scale;
       a.lo_scale = rs->lo_scale;
       in.block_n = n;
       in.executed_flops_per_point = 3.0 * 2.0 * in.k_rows;
-      in.rank1_per_block = (int64_t)W * (2 * R + n);
     }
   } else {
-    return STENCIL_EUNSUPPORTED;  // 3D families are added below as they are built
+    // 3D: workgroup tile kTJ x kTK in (j, k), a chunk of planes along i.
+    const int64_t t0 = ceil_div(d.dims[1], kTJ), t1 = ceil_div(d.dims[2], kTK);
+    const int64_t tiles = t0 * t1;
+    int64_t chunk = d.dims[0] * tiles / 1024;  // aim for >= ~1024 workgroups
+    if (chunk < 16) chunk = 16;
+    if (chunk > d.dims[0]) chunk = d.dims[0];
+    const int64_t nch = ceil_div(d.dims[0], chunk);
+    if (tiles * nch > (int64_t(1) << 31) - 1 || tiles > (int64_t(1) << 30)) return STENCIL_EUNSUPPORTED;
+    a.tiles0 = (int32_t)t0;
+    a.tiles1 = (int32_t)t1;
+    a.chunk = (int32_t)chunk;
+    a.nchunks = (int32_t)nch;
+    rs->grid = dim3((unsigned)(tiles * nch));
+    in.tile_rows = kTJ;
+    in.tile_cols = kTK;
+    if (path == STENCIL_PATH_GATHER) {
+      rs->family = FAM_GATHER3D;
+      rs->launch = find_gather3d(d.dtype, R, box);
+      in.executed_flops_per_point = 2.0 * in.taps;
+      lines = STENCIL_LINES_AUTO;
+    } else if (path == STENCIL_PATH_MFMA) {
+      if (!box && lines != STENCIL_LINES_HYBRID) return STENCIL_EUNSUPPORTED;
+      rs->family = box ? FAM_MFMA3D_BOX : FAM_MFMA3D_STAR;
+      rs->launch = find_mfma3d(d.dtype, R, box);
+      std::vector<Line> col, row;
+      if (box) {
+        for (int ap = 0; ap < W; ++ap)
+          for (int c = 0; c < W; ++c) {
+            const int fx[3] = {ap, 0, c};
+            col.push_back(line_of(cg, 3, R, 1, fx, false));  // CLS(a, *, c)
+          }
+        in.mfma_lines = W * W;
+        in.valu_lines = 0;
+        in.rank1_per_block = (int64_t)W * W * (2 * R + n);
+      } else {
+        const int fx[3] = {R, 0, R};
+        col.push_back(line_of(cg, 3, R, 1, fx, false));  // CLS(r, *, r), centre included
+        const int fk[3] = {R, R, 0};
+        row.push_back(line_of(cg, 3, R, 2, fk, true));   // CLS(r, r, *), centre excluded
+        in.mfma_lines = 2;
+        in.valu_lines = 2 * R;
+        in.rank1_per_block = 2 * (2 * R + n) + (int64_t)2 * R * n;  // Table 2, hybrid
+      }
+      if (pack) pack_mfma(rs, R, d.dtype, col, row);
+      else in.k_rows = (int)(col.size() + row.size()) * KL;
+      in.block_n = n;
+      in.executed_flops_per_point = 2.0 * in.k_rows + 2.0 * in.valu_lines;
+    } else {
+      if (!box && lines != STENCIL_LINES_PARALLEL) return STENCIL_EUNSUPPORTED;
+      rs->family = box ? FAM_SPLIT3D_BOX : FAM_SPLIT3D_STAR;
+      rs->launch = find_split3d(rs->split16, R, box);
+      std::vector<Line> row;
+      if (box) {
+        for (int ap = 0; ap < W; ++ap)
+          for (int b = 0; b < W; ++b) {
+            const int fx[3] = {ap, b, 0};
+            row.push_back(line_of(cg, 3, R, 2, fx, false));  // CLS(a, b, *)
+          }
+        in.mfma_lines = W * W;
+        in.valu_lines = 0;
+        in.rank1_per_block = (int64_t)W * W * (2 * R + n);
+      } else {
+        const int fk[3] = {R, R, 0};
+        row.push_back(line_of(cg, 3, R, 2, fk, false));  // CLS(r, r, *), centre included
+        in.mfma_lines = 1;
+        in.valu_lines = 4 * R;
+        in.rank1_per_block = (2 * R + n) + (int64_t)4 * R * n;  // Table 2, parallel
+      }
+      if (pack) pack_split(rs, R, rs->split16, row);
+      else in.k_rows = (int)row.size() * 32;
+      a.out_scale = rs->out_scale;
+      a.lo_scale = rs->lo_scale;
+      in.block_n = n;
+      in.executed_flops_per_point = 3.0 * 2.0 * in.k_rows + 2.0 * in.valu_lines;
+    }
   }
   in.path = path;
   in.lines = lines;

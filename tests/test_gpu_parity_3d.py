@@ -1,0 +1,99 @@
+"""GPU parity of the 3D paths against the CPU FP64 oracle (elementwise).
+
+Extents span two 32 x 64 (j, k) workgroup tiles with ragged tails and two
+chunks of planes along i (chunk boundaries exercise the warm-up of the
+plane ring); edge cases: extents of 1 and below the stencil width, integer
+data (bit-exact) and pure shifts along each axis (orientation)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_16298_amd import inputs
+from paper_2310_16298_amd import stencil as st
+
+from gpu_helpers import eff_coeffs, error_bound, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+BF, FH = st.PATH_MFMA_BF16X3, st.PATH_MFMA_F16X3
+
+
+def combos():
+    out = []
+    for r in (1, 2, 3, 4):
+        for dt in (st.F32, st.F64):
+            out.append((st.PATH_GATHER, dt, st.BOX, r))
+            out.append((st.PATH_GATHER, dt, st.STAR, r))
+            out.append((st.PATH_MFMA, dt, st.STAR, r))
+            if r <= 2:
+                out.append((st.PATH_MFMA, dt, st.BOX, r))
+        for p in (BF, FH):
+            out.append((p, st.F32, st.STAR, r))
+            if r == 1:
+                out.append((p, st.F32, st.BOX, r))
+    return out
+
+
+COMBOS = combos()
+
+
+def _case(dims, r, shape, bc, dtype, path, steps, seed):
+    c = inputs.coefficients(3, r, shape, seed=seed, dtype=np.float64)
+    ce = eff_coeffs(c, dtype)
+    a0 = inputs.grid(dims, seed=seed + 1, dtype=np.float32 if dtype == st.F32 else np.float64)
+    want = oracle.run(a0, ce, r, shape, bc, steps)
+    got = run_gpu(a0, c, r, shape, bc, dtype, path, steps)
+    tol = error_bound(ce, 3, r, shape, dtype, path, steps, np.abs(a0).max())
+    err = np.abs(got - want).max()
+    assert err <= tol, f"max err {err:.3e} > bound {tol:.3e}"
+
+
+@pytest.mark.parametrize("path,dtype,shape,r", COMBOS)
+@pytest.mark.parametrize("bc", [st.BC_ZERO, st.BC_PERIODIC])
+def test_random_ragged(path, dtype, shape, r, bc):
+    _case((37, 45, 77), r, shape, bc, dtype, path, 2, seed=100 + 10 * r + bc)
+
+
+@pytest.mark.parametrize("path,dtype,shape,r", [c for c in COMBOS if c[3] in (1, 4) or c[2] == st.BOX])
+@pytest.mark.parametrize("dims", [(1, 1, 1), (3, 2, 5), (1, 40, 70), (20, 1, 1), (9, 33, 3)])
+def test_small_extents(path, dtype, shape, r, dims):
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        _case(dims, r, shape, bc, dtype, path, 2, seed=200 + r)
+
+
+@pytest.mark.parametrize("path,dtype,shape,r", COMBOS)
+def test_integer_bit_exact(path, dtype, shape, r):
+    c = inputs.int_coefficients(3, r, shape, seed=300 + r)
+    s = float(np.abs(c).sum())
+    limit = 6.0e4 if path in (BF, FH) else 2.0 ** 24
+    steps = 2 if 8 * s * s < limit else 1
+    a0 = inputs.int_grid((18, 40, 70), seed=310 + r, dtype=np.float32 if dtype == st.F32 else np.float64)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        want = oracle.run(a0, c, r, shape, bc, steps)
+        got = run_gpu(a0, c, r, shape, bc, dtype, path, steps)
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("path,dtype,shape,r", [c for c in COMBOS if c[3] in (1, 2)])
+@pytest.mark.parametrize("offset", [(1, 0, 0), (0, -1, 0), (0, 0, 1), (-1, 0, 0), (1, 1, -1)])
+def test_pure_shift_orientation(path, dtype, shape, r, offset):
+    if shape == st.STAR and sum(1 for v in offset if v) > 1:
+        pytest.skip("off-axis offset is not a star tap")
+    c = inputs.shift_coefficients(3, r, offset)
+    if path in (BF, FH):
+        a0 = inputs.int_grid((19, 35, 66), seed=400, lo=-30000, hi=30000)
+    else:
+        a0 = inputs.grid((19, 35, 66), seed=400, dtype=np.float32 if dtype == st.F32 else np.float64)
+    got = run_gpu(a0, c, r, shape, st.BC_PERIODIC, dtype, path, 1)
+    want = np.roll(a0.astype(np.float64), shift=tuple(-o for o in offset), axis=(0, 1, 2))
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("shape,r", [(st.BOX, 3), (st.STAR, 2), (st.BOX, 1)])
+def test_auto_path(shape, r):
+    c = inputs.coefficients(3, r, shape, seed=500, dtype=np.float64)
+    ce = eff_coeffs(c, st.F32)
+    a0 = inputs.grid((30, 33, 65), seed=501)
+    got = run_gpu(a0, c, r, shape, st.BC_ZERO, st.F32, st.PATH_AUTO, 2)
+    want = oracle.run(a0, ce, r, shape, st.BC_ZERO, 2)
+    assert np.abs(got - want).max() <= error_bound(ce, 3, r, shape, st.F32, st.PATH_MFMA, 2, 1.0)
