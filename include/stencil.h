@@ -27,8 +27,9 @@
  *     unpadded, C order, dims slowest to fastest, element type = plan dtype.
  *   - Streams are hipStream_t handles passed as void*; NULL means the
  *     default (null) stream of the current device.
- *   - Entry points that take a stream only enqueue work on it: they neither
- *     synchronise nor allocate, so they can be captured into a HIP graph.
+ *   - Entry points that take a stream only enqueue work on it: they do not
+ *     synchronise and do not allocate device memory, so they can be captured
+ *     into a HIP graph (see stencil_run_steps for its own graph cache).
  *     Kernel faults surface at the caller's next synchronisation.
  *   - A plan belongs to the device that was current when it was created and
  *     must be used with that device current.  A plan is immutable after
@@ -171,9 +172,17 @@ stencil_status_t stencil_plan_destroy(stencil_plan_t plan);
 stencil_status_t stencil_apply(stencil_plan_t plan, const void* in, void* out, void* stream);
 
 /* `steps` Jacobi steps with two buffers used alternately: step t reads
- * buf[t % 2] and writes buf[(t+1) % 2], starting from the state in buf0.
- * *result_index (may be NULL) receives steps % 2, the buffer holding the
- * final state.  steps == 0 enqueues nothing.  Negative steps: EINVAL. */
+ * buf[t % 2] and writes buf[(t+1) % 2], starting from the state in buf0
+ * (Section 2.2).  *result_index (may be NULL) receives steps % 2, the buffer
+ * holding the final state.  steps == 0 enqueues nothing.  Negative steps:
+ * EINVAL; overlapping buffers: EALIAS.
+ * Launch mode: when 2 <= steps <= 4096 and `stream` is not being captured by
+ * the caller, the launches are recorded once into a HIP graph, cached in the
+ * plan per (buf0, buf1, steps) (four entries, least recently used replaced),
+ * and replayed with one graph launch; the first call for a key instantiates
+ * the graph (host-side work, no device synchronisation).  While the caller is
+ * capturing `stream`, or with the environment variable STENCIL_NO_GRAPH=1,
+ * the kernels are enqueued one by one. */
 stencil_status_t stencil_run_steps(stencil_plan_t plan, void* buf0, void* buf1, int64_t steps,
                                    void* stream, int32_t* result_index);
 

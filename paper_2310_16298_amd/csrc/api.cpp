@@ -1,16 +1,33 @@
 // The extern "C" entry points declared in include/stencil.h.
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <vector>
 
 #include "plan.hpp"
 
 using namespace stencil;
 
+// A captured run of `steps` Jacobi steps between two fixed buffers.
+struct GraphEntry {
+  void* buf0 = nullptr;
+  void* buf1 = nullptr;
+  int64_t steps = 0;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
+
 struct stencil_plan_s {
   Resolved rs;
   int device = -1;
+  std::mutex graph_mu;                 // guards the graph cache and the capture stream
+  std::vector<GraphEntry> graphs;      // small LRU cache
+  hipStream_t capture_stream = nullptr;
+  uint64_t use_clock = 0;
   void* d_frag = nullptr;
   void* d_coef = nullptr;
+  void* d_zeros = nullptr;
   size_t grid_bytes = 0;
 };
 
@@ -18,8 +35,12 @@ namespace {
 
 void free_plan(stencil_plan_s* p) {
   if (!p) return;
+  for (GraphEntry& g : p->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   if (p->d_frag) (void)hipFree(p->d_frag);
   if (p->d_coef) (void)hipFree(p->d_coef);
+  if (p->d_zeros) (void)hipFree(p->d_zeros);
   delete p;
 }
 
@@ -39,6 +60,67 @@ stencil_status_t launch_one(const stencil_plan_s* p, const void* in, void* out, 
   a.in = in;
   a.out = out;
   return p->rs.launch(a, p->rs.grid, s) == hipSuccess ? STENCIL_OK : STENCIL_EHIP;
+}
+
+constexpr size_t kGraphCache = 4;
+constexpr int64_t kGraphMinSteps = 2;
+constexpr int64_t kGraphMaxSteps = 4096;
+
+stencil_status_t launch_steps(const stencil_plan_s* p, void* buf0, void* buf1, int64_t steps, hipStream_t s) {
+  void* buf[2] = {buf0, buf1};
+  for (int64_t t = 0; t < steps; ++t) {
+    const stencil_status_t st = launch_one(p, buf[t & 1], buf[(t + 1) & 1], s);
+    if (st != STENCIL_OK) return st;
+  }
+  return STENCIL_OK;
+}
+
+// Replay `steps` launches as one captured graph (built on first use and kept
+// in the plan's cache).  Returns STENCIL_EUNSUPPORTED when graphs are not
+// used for this call, so the caller launches eagerly instead.
+stencil_status_t run_steps_graph(stencil_plan_s* p, void* buf0, void* buf1, int64_t steps, hipStream_t s) {
+  if (steps < kGraphMinSteps || steps > kGraphMaxSteps) return STENCIL_EUNSUPPORTED;
+  const char* off = std::getenv("STENCIL_NO_GRAPH");
+  if (off && off[0] == '1') return STENCIL_EUNSUPPORTED;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return STENCIL_EHIP;
+  if (cs != hipStreamCaptureStatusNone) return STENCIL_EUNSUPPORTED;  // the caller is capturing: stay eager
+  std::lock_guard<std::mutex> lock(p->graph_mu);
+  GraphEntry* hit = nullptr;
+  for (GraphEntry& g : p->graphs)
+    if (g.buf0 == buf0 && g.buf1 == buf1 && g.steps == steps) hit = &g;
+  if (!hit) {
+    if (!p->capture_stream && hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess)
+      return STENCIL_EHIP;
+    if (hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return STENCIL_EHIP;
+    const stencil_status_t st = launch_steps(p, buf0, buf1, steps, p->capture_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->capture_stream, &graph);
+    if (st != STENCIL_OK || e != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st != STENCIL_OK ? st : STENCIL_EHIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return STENCIL_EHIP;
+    if (p->graphs.size() >= kGraphCache) {
+      size_t victim = 0;
+      for (size_t k = 1; k < p->graphs.size(); ++k)
+        if (p->graphs[k].last_use < p->graphs[victim].last_use) victim = k;
+      (void)hipGraphExecDestroy(p->graphs[victim].exec);
+      p->graphs.erase(p->graphs.begin() + victim);
+    }
+    GraphEntry g;
+    g.buf0 = buf0;
+    g.buf1 = buf1;
+    g.steps = steps;
+    g.exec = exec;
+    p->graphs.push_back(g);
+    hit = &p->graphs.back();
+  }
+  hit->last_use = ++p->use_clock;
+  return hipGraphLaunch(hit->exec, s) == hipSuccess ? STENCIL_OK : STENCIL_EHIP;
 }
 
 }  // namespace
@@ -136,8 +218,18 @@ stencil_status_t stencil_plan(const stencil_desc_t* desc, stencil_plan_t* out) {
       free_plan(p);
       return STENCIL_EHIP;
     }
+    if (hipMalloc(&p->d_zeros, 256) != hipSuccess) {
+      free_plan(p);
+      return STENCIL_ENOMEM;
+    }
+    static const unsigned char zero_line[256] = {0};
+    if (hipMemcpy(p->d_zeros, zero_line, 256, hipMemcpyHostToDevice) != hipSuccess) {
+      free_plan(p);
+      return STENCIL_EHIP;
+    }
     p->rs.args.frag = p->d_frag;
     p->rs.args.coef = p->d_coef;
+    p->rs.args.zeros = p->d_zeros;
     *out = p;
     return STENCIL_OK;
   } catch (const std::bad_alloc&) {
@@ -183,11 +275,9 @@ stencil_status_t stencil_run_steps(stencil_plan_t plan, void* buf0, void* buf1, 
   try {
     const stencil_status_t d = check_device(plan);
     if (d != STENCIL_OK) return d;
-    void* buf[2] = {buf0, buf1};
-    for (int64_t t = 0; t < steps; ++t) {
-      const stencil_status_t st = launch_one(plan, buf[t & 1], buf[(t + 1) & 1], (hipStream_t)stream);
-      if (st != STENCIL_OK) return st;
-    }
+    stencil_status_t st = run_steps_graph(plan, buf0, buf1, steps, (hipStream_t)stream);
+    if (st == STENCIL_EUNSUPPORTED) st = launch_steps(plan, buf0, buf1, steps, (hipStream_t)stream);
+    if (st != STENCIL_OK) return st;
     if (result_index) *result_index = (int32_t)(steps & 1);
     return STENCIL_OK;
   } catch (...) {

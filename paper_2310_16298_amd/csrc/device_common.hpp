@@ -26,6 +26,7 @@ struct KArgs {
   void* out;            // output grid (device)
   const void* frag;     // packed MFMA operand fragments (device, plan-owned)
   const void* coef;     // dense C^g in the arithmetic dtype (device, plan-owned)
+  const void* zeros;    // 256 bytes of zeros (device, plan-owned): source of zero-halo lines
   int64_t d0, d1, d2;   // extents; d2 == 1 for 2D
   int32_t periodic;     // 1 = wrap, 0 = zero halo
   int32_t tiles0;       // tiles along the first tiled axis

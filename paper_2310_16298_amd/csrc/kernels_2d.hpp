@@ -249,4 +249,122 @@ __global__ __launch_bounds__(kThreads) void mfma2d_kernel(KArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Outer-product form with n = 4 blocks on v_mfma_f32_4x4x1_16b_f32 (FP32).
+//
+// One instruction performs sixteen independent rank-1 updates of 4 x 4 output
+// blocks: exactly the vector outer product of Eq. (8) with n = 4.  The sixteen
+// blocks of a wave sit side by side along j, so a wave covers 4 rows x 64
+// columns per accumulator; with four accumulators (the i unrolling of
+// Section 4.2, ui = 4) a wave owns 16 rows x 64 columns.
+//   A operand (lane l): the coefficient vector of Eq. (9)-(10) for line b and
+//     band offset d: T_b[l % 4][d] = C^g[d - l % 4][b] (zero outside the band);
+//     all (2r+1) x (4 + 2r) vectors stay in VGPRs.
+//   B operand (lane l): window row x, column l + b -- one conflict-free LDS
+//     read of 64 consecutive floats, scattered to every accumulator whose rows
+//     it reaches (Section 4.3: group the outer products by input vector).
+//   D (lane l, register v): row 4 s + v, column l -- full 256-byte rows.
+// Padding per line is (4 + 2r) / (2r + 1) instead of (16 + 2r) / (2r + 1).
+// BOX: all 2r+1 lines along i; STAR (parallel option, Table 1): the centre
+// line on MFMA, the single-weight lines as vector FMAs.
+// ---------------------------------------------------------------------------
+template <int R, bool BOX>
+struct MfmaB4Shape {
+  static constexpr int NB = 4 + 2 * R;              // band offsets per line
+  static constexpr int NL = BOX ? 2 * R + 1 : 1;    // lines on MFMA
+  static constexpr int NF = NL * NB;                // coefficient vectors per lane
+  static constexpr int TM = kTile2D, TN = kTile2D;
+  static constexpr int WROWS = TM + 2 * R, WCOLS = TN + 2 * R;
+  static constexpr int COL0 = lds_col0<float, R>();
+  static constexpr int PITCH = round_up(COL0 + WCOLS, 4);
+};
+
+template <int R, bool BOX>
+__global__ __launch_bounds__(kThreads) void mfma2d_b4_kernel(KArgs a) {
+  typedef MfmaB4Shape<R, BOX> S;
+  constexpr int BM = S::TM;
+  __shared__ __attribute__((aligned(16))) float lds[S::WROWS * S::PITCH];
+
+  const int64_t M = a.d0, N = a.d1;
+  const bool periodic = a.periodic != 0;
+  const float* __restrict__ in = (const float*)a.in;
+  float* __restrict__ out = (float*)a.out;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const Strip2D sp = decode_strip(a, S::TN);
+  const bool fast = strip_fast(in, N, sp.j0, S::TN);
+
+  const float* __restrict__ frag = (const float*)a.frag;
+  float af[S::NF];
+#pragma unroll
+  for (int c = 0; c < S::NF; ++c) af[c] = frag[c * 64 + lane];
+  float cw[2 * R + 1];
+  if constexpr (!BOX) {
+    const float* __restrict__ c = (const float*)a.coef;
+#pragma unroll
+    for (int b = 0; b <= 2 * R; ++b) cw[b] = c[R * (2 * R + 1) + b];
+  }
+
+  stage_window<float, R, S::WROWS, S::TN, S::PITCH, kThreads>(lds, in, M, N, sp.i0 - R, sp.j0, periodic);
+  __syncthreads();
+
+  PlainWriter<float, R, S::PITCH> wr{lds};
+  RowPrefetch<float, R, BM, S::TN, kThreads> pf;
+  RowMover<float, R, S::WCOLS, kThreads> mv;
+  const float* rowp = lds + (16 * w) * S::PITCH + S::COL0 + lane;
+  for (int64_t ib = sp.i0; ib < sp.i1; ib += BM) {
+    const bool more = ib + BM < sp.i1;
+    if (more) pf.fetch(in, M, N, ib + BM + R, sp.j0, periodic, fast);
+    floatx4 acc[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = floatx4{0, 0, 0, 0};
+#pragma unroll
+    for (int li = 0; li < S::NL; ++li) {
+      const int b = BOX ? li : R;
+#pragma unroll
+      for (int x = 0; x < 16 + 2 * R; ++x) {
+        const float bv = rowp[x * S::PITCH + b];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int d = x - 4 * s;
+          if (d < 0 || d >= S::NB) continue;
+          acc[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(af[li * S::NB + d], bv, acc[s], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keep each line's LDS reads next to its MFMAs
+    }
+    if constexpr (!BOX) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float* rp = rowp + (4 * s + v + R) * S::PITCH;
+          float sum = 0.0f;
+#pragma unroll
+          for (int b = 0; b <= 2 * R; ++b) {
+            if (b == R) continue;
+            sum += cw[b] * rp[b];
+          }
+          acc[s][v] += sum;
+        }
+    }
+    const int64_t gj = sp.j0 + lane;
+    if (gj < N) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t gi = ib + 16 * w + 4 * s + v;
+          if (gi < sp.i1) out[gi * N + gj] = acc[s][v];
+        }
+    }
+    if (more) mv.load([&](int rr, int cc) { return lds[(BM + rr) * S::PITCH + S::COL0 + cc]; });
+    __syncthreads();
+    if (more) {
+      mv.store([&](int rr, int cc, float v) { lds[rr * S::PITCH + S::COL0 + cc] = v; });
+      pf.commit(2 * R, wr);
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace stencil

@@ -1,11 +1,21 @@
 // Instantiations of the 2D gather-form baseline kernel.
+#include "dma2d.hpp"
 #include "kernels_2d.hpp"
 #include "plan.hpp"
 
 namespace stencil {
 
 template <typename T, int R, bool BOX>
-static hipError_t launch_gather2d(const KArgs& a, dim3 grid, hipStream_t s) {
+static hipError_t launch_gather2d(const KArgs& a0, dim3, hipStream_t s) {
+  KArgs a = a0;
+  if constexpr (sizeof(T) == 4) {
+    if (dma2d_ok(a)) {
+      const dim3 grid = strip_grid(a, kDmaTN, kDmaBM);
+      gather2d_dma_kernel<R, BOX><<<grid, dim3(kThreads), 0, s>>>(a);
+      return hipGetLastError();
+    }
+  }
+  const dim3 grid = strip_grid(a, kTile2D, kTile2D, 2048);
   gather2d_kernel<T, R, BOX><<<grid, dim3(kThreads), 0, s>>>(a);
   return hipGetLastError();
 }

@@ -1,12 +1,20 @@
 // Instantiations of the 2D split-precision (BF16x3 / FP16x3) kernel.
+#include "dma2d.hpp"
 #include "kernels_split2d.hpp"
 #include "plan.hpp"
 
 namespace stencil {
 
 template <int KIND, int R>
-static hipError_t launch_split2d(const KArgs& a, dim3 grid, hipStream_t s) {
-  split2d_kernel<KIND, R><<<grid, dim3(256), 0, s>>>(a);
+static hipError_t launch_split2d(const KArgs& a0, dim3, hipStream_t s) {
+  KArgs a = a0;
+  if (dma2d_ok(a)) {
+    const dim3 grid = strip_grid(a, kSplitTN, kDmaBM);
+    split2d_dma_kernel<KIND, R><<<grid, dim3(256), 0, s>>>(a);
+  } else {
+    const dim3 grid = strip_grid(a, 64, 64, 2048);
+    split2d_kernel<KIND, R><<<grid, dim3(256), 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 #include "plan.hpp"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "kernels_3d.hpp"
@@ -155,6 +156,22 @@ static void pack_mfma(Resolved* rs, int R, int dtype, const std::vector<Line>& c
     }
   }
   rs->info.k_rows = NCH * 4;
+}
+
+// FP32 fragments for n = 4 blocks on 4x4x1 (16 blocks): lane l of vector
+// (line, d) holds T[p = l % 4][d] = w[d - p], d = 0 .. 3 + 2r.
+static void pack_mfma_b4(Resolved* rs, int R, const std::vector<Line>& col) {
+  const int NB = 4 + 2 * R;
+  const int NF = (int)col.size() * NB;
+  rs->frag.assign((size_t)NF * 64 * 4, 0);
+  for (int li = 0; li < (int)col.size(); ++li)
+    for (int dd = 0; dd < NB; ++dd)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int e = dd - lane % 4;
+        const double v = (e >= 0 && e <= 2 * R) ? col[li][e] : 0.0;
+        put<float>(rs->frag, (size_t)(li * NB + dd) * 64 + lane, (float)v);
+      }
+  rs->info.k_rows = NF;
 }
 
 // 16-bit split fragments for row lines on 16x16x32 (B operand: lane l,
@@ -309,7 +326,11 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     } else if (path == STENCIL_PATH_MFMA) {
       rs->family = FAM_MFMA2D;
       rs->variant = box ? VAR_BOX : (lines == STENCIL_LINES_PARALLEL ? VAR_STAR_PARALLEL : VAR_STAR_ORTHO);
-      rs->launch = find_mfma2d(d.dtype, R, rs->variant);
+      // FP32 box / parallel star: n = 4 blocks on 4x4x1 (less band padding);
+      // STENCIL_MFMA_BLOCK=16 keeps the 16x16x4 kernel (ablation).
+      const char* blk = std::getenv("STENCIL_MFMA_BLOCK");
+      const bool b4 = d.dtype == STENCIL_F32 && rs->variant != VAR_STAR_ORTHO && !(blk && std::atoi(blk) == 16);
+      rs->launch = b4 ? find_mfma2d_b4(R, box) : find_mfma2d(d.dtype, R, rs->variant);
       std::vector<Line> col, row;
       const int fixed_r[3] = {R, R, 0};
       for (int b = 0; b < W; ++b) {
@@ -319,9 +340,16 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       }
       if (rs->variant == VAR_STAR_ORTHO) row.push_back(line_of(cg, 2, R, 1, fixed_r, true));  // C^g row r
       fill_2d_counts(rs, R, rs->variant, false);
-      if (pack) pack_mfma(rs, R, d.dtype, col, row);
-      else in.k_rows = (int)(col.size() + row.size()) * KL;
-      in.block_n = n;
+      if (b4) {
+        if (pack) pack_mfma_b4(rs, R, col);
+        else in.k_rows = (int)col.size() * (4 + 2 * R);
+        in.block_n = 4;
+        in.rank1_per_block = rs->variant == VAR_BOX ? (int64_t)W * (2 * R + 4) : (2 * R + 4) + (int64_t)2 * R * 4;
+      } else {
+        if (pack) pack_mfma(rs, R, d.dtype, col, row);
+        else in.k_rows = (int)(col.size() + row.size()) * KL;
+        in.block_n = n;
+      }
       in.executed_flops_per_point = 2.0 * in.k_rows + 2.0 * in.valu_lines;
     } else {
       // Split precision: lines along j (C^g rows), star as a box with zero weights.

@@ -50,6 +50,7 @@ double band_value(const double* cg2d, int R, int n, int axis, int index, int i, 
 // Kernel lookups, one per family (defined next to the kernels).
 LaunchFn find_gather2d(int dtype, int R, bool box);
 LaunchFn find_mfma2d(int dtype, int R, int variant);
+LaunchFn find_mfma2d_b4(int R, bool box);
 LaunchFn find_split2d(int kind, int R, int variant);
 LaunchFn find_gather3d(int dtype, int R, bool box);
 LaunchFn find_mfma3d(int dtype, int R, bool box);

@@ -144,6 +144,23 @@ __device__ __forceinline__ bool strip_fast(const T* src, int64_t N, int64_t c0, 
   return (c0 + TN <= N) && (N % (16 / (int)sizeof(T)) == 0) && ((reinterpret_cast<uintptr_t>(src) & 15) == 0);
 }
 
+// Grid of (column strip x row chunk) workgroups for strips of TN columns
+// walked in blocks of BM rows; chunks are sized for about `target`
+// workgroups.  Fills a.tiles0 (chunks), a.tiles1 (strips), a.chunk (rows).
+inline dim3 strip_grid(KArgs& a, int TN, int BM, int64_t target = 1024) {
+  const int64_t strips = (a.d1 + TN - 1) / TN;
+  const int64_t rows = (a.d0 + BM - 1) / BM * BM;
+  int64_t chunk = a.d0 * strips / target;
+  chunk = (chunk < BM ? BM : chunk + BM - 1) / BM * BM;
+  if (chunk > rows) chunk = rows;
+  const int64_t nch = (a.d0 + chunk - 1) / chunk;
+  a.tiles0 = (int32_t)nch;
+  a.tiles1 = (int32_t)strips;
+  a.chunk = (int32_t)chunk;
+  a.nchunks = (int32_t)nch;
+  return dim3((unsigned)(strips * nch));
+}
+
 // Strip decomposition of a 2D grid: tiles0 = row chunks, tiles1 = column strips.
 struct Strip2D {
   int64_t i0, i1, j0;  // output rows [i0, i1), strip column origin j0

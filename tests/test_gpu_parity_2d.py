@@ -155,3 +155,56 @@ def test_error_norms_kernel():
     assert np.isclose(out[0], (d ** 2).sum(), rtol=1e-12)
     assert np.isclose(out[1], (ref.cpu().numpy() ** 2).sum(), rtol=1e-12)
     assert out[2] == np.abs(d).max()
+
+
+@pytest.mark.parametrize("path,dtype", [(st.PATH_GATHER, st.F32), (st.PATH_MFMA, st.F32),
+                                        (st.PATH_MFMA_BF16X3, st.F32), (st.PATH_MFMA_F16X3, st.F32)])
+@pytest.mark.parametrize("shape,lines", [(st.BOX, st.LINES_AUTO), (st.STAR, st.LINES_PARALLEL)])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("dims", [(133, 192), (64, 64), (1, 128), (257, 320), (10, 4), (7, 12), (40, 260)])
+def test_full_strip_extents(path, dtype, shape, lines, r, dims):
+    """Column extents that are multiples of the 64-column strip take the
+    direct-to-LDS window loads (16-byte lines inside or outside the grid)."""
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        _case(dims, r, shape, lines, bc, dtype, path, 3, seed=90 + r)
+
+
+@pytest.mark.parametrize("path", [st.PATH_GATHER, st.PATH_MFMA, st.PATH_MFMA_F16X3])
+@pytest.mark.parametrize("r", [1, 4])
+def test_full_strip_integer_bit_exact(path, r):
+    c = inputs.int_coefficients(2, r, st.BOX, seed=95 + r)
+    steps = _int_steps(c, 6.0e4 if path == st.PATH_MFMA_F16X3 else 2.0 ** 24)
+    a0 = inputs.int_grid((200, 256), seed=96)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        assert np.array_equal(run_gpu(a0, c, r, st.BOX, bc, st.F32, path, steps),
+                              oracle.run(a0, c, r, st.BOX, bc, steps))
+
+
+@pytest.mark.parametrize("path", [st.PATH_MFMA, st.PATH_MFMA_F16X3, st.PATH_GATHER])
+def test_graph_replays_match_eager(path):
+    """run_steps replays a cached HIP graph; every replay, with eager work and
+    synchronisations between replays, equals the eager one-launch-per-step result."""
+    torch = torch_cuda()
+    c = inputs.coefficients(2, 3, st.BOX, seed=97, dtype=np.float64)
+    a0 = inputs.grid((192, 256), seed=98)
+    plan = st.Plan(a0.shape, 3, st.BOX, c, boundary=st.BC_PERIODIC, dtype=st.F32, path=path)
+    x0 = torch.from_numpy(a0).cuda()
+    eager = x0.clone()
+    for _ in range(6):
+        nxt = torch.empty_like(eager)
+        plan.apply(eager, nxt)
+        eager = nxt
+    torch.cuda.synchronize()
+    x = torch.empty_like(x0)
+    tmp = torch.empty_like(x0)
+    for rep in range(4):
+        x.copy_(x0)
+        res = plan.run_steps(x, tmp, 6)          # graph replay after the first call
+        torch.cuda.synchronize()
+        assert res.data_ptr() == x.data_ptr()
+        assert torch.equal(res, eager), rep
+        junk = torch.empty_like(x0)
+        plan.apply(x0, junk)                      # eager work between replays
+        junk.mul_(2.0)
+        torch.cuda.synchronize()
+    plan.close()

@@ -206,17 +206,21 @@ def test_line_band_rejects(lib):
 
 @pytest.mark.parametrize("r", [1, 2, 3, 4])
 def test_counts_2d(lib, r):
-    n = 16
-    box = st.describe((64, 64), r, inputs.BOX, _box(2, r), path=st.PATH_MFMA)
-    assert box["taps"] == (2 * r + 1) ** 2
-    assert box["rank1_per_block"] == (2 * r + 1) * (2 * r + n)      # Section 3.4
-    assert box["mfma_lines"] == 2 * r + 1
-    assert box["k_rows"] >= box["rank1_per_block"]
+    for dt in (st.F32, st.F64):
+        box = st.describe((64, 64), r, inputs.BOX, _box(2, r), path=st.PATH_MFMA, dtype=dt)
+        n = box["block_n"]
+        assert n == (4 if dt == st.F32 else 16)
+        assert box["taps"] == (2 * r + 1) ** 2
+        assert box["rank1_per_block"] == (2 * r + 1) * (2 * r + n)      # Section 3.4
+        assert box["mfma_lines"] == 2 * r + 1
+        assert box["k_rows"] >= box["rank1_per_block"]
     s = inputs.coefficients(2, r, inputs.STAR, seed=5, dtype=np.float64)
     par = st.describe((64, 64), r, inputs.STAR, s, path=st.PATH_MFMA, lines=st.LINES_PARALLEL)
+    n = par["block_n"]
     assert par["rank1_per_block"] == (2 * r + n) + 2 * r * n        # Table 1, parallel
     assert par["mfma_lines"] == 1 and par["valu_lines"] == 2 * r
     orth = st.describe((64, 64), r, inputs.STAR, s, path=st.PATH_MFMA, lines=st.LINES_ORTHOGONAL)
+    n = orth["block_n"]
     assert orth["rank1_per_block"] == 2 * (2 * r + n)               # Table 1, orthogonal
     assert orth["taps"] == 4 * r + 1
     auto = st.describe((64, 64), r, inputs.STAR, s, path=st.PATH_MFMA)
