@@ -153,6 +153,19 @@ stencil_status_t stencil_plan_describe(const stencil_desc_t* desc, stencil_plan_
 stencil_status_t stencil_line_band(const double* coeffs, int32_t radius, int32_t n, int32_t axis,
                                    int32_t index, double* out);
 
+/* Host-only: a minimum set of axis-parallel coefficient lines covering every
+ * nonzero weight of a 2D C^g (Section 3.5).  The nonzeros are the edges of a
+ * bipartite graph between row indices and column indices; a minimum vertex
+ * cover (König's theorem: its size equals a maximum matching's) gives the
+ * lines: row i in the cover is the line CLS(i, *) along j, column j the line
+ * CLS(*, j) along i.
+ * coeffs: host (2r+1)x(2r+1) C^g, C order.  rows_out, cols_out: host arrays of
+ * 2r+1 int32, set to 1 for lines in the cover and 0 otherwise.  *count (may be
+ * NULL) receives the number of lines.  Returns STENCIL_EINVAL for null
+ * pointers or radius outside 1..4. */
+stencil_status_t stencil_line_cover(const double* coeffs, int32_t radius, int32_t* rows_out, int32_t* cols_out,
+                                    int32_t* count);
+
 /* Create a plan on the current device: validates the descriptor, builds the
  * line cover and the banded operand fragments in MFMA lane order, and copies
  * them to the device (the only allocation the library makes).  The caller

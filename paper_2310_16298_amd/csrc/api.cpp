@@ -180,6 +180,23 @@ stencil_status_t stencil_line_band(const double* coeffs, int32_t radius, int32_t
   return STENCIL_OK;
 }
 
+stencil_status_t stencil_line_cover(const double* coeffs, int32_t radius, int32_t* rows_out, int32_t* cols_out,
+                                    int32_t* count) {
+  if (!coeffs || !rows_out || !cols_out || radius < 1 || radius > 4) return STENCIL_EINVAL;
+  try {
+    int r[9], c[9];
+    const int n = line_cover(coeffs, radius, r, c);
+    for (int k = 0; k < 2 * radius + 1; ++k) {
+      rows_out[k] = r[k];
+      cols_out[k] = c[k];
+    }
+    if (count) *count = n;
+    return STENCIL_OK;
+  } catch (...) {
+    return STENCIL_EINTERNAL;
+  }
+}
+
 stencil_status_t stencil_plan(const stencil_desc_t* desc, stencil_plan_t* out) {
   if (!out) return STENCIL_EINVAL;
   *out = nullptr;

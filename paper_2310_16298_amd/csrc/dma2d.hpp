@@ -9,15 +9,19 @@
 // reads long and contiguous (TN = 256: 1 KiB), which HBM serves far better
 // than short scattered segments.
 //
-// Every wave issues exactly NPW load instructions per window with all lanes
-// active (lanes past the window end read a 16-byte zero line into slack at the
-// end of the buffer), so "s_waitcnt vmcnt(NPW)" right after issuing window b+1
-// guarantees that this wave's loads of window b (and its older stores) have
-// completed; a barrier then makes all waves' loads visible.
+// Every wave issues the same number of load instructions per window with all
+// lanes active (lanes past the window end read a 16-byte zero line into slack
+// at the end of the buffer), so "s_waitcnt vmcnt(n)" with n = the loads just
+// issued for window b+1 guarantees that this wave's loads of window b (and
+// its older stores) have completed; a barrier then makes all waves' loads
+// visible.  Only the first window of a strip is loaded whole; later windows
+// load their BM new rows and receive the 2r halo rows from the previous
+// window by an LDS copy.
 //
 // Requirements (checked on the host before choosing these kernels): the
-// column extent is a multiple of 4 and the grid pointer is 16-byte aligned, so
-// every 16-byte line lies entirely inside or outside the grid.  Lines outside
+// column extent is a multiple of 4 and both grid pointers are 16-byte
+// aligned, so every 16-byte line lies entirely inside or outside the grid and
+// results can be stored as 16-byte rows.  Lines outside
 // the grid come from the zero line (zero halo) or wrap (periodic).
 #pragma once
 
@@ -36,21 +40,31 @@ struct DmaWindow {
   static constexpr int LPR = PITCH / 4;         // 16-byte lines per row
   static constexpr int WCOL0 = 4 - R;           // LDS column of window column 0 (global j0 - r)
   static constexpr int ROWS = BM + 2 * R;
-  static constexpr int LINES = ROWS * LPR;
   static constexpr int NWAVES = NT / 64;
-  static constexpr int NI = (LINES + 63) / 64;              // wave instructions per window
-  static constexpr int NPW = (NI + NWAVES - 1) / NWAVES;    // per wave
-  static constexpr int BUF = NPW * NWAVES * 64 * 4;          // floats per buffer, incl. slack
+  // Loads per wave for `rows` window rows; the first window of a strip loads
+  // all BM + 2r rows, later windows only the BM new rows (the 2r halo rows
+  // are carried over in LDS).
+  static constexpr int npw(int rows) { return ((rows * LPR + 63) / 64 + NWAVES - 1) / NWAVES; }
+  static constexpr int NPW_FULL = npw(ROWS);
+  static constexpr int NPW_NEW = npw(BM);
+  // floats per buffer, incl. slack: the first window's loads start at row 0,
+  // later windows' loads at row 2r
+  static constexpr int BUF = cmax(NPW_FULL * NWAVES * 256, 2 * R * PITCH + NPW_NEW * NWAVES * 256);
   static_assert(R <= 4, "window covers at most 4 halo columns");
-  static_assert(NPW < 64, "vmcnt range");
+  static_assert(NPW_FULL < 64, "vmcnt range");
+  static_assert(BM >= 2 * R, "carried halo rows must come from one buffer");
 
-  // Issue the loads of window rows grow0 .. grow0 + ROWS - 1 into `buf`.
-  static __device__ __forceinline__ void issue(float* buf, const float* __restrict__ src,
+  // Issue the loads of NROWS window rows, global rows grow0 .., into LDS rows
+  // starting at `dst` (a row boundary of a buffer).  Every wave issues exactly
+  // npw(NROWS) instructions with all lanes active.
+  template <int NROWS>
+  static __device__ __forceinline__ void issue(float* dst, const float* __restrict__ src,
                                                const float* __restrict__ zeros, int64_t M, int64_t N,
                                                int64_t grow0, int64_t j0, bool periodic) {
+    constexpr int LINES = NROWS * LPR, NP = npw(NROWS);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-    for (int k = 0; k < NPW; ++k) {
+    for (int k = 0; k < NP; ++k) {
       const int inst = k * NWAVES + w;
       const int line = inst * 64 + lane;
       const float* s = zeros;
@@ -60,51 +74,67 @@ struct DmaWindow {
         const int64_t c = map_index(j0 - 4 + 4 * lc, N, periodic);
         if (g >= 0 && c >= 0) s = src + g * N + c;
       }
-      __builtin_amdgcn_global_load_lds(s, (lds_void_t*)(buf + inst * 256), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(s, (lds_void_t*)(dst + inst * 256), 16, 0, 0);
     }
   }
 
-  // Wait until this wave's loads issued before its latest NPW load
-  // instructions have landed (wait_all: every load).
-  static __device__ __forceinline__ void wait_previous() {
-    // s_waitcnt vmcnt(NPW): vmcnt[3:0] in bits 3:0, vmcnt[5:4] in bits 15:14;
-    // expcnt (bits 6:4) and lgkmcnt (bits 11:8) left at their maxima.
-    __builtin_amdgcn_s_waitcnt((NPW & 0xf) | ((NPW >> 4) << 14) | (0x7 << 4) | (0xf << 8));
+  // s_waitcnt vmcnt(n): vmcnt[3:0] in bits 3:0, vmcnt[5:4] in bits 15:14;
+  // expcnt (bits 6:4) and lgkmcnt (bits 11:8) left at their maxima.
+  template <int n>
+  static __device__ __forceinline__ void wait_vm() {
+    __builtin_amdgcn_s_waitcnt((n & 0xf) | ((n >> 4) << 14) | (0x7 << 4) | (0xf << 8));
   }
-  static __device__ __forceinline__ void wait_all() { __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xf << 8)); }
 };
 
 // Host-side condition for the direct-to-LDS kernels.
 inline bool dma2d_ok(const KArgs& a) {
-  return a.d1 % 4 == 0 && (reinterpret_cast<uintptr_t>(a.in) & 15) == 0 && a.zeros != nullptr;
+  return a.d1 % 4 == 0 && (reinterpret_cast<uintptr_t>(a.in) & 15) == 0 &&
+         (reinterpret_cast<uintptr_t>(a.out) & 15) == 0 && a.zeros != nullptr;
 }
 
 // Block loop shared by the DMA kernels: body(cur, ib) computes and stores the
-// block of rows [ib, min(ib + BM, i1)) from the window in `cur`.
+// block of rows [ib, min(ib + BM, i1)) from the window in `cur` (window row 0
+// = global row ib - r).  The first window is loaded whole; afterwards the
+// loads of window b+1 (its BM new rows) are issued before block b is
+// computed, and block b's last 2r rows are copied to the top of window b+1.
 template <class D, int BM, class Body>
 __device__ __forceinline__ void dma_block_loop(float* bufs, const KArgs& a, const Strip2D& sp, Body body) {
+  constexpr int R = D::RAD;
   const float* __restrict__ in = (const float*)a.in;
   const float* __restrict__ zeros = (const float*)a.zeros;
   const bool periodic = a.periodic != 0;
   const int nb = (int)((sp.i1 - sp.i0 + BM - 1) / BM);
-  D::issue(bufs, in, zeros, a.d0, a.d1, sp.i0 - D::RAD, sp.j0, periodic);
+  D::template issue<D::ROWS>(bufs, in, zeros, a.d0, a.d1, sp.i0 - R, sp.j0, periodic);
   for (int bi = 0; bi < nb; ++bi) {
     const int64_t ib = sp.i0 + (int64_t)bi * BM;
+    float* cur = bufs + (bi & 1) * D::BUF;
+    float* nxt = bufs + ((bi + 1) & 1) * D::BUF;
     if (bi + 1 < nb) {
-      D::issue(bufs + ((bi + 1) & 1) * D::BUF, in, zeros, a.d0, a.d1, ib + BM - D::RAD, sp.j0, periodic);
-      D::wait_previous();
+      D::template issue<BM>(nxt + 2 * R * D::PITCH, in, zeros, a.d0, a.d1, ib + BM + R, sp.j0, periodic);
+      D::template wait_vm<D::NPW_NEW>();
     } else {
-      D::wait_all();
+      D::template wait_vm<0>();
     }
     __syncthreads();
-    body(bufs + (bi & 1) * D::BUF, ib);
+    if (bi + 1 < nb) {
+      // carry window rows BM .. BM + 2r - 1 to rows 0 .. 2r - 1 of the next window
+      constexpr int N4 = 2 * R * D::PITCH / 4;
+      for (int idx = threadIdx.x; idx < N4; idx += 256)
+        reinterpret_cast<float4*>(nxt)[idx] = reinterpret_cast<const float4*>(cur + BM * D::PITCH)[idx];
+    }
+    body(cur, ib);
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// n = 4 block outer products (see mfma2d_b4_kernel) on DMA-fed windows:
-// 256-column strips, 16-row blocks; wave w owns columns 64 w .. 64 w + 63.
+// n = 4 block outer products on DMA-fed windows: 256-column strips, 16-row
+// blocks; wave w owns columns 64 w .. 64 w + 63 and all 16 rows (four
+// accumulators of 4 rows, the i unrolling ui = 4).  The input row segment is
+// the MFMA A operand and the coefficient vector the B operand, so block beta
+// of the instruction holds D[i][j] = input column 4 beta + i times the weight
+// for block row j: lane 4 beta + j then owns four consecutive columns of one
+// output row and stores them with one 16-byte write.
 // ---------------------------------------------------------------------------
 constexpr int kDmaTN = 256, kDmaBM = 16;
 
@@ -129,7 +159,8 @@ __global__ __launch_bounds__(256) void mfma2d_b4_dma_kernel(KArgs a) {
 #pragma unroll
     for (int b = 0; b <= 2 * R; ++b) cw[b] = c[R * (2 * R + 1) + b];
   }
-  const int64_t gj = sp.j0 + 64 * w + lane;
+  const int orow = lane & 3;                      // block row owned by this lane
+  const int64_t gj = sp.j0 + 64 * w + 4 * (lane >> 2);  // first of its four columns
 
   dma_block_loop<D, BM>(bufs, a, sp, [&](const float* cur, int64_t ib) {
     const float* rowp = cur + D::WCOL0 + 64 * w + lane;
@@ -141,47 +172,48 @@ __global__ __launch_bounds__(256) void mfma2d_b4_dma_kernel(KArgs a) {
       const int b = BOX ? li : R;
 #pragma unroll
       for (int x = 0; x < 16 + 2 * R; ++x) {
-        const float bv = rowp[x * D::PITCH + b];
+        const float hv = rowp[x * D::PITCH + b];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int d = x - 4 * s;
           if (d < 0 || d >= NB) continue;
-          acc[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(af[li * NB + d], bv, acc[s], 0, 0, 0);
+          acc[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv, af[li * NB + d], acc[s], 0, 0, 0);
         }
       }
       __builtin_amdgcn_sched_barrier(0);  // keep each line's LDS reads next to its MFMAs
     }
     if constexpr (!BOX) {
+      // single-weight lines b != r: D[row][col] += C^g[r][b] * H[row + r][col + b]
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
+      for (int s = 0; s < 4; ++s) {
+        const float* rp = cur + (4 * s + orow + R) * D::PITCH + D::WCOL0 + 64 * w + 4 * (lane >> 2);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const float* rp = rowp + (4 * s + v + R) * D::PITCH;
           float sum = 0.0f;
 #pragma unroll
           for (int b = 0; b <= 2 * R; ++b) {
             if (b == R) continue;
-            sum += cw[b] * rp[b];
+            sum += cw[b] * rp[v + b];
           }
           acc[s][v] += sum;
         }
+      }
     }
     if (gj < N) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t gi = ib + 4 * s + v;
-          if (gi < sp.i1) out[gi * N + gj] = acc[s][v];
-        }
+      for (int s = 0; s < 4; ++s) {
+        const int64_t gi = ib + 4 * s + orow;
+        if (gi < sp.i1) *reinterpret_cast<float4*>(out + gi * N + gj) = float4{acc[s][0], acc[s][1], acc[s][2], acc[s][3]};
+      }
     }
   });
 }
 
 // ---------------------------------------------------------------------------
-// Gather-form baseline on DMA-fed windows: thread t owns column t of the
-// 256-column strip and the 16 rows of each block (register window down the
-// column, wave-uniform coefficients).
+// Gather-form baseline on DMA-fed windows: thread t owns a 4 x 4 block of
+// outputs (rows 4 (t / 64) .., columns 4 (t % 64) .. of the strip), reads
+// its input rows as three aligned 16-byte LDS vectors, applies the taps with
+// wave-uniform coefficients and stores 16-byte rows.
 // ---------------------------------------------------------------------------
 template <int R, bool BOX>
 __global__ __launch_bounds__(256) void gather2d_dma_kernel(KArgs a) {
@@ -192,46 +224,52 @@ __global__ __launch_bounds__(256) void gather2d_dma_kernel(KArgs a) {
   const int64_t N = a.d1;
   float* __restrict__ out = (float*)a.out;
   const float* __restrict__ c = (const float*)a.coef;
-  const int t = threadIdx.x;
+  const int rg = threadIdx.x >> 6, c4 = 4 * (threadIdx.x & 63);
   const Strip2D sp = decode_strip(a, TN);
-  const int64_t gj = sp.j0 + t;
+  const int64_t gj = sp.j0 + c4;
 
   dma_block_loop<D, BM>(bufs, a, sp, [&](const float* cur, int64_t ib) {
-    const float* base = cur + D::WCOL0 + t;
-    float acc[BM];
+    float acc[4][4];
 #pragma unroll
-    for (int p = 0; p < BM; ++p) acc[p] = 0.0f;
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int x = 0; x < BM + 2 * R; ++x) {
-      float h[W];
+      for (int qq = 0; qq < 4; ++qq) acc[p][qq] = 0.0f;
 #pragma unroll
-      for (int b = 0; b < W; ++b) h[b] = base[x * D::PITCH + b];
+    for (int x = 0; x < 4 + 2 * R; ++x) {
+      // LDS columns c4 .. c4 + 11 hold window columns c4 - 4 + r .. c4 + 7 + r
+      const float4* rp = reinterpret_cast<const float4*>(cur + (4 * rg + x) * D::PITCH + c4);
+      const float4 v0 = rp[0], v1 = rp[1], v2 = rp[2];
+      const float vv[12] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x, v2.y, v2.z, v2.w};
 #pragma unroll
-      for (int p = 0; p < BM; ++p) {
+      for (int p = 0; p < 4; ++p) {
         const int aa = x - p;
         if (aa < 0 || aa > 2 * R) continue;
 #pragma unroll
         for (int b = 0; b < W; ++b) {
           if (!BOX && aa != R && b != R) continue;
-          acc[p] += c[aa * W + b] * h[b];
+          const float cf = c[aa * W + b];
+#pragma unroll
+          for (int qq = 0; qq < 4; ++qq) acc[p][qq] += cf * vv[D::WCOL0 + qq + b];
         }
       }
     }
     if (gj < N) {
 #pragma unroll
-      for (int p = 0; p < BM; ++p) {
-        const int64_t gi = ib + p;
-        if (gi < sp.i1) out[gi * N + gj] = acc[p];
+      for (int p = 0; p < 4; ++p) {
+        const int64_t gi = ib + 4 * rg + p;
+        if (gi < sp.i1) *reinterpret_cast<float4*>(out + gi * N + gj) = float4{acc[p][0], acc[p][1], acc[p][2], acc[p][3]};
       }
     }
   });
 }
 
 // ---------------------------------------------------------------------------
-// Split-precision outer products (see split2d_kernel) on DMA-fed FP32
-// windows: 128-column strips, 16-row blocks, wave w owns columns
-// 32 w .. 32 w + 31 (two 16 x 16 output blocks).  After a window lands, one
-// pass splits it into the hi/lo 16-bit LDS planes read by the 16x16x32 MFMAs.
+// Split-precision outer products on DMA-fed FP32 windows: 128-column strips,
+// 16-row blocks, wave w owns columns 32 w .. 32 w + 31 (two 16 x 16 blocks).
+// After a window lands, one pass splits it into the hi/lo 16-bit LDS planes.
+// The band is the MFMA A operand and the input the B operand, so
+// D[m][n] = sum_y S_a[y][m] H[n + a][y]: lane l holds output row l % 16 and
+// four consecutive columns, stored with one 16-byte write.
 // ---------------------------------------------------------------------------
 constexpr int kSplitTN = 128;
 
@@ -291,19 +329,20 @@ __global__ __launch_bounds__(256) void split2d_dma_kernel(KArgs a) {
       for (int t = 0; t < 2; ++t) {
         const u16x8 ah = *reinterpret_cast<const u16x8*>(ph + 16 * t);
         const u16x8 al = *reinterpret_cast<const u16x8*>(pl + 16 * t);
-        acc[t] = Split16<KIND>::mma(ah, bh[l], acc[t]);
-        acx[t] = Split16<KIND>::mma(ah, bl[l], acx[t]);
-        acx[t] = Split16<KIND>::mma(al, bh[l], acx[t]);
+        acc[t] = Split16<KIND>::mma(bh[l], ah, acc[t]);
+        acx[t] = Split16<KIND>::mma(bl[l], ah, acx[t]);
+        acx[t] = Split16<KIND>::mma(bh[l], al, acx[t]);
       }
     }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t gi = ib + 4 * g + v;
-      if (gi >= sp.i1) continue;
+    const int64_t gi = ib + q;
+    if (gi < sp.i1) {
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        const int64_t gj = sp.j0 + 32 * w + 16 * t + q;
-        if (gj < N) out[gi * N + gj] = (acc[t][v] + ls * acx[t][v]) * os;
+        const int64_t gj = sp.j0 + 32 * w + 16 * t + 4 * g;
+        if (gj < N)
+          *reinterpret_cast<float4*>(out + gi * N + gj) =
+              float4{(acc[t][0] + ls * acx[t][0]) * os, (acc[t][1] + ls * acx[t][1]) * os,
+                     (acc[t][2] + ls * acx[t][2]) * os, (acc[t][3] + ls * acx[t][3]) * os};
       }
     }
   });

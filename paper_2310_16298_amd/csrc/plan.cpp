@@ -81,6 +81,77 @@ double band_value(const double* cg2d, int R, int n, int axis, int index, int i, 
   return cg2d[index * W + b];
 }
 
+int line_cover(const double* cg2d, int R, int* rows_out, int* cols_out) {
+  // Maximum matching by augmenting paths (Kuhn), then König's construction:
+  // Z = vertices reachable from unmatched rows by alternating paths; the
+  // cover is (rows not in Z) + (columns in Z).
+  const int W = 2 * R + 1;
+  std::vector<int> match_col(W, -1), match_row(W, -1);
+  auto edge = [&](int i, int j) { return cg2d[i * W + j] != 0.0; };
+  for (int i = 0; i < W; ++i) {
+    std::vector<char> seen(W, 0);
+    std::vector<int> stack;
+    // iterative DFS for an augmenting path from row i
+    std::vector<int> parent_col(W, -1), via_row(W, -1);
+    bool found = false;
+    int end_col = -1;
+    stack.push_back(i);
+    while (!stack.empty() && !found) {
+      const int u = stack.back();
+      stack.pop_back();
+      for (int j = 0; j < W && !found; ++j) {
+        if (!edge(u, j) || seen[j]) continue;
+        seen[j] = 1;
+        via_row[j] = u;
+        if (match_row[j] < 0) {
+          found = true;
+          end_col = j;
+        } else {
+          stack.push_back(match_row[j]);
+        }
+      }
+    }
+    if (found) {
+      int j = end_col;
+      while (j >= 0) {
+        const int u = via_row[j];
+        const int prev = match_col[u];
+        match_col[u] = j;
+        match_row[j] = u;
+        j = (u == i) ? -1 : prev;
+      }
+    }
+    (void)parent_col;
+  }
+  std::vector<char> zr(W, 0), zc(W, 0);
+  std::vector<int> queue;
+  for (int i = 0; i < W; ++i)
+    if (match_col[i] < 0) {
+      zr[i] = 1;
+      queue.push_back(i);
+    }
+  while (!queue.empty()) {
+    const int u = queue.back();
+    queue.pop_back();
+    for (int j = 0; j < W; ++j) {
+      if (!edge(u, j) || zc[j] || match_col[u] == j) continue;
+      zc[j] = 1;
+      const int v = match_row[j];
+      if (v >= 0 && !zr[v]) {
+        zr[v] = 1;
+        queue.push_back(v);
+      }
+    }
+  }
+  int count = 0;
+  for (int i = 0; i < W; ++i) {
+    rows_out[i] = zr[i] ? 0 : 1;
+    cols_out[i] = zc[i] ? 1 : 0;
+    count += rows_out[i] + cols_out[i];
+  }
+  return count;
+}
+
 static int validate(const stencil_desc_t* d) {
   if (!d || !d->coeffs) return STENCIL_EINVAL;
   if (d->ndim != 2 && d->ndim != 3) return STENCIL_EINVAL;

@@ -47,6 +47,9 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* out, bool pack);
 // Banded operand of a 2D coefficient line (see stencil_line_band).
 double band_value(const double* cg2d, int R, int n, int axis, int index, int i, int j);
 
+// Minimum axis-parallel line cover of a 2D C^g (Section 3.5); returns its size.
+int line_cover(const double* cg2d, int R, int* rows_out, int* cols_out);
+
 // Kernel lookups, one per family (defined next to the kernels).
 LaunchFn find_gather2d(int dtype, int R, bool box);
 LaunchFn find_mfma2d(int dtype, int R, int variant);

@@ -61,7 +61,7 @@ class PlanInfo(ctypes.Structure):
 
 EXPORTS = [
     "stencil_version", "stencil_status_string", "stencil_desc_check", "stencil_plan_describe",
-    "stencil_line_band", "stencil_plan", "stencil_plan_info", "stencil_plan_destroy",
+    "stencil_line_band", "stencil_line_cover", "stencil_plan", "stencil_plan_info", "stencil_plan_destroy",
     "stencil_apply", "stencil_run_steps", "stencil_error_norms",
 ]
 
@@ -84,6 +84,8 @@ def load_library(path: str = LIB_PATH):
     lib.stencil_desc_check.argtypes = [ctypes.POINTER(Desc)]
     lib.stencil_plan_describe.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(PlanInfo)]
     lib.stencil_line_band.argtypes = [dp, i32, i32, i32, i32, dp]
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lib.stencil_line_cover.argtypes = [dp, i32, ip, ip, ip]
     lib.stencil_plan.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(vp)]
     lib.stencil_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.stencil_plan_destroy.argtypes = [vp]
@@ -146,6 +148,23 @@ def line_band(coeffs, radius: int, n: int, axis: int, index: int) -> np.ndarray:
     _check(load_library().stencil_line_band(c.ctypes.data_as(dp), radius, n, axis, index,
                                             out.ctypes.data_as(dp)), "stencil_line_band")
     return out
+
+
+def line_cover(coeffs, radius: int):
+    """Host-only: minimum axis-parallel line cover of a 2D C^g (Section 3.5).
+    Returns (row_lines, col_lines): the indices a of lines CLS(a, *) and b of
+    lines CLS(*, b) in the cover."""
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    w = 2 * radius + 1
+    rows = (ctypes.c_int32 * w)()
+    cols = (ctypes.c_int32 * w)()
+    cnt = ctypes.c_int32(0)
+    _check(load_library().stencil_line_cover(c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), radius, rows,
+                                             cols, ctypes.byref(cnt)), "stencil_line_cover")
+    rl = [k for k in range(w) if rows[k]]
+    cl = [k for k in range(w) if cols[k]]
+    assert len(rl) + len(cl) == cnt.value
+    return rl, cl
 
 
 def _torch():

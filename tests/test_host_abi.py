@@ -229,3 +229,47 @@ def test_counts_2d(lib, r):
     assert g["executed_flops_per_point"] == 2 * (2 * r + 1) ** 2
     assert g["bytes_per_point"] == 8
     assert st.describe((64, 64), r, inputs.BOX, _box(2, r), dtype=st.F64, path=st.PATH_GATHER)["bytes_per_point"] == 16
+
+
+# ------------------------------------------------------ minimum line cover
+
+def _brute_cover(nz):
+    w = nz.shape[0]
+    best = 2 * w
+    for mask in range(1 << (2 * w)):
+        rows = [i for i in range(w) if mask >> i & 1]
+        cols = [j for j in range(w) if mask >> (w + j) & 1]
+        k = len(rows) + len(cols)
+        if k >= best:
+            continue
+        if all(i in rows or j in cols for i, j in zip(*np.nonzero(nz))):
+            best = k
+    return best
+
+
+def test_line_cover_closed_cases(lib):
+    """Section 3.5: box -> 2r+1 parallel lines; star -> the two centre lines
+    (the orthogonal option of Table 1); a diagonal pattern (Eq. (15)) needs
+    2r+1 axis-parallel lines."""
+    for r in (1, 2, 3, 4):
+        w = 2 * r + 1
+        rl, cl = st.line_cover(np.ones((w, w)), r)
+        assert len(rl) + len(cl) == w
+        star = inputs.coefficients(2, r, inputs.STAR, seed=r, dtype=np.float64)
+        rl, cl = st.line_cover(star, r)
+        assert (rl, cl) == ([r], [r])
+        rl, cl = st.line_cover(np.eye(w), r)
+        assert len(rl) + len(cl) == w
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_line_cover_is_minimum(lib, seed):
+    rng = np.random.default_rng(seed)
+    r = 1 + seed % 2
+    w = 2 * r + 1
+    nz = rng.random((w, w)) < rng.uniform(0.1, 0.6)
+    c = np.where(nz, rng.uniform(0.5, 1.0, (w, w)), 0.0)
+    rl, cl = st.line_cover(c, r)
+    for i, j in zip(*np.nonzero(nz)):
+        assert i in rl or j in cl
+    assert len(rl) + len(cl) == _brute_cover(nz)
