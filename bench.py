@@ -9,6 +9,11 @@ headline path; the gather-form baseline and the other outer-product variants
 are timed beside it on the same inputs.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Other configurations (their own JSON line each; not the headline):
+    --workload star2d_512   2D five-point star, 512 x 512 FP64, zero halo, 10 steps
+    --workload grid3d       3D stars r=1..4 and the 27-point box, 512^3 FP32/FP64, 50 steps
+    --workload mixed        BF16x3 / FP16x3 with an FP64 shadow, drift check every 50 steps
 """
 from __future__ import annotations
 
@@ -34,10 +39,16 @@ INPUT_SEED = 201
 COEF_SEED0 = 2100
 
 
+# Sources of the 2D kernels timed by the default workload: a counter summary
+# in profiles/traffic.json is used only while these files are unchanged.
+KERNEL_SOURCES_2D = ["device_common.hpp", "stream2d.hpp", "dma2d.hpp", "kernels_2d.hpp", "kernels_split2d.hpp",
+                     "mfma_traits.hpp", "kernels_mfma2d.hip", "kernels_split2d.hip", "kernels_gather2d.hip"]
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2310_16298_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in KERNEL_SOURCES_2D:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
@@ -111,6 +122,149 @@ def load_traffic(kernel_key: str, src_hash: str):
     return ent.get("hbm_bytes_per_launch")
 
 
+def _time_solve(torch, plan, x0, steps, reps, warmup, stream):
+    x = x0.clone()
+    tmp = torch.empty_like(x)
+    for _ in range(warmup):
+        plan.run_steps(x, tmp, steps, stream=stream)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for s0, e0 in evs:
+        s0.record(stream)
+        plan.run_steps(x, tmp, steps, stream=stream)
+        e0.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
+
+
+def workload_star2d_512(args, torch, st, inputs) -> dict:
+    """2D five-point star (r = 1), 512 x 512 FP64, centre 1/2, neighbours 1/8,
+    zero halo, 10 Jacobi steps: GPU latency p50/p99 and the CPU oracle's time."""
+    import oracle
+    dims, steps = (512, 512), 10
+    c = inputs.diffusion_5pt()
+    a0 = inputs.grid(dims, seed=101, dtype=np.float64)
+    x0 = torch.from_numpy(a0).cuda()
+    stream = torch.cuda.Stream()
+    out = {"metric": "10-step solve latency (us) and GStencil/s", "workload":
+           "2D 5-point star r=1, 512x512 FP64, zero halo, 10 Jacobi steps, seed 101", "paths": {}}
+    for name, path in (("gather", st.PATH_GATHER), ("mfma", st.PATH_MFMA)):
+        plan = st.Plan(dims, 1, st.STAR, c, boundary=st.BC_ZERO, dtype=st.F64, path=path)
+        times = _time_solve(torch, plan, x0, steps, max(args.steps, 20), args.warmup, stream)
+        res = plan.run_steps(x0.clone(), torch.empty_like(x0), steps)
+        torch.cuda.synchronize()
+        want = oracle.run(a0, c, 1, st.STAR, st.BC_ZERO, steps)
+        err = float(np.abs(res.cpu().numpy() - want).max())
+        out["paths"][name] = {"p50_us": float(np.percentile(times, 50)) * 1e3,
+                              "p99_us": float(np.percentile(times, 99)) * 1e3,
+                              "gstencil_s": dims[0] * dims[1] * steps / (np.median(times) * 1e-3) / 1e9,
+                              "max_abs_err_vs_oracle": err, "block_n": plan.info["block_n"]}
+        plan.close()
+    oracle.build(force=False)
+    used = oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    t0 = time.perf_counter()
+    oracle.run(a0, c, 1, st.STAR, st.BC_ZERO, steps)
+    out["cpu_oracle_seconds"] = time.perf_counter() - t0
+    out["cpu_oracle_threads"] = used
+    return out
+
+
+def workload_grid3d(args, torch, st, inputs) -> dict:
+    """3D stars r = 1..4 and the 27-point box on 512^3, FP32 and FP64, zero
+    halo, 50 Jacobi steps: gather vs outer-product paths."""
+    dims, steps = (512, 512, 512), 50
+    a64 = inputs.grid(dims, seed=301, dtype=np.float64)
+    stream = torch.cuda.Stream()
+    out = {"metric": "GStencil/s", "workload": "3D 512^3, zero halo, 50 Jacobi steps", "cases": {}}
+    cases = [(st.STAR, r) for r in (1, 2, 3, 4)] + [(st.BOX, 1)]
+    for dt, tdt in ((st.F32, np.float32), (st.F64, np.float64)):
+        x0 = torch.from_numpy(a64.astype(tdt)).cuda()
+        paths = [("gather", st.PATH_GATHER), ("mfma", st.PATH_MFMA)]
+        if dt == st.F32:
+            paths += [("mfma_f16x3", st.PATH_MFMA_F16X3), ("mfma_bf16x3", st.PATH_MFMA_BF16X3)]
+        for shape, r in cases:
+            c = inputs.coefficients(3, r, shape, seed=3100 + 10 * shape + r, dtype=np.float64)
+            key = f"{'f32' if dt == st.F32 else 'f64'}_{'box' if shape == st.BOX else 'star'}_r{r}"
+            out["cases"][key] = {}
+            for name, path in paths:
+                plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=dt, path=path)
+                times = _time_solve(torch, plan, x0, steps, args.steps, args.warmup, stream)
+                g = dims[0] * dims[1] * dims[2] * steps / (np.median(times) * 1e-3) / 1e9
+                bpp = 8 if dt == st.F32 else 16
+                out["cases"][key][name] = {"gstencil_s": round(g, 2), "hbm_frac": round(g * bpp / HBM_PEAK_GBS, 4),
+                                           "ms_per_solve": round(float(np.median(times)), 3)}
+                print(f"[bench] {key} {name}: {g:.1f} GStencil/s", file=sys.stderr, flush=True)
+                plan.close()
+        del x0
+        torch.cuda.empty_cache()
+    return out
+
+
+def workload_mixed(args, torch, st, inputs) -> dict:
+    """BF16x3 / FP16x3 outer products with FP32 state for 200 steps; an FP64
+    shadow trajectory (FP64 gather path) on the GPU; rel-L2 and max-abs of the
+    state against it every 50 steps."""
+    import oracle
+    out = {"metric": "GStencil/s and drift vs FP64", "cases": {}}
+    stream = torch.cuda.Stream()
+    specs = [("box2d_r2_4096", (4096, 4096), 2, st.BOX, 401, 4100),
+             ("star3d_r4_384", (384, 384, 384), 4, st.STAR, 402, 4200)]
+    for key, dims, r, shape, iseed, cseed in specs:
+        nd = len(dims)
+        c = inputs.coefficients(nd, r, shape, seed=cseed, dtype=np.float64)
+        c32 = c.astype(np.float32).astype(np.float64)
+        a32 = inputs.grid(dims, seed=iseed, dtype=np.float32)
+        x0 = torch.from_numpy(a32).cuda()
+        shadow_plan = st.Plan(dims, r, shape, c32, boundary=st.BC_ZERO, dtype=st.F64, path=st.PATH_GATHER)
+        sh = x0.double()
+        sh_tmp = torch.empty_like(sh)
+        out["cases"][key] = {}
+        for name, path in (("mfma_bf16x3", st.PATH_MFMA_BF16X3), ("mfma_f16x3", st.PATH_MFMA_F16X3),
+                           ("mfma", st.PATH_MFMA), ("gather", st.PATH_GATHER)):
+            plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=st.F32, path=path)
+            times = _time_solve(torch, plan, x0, 200, args.steps, args.warmup, stream)
+            g = float(np.prod(dims)) * 200 / (np.median(times) * 1e-3) / 1e9
+            # drift: state and FP64 shadow advanced 50 steps at a time
+            x = x0.clone()
+            tmp = torch.empty_like(x)
+            s64 = sh.clone()
+            drift = []
+            for k in range(4):
+                res = plan.run_steps(x, tmp, 50)
+                if res.data_ptr() != x.data_ptr():
+                    x, tmp = tmp, x
+                r64 = shadow_plan.run_steps(s64, sh_tmp, 50)
+                if r64.data_ptr() != s64.data_ptr():
+                    s64, sh_tmp = sh_tmp, s64
+                nrm = st.error_norms(x, s64).cpu().numpy()
+                drift.append({"step": 50 * (k + 1), "rel_l2": float(np.sqrt(nrm[0] / nrm[1])),
+                              "max_abs": float(nrm[2])})
+            entry = {"gstencil_s": round(g, 2), "hbm_frac": round(g * 8 / HBM_PEAK_GBS, 4), "drift": drift}
+            if nd == 2:
+                # CPU FP64 oracle on light-cone windows of the final state
+                fin = x.cpu().numpy().astype(np.float64)
+                errs = []
+                for lo in [(0, 0), (2000, 3000)]:
+                    want = oracle.window(a32, c32, r, shape, st.BC_ZERO, 200, lo, (8, 8))
+                    errs.append(float(np.abs(fin[lo[0]:lo[0] + 8, lo[1]:lo[1] + 8] - want).max()))
+                entry["max_abs_vs_cpu_oracle_windows"] = max(errs)
+            out["cases"][key][name] = entry
+            print(f"[bench] {key} {name}: {g:.1f} GStencil/s drift@200 rel_l2={drift[-1]['rel_l2']:.2e}",
+                  file=sys.stderr, flush=True)
+            plan.close()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        shadow_plan.run_steps(sh.clone(), sh_tmp, 200, stream=stream)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        out["cases"][key]["fp64_shadow_ms_per_200_steps"] = t0.elapsed_time(t1)
+        shadow_plan.close()
+        del x0, sh, sh_tmp
+        torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     global RADII, JACOBI_STEPS
     ap = argparse.ArgumentParser()
@@ -123,6 +277,7 @@ def main() -> int:
     ap.add_argument("--radii", default="1,2,3,4", help="orders to run (profiling runs use a subset)")
     ap.add_argument("--jacobi-steps", type=int, default=JACOBI_STEPS,
                     help="Jacobi steps per solve (profiling runs only; the benchmark uses 100)")
+    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed"])
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="first run N plain device copies of one grid (known bytes) for counter scaling")
     args = ap.parse_args()
@@ -139,6 +294,12 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     st.load_library()
+    if args.workload != "box2d":
+        fn = {"star2d_512": workload_star2d_512, "grid3d": workload_grid3d, "mixed": workload_mixed}[args.workload]
+        res = fn(args, torch, st, inputs)
+        res.update({"n_gpus": 1, "data": "synthetic"})
+        print(json.dumps(res))
+        return 0
     name_to_path = {"gather": st.PATH_GATHER, "mfma": st.PATH_MFMA, "mfma_f16x3": st.PATH_MFMA_F16X3,
                     "mfma_bf16x3": st.PATH_MFMA_BF16X3, "auto": st.PATH_AUTO}
     paths = [p for p in args.paths.split(",") if p]

@@ -14,9 +14,14 @@
 // slot reached through coefficient plane a (o = i - a + r) is
 // (uu + 2r - a) mod (2r+1) and the completed plane sits in slot uu: all slot
 // indices are compile-time constants.
+//
+// Staging: with DMA = true the window of plane i+1 is loaded straight into
+// LDS (dma3d.hpp) while plane i is computed; otherwise (extents or pointers
+// that do not allow 16-byte lines) each plane is staged synchronously.
 #pragma once
 
 #include "device_common.hpp"
+#include "dma3d.hpp"
 #include "kernels_2d.hpp"
 #include "kernels_split2d.hpp"
 #include "mfma_traits.hpp"
@@ -44,24 +49,84 @@ __device__ __forceinline__ Chunk3D decode_chunk(const KArgs& a) {
   return c;
 }
 
+// Walk the input planes of a chunk.  LROWS window rows (global j0 - r ..) of
+// each plane are staged into a buffer of pitch PITCH, window column y at LDS
+// column COL0 + y; body(win, uu, valid) scatters the plane (win = window base,
+// uu = compile-time ring phase, valid = false for a zero-halo plane outside
+// the grid); store(uu, o, live) writes completed output plane o from slot uu
+// when live (o >= ib; warm-up planes reach outputs below the chunk) and always
+// resets the slot for the output plane that reuses it.
+template <typename T, int R, int LROWS, bool DMA>
+struct PlaneWalk {
+  static constexpr int W = 2 * R + 1;
+  typedef DmaPlane<T, R, LROWS, kTK, kThreads> D;
+  static constexpr int PITCH = DMA ? D::PITCH : pick_pitch<T, true>(lds_col0<T, R>() + kTK + 2 * R + 8);
+  static constexpr int COL0 = DMA ? D::COL0 : lds_col0<T, R>();
+  static constexpr int BUF = DMA ? D::BUF : LROWS * PITCH;  // elements per buffer
+  static constexpr int NBUF = DMA ? 2 : 1;
+
+  template <class Body, class Store>
+  static __device__ __forceinline__ void run(T* bufs, const KArgs& a, const Chunk3D& ch, Body body, Store store) {
+    const int64_t Ni = a.d0, Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
+    const bool periodic = a.periodic != 0;
+    const T* __restrict__ in = (const T*)a.in;
+    const T* __restrict__ zeros = (const T*)a.zeros;
+    const int nu = (int)(ch.iend - ch.ib) + 2 * R;
+    if constexpr (DMA) {
+      const int64_t g0 = map_index(ch.ib - R, Ni, periodic);
+      D::issue(bufs, g0 >= 0 ? in + g0 * plane : nullptr, zeros, Nj, Nk, ch.j0 - R, ch.k0, periodic);
+    } else {
+      // rows and columns past the window (K padding of the MFMA kernels) carry zero weights
+      zero_region<T, kThreads>(bufs, LROWS, PITCH, PITCH, 0, 0);
+    }
+    for (int ug = 0; ug < nu; ug += W) {
+#pragma unroll
+      for (int uu = 0; uu < W; ++uu) {
+        const int u = ug + uu;
+        if (u >= nu) break;
+        const int64_t gi = map_index(ch.ib - R + u, Ni, periodic);
+        const T* win;
+        if constexpr (DMA) {
+          win = bufs + (u & 1) * BUF;
+          if (u + 1 < nu) {
+            const int64_t g1 = map_index(ch.ib - R + u + 1, Ni, periodic);
+            D::issue(bufs + ((u + 1) & 1) * BUF, g1 >= 0 ? in + g1 * plane : nullptr, zeros, Nj, Nk, ch.j0 - R,
+                     ch.k0, periodic);
+            D::template wait_vm<D::NPW>();
+          } else {
+            D::template wait_vm<0>();
+          }
+          __syncthreads();
+        } else {
+          win = bufs;
+          __syncthreads();
+          if (gi >= 0)
+            stage_window<T, R, kTJ + 2 * R, kTK, PITCH, kThreads>(bufs, in + gi * plane, Nj, Nk, ch.j0 - R, ch.k0,
+                                                                 periodic);
+          __syncthreads();
+        }
+        body(win, uu, gi >= 0);
+        store(uu, ch.ib + u - 2 * R, u >= 2 * R);
+        if constexpr (DMA) __syncthreads();
+      }
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Gather-form baseline (Eq. (1) in 3D).  Thread (s, q) owns k column q and
 // j rows 8 s .. 8 s + 7 of the tile.  Box: each input plane adds its
 // (2r+1)^2 in-plane taps to the 2r+1 output planes it reaches; star: the
 // centre plane adds the j and k arms, every plane adds its i-arm weight.
 // ---------------------------------------------------------------------------
-template <typename T, int R, bool BOX>
+template <typename T, int R, bool BOX, bool DMA>
 __global__ __launch_bounds__(kThreads) void gather3d_kernel(KArgs a) {
   constexpr int W = 2 * R + 1, ROWS = 8;
-  constexpr int WROWS = kTJ + 2 * R;
-  constexpr int COL0 = lds_col0<T, R>();
-  constexpr int PITCH = pick_pitch<T, false>(COL0 + kTK + 2 * R);
-  __shared__ __attribute__((aligned(16))) T lds[WROWS * PITCH];
+  typedef PlaneWalk<T, R, kTJ + 2 * R, DMA> PW;
+  __shared__ __attribute__((aligned(16))) T bufs[PW::NBUF * PW::BUF];
 
   const Chunk3D ch = decode_chunk(a);
-  const int64_t Ni = a.d0, Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
-  const bool periodic = a.periodic != 0;
-  const T* __restrict__ in = (const T*)a.in;
+  const int64_t Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
   T* __restrict__ out = (T*)a.out;
   const T* __restrict__ c = (const T*)a.coef;
   const int q = threadIdx.x & 63, s = threadIdx.x >> 6;
@@ -72,24 +137,17 @@ __global__ __launch_bounds__(kThreads) void gather3d_kernel(KArgs a) {
 #pragma unroll
     for (int p = 0; p < ROWS; ++p) ring[z][p] = T(0);
 
-  const int nu = (int)(ch.iend - ch.ib) + 2 * R;
-  const T* base = lds + (ROWS * s) * PITCH + COL0 + q;
-  for (int ug = 0; ug < nu; ug += W) {
-#pragma unroll
-    for (int uu = 0; uu < W; ++uu) {
-      const int u = ug + uu;
-      if (u >= nu) break;
-      const int64_t gi = map_index(ch.ib - R + u, Ni, periodic);
-      __syncthreads();
-      if (gi >= 0) {
-        stage_window<T, R, WROWS, kTK, PITCH, kThreads>(lds, in + gi * plane, Nj, Nk, ch.j0 - R, ch.k0, periodic);
-        __syncthreads();
+  PW::run(
+      bufs, a, ch,
+      [&](const T* win, int uu, bool valid) {
+        if (!valid) return;
+        const T* base = win + (ROWS * s) * PW::PITCH + PW::COL0 + q;
         if constexpr (BOX) {
 #pragma unroll
           for (int x = 0; x < ROWS + 2 * R; ++x) {
             T h[W];
 #pragma unroll
-            for (int cc = 0; cc < W; ++cc) h[cc] = base[x * PITCH + cc];
+            for (int cc = 0; cc < W; ++cc) h[cc] = base[x * PW::PITCH + cc];
 #pragma unroll
             for (int ap = 0; ap < W; ++ap) {
               const int slot = (uu + 2 * R - ap) % W;
@@ -106,7 +164,7 @@ __global__ __launch_bounds__(kThreads) void gather3d_kernel(KArgs a) {
           // centre plane (slot of output plane i): j arm (column k = q + r) and k arm (row j = p + r)
 #pragma unroll
           for (int x = 0; x < ROWS + 2 * R; ++x) {
-            const T hv = base[x * PITCH + R];
+            const T hv = base[x * PW::PITCH + R];
 #pragma unroll
             for (int p = 0; p < ROWS; ++p) {
               const int bb = x - p;
@@ -116,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void gather3d_kernel(KArgs a) {
           }
 #pragma unroll
           for (int p = 0; p < ROWS; ++p) {
-            const T* rowp = base + (p + R) * PITCH;
+            const T* rowp = base + (p + R) * PW::PITCH;
 #pragma unroll
             for (int cc = 0; cc < W; ++cc) {
               if (cc == R) continue;
@@ -131,23 +189,17 @@ __global__ __launch_bounds__(kThreads) void gather3d_kernel(KArgs a) {
             }
           }
         }
-      }
-      // output plane ib + u - 2r is complete (slot uu)
-      const int64_t o = ch.ib + u - 2 * R;
-      if (u >= 2 * R) {
+      },
+      [&](int uu, int64_t o, bool live) {
         const int64_t gk = ch.k0 + q;
 #pragma unroll
         for (int p = 0; p < ROWS; ++p) {
           const int64_t gj = ch.j0 + ROWS * s + p;
-          if (gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = ring[uu][p];
+          if (live && gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = ring[uu][p];
+          ring[uu][p] = T(0);
         }
-      }
-#pragma unroll
-      for (int p = 0; p < ROWS; ++p) ring[uu][p] = T(0);
-    }
-  }
+      });
 }
-
 
 // ---------------------------------------------------------------------------
 // Outer-product form on MFMA (FP32 / FP64).  Waves form a 2 x 2 grid over the
@@ -162,6 +214,8 @@ __global__ __launch_bounds__(kThreads) void gather3d_kernel(KArgs a) {
 // along j (band, rows of the window as B operand) and CLS(r, r, *) along k
 // (window column segments as A operand, centre excluded); the lines CLS(a, *, r)
 // with a != r hold one weight each and are the vector FMAs of the i arm.
+// K padding reads rows and columns past the band; they carry zero weights
+// (rows are loaded or zeroed; columns past a row end read the next row).
 // ---------------------------------------------------------------------------
 template <typename T, int R, bool BOX>
 struct Mfma3DShape {
@@ -170,27 +224,20 @@ struct Mfma3DShape {
   static constexpr int CPL = KL / 4;
   static constexpr int NLINES = BOX ? W * W : 2;
   static constexpr int NCH = NLINES * CPL;
-  static constexpr int WROWS = kTJ + 2 * R;
-  static constexpr int LROWS = (kTJ - 16) + KL;
-  static constexpr int COL0 = lds_col0<T, R>();
-  static constexpr int WEND = COL0 + kTK + 2 * R;
-  static constexpr int REND = COL0 + (kTK - 16) + KL;
-  static constexpr int LCOLS = cmax(WEND, BOX ? 0 : REND);
-  static constexpr int PITCH = pick_pitch<T, !BOX>(LCOLS);
+  static constexpr int LROWS = cmax(kTJ + 2 * R, (kTJ - 16) + KL);
 };
 
-template <typename T, int R, bool BOX>
+template <typename T, int R, bool BOX, bool DMA>
 __global__ __launch_bounds__(kThreads) void mfma3d_kernel(KArgs a) {
   typedef Mfma16<T> MM;
   typedef typename MM::acc_t acc_t;
   typedef Mfma3DShape<T, R, BOX> S;
+  typedef PlaneWalk<T, R, S::LROWS, DMA> PW;
   constexpr int W = S::W;
-  __shared__ __attribute__((aligned(16))) T lds[S::LROWS * S::PITCH];
+  __shared__ __attribute__((aligned(16))) T bufs[PW::NBUF * PW::BUF];
 
   const Chunk3D ch = decode_chunk(a);
-  const int64_t Ni = a.d0, Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
-  const bool periodic = a.periodic != 0;
-  const T* __restrict__ in = (const T*)a.in;
+  const int64_t Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
   T* __restrict__ out = (T*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wj = w >> 1, wk = w & 1;
@@ -207,31 +254,18 @@ __global__ __launch_bounds__(kThreads) void mfma3d_kernel(KArgs a) {
     for (int ap = 0; ap < W; ++ap) ci[ap] = c[(ap * W + R) * W + R];
   }
 
-  if constexpr (S::LROWS > S::WROWS)
-    zero_region<T, kThreads>(lds, S::LROWS - S::WROWS, S::PITCH, S::PITCH, S::WROWS, 0);
-  if constexpr (S::LCOLS > S::WEND)
-    zero_region<T, kThreads>(lds, S::WROWS, S::LCOLS - S::WEND, S::PITCH, 0, S::WEND);
-
   acc_t ring[W][2];
 #pragma unroll
   for (int z = 0; z < W; ++z) {
     ring[z][0] = acc_t{};
     ring[z][1] = acc_t{};
   }
-  const T* colbase = lds + (16 * wj + g) * S::PITCH + S::COL0 + 32 * wk + q;
-  const T* rowbase = lds + (16 * wj + R + q) * S::PITCH + S::COL0 + 32 * wk + g;
-  const int nu = (int)(ch.iend - ch.ib) + 2 * R;
-  for (int ug = 0; ug < nu; ug += W) {
-#pragma unroll
-    for (int uu = 0; uu < W; ++uu) {
-      const int u = ug + uu;
-      if (u >= nu) break;
-      const int64_t gi = map_index(ch.ib - R + u, Ni, periodic);
-      __syncthreads();
-      if (gi >= 0) {
-        stage_window<T, R, S::WROWS, kTK, S::PITCH, kThreads>(lds, in + gi * plane, Nj, Nk, ch.j0 - R, ch.k0,
-                                                              periodic);
-        __syncthreads();
+  PW::run(
+      bufs, a, ch,
+      [&](const T* win, int uu, bool valid) {
+        if (!valid) return;
+        const T* colbase = win + (16 * wj + g) * PW::PITCH + PW::COL0 + 32 * wk + q;
+        const T* rowbase = win + (16 * wj + R + q) * PW::PITCH + PW::COL0 + 32 * wk + g;
         if constexpr (BOX) {
 #pragma unroll
           for (int ap = 0; ap < W; ++ap) {
@@ -243,7 +277,7 @@ __global__ __launch_bounds__(kThreads) void mfma3d_kernel(KArgs a) {
                 const T av = af[(ap * W + cs) * S::CPL + cc];
 #pragma unroll
                 for (int t = 0; t < 2; ++t) {
-                  const T bv = colbase[(4 * cc) * S::PITCH + 16 * t + cs];
+                  const T bv = colbase[(4 * cc) * PW::PITCH + 16 * t + cs];
                   ring[slot][t] = MM::mma(av, bv, ring[slot][t]);
                 }
               }
@@ -256,7 +290,7 @@ __global__ __launch_bounds__(kThreads) void mfma3d_kernel(KArgs a) {
             const T av = af[cc];
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-              const T bv = colbase[(4 * cc) * S::PITCH + 16 * t + R];
+              const T bv = colbase[(4 * cc) * PW::PITCH + 16 * t + R];
               ring[slot][t] = MM::mma(av, bv, ring[slot][t]);
             }
           }
@@ -272,7 +306,7 @@ __global__ __launch_bounds__(kThreads) void mfma3d_kernel(KArgs a) {
           // i arm: lines CLS(a, *, r), a != r, one weight each
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const T* cp = lds + (16 * wj + R + MM::row(lane, v)) * S::PITCH + S::COL0 + 32 * wk + MM::col(lane) + R;
+            const T* cp = win + (16 * wj + R + MM::row(lane, v)) * PW::PITCH + PW::COL0 + 32 * wk + MM::col(lane) + R;
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
               const T ctr = cp[16 * t];
@@ -284,24 +318,20 @@ __global__ __launch_bounds__(kThreads) void mfma3d_kernel(KArgs a) {
             }
           }
         }
-      }
-      const int64_t o = ch.ib + u - 2 * R;
-      if (u >= 2 * R) {
+      },
+      [&](int uu, int64_t o, bool live) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t gj = ch.j0 + 16 * wj + MM::row(lane, v);
-          if (gj >= Nj) continue;
 #pragma unroll
           for (int t = 0; t < 2; ++t) {
             const int64_t gk = ch.k0 + 32 * wk + 16 * t + MM::col(lane);
-            if (gk < Nk) out[o * plane + gj * Nk + gk] = ring[uu][t][v];
+            if (live && gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = ring[uu][t][v];
           }
         }
-      }
-      ring[uu][0] = acc_t{};
-      ring[uu][1] = acc_t{};
-    }
-  }
+        ring[uu][0] = acc_t{};
+        ring[uu][1] = acc_t{};
+      });
 }
 
 // ---------------------------------------------------------------------------
@@ -311,8 +341,9 @@ __global__ __launch_bounds__(kThreads) void mfma3d_kernel(KArgs a) {
 // to output plane i - a + r (window rows shifted by b as the A operand).
 // Box (27-point, r = 1): all (2r+1)^2 lines on MFMA.  Star: the k line
 // CLS(r, r, *) on MFMA; the other 4r lines hold one weight each and are vector
-// FMAs on an FP32 copy of the window (j arm on the centre plane, i arm into the
-// other ring slots), pre-multiplied by the plan's coefficient scale.
+// FMAs on the FP32 window (j arm on the centre plane, i arm into the other
+// ring slots), pre-multiplied by the plan's coefficient scale.  Each staged
+// FP32 window is split once into hi/lo 16-bit planes.
 // ---------------------------------------------------------------------------
 template <int R, bool BOX>
 struct Split3DShape {
@@ -321,23 +352,20 @@ struct Split3DShape {
   static constexpr int WROWS = kTJ + 2 * R;
   static constexpr int WEND = kTK + 2 * R;
   static constexpr int P = 88;  // 16-bit pitch: multiple of 8, covers columns read by K = 32
-  static constexpr int COL0F = lds_col0<float, R>();
-  static constexpr int P32 = BOX ? 1 : pick_pitch<float, false>(COL0F + kTK + 2 * R);
   static_assert((kTK - 32) + 16 + 32 <= P && WEND <= P, "pitch too small");
 };
 
-template <int KIND, int R, bool BOX>
+template <int KIND, int R, bool BOX, bool DMA>
 __global__ __launch_bounds__(kThreads) void split3d_kernel(KArgs a) {
   typedef Split3DShape<R, BOX> S;
+  typedef PlaneWalk<float, R, S::WROWS, DMA> PW;
   constexpr int W = S::W;
+  __shared__ __attribute__((aligned(16))) float bufs[PW::NBUF * PW::BUF];
   __shared__ __attribute__((aligned(16))) uint16_t lhi[S::WROWS * S::P];
   __shared__ __attribute__((aligned(16))) uint16_t llo[S::WROWS * S::P];
-  __shared__ __attribute__((aligned(16))) float l32[BOX ? 4 : S::WROWS * S::P32];
 
   const Chunk3D ch = decode_chunk(a);
-  const int64_t Ni = a.d0, Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
-  const bool periodic = a.periodic != 0;
-  const float* __restrict__ in = (const float*)a.in;
+  const int64_t Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
   float* __restrict__ out = (float*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wj = w >> 1, wk = w & 1;
@@ -363,6 +391,7 @@ __global__ __launch_bounds__(kThreads) void split3d_kernel(KArgs a) {
   zero_region<uint16_t, kThreads>(lhi, S::WROWS, S::P - S::WEND, S::P, 0, S::WEND);
   zero_region<uint16_t, kThreads>(llo, S::WROWS, S::P - S::WEND, S::P, 0, S::WEND);
   const float lo_mul = 1.0f / a.lo_scale;
+  const float ls = a.lo_scale, os = a.out_scale;
 
   floatx4 acc[W][2], acx[W][2];
 #pragma unroll
@@ -372,20 +401,21 @@ __global__ __launch_bounds__(kThreads) void split3d_kernel(KArgs a) {
       acc[z][t] = floatx4{0, 0, 0, 0};
       acx[z][t] = floatx4{0, 0, 0, 0};
     }
-  const int nu = (int)(ch.iend - ch.ib) + 2 * R;
-  for (int ug = 0; ug < nu; ug += W) {
-#pragma unroll
-    for (int uu = 0; uu < W; ++uu) {
-      const int u = ug + uu;
-      if (u >= nu) break;
-      const int64_t gi = map_index(ch.ib - R + u, Ni, periodic);
-      __syncthreads();
-      if (gi >= 0) {
-        stage_split<KIND, R, S::WROWS, kTK, S::P, kThreads>(lhi, llo, in + gi * plane, Nj, Nk, ch.j0 - R, ch.k0,
-                                                             periodic, lo_mul);
-        if constexpr (!BOX)
-          stage_window<float, R, S::WROWS, kTK, S::P32, kThreads>(l32, in + gi * plane, Nj, Nk, ch.j0 - R, ch.k0,
-                                                                  periodic);
+  PW::run(
+      bufs, a, ch,
+      [&](const float* win, int uu, bool valid) {
+        if (!valid) return;
+        // split the FP32 window into hi/lo planes
+        constexpr int HALF = S::WEND / 2;
+        for (int idx = threadIdx.x; idx < S::WROWS * HALF; idx += kThreads) {
+          const int row = idx / HALF, y = 2 * (idx - (idx / HALF) * HALF);
+          const float* src = win + row * PW::PITCH + PW::COL0 + y;
+          uint16_t h0, l0, h1, l1;
+          Split16<KIND>::split(src[0], lo_mul, h0, l0);
+          Split16<KIND>::split(src[1], lo_mul, h1, l1);
+          *reinterpret_cast<uint32_t*>(lhi + row * S::P + y) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+          *reinterpret_cast<uint32_t*>(llo + row * S::P + y) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+        }
         __syncthreads();
 #pragma unroll
         for (int ap = 0; ap < W; ++ap) {
@@ -410,17 +440,17 @@ __global__ __launch_bounds__(kThreads) void split3d_kernel(KArgs a) {
         if constexpr (!BOX) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const float* cp = l32 + (16 * wj + 4 * g + v) * S::P32 + S::COL0F + 32 * wk + q + R;
+            const float* cp = win + (16 * wj + 4 * g + v) * PW::PITCH + PW::COL0 + 32 * wk + q + R;
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
               float sj = 0.0f;
 #pragma unroll
               for (int b = 0; b < W; ++b) {
                 if (b == R) continue;
-                sj += cj[b] * cp[b * S::P32 + 16 * t];
+                sj += cj[b] * cp[b * PW::PITCH + 16 * t];
               }
               acc[(uu + R) % W][t][v] += sj;
-              const float ctr = cp[R * S::P32 + 16 * t];
+              const float ctr = cp[R * PW::PITCH + 16 * t];
 #pragma unroll
               for (int ap = 0; ap < W; ++ap) {
                 if (ap == R) continue;
@@ -429,28 +459,23 @@ __global__ __launch_bounds__(kThreads) void split3d_kernel(KArgs a) {
             }
           }
         }
-      }
-      const int64_t o = ch.ib + u - 2 * R;
-      if (u >= 2 * R) {
-        const float ls = a.lo_scale, os = a.out_scale;
+      },
+      [&](int uu, int64_t o, bool live) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int64_t gj = ch.j0 + 16 * wj + 4 * g + v;
-          if (gj >= Nj) continue;
 #pragma unroll
           for (int t = 0; t < 2; ++t) {
             const int64_t gk = ch.k0 + 32 * wk + 16 * t + q;
-            if (gk < Nk) out[o * plane + gj * Nk + gk] = (acc[uu][t][v] + ls * acx[uu][t][v]) * os;
+            if (live && gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = (acc[uu][t][v] + ls * acx[uu][t][v]) * os;
           }
         }
-      }
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        acc[uu][t] = floatx4{0, 0, 0, 0};
-        acx[uu][t] = floatx4{0, 0, 0, 0};
-      }
-    }
-  }
+        for (int t = 0; t < 2; ++t) {
+          acc[uu][t] = floatx4{0, 0, 0, 0};
+          acx[uu][t] = floatx4{0, 0, 0, 0};
+        }
+      });
 }
 
 }  // namespace stencil

@@ -6,7 +6,10 @@ namespace stencil {
 
 template <int R, bool BOX>
 static hipError_t launch_gather3d(const KArgs& a, dim3 grid, hipStream_t s) {
-  gather3d_kernel<float, R, BOX><<<grid, dim3(kThreads), 0, s>>>(a);
+  if (dma3d_ok<float>(a))
+    gather3d_kernel<float, R, BOX, true><<<grid, dim3(kThreads), 0, s>>>(a);
+  else
+    gather3d_kernel<float, R, BOX, false><<<grid, dim3(kThreads), 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -7,7 +7,10 @@ namespace stencil {
 
 template <typename T, int R, bool BOX>
 static hipError_t launch_mfma3d(const KArgs& a, dim3 grid, hipStream_t s) {
-  mfma3d_kernel<T, R, BOX><<<grid, dim3(kThreads), 0, s>>>(a);
+  if (dma3d_ok<T>(a))
+    mfma3d_kernel<T, R, BOX, true><<<grid, dim3(kThreads), 0, s>>>(a);
+  else
+    mfma3d_kernel<T, R, BOX, false><<<grid, dim3(kThreads), 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -6,7 +6,10 @@ namespace stencil {
 
 template <int KIND, int R, bool BOX>
 static hipError_t launch_split3d(const KArgs& a, dim3 grid, hipStream_t s) {
-  split3d_kernel<KIND, R, BOX><<<grid, dim3(kThreads), 0, s>>>(a);
+  if (dma3d_ok<float>(a))
+    split3d_kernel<KIND, R, BOX, true><<<grid, dim3(kThreads), 0, s>>>(a);
+  else
+    split3d_kernel<KIND, R, BOX, false><<<grid, dim3(kThreads), 0, s>>>(a);
   return hipGetLastError();
 }
 

@@ -97,3 +97,24 @@ def test_auto_path(shape, r):
     got = run_gpu(a0, c, r, shape, st.BC_ZERO, st.F32, st.PATH_AUTO, 2)
     want = oracle.run(a0, ce, r, shape, st.BC_ZERO, 2)
     assert np.abs(got - want).max() <= error_bound(ce, 3, r, shape, st.F32, st.PATH_MFMA, 2, 1.0)
+
+
+@pytest.mark.parametrize("path,dtype,shape,r", COMBOS)
+@pytest.mark.parametrize("dims", [(21, 45, 132), (9, 40, 64), (5, 3, 4), (34, 1, 8)])
+def test_dma_plane_extents(path, dtype, shape, r, dims):
+    """k extents that are multiples of the 16-byte vector take the
+    direct-to-LDS plane windows (double-buffered across planes)."""
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        _case(dims, r, shape, bc, dtype, path, 2, seed=600 + r)
+
+
+@pytest.mark.parametrize("path,dtype,shape,r", [c for c in COMBOS if c[3] in (1, 2)])
+def test_dma_plane_integer_bit_exact(path, dtype, shape, r):
+    c = inputs.int_coefficients(3, r, shape, seed=610 + r)
+    s = float(np.abs(c).sum())
+    limit = 6.0e4 if path in (BF, FH) else 2.0 ** 24
+    steps = 2 if 8 * s * s < limit else 1
+    a0 = inputs.int_grid((20, 37, 68), seed=620 + r, dtype=np.float32 if dtype == st.F32 else np.float64)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        assert np.array_equal(run_gpu(a0, c, r, shape, bc, dtype, path, steps),
+                              oracle.run(a0, c, r, shape, bc, steps))
