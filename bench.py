@@ -14,6 +14,7 @@ Other configurations (their own JSON line each; not the headline):
     --workload star2d_512   2D five-point star, 512 x 512 FP64, zero halo, 10 steps
     --workload grid3d       3D stars r=1..4 and the 27-point box, 512^3 FP32/FP64, 50 steps
     --workload mixed        BF16x3 / FP16x3 with an FP64 shadow, drift check every 50 steps
+    --workload batch        many small FP64 grids (Table 3 shapes) per batched launch vs one by one
 """
 from __future__ import annotations
 
@@ -200,6 +201,75 @@ def workload_grid3d(args, torch, st, inputs) -> dict:
     return out
 
 
+def workload_batch(args, torch, st, inputs) -> dict:
+    """Many small FP64 grids of the paper's Table 3 shapes (2D box/star r = 1..3
+    at 64^2..512^2, 3D box r = 1, 2 and star r = 1..3 at 8^3..64^3), zero halo,
+    10 Jacobi steps: one batched launch per step over 2^24 points of grids of
+    one size (a shared plan), against launching the grids one by one."""
+    steps = 10
+    total_pts = 1 << 24
+    stream = torch.cuda.Stream()
+    out = {"metric": "GStencil/s", "workload": "batches of FP64 Table 3 grids, 2^24 points per batch, "
+           "zero halo, 10 Jacobi steps", "cases": {}}
+    cases = [(2, st.BOX, r) for r in (1, 2, 3)] + [(2, st.STAR, r) for r in (1, 2, 3)]
+    cases += [(3, st.BOX, r) for r in (1, 2)] + [(3, st.STAR, r) for r in (1, 2, 3)]
+    for nd, shape, r in cases:
+        sizes = (64, 128, 256, 512) if nd == 2 else (8, 16, 32, 64)
+        for n in sizes:
+            dims = (n,) * nd
+            pts = n ** nd
+            count = total_pts // pts
+            c = inputs.coefficients(nd, r, shape, seed=8000 + 10 * nd + r + 100 * shape, dtype=np.float64)
+            plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=st.F64)
+            a0 = torch.from_numpy(inputs.grid((count,) + dims, seed=8001, dtype=np.float64)).cuda()
+            b0 = a0.clone()
+            b1 = torch.empty_like(b0)
+            batch = st.Batch([plan] * count, list(b0.unbind(0)), list(b1.unbind(0)))
+            for _ in range(max(args.warmup, 1)):
+                batch.run_steps(steps, stream=stream)
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(max(args.steps, 3)):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                batch.run_steps(steps, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            g_batch = total_pts * steps / (np.median(times) * 1e-3) / 1e9
+            # one by one: a sample of the grids, each launched eagerly step by step
+            ns = min(count, 64)
+            x = a0[:ns].clone()
+            y = torch.empty_like(x)
+            os.environ["STENCIL_NO_GRAPH"] = "1"
+            try:
+                for k in range(ns):
+                    plan.run_steps(x[k], y[k], steps, stream=stream)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for k in range(ns):
+                    plan.run_steps(x[k], y[k], steps, stream=stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+            finally:
+                del os.environ["STENCIL_NO_GRAPH"]
+            g_single = ns * pts * steps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+            key = f"{nd}d_{'box' if shape == st.BOX else 'star'}_r{r}_{n}"
+            info = batch.info()
+            out["cases"][key] = {"grids": count, "batched_gstencil_s": round(g_batch, 2),
+                                 "one_by_one_gstencil_s": round(g_single, 2),
+                                 "speedup": round(g_batch / g_single, 2), "path": st.PATH_NAMES[plan.info["path"]],
+                                 "items": info["items"], "workgroups": info["blocks"]}
+            print(f"[bench] batch {key}: {g_batch:.1f} GStencil/s batched, {g_single:.2f} one by one "
+                  f"({count} grids)", file=sys.stderr, flush=True)
+            batch.close()
+            plan.close()
+            del a0, b0, b1, x, y
+            torch.cuda.empty_cache()
+    return out
+
+
 def workload_mixed(args, torch, st, inputs) -> dict:
     """BF16x3 / FP16x3 outer products with FP32 state for 200 steps; an FP64
     shadow trajectory (FP64 gather path) on the GPU; rel-L2 and max-abs of the
@@ -277,7 +347,7 @@ def main() -> int:
     ap.add_argument("--radii", default="1,2,3,4", help="orders to run (profiling runs use a subset)")
     ap.add_argument("--jacobi-steps", type=int, default=JACOBI_STEPS,
                     help="Jacobi steps per solve (profiling runs only; the benchmark uses 100)")
-    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed"])
+    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch"])
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="first run N plain device copies of one grid (known bytes) for counter scaling")
     args = ap.parse_args()
@@ -295,7 +365,8 @@ def main() -> int:
         return 2
     st.load_library()
     if args.workload != "box2d":
-        fn = {"star2d_512": workload_star2d_512, "grid3d": workload_grid3d, "mixed": workload_mixed}[args.workload]
+        fn = {"star2d_512": workload_star2d_512, "grid3d": workload_grid3d, "mixed": workload_mixed,
+              "batch": workload_batch}[args.workload]
         res = fn(args, torch, st, inputs)
         res.update({"n_gpus": 1, "data": "synthetic"})
         print(json.dumps(res))

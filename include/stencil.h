@@ -95,7 +95,13 @@ typedef struct {
   int32_t dtype;        /* stencil_dtype_t */
   int32_t path;         /* stencil_path_t */
   int32_t lines;        /* stencil_lines_t */
-  int32_t reserved;     /* must be 0 */
+  int32_t block_n;      /* edge n of the MFMA output block: 0 = library choice; 4 selects
+                           v_mfma_f32_4x4x1_16b blocks (FP32 2D box and parallel-line star only),
+                           16 the 16x16 instructions; any other resolved block edge: EUNSUPPORTED;
+                           ignored by the GATHER path */
+  int32_t chunk;        /* output rows (2D) or i-planes (3D) per workgroup work item: 0 = library
+                           choice; rounded up to the kernel's row block and clipped to the extent */
+  int32_t time_block;   /* steps fused per launch: 0 or 1 = one step per launch */
   const double* coeffs; /* host pointer to (2r+1)^ndim gather coefficients C^g,
                            C order, index o + r for offset o; copied by the call.
                            For an F32 plan they are rounded to float first. */
@@ -198,6 +204,44 @@ stencil_status_t stencil_apply(stencil_plan_t plan, const void* in, void* out, v
  * the kernels are enqueued one by one. */
 stencil_status_t stencil_run_steps(stencil_plan_t plan, void* buf0, void* buf1, int64_t steps,
                                    void* stream, int32_t* result_index);
+
+/* ---------------------------------------------------------------- batches
+ * Many grids of uneven sizes (each with its own plan: dims, radius, shape,
+ * coefficients, boundary) advanced by the same number of Jacobi steps with one
+ * launch per kernel and step instead of one per grid: small grids (the
+ * paper's 64^2..512^2 and 8^3..64^3 cases, Section 5) leave most of the GPU
+ * idle one at a time.  Grids whose plans resolve to the same kernel form a
+ * group; a group's launch is persistent -- at most (resident workgroups per
+ * CU) x (CUs) workgroups loop over the (grid, tile) work items of all its
+ * grids.  The groups of a step run concurrently on streams forked from the
+ * caller's stream and joined back into it; multi-step runs are replayed from a
+ * captured HIP graph under the same rule as stencil_run_steps. */
+typedef struct stencil_batch_s* stencil_batch_t;
+
+/* Create a batch on the current device.  plans[i] (device = current device)
+ * advances the grid held in buffers buf0[i] / buf1[i] (device pointers of
+ * plans[i]'s dims and dtype).  Allocates the device work table (one
+ * allocation) and count-1 streams at most.  The plans and buffers must outlive
+ * the batch; the plans may be shared between batches.  Errors: EINVAL (null
+ * pointers, count < 1, a plan of another device), EALIAS (any two of the
+ * 2 x count buffers overlap), EUNSUPPORTED (more than 2^31-1 work items in
+ * one group), ENOMEM, EHIP.  On error *out is NULL. */
+stencil_status_t stencil_batch_create(const stencil_plan_t* plans, void* const* buf0, void* const* buf1,
+                                      int32_t count, stencil_batch_t* out);
+
+/* `steps` Jacobi steps of every grid of the batch, enqueued on `stream`: step
+ * t reads buf[t % 2] and writes buf[(t+1) % 2] of each grid, starting from
+ * buf0 (Section 2.2).  *result_index (may be NULL) receives steps % 2.  Calls
+ * on one batch must not overlap in time (they share its buffers). */
+stencil_status_t stencil_batch_run_steps(stencil_batch_t batch, int64_t steps, void* stream,
+                                         int32_t* result_index);
+
+/* Number of kernel groups, total work items and persistent workgroups per
+ * step of a batch (any pointer may be NULL). */
+stencil_status_t stencil_batch_info(stencil_batch_t batch, int32_t* groups, int64_t* items, int64_t* blocks);
+
+/* Release a batch (NULL accepted); enqueued work must have completed. */
+stencil_status_t stencil_batch_destroy(stencil_batch_t batch);
 
 /* Error norms of a state against a reference, for the drift check of
  * mixed-precision runs.  a: device array of n elements of a_dtype

@@ -1,70 +1,27 @@
 // The extern "C" entry points declared in include/stencil.h.
-#include <cstdlib>
 #include <cstring>
-#include <mutex>
 #include <new>
-#include <vector>
 
-#include "plan.hpp"
+#include "runtime.hpp"
 
 using namespace stencil;
-
-// A captured run of `steps` Jacobi steps between two fixed buffers.
-struct GraphEntry {
-  void* buf0 = nullptr;
-  void* buf1 = nullptr;
-  int64_t steps = 0;
-  hipGraphExec_t exec = nullptr;
-  uint64_t last_use = 0;
-};
-
-struct stencil_plan_s {
-  Resolved rs;
-  int device = -1;
-  std::mutex graph_mu;                 // guards the graph cache and the capture stream
-  std::vector<GraphEntry> graphs;      // small LRU cache
-  hipStream_t capture_stream = nullptr;
-  uint64_t use_clock = 0;
-  void* d_frag = nullptr;
-  void* d_coef = nullptr;
-  void* d_zeros = nullptr;
-  size_t grid_bytes = 0;
-};
 
 namespace {
 
 void free_plan(stencil_plan_s* p) {
   if (!p) return;
-  for (GraphEntry& g : p->graphs)
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   if (p->d_frag) (void)hipFree(p->d_frag);
   if (p->d_coef) (void)hipFree(p->d_coef);
   if (p->d_zeros) (void)hipFree(p->d_zeros);
   delete p;
 }
 
-bool overlaps(const void* a, const void* b, size_t n) {
-  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
-  return x < y + n && y < x + n;
-}
-
-stencil_status_t check_device(const stencil_plan_s* p) {
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess) return STENCIL_EHIP;
-  return dev == p->device ? STENCIL_OK : STENCIL_EINVAL;
-}
-
 stencil_status_t launch_one(const stencil_plan_s* p, const void* in, void* out, hipStream_t s) {
-  KArgs a = p->rs.args;
-  a.in = in;
-  a.out = out;
-  return p->rs.launch(a, p->rs.grid, s) == hipSuccess ? STENCIL_OK : STENCIL_EHIP;
+  KArgs a;
+  const Kernel k = plan_kernel(p, in, out, &a);
+  if (!k.launch || k.items < 1 || k.items > (int64_t(1) << 31) - 1) return STENCIL_EINTERNAL;
+  return k.launch(a, (unsigned)k.items, s) == hipSuccess ? STENCIL_OK : STENCIL_EHIP;
 }
-
-constexpr size_t kGraphCache = 4;
-constexpr int64_t kGraphMinSteps = 2;
-constexpr int64_t kGraphMaxSteps = 4096;
 
 stencil_status_t launch_steps(const stencil_plan_s* p, void* buf0, void* buf1, int64_t steps, hipStream_t s) {
   void* buf[2] = {buf0, buf1};
@@ -73,54 +30,6 @@ stencil_status_t launch_steps(const stencil_plan_s* p, void* buf0, void* buf1, i
     if (st != STENCIL_OK) return st;
   }
   return STENCIL_OK;
-}
-
-// Replay `steps` launches as one captured graph (built on first use and kept
-// in the plan's cache).  Returns STENCIL_EUNSUPPORTED when graphs are not
-// used for this call, so the caller launches eagerly instead.
-stencil_status_t run_steps_graph(stencil_plan_s* p, void* buf0, void* buf1, int64_t steps, hipStream_t s) {
-  if (steps < kGraphMinSteps || steps > kGraphMaxSteps) return STENCIL_EUNSUPPORTED;
-  const char* off = std::getenv("STENCIL_NO_GRAPH");
-  if (off && off[0] == '1') return STENCIL_EUNSUPPORTED;
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return STENCIL_EHIP;
-  if (cs != hipStreamCaptureStatusNone) return STENCIL_EUNSUPPORTED;  // the caller is capturing: stay eager
-  std::lock_guard<std::mutex> lock(p->graph_mu);
-  GraphEntry* hit = nullptr;
-  for (GraphEntry& g : p->graphs)
-    if (g.buf0 == buf0 && g.buf1 == buf1 && g.steps == steps) hit = &g;
-  if (!hit) {
-    if (!p->capture_stream && hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess)
-      return STENCIL_EHIP;
-    if (hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return STENCIL_EHIP;
-    const stencil_status_t st = launch_steps(p, buf0, buf1, steps, p->capture_stream);
-    hipGraph_t graph = nullptr;
-    const hipError_t e = hipStreamEndCapture(p->capture_stream, &graph);
-    if (st != STENCIL_OK || e != hipSuccess || !graph) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return st != STENCIL_OK ? st : STENCIL_EHIP;
-    }
-    hipGraphExec_t exec = nullptr;
-    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ei != hipSuccess) return STENCIL_EHIP;
-    if (p->graphs.size() >= kGraphCache) {
-      size_t victim = 0;
-      for (size_t k = 1; k < p->graphs.size(); ++k)
-        if (p->graphs[k].last_use < p->graphs[victim].last_use) victim = k;
-      (void)hipGraphExecDestroy(p->graphs[victim].exec);
-      p->graphs.erase(p->graphs.begin() + victim);
-    }
-    GraphEntry g;
-    g.buf0 = buf0;
-    g.buf1 = buf1;
-    g.steps = steps;
-    g.exec = exec;
-    p->graphs.push_back(g);
-    hit = &p->graphs.back();
-  }
-  hit->last_use = ++p->use_clock;
-  return hipGraphLaunch(hit->exec, s) == hipSuccess ? STENCIL_OK : STENCIL_EHIP;
 }
 
 }  // namespace
@@ -277,7 +186,7 @@ stencil_status_t stencil_apply(stencil_plan_t plan, const void* in, void* out, v
   if (!plan || !in || !out) return STENCIL_EINVAL;
   if (overlaps(in, out, plan->grid_bytes)) return STENCIL_EALIAS;
   try {
-    const stencil_status_t d = check_device(plan);
+    const stencil_status_t d = check_device(plan->device);
     if (d != STENCIL_OK) return d;
     return launch_one(plan, in, out, (hipStream_t)stream);
   } catch (...) {
@@ -290,9 +199,12 @@ stencil_status_t stencil_run_steps(stencil_plan_t plan, void* buf0, void* buf1, 
   if (!plan || !buf0 || !buf1 || steps < 0) return STENCIL_EINVAL;
   if (overlaps(buf0, buf1, plan->grid_bytes)) return STENCIL_EALIAS;
   try {
-    const stencil_status_t d = check_device(plan);
+    const stencil_status_t d = check_device(plan->device);
     if (d != STENCIL_OK) return d;
-    stencil_status_t st = run_steps_graph(plan, buf0, buf1, steps, (hipStream_t)stream);
+    const stencil_plan_s* p = plan;
+    stencil_status_t st = plan->graphs.run(buf0, buf1, steps, (hipStream_t)stream, [&](hipStream_t cs) {
+      return launch_steps(p, buf0, buf1, steps, cs);
+    });
     if (st == STENCIL_EUNSUPPORTED) st = launch_steps(plan, buf0, buf1, steps, (hipStream_t)stream);
     if (st != STENCIL_OK) return st;
     if (result_index) *result_index = (int32_t)(steps & 1);

@@ -37,6 +37,11 @@ struct KArgs {
   float lo_scale;       // split-precision paths: weight of the cross-term accumulator
 };
 
+// Pointer to data that no lane writes during a kernel (constant address
+// space): uniform reads through it compile to scalar loads.
+template <typename T>
+using ConstPtr = const __attribute__((address_space(4))) T*;
+
 __host__ __device__ constexpr int round_up(int v, int m) { return (v + m - 1) / m * m; }
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
@@ -64,13 +69,13 @@ template <> struct Vec16<double> { typedef double2 type; };
 //   src          : the 2D slice (rows x cols = M x N), C order
 //   r0           : global row of window row 0
 //   c0           : global column of the tile body (window column R); c0 % VEC == 0
-//   lds[row * PITCH + COL0 + y] receives window element (row, y).
+//   lds[row * PITCH + COL0 + y] receives window element (row, y); COL0 + R
+//   must be a multiple of VEC.
 // All NT threads of the block must call it.
-template <typename T, int R, int ROWS, int BODY, int PITCH, int NT>
+template <typename T, int R, int ROWS, int BODY, int PITCH, int NT, int COL0 = lds_col0<T, R>()>
 __device__ __forceinline__ void stage_window(T* __restrict__ lds, const T* __restrict__ src,
                                              int64_t M, int64_t N, int64_t r0, int64_t c0,
                                              bool periodic) {
-  constexpr int COL0 = lds_col0<T, R>();
   constexpr int VEC = 16 / (int)sizeof(T);
   constexpr int NV = BODY / VEC;
   constexpr int WCOLS = BODY + 2 * R;
@@ -138,6 +143,61 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   const int full = per * NXCD;
   if (bid >= full) return bid;
   return (bid % NXCD) * per + bid / NXCD;
+}
+
+// Several grids in one launch.  Grid g of a table owns the work items
+// (workgroup tiles) [table[g].first, table[g+1].first); table[ngrids].first is
+// the total.  Its args hold buffer 0 in `in` and buffer 1 in `out`; a launch
+// whose step parity p has (p ^ phase) odd reads buffer 1 and writes buffer 0,
+// so grids that joined a batch at different steps advance together.
+struct BatchGrid {
+  KArgs args;
+  int32_t first;  // first work item of this grid
+  int32_t phase;  // step parity offset of this grid
+};
+
+struct BatchArgs {
+  const BatchGrid* table;  // nullptr: one grid, described by the kernel's own KArgs
+  int32_t ngrids;
+  int32_t total;           // work items over all grids
+  int32_t parity;          // step parity of this launch
+  int32_t pad;
+};
+
+// Load a struct whose address is the same in every lane into scalar registers.
+template <typename S>
+__device__ __forceinline__ S uniform_load(const S* p) {
+  static_assert(sizeof(S) % 4 == 0, "dword-sized struct");
+  S v;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(p);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&v);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(S) / 4); ++k) dst[k] = __builtin_amdgcn_readfirstlane(src[k]);
+  return v;
+}
+
+// Batched launch: a persistent loop over work items blockIdx.x,
+// blockIdx.x + gridDim.x, ... of all grids in the table (every workgroup ends
+// after the last item); each item finds its grid by binary search over
+// `first` and runs item(args, id) with the grid's args in scalar registers.
+template <class F>
+__device__ __forceinline__ void for_each_batch_item(const BatchArgs& b, F item) {
+  for (int it = blockIdx.x; it < b.total; it += gridDim.x) {
+    int lo = 0, hi = b.ngrids - 1;  // last grid with first <= it
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (__builtin_amdgcn_readfirstlane(b.table[mid].first) <= it) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchGrid e = uniform_load(&b.table[lo]);
+    KArgs g = e.args;
+    if ((b.parity ^ e.phase) & 1) {
+      g.in = e.args.out;
+      g.out = const_cast<void*>(e.args.in);
+    }
+    __syncthreads();  // the previous item's LDS reads are done
+    item(g, it - e.first);
+  }
 }
 
 }  // namespace stencil

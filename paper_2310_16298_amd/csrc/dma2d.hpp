@@ -139,7 +139,7 @@ __device__ __forceinline__ void dma_block_loop(float* bufs, const KArgs& a, cons
 constexpr int kDmaTN = 256, kDmaBM = 16;
 
 template <int R, bool BOX>
-__global__ __launch_bounds__(256) void mfma2d_b4_dma_kernel(KArgs a) {
+__device__ __forceinline__ void mfma2d_b4_dma_item(const KArgs& a, int item) {
   constexpr int BM = kDmaBM, TN = kDmaTN, NB = 4 + 2 * R, NL = BOX ? 2 * R + 1 : 1;
   typedef DmaWindow<R, BM, TN, 256> D;
   __shared__ __attribute__((aligned(16))) float bufs[2 * D::BUF];
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void mfma2d_b4_dma_kernel(KArgs a) {
   const int64_t N = a.d1;
   float* __restrict__ out = (float*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const Strip2D sp = decode_strip(a, TN);
+  const Strip2D sp = decode_strip(a, item, TN);
 
   const float* __restrict__ frag = (const float*)a.frag;
   float af[NL * NB];
@@ -209,6 +209,16 @@ __global__ __launch_bounds__(256) void mfma2d_b4_dma_kernel(KArgs a) {
   });
 }
 
+template <int R, bool BOX>
+__global__ __launch_bounds__(256) void mfma2d_b4_dma_kernel(KArgs a) {
+  mfma2d_b4_dma_item<R, BOX>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <int R, bool BOX>
+__global__ __launch_bounds__(256) void mfma2d_b4_dma_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { mfma2d_b4_dma_item<R, BOX>(x, id); });
+}
+
 // ---------------------------------------------------------------------------
 // Gather-form baseline on DMA-fed windows: thread t owns a 4 x 4 block of
 // outputs (rows 4 (t / 64) .., columns 4 (t % 64) .. of the strip), reads
@@ -216,7 +226,7 @@ __global__ __launch_bounds__(256) void mfma2d_b4_dma_kernel(KArgs a) {
 // wave-uniform coefficients and stores 16-byte rows.
 // ---------------------------------------------------------------------------
 template <int R, bool BOX>
-__global__ __launch_bounds__(256) void gather2d_dma_kernel(KArgs a) {
+__device__ __forceinline__ void gather2d_dma_item(const KArgs& a, int item) {
   constexpr int BM = kDmaBM, TN = kDmaTN, W = 2 * R + 1;
   typedef DmaWindow<R, BM, TN, 256> D;
   __shared__ __attribute__((aligned(16))) float bufs[2 * D::BUF];
@@ -225,7 +235,7 @@ __global__ __launch_bounds__(256) void gather2d_dma_kernel(KArgs a) {
   float* __restrict__ out = (float*)a.out;
   const float* __restrict__ c = (const float*)a.coef;
   const int rg = threadIdx.x >> 6, c4 = 4 * (threadIdx.x & 63);
-  const Strip2D sp = decode_strip(a, TN);
+  const Strip2D sp = decode_strip(a, item, TN);
   const int64_t gj = sp.j0 + c4;
 
   dma_block_loop<D, BM>(bufs, a, sp, [&](const float* cur, int64_t ib) {
@@ -263,6 +273,16 @@ __global__ __launch_bounds__(256) void gather2d_dma_kernel(KArgs a) {
   });
 }
 
+template <int R, bool BOX>
+__global__ __launch_bounds__(256) void gather2d_dma_kernel(KArgs a) {
+  gather2d_dma_item<R, BOX>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <int R, bool BOX>
+__global__ __launch_bounds__(256) void gather2d_dma_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { gather2d_dma_item<R, BOX>(x, id); });
+}
+
 // ---------------------------------------------------------------------------
 // Split-precision outer products on DMA-fed FP32 windows: 128-column strips,
 // 16-row blocks, wave w owns columns 32 w .. 32 w + 31 (two 16 x 16 blocks).
@@ -274,7 +294,7 @@ __global__ __launch_bounds__(256) void gather2d_dma_kernel(KArgs a) {
 constexpr int kSplitTN = 128;
 
 template <int KIND, int R>
-__global__ __launch_bounds__(256) void split2d_dma_kernel(KArgs a) {
+__device__ __forceinline__ void split2d_dma_item(const KArgs& a, int item) {
   constexpr int NL = 2 * R + 1, BM = kDmaBM, TN = kSplitTN;
   constexpr int WROWS = BM + 2 * R, WEND = TN + 2 * R;
   constexpr int P = 152;  // 16-bit pitch: multiple of 8, odd number of 16-byte units, >= 96 + 16 + 32
@@ -288,7 +308,7 @@ __global__ __launch_bounds__(256) void split2d_dma_kernel(KArgs a) {
   float* __restrict__ out = (float*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, q = lane & 15;
-  const Strip2D sp = decode_strip(a, TN);
+  const Strip2D sp = decode_strip(a, item, TN);
 
   const u16x8* __restrict__ frag = (const u16x8*)a.frag;
   u16x8 bh[NL], bl[NL];
@@ -346,6 +366,16 @@ __global__ __launch_bounds__(256) void split2d_dma_kernel(KArgs a) {
       }
     }
   });
+}
+
+template <int KIND, int R>
+__global__ __launch_bounds__(256) void split2d_dma_kernel(KArgs a) {
+  split2d_dma_item<KIND, R>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <int KIND, int R>
+__global__ __launch_bounds__(256) void split2d_dma_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { split2d_dma_item<KIND, R>(x, id); });
 }
 
 }  // namespace stencil

@@ -31,23 +31,38 @@ struct DmaPlane {
   static_assert(R <= 4, "window covers at most 4 halo columns");
   static_assert(NPW < 64, "vmcnt range");
 
-  // Issue the loads of window rows (global j) grow0 .. grow0 + ROWS - 1 of a
-  // plane starting at `plane` (nullptr: a zero-halo plane outside the grid).
-  static __device__ __forceinline__ void issue(T* dst, const T* __restrict__ plane, const T* __restrict__ zeros,
-                                               int64_t Nj, int64_t Nk, int64_t grow0, int64_t k0, bool periodic) {
+  // Per-lane source offsets (elements from the plane's start) of the lines
+  // this lane loads, -1 for a zero line.  They are the same for every plane
+  // of a work item, so they are computed once: window rows (global j)
+  // grow0 .. grow0 + ROWS - 1, columns k0 - 4 .., under the boundary rule.
+  struct Lines {
+    int64_t off[NPW];
+  };
+
+  static __device__ __forceinline__ void prepare(Lines& L, int64_t Nj, int64_t Nk, int64_t grow0, int64_t k0,
+                                                 bool periodic) {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
     for (int k = 0; k < NPW; ++k) {
-      const int inst = k * NWAVES + w;
-      const int line = inst * 64 + lane;
-      const T* s = zeros;
-      if (plane != nullptr && line < LINES) {
+      const int line = (k * NWAVES + w) * 64 + lane;
+      L.off[k] = -1;
+      if (line < LINES) {
         const int row = line / LPR, lc = line - (line / LPR) * LPR;
         const int64_t g = map_index(grow0 + row, Nj, periodic);
         const int64_t c = map_index(k0 - 4 + VEC * lc, Nk, periodic);
-        if (g >= 0 && c >= 0) s = plane + g * Nk + c;
+        if (g >= 0 && c >= 0) L.off[k] = g * Nk + c;
       }
-      __builtin_amdgcn_global_load_lds(s, (lds_void3_t*)(dst + inst * 64 * VEC), 16, 0, 0);
+    }
+  }
+
+  // Issue the loads of one plane (nullptr: a zero-halo plane outside the grid).
+  static __device__ __forceinline__ void issue(T* dst, const T* __restrict__ plane, const T* __restrict__ zeros,
+                                               const Lines& L) {
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NPW; ++k) {
+      const T* s = (plane != nullptr && L.off[k] >= 0) ? plane + L.off[k] : zeros;
+      __builtin_amdgcn_global_load_lds(s, (lds_void3_t*)(dst + (k * NWAVES + w) * 64 * VEC), 16, 0, 0);
     }
   }
 

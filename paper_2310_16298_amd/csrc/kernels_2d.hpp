@@ -37,7 +37,7 @@ __host__ __device__ constexpr int pick_pitch(int cols) {
 // on-axis taps only.
 // ---------------------------------------------------------------------------
 template <typename T, int R, bool BOX>
-__global__ __launch_bounds__(kThreads) void gather2d_kernel(KArgs a) {
+__device__ __forceinline__ void gather2d_item(const KArgs& a, int item) {
   constexpr int BM = kTile2D, TN = kTile2D, W = 2 * R + 1;
   constexpr int WROWS = BM + 2 * R, WCOLS = TN + 2 * R;
   constexpr int COL0 = lds_col0<T, R>();
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kThreads) void gather2d_kernel(KArgs a) {
   const bool periodic = a.periodic != 0;
   const T* __restrict__ in = (const T*)a.in;
   T* __restrict__ out = (T*)a.out;
-  const Strip2D sp = decode_strip(a, TN);
+  const Strip2D sp = decode_strip(a, item, TN);
   const bool fast = strip_fast(in, N, sp.j0, TN);
   PlainWriter<T, R, PITCH> wr{lds};
   stage_window<T, R, WROWS, TN, PITCH, kThreads>(lds, in, M, N, sp.i0 - R, sp.j0, periodic);
@@ -99,6 +99,16 @@ __global__ __launch_bounds__(kThreads) void gather2d_kernel(KArgs a) {
   }
 }
 
+template <typename T, int R, bool BOX>
+__global__ __launch_bounds__(kThreads) void gather2d_kernel(KArgs a) {
+  gather2d_item<T, R, BOX>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int R, bool BOX>
+__global__ __launch_bounds__(kThreads) void gather2d_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { gather2d_item<T, R, BOX>(x, id); });
+}
+
 // ---------------------------------------------------------------------------
 // Outer-product form on MFMA (Section 3.2, Eq. (7)-(12); Section 3.3 for star
 // stencils; Table 1 for the line options).
@@ -139,7 +149,7 @@ struct Mfma2DShape {
 };
 
 template <typename T, int R, int VAR>
-__global__ __launch_bounds__(kThreads) void mfma2d_kernel(KArgs a) {
+__device__ __forceinline__ void mfma2d_item(const KArgs& a, int item) {
   typedef Mfma16<T> MM;
   typedef typename MM::acc_t acc_t;
   typedef Mfma2DShape<T, R, VAR> S;
@@ -152,7 +162,7 @@ __global__ __launch_bounds__(kThreads) void mfma2d_kernel(KArgs a) {
   T* __restrict__ out = (T*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, q = lane & 15;
-  const Strip2D sp = decode_strip(a, S::TN);
+  const Strip2D sp = decode_strip(a, item, S::TN);
   const bool fast = strip_fast(in, N, sp.j0, S::TN);
 
   // Band fragments for this lane (packed by the plan in lane order).
@@ -249,6 +259,16 @@ __global__ __launch_bounds__(kThreads) void mfma2d_kernel(KArgs a) {
   }
 }
 
+template <typename T, int R, int VAR>
+__global__ __launch_bounds__(kThreads) void mfma2d_kernel(KArgs a) {
+  mfma2d_item<T, R, VAR>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int R, int VAR>
+__global__ __launch_bounds__(kThreads) void mfma2d_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { mfma2d_item<T, R, VAR>(x, id); });
+}
+
 // ---------------------------------------------------------------------------
 // Outer-product form with n = 4 blocks on v_mfma_f32_4x4x1_16b_f32 (FP32).
 //
@@ -280,7 +300,7 @@ struct MfmaB4Shape {
 };
 
 template <int R, bool BOX>
-__global__ __launch_bounds__(kThreads) void mfma2d_b4_kernel(KArgs a) {
+__device__ __forceinline__ void mfma2d_b4_item(const KArgs& a, int item) {
   typedef MfmaB4Shape<R, BOX> S;
   constexpr int BM = S::TM;
   __shared__ __attribute__((aligned(16))) float lds[S::WROWS * S::PITCH];
@@ -290,7 +310,7 @@ __global__ __launch_bounds__(kThreads) void mfma2d_b4_kernel(KArgs a) {
   const float* __restrict__ in = (const float*)a.in;
   float* __restrict__ out = (float*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const Strip2D sp = decode_strip(a, S::TN);
+  const Strip2D sp = decode_strip(a, item, S::TN);
   const bool fast = strip_fast(in, N, sp.j0, S::TN);
 
   const float* __restrict__ frag = (const float*)a.frag;
@@ -365,6 +385,16 @@ __global__ __launch_bounds__(kThreads) void mfma2d_b4_kernel(KArgs a) {
     }
     __syncthreads();
   }
+}
+
+template <int R, bool BOX>
+__global__ __launch_bounds__(kThreads) void mfma2d_b4_kernel(KArgs a) {
+  mfma2d_b4_item<R, BOX>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <int R, bool BOX>
+__global__ __launch_bounds__(kThreads) void mfma2d_b4_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { mfma2d_b4_item<R, BOX>(x, id); });
 }
 
 }  // namespace stencil

@@ -35,8 +35,10 @@ struct Chunk3D {
   int64_t ib, iend, j0, k0;  // output planes [ib, iend), tile origin
 };
 
-__device__ __forceinline__ Chunk3D decode_chunk(const KArgs& a) {
-  const int id = xcd_remap(blockIdx.x, gridDim.x);
+// Work items of a 3D grid: (j, k) tiles x i-chunks (set by the plan).
+inline int64_t chunk3d_items(const KArgs& a) { return (int64_t)a.tiles0 * a.tiles1 * a.nchunks; }
+
+__device__ __forceinline__ Chunk3D decode_chunk(const KArgs& a, int id) {
   const int per_plane = a.tiles0 * a.tiles1;
   const int chunk = id / per_plane;
   const int t = id - chunk * per_plane;
@@ -56,12 +58,14 @@ __device__ __forceinline__ Chunk3D decode_chunk(const KArgs& a) {
 // the grid); store(uu, o, live) writes completed output plane o from slot uu
 // when live (o >= ib; warm-up planes reach outputs below the chunk) and always
 // resets the slot for the output plane that reuses it.
-template <typename T, int R, int LROWS, bool DMA>
+template <typename T, int R, int LROWS, bool DMA, bool BODY4 = false>
 struct PlaneWalk {
   static constexpr int W = 2 * R + 1;
   typedef DmaPlane<T, R, LROWS, kTK, kThreads> D;
-  static constexpr int PITCH = DMA ? D::PITCH : pick_pitch<T, true>(lds_col0<T, R>() + kTK + 2 * R + 8);
-  static constexpr int COL0 = DMA ? D::COL0 : lds_col0<T, R>();
+  // BODY4: the tile body (window column r) sits at LDS column 4 in both
+  // staging modes, as in the direct-to-LDS layout.
+  static constexpr int PITCH = (DMA || BODY4) ? D::PITCH : pick_pitch<T, true>(lds_col0<T, R>() + kTK + 2 * R + 8);
+  static constexpr int COL0 = (DMA || BODY4) ? D::COL0 : lds_col0<T, R>();
   static constexpr int BUF = DMA ? D::BUF : LROWS * PITCH;  // elements per buffer
   static constexpr int NBUF = DMA ? 2 : 1;
 
@@ -72,9 +76,11 @@ struct PlaneWalk {
     const T* __restrict__ in = (const T*)a.in;
     const T* __restrict__ zeros = (const T*)a.zeros;
     const int nu = (int)(ch.iend - ch.ib) + 2 * R;
+    typename D::Lines lines;
     if constexpr (DMA) {
+      D::prepare(lines, Nj, Nk, ch.j0 - R, ch.k0, periodic);
       const int64_t g0 = map_index(ch.ib - R, Ni, periodic);
-      D::issue(bufs, g0 >= 0 ? in + g0 * plane : nullptr, zeros, Nj, Nk, ch.j0 - R, ch.k0, periodic);
+      D::issue(bufs, g0 >= 0 ? in + g0 * plane : nullptr, zeros, lines);
     } else {
       // rows and columns past the window (K padding of the MFMA kernels) carry zero weights
       zero_region<T, kThreads>(bufs, LROWS, PITCH, PITCH, 0, 0);
@@ -90,8 +96,7 @@ struct PlaneWalk {
           win = bufs + (u & 1) * BUF;
           if (u + 1 < nu) {
             const int64_t g1 = map_index(ch.ib - R + u + 1, Ni, periodic);
-            D::issue(bufs + ((u + 1) & 1) * BUF, g1 >= 0 ? in + g1 * plane : nullptr, zeros, Nj, Nk, ch.j0 - R,
-                     ch.k0, periodic);
+            D::issue(bufs + ((u + 1) & 1) * BUF, g1 >= 0 ? in + g1 * plane : nullptr, zeros, lines);
             D::template wait_vm<D::NPW>();
           } else {
             D::template wait_vm<0>();
@@ -101,8 +106,8 @@ struct PlaneWalk {
           win = bufs;
           __syncthreads();
           if (gi >= 0)
-            stage_window<T, R, kTJ + 2 * R, kTK, PITCH, kThreads>(bufs, in + gi * plane, Nj, Nk, ch.j0 - R, ch.k0,
-                                                                 periodic);
+            stage_window<T, R, kTJ + 2 * R, kTK, PITCH, kThreads, COL0>(bufs, in + gi * plane, Nj, Nk, ch.j0 - R,
+                                                                       ch.k0, periodic);
           __syncthreads();
         }
         body(win, uu, gi >= 0);
@@ -111,94 +116,212 @@ struct PlaneWalk {
       }
     }
   }
+
+  // The same walk without the ring-phase unrolling: body(win, valid) then
+  // finish(o, live) once per input plane; the caller keeps its ring in a
+  // fixed order and rotates it in finish.
+  template <class Body, class Finish>
+  static __device__ __forceinline__ void walk(T* bufs, const KArgs& a, const Chunk3D& ch, Body body, Finish finish) {
+    const int64_t Ni = a.d0, Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
+    const bool periodic = a.periodic != 0;
+    const T* __restrict__ in = (const T*)a.in;
+    const T* __restrict__ zeros = (const T*)a.zeros;
+    const int nu = (int)(ch.iend - ch.ib) + 2 * R;
+    typename D::Lines lines;
+    if constexpr (DMA) {
+      D::prepare(lines, Nj, Nk, ch.j0 - R, ch.k0, periodic);
+      const int64_t g0 = map_index(ch.ib - R, Ni, periodic);
+      D::issue(bufs, g0 >= 0 ? in + g0 * plane : nullptr, zeros, lines);
+    }
+    for (int u = 0; u < nu; ++u) {
+      const int64_t gi = map_index(ch.ib - R + u, Ni, periodic);
+      const T* win;
+      if constexpr (DMA) {
+        win = bufs + (u & 1) * BUF;
+        if (u + 1 < nu) {
+          const int64_t g1 = map_index(ch.ib - R + u + 1, Ni, periodic);
+          D::issue(bufs + ((u + 1) & 1) * BUF, g1 >= 0 ? in + g1 * plane : nullptr, zeros, lines);
+          D::template wait_vm<D::NPW>();
+        } else {
+          D::template wait_vm<0>();
+        }
+        __syncthreads();
+      } else {
+        win = bufs;
+        __syncthreads();
+        if (gi >= 0)
+          stage_window<T, R, kTJ + 2 * R, kTK, PITCH, kThreads, COL0>(bufs, in + gi * plane, Nj, Nk, ch.j0 - R,
+                                                                     ch.k0, periodic);
+        __syncthreads();
+      }
+      body(win, gi >= 0);
+      finish(ch.ib + u - 2 * R, u >= 2 * R);
+      if constexpr (DMA) __syncthreads();
+    }
+  }
 };
 
 // ---------------------------------------------------------------------------
-// Gather-form baseline (Eq. (1) in 3D).  Thread (s, q) owns k column q and
-// j rows 8 s .. 8 s + 7 of the tile.  Box: each input plane adds its
+// Gather-form baseline (Eq. (1) in 3D).  Thread t owns a 2 x 4 register
+// block: j rows 2 (t / 16) .. +1 and k columns 4 (t % 16) .. +3 of the tile.
+// Each window row it needs is read as 12 consecutive values (16-byte LDS
+// vectors, columns 4 (t % 16) - 4 .. + 7 around the block), which cover
+// the k offsets -r .. r of all four columns.  Box: each input plane adds its
 // (2r+1)^2 in-plane taps to the 2r+1 output planes it reaches; star: the
 // centre plane adds the j and k arms, every plane adds its i-arm weight.
+// Ring: ring[z] accumulates output plane i - r + z while input plane i is
+// scattered (coefficient plane a reaches z = 2r - a); afterwards ring[0] is
+// complete and the ring shifts down by one.
 // ---------------------------------------------------------------------------
 template <typename T, int R, bool BOX, bool DMA>
-__global__ __launch_bounds__(kThreads) void gather3d_kernel(KArgs a) {
-  constexpr int W = 2 * R + 1, ROWS = 8;
-  typedef PlaneWalk<T, R, kTJ + 2 * R, DMA> PW;
+__device__ __forceinline__ void gather3d_item(const KArgs& a, int item) {
+  constexpr int W = 2 * R + 1, VEC = 16 / (int)sizeof(T), NV = 12 / VEC;
+  typedef typename Vec16<T>::type V;
+  typedef PlaneWalk<T, R, kTJ + 2 * R, DMA, true> PW;
+  static_assert(PW::COL0 + R == 4, "tile body at LDS column 4");
   __shared__ __attribute__((aligned(16))) T bufs[PW::NBUF * PW::BUF];
 
-  const Chunk3D ch = decode_chunk(a);
+  const Chunk3D ch = decode_chunk(a, item);
   const int64_t Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
   T* __restrict__ out = (T*)a.out;
-  const T* __restrict__ c = (const T*)a.coef;
-  const int q = threadIdx.x & 63, s = threadIdx.x >> 6;
+  const ConstPtr<T> c = (ConstPtr<T>)a.coef;  // uniform reads: scalar loads
+  const int q4 = threadIdx.x & 15, rg = threadIdx.x >> 4;
 
-  T ring[W][ROWS];
+  T ring[W][2][4];
 #pragma unroll
   for (int z = 0; z < W; ++z)
 #pragma unroll
-    for (int p = 0; p < ROWS; ++p) ring[z][p] = T(0);
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ring[z][p][e] = T(0);
 
-  PW::run(
+  // v[m] = window row x, LDS column 4 q4 + m (tile column 4 q4 + m - 4)
+  auto row12 = [&](const T* win, int x, T v[12]) {
+    const V* rp = reinterpret_cast<const V*>(win + (2 * rg + x) * PW::PITCH + 4 * q4);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const V t = rp[k];
+      const T* pt = reinterpret_cast<const T*>(&t);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) v[k * VEC + e] = pt[e];
+    }
+  };
+
+  PW::walk(
       bufs, a, ch,
-      [&](const T* win, int uu, bool valid) {
-        if (!valid) return;
-        const T* base = win + (ROWS * s) * PW::PITCH + PW::COL0 + q;
+      [&](const T* win, bool valid) {
+        if (!valid) return;  // a zero-halo plane adds nothing
         if constexpr (BOX) {
 #pragma unroll
-          for (int x = 0; x < ROWS + 2 * R; ++x) {
-            T h[W];
+          for (int x = 0; x < 2 + 2 * R; ++x) {
+            T v[12];
+            row12(win, x, v);
 #pragma unroll
-            for (int cc = 0; cc < W; ++cc) h[cc] = base[x * PW::PITCH + cc];
+            for (int p = 0; p < 2; ++p) {
+              const int bb = x - p;
+              if (bb < 0 || bb > 2 * R) continue;
 #pragma unroll
-            for (int ap = 0; ap < W; ++ap) {
-              const int slot = (uu + 2 * R - ap) % W;
+              for (int ap = 0; ap < W; ++ap)
 #pragma unroll
-              for (int p = 0; p < ROWS; ++p) {
-                const int bb = x - p;
-                if (bb < 0 || bb > 2 * R) continue;
+                for (int cc = 0; cc < W; ++cc) {
+                  const T w = c[(ap * W + bb) * W + cc];
 #pragma unroll
-                for (int cc = 0; cc < W; ++cc) ring[slot][p] += c[(ap * W + bb) * W + cc] * h[cc];
-              }
+                  for (int e = 0; e < 4; ++e) ring[2 * R - ap][p][e] += w * v[4 - R + e + cc];
+                }
             }
           }
         } else {
-          // centre plane (slot of output plane i): j arm (column k = q + r) and k arm (row j = p + r)
+          // j arm into the centre plane's slot r: column block at LDS columns 4 q4 + 4 ..
 #pragma unroll
-          for (int x = 0; x < ROWS + 2 * R; ++x) {
-            const T hv = base[x * PW::PITCH + R];
+          for (int x = 0; x < 2 + 2 * R; ++x) {
+            const V* rp = reinterpret_cast<const V*>(win + (2 * rg + x) * PW::PITCH + 4 * q4 + 4);
+            T v[4];
 #pragma unroll
-            for (int p = 0; p < ROWS; ++p) {
+            for (int k = 0; k < 4 / VEC; ++k) {
+              const V t = rp[k];
+              const T* pt = reinterpret_cast<const T*>(&t);
+#pragma unroll
+              for (int e = 0; e < VEC; ++e) v[k * VEC + e] = pt[e];
+            }
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
               const int bb = x - p;
               if (bb < 0 || bb > 2 * R) continue;
-              ring[(uu + R) % W][p] += c[(R * W + bb) * W + R] * hv;
+              const T w = c[(R * W + bb) * W + R];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) ring[R][p][e] += w * v[e];
             }
           }
+          // k arm (centre excluded) and i arm from the block's own rows
 #pragma unroll
-          for (int p = 0; p < ROWS; ++p) {
-            const T* rowp = base + (p + R) * PW::PITCH;
+          for (int p = 0; p < 2; ++p) {
+            T v[12];
+            row12(win, p + R, v);
 #pragma unroll
             for (int cc = 0; cc < W; ++cc) {
               if (cc == R) continue;
-              ring[(uu + R) % W][p] += c[(R * W + R) * W + cc] * rowp[cc];
+              const T w = c[(R * W + R) * W + cc];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) ring[R][p][e] += w * v[4 - R + e + cc];
             }
-            // i arm: this plane reaches output plane i - ap + r with C^g[ap][r][r]
-            const T ctr = rowp[R];
 #pragma unroll
             for (int ap = 0; ap < W; ++ap) {
               if (ap == R) continue;
-              ring[(uu + 2 * R - ap) % W][p] += c[(ap * W + R) * W + R] * ctr;
+              const T w = c[(ap * W + R) * W + R];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) ring[2 * R - ap][p][e] += w * v[4 + e];
             }
           }
         }
       },
-      [&](int uu, int64_t o, bool live) {
-        const int64_t gk = ch.k0 + q;
+      [&](int64_t o, bool live) {
+        const int64_t gk = ch.k0 + 4 * q4;
+        if (live) {
 #pragma unroll
-        for (int p = 0; p < ROWS; ++p) {
-          const int64_t gj = ch.j0 + ROWS * s + p;
-          if (live && gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = ring[uu][p];
-          ring[uu][p] = T(0);
+          for (int p = 0; p < 2; ++p) {
+            const int64_t gj = ch.j0 + 2 * rg + p;
+            if (gj >= Nj) continue;
+            T* dst = out + o * plane + gj * Nk + gk;
+            if constexpr (DMA) {
+              // k extent a multiple of the vector and output 16-byte aligned:
+              // a vector starting inside the row lies inside it
+#pragma unroll
+              for (int k = 0; k < 4 / VEC; ++k) {
+                if (gk + k * VEC >= Nk) break;
+                V t;
+                T* pt = reinterpret_cast<T*>(&t);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) pt[e] = ring[0][p][k * VEC + e];
+                reinterpret_cast<V*>(dst)[k] = t;
+              }
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (gk + e < Nk) dst[e] = ring[0][p][e];
+            }
+          }
         }
+#pragma unroll
+        for (int z = 0; z < 2 * R; ++z)
+#pragma unroll
+          for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ring[z][p][e] = ring[z + 1][p][e];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) ring[2 * R][p][e] = T(0);
       });
+}
+
+template <typename T, int R, bool BOX, bool DMA>
+__global__ __launch_bounds__(kThreads) void gather3d_kernel(KArgs a) {
+  gather3d_item<T, R, BOX, DMA>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int R, bool BOX, bool DMA>
+__global__ __launch_bounds__(kThreads) void gather3d_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { gather3d_item<T, R, BOX, DMA>(x, id); });
 }
 
 // ---------------------------------------------------------------------------
@@ -228,7 +351,7 @@ struct Mfma3DShape {
 };
 
 template <typename T, int R, bool BOX, bool DMA>
-__global__ __launch_bounds__(kThreads) void mfma3d_kernel(KArgs a) {
+__device__ __forceinline__ void mfma3d_item(const KArgs& a, int item) {
   typedef Mfma16<T> MM;
   typedef typename MM::acc_t acc_t;
   typedef Mfma3DShape<T, R, BOX> S;
@@ -236,7 +359,7 @@ __global__ __launch_bounds__(kThreads) void mfma3d_kernel(KArgs a) {
   constexpr int W = S::W;
   __shared__ __attribute__((aligned(16))) T bufs[PW::NBUF * PW::BUF];
 
-  const Chunk3D ch = decode_chunk(a);
+  const Chunk3D ch = decode_chunk(a, item);
   const int64_t Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
   T* __restrict__ out = (T*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -334,6 +457,16 @@ __global__ __launch_bounds__(kThreads) void mfma3d_kernel(KArgs a) {
       });
 }
 
+template <typename T, int R, bool BOX, bool DMA>
+__global__ __launch_bounds__(kThreads) void mfma3d_kernel(KArgs a) {
+  mfma3d_item<T, R, BOX, DMA>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int R, bool BOX, bool DMA>
+__global__ __launch_bounds__(kThreads) void mfma3d_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { mfma3d_item<T, R, BOX, DMA>(x, id); });
+}
+
 // ---------------------------------------------------------------------------
 // Outer-product form with 16-bit split operands (see kernels_split2d.hpp) in
 // the plane order of Algorithm 1.  Lines run along k: CLS(a, b, *) adds
@@ -356,7 +489,7 @@ struct Split3DShape {
 };
 
 template <int KIND, int R, bool BOX, bool DMA>
-__global__ __launch_bounds__(kThreads) void split3d_kernel(KArgs a) {
+__device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
   typedef Split3DShape<R, BOX> S;
   typedef PlaneWalk<float, R, S::WROWS, DMA> PW;
   constexpr int W = S::W;
@@ -364,7 +497,7 @@ __global__ __launch_bounds__(kThreads) void split3d_kernel(KArgs a) {
   __shared__ __attribute__((aligned(16))) uint16_t lhi[S::WROWS * S::P];
   __shared__ __attribute__((aligned(16))) uint16_t llo[S::WROWS * S::P];
 
-  const Chunk3D ch = decode_chunk(a);
+  const Chunk3D ch = decode_chunk(a, item);
   const int64_t Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
   float* __restrict__ out = (float*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -476,6 +609,16 @@ __global__ __launch_bounds__(kThreads) void split3d_kernel(KArgs a) {
           acx[uu][t] = floatx4{0, 0, 0, 0};
         }
       });
+}
+
+template <int KIND, int R, bool BOX, bool DMA>
+__global__ __launch_bounds__(kThreads) void split3d_kernel(KArgs a) {
+  split3d_item<KIND, R, BOX, DMA>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <int KIND, int R, bool BOX, bool DMA>
+__global__ __launch_bounds__(kThreads) void split3d_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { split3d_item<KIND, R, BOX, DMA>(x, id); });
 }
 
 }  // namespace stencil

@@ -4,10 +4,10 @@
 
 namespace stencil {
 
-LaunchFn find_gather3d_f32(int R, bool box);
-LaunchFn find_gather3d_f64(int R, bool box);
+Picker find_gather3d_f32(int R, bool box);
+Picker find_gather3d_f64(int R, bool box);
 
-LaunchFn find_gather3d(int dtype, int R, bool box) {
+Picker find_gather3d(int dtype, int R, bool box) {
   return dtype == STENCIL_F64 ? find_gather3d_f64(R, box) : find_gather3d_f32(R, box);
 }
 

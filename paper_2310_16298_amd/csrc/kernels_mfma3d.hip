@@ -1,38 +1,37 @@
 // Instantiations of the 3D outer-product kernels (FP32 / FP64 MFMA).
 // Box: r <= 2 (the band fragments of all (2r+1)^2 lines stay in VGPRs).
 #include "kernels_3d.hpp"
+#include "launch.hpp"
 #include "plan.hpp"
 
 namespace stencil {
 
 template <typename T, int R, bool BOX>
-static hipError_t launch_mfma3d(const KArgs& a, dim3 grid, hipStream_t s) {
-  if (dma3d_ok<T>(a))
-    mfma3d_kernel<T, R, BOX, true><<<grid, dim3(kThreads), 0, s>>>(a);
-  else
-    mfma3d_kernel<T, R, BOX, false><<<grid, dim3(kThreads), 0, s>>>(a);
-  return hipGetLastError();
+static Kernel pick_mfma3d(KArgs& a, int32_t) {
+  const int64_t items = chunk3d_items(a);
+  if (dma3d_ok<T>(a)) return kernel_of<mfma3d_kernel<T, R, BOX, true>, mfma3d_batch<T, R, BOX, true>>(items);
+  return kernel_of<mfma3d_kernel<T, R, BOX, false>, mfma3d_batch<T, R, BOX, false>>(items);
 }
 
 template <typename T>
-static LaunchFn pick(int R, bool box) {
+static Picker pick(int R, bool box) {
   if (box) {
     switch (R) {
-      case 1: return launch_mfma3d<T, 1, true>;
-      case 2: return launch_mfma3d<T, 2, true>;
+      case 1: return pick_mfma3d<T, 1, true>;
+      case 2: return pick_mfma3d<T, 2, true>;
     }
     return nullptr;
   }
   switch (R) {
-    case 1: return launch_mfma3d<T, 1, false>;
-    case 2: return launch_mfma3d<T, 2, false>;
-    case 3: return launch_mfma3d<T, 3, false>;
-    case 4: return launch_mfma3d<T, 4, false>;
+    case 1: return pick_mfma3d<T, 1, false>;
+    case 2: return pick_mfma3d<T, 2, false>;
+    case 3: return pick_mfma3d<T, 3, false>;
+    case 4: return pick_mfma3d<T, 4, false>;
   }
   return nullptr;
 }
 
-LaunchFn find_mfma3d(int dtype, int R, bool box) {
+Picker find_mfma3d(int dtype, int R, bool box) {
   return dtype == STENCIL_F64 ? pick<double>(R, box) : pick<float>(R, box);
 }
 

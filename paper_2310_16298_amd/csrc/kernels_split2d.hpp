@@ -119,7 +119,7 @@ struct SplitWriter {
 };
 
 template <int KIND, int R>
-__global__ __launch_bounds__(256) void split2d_kernel(KArgs a) {
+__device__ __forceinline__ void split2d_item(const KArgs& a, int item) {
   typedef Split2DShape<R> S;
   constexpr int NL = 2 * R + 1, BM = S::TM;
   __shared__ __attribute__((aligned(16))) uint16_t lhi[S::WROWS * S::P];
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void split2d_kernel(KArgs a) {
   float* __restrict__ out = (float*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 4, q = lane & 15;
-  const Strip2D sp = decode_strip(a, S::TN);
+  const Strip2D sp = decode_strip(a, item, S::TN);
   const bool fast = strip_fast(in, N, sp.j0, S::TN);
 
   // Band fragments S_a (hi, lo) for this lane: 16 bytes each.
@@ -197,6 +197,16 @@ __global__ __launch_bounds__(256) void split2d_kernel(KArgs a) {
     }
     __syncthreads();
   }
+}
+
+template <int KIND, int R>
+__global__ __launch_bounds__(256) void split2d_kernel(KArgs a) {
+  split2d_item<KIND, R>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <int KIND, int R>
+__global__ __launch_bounds__(256) void split2d_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { split2d_item<KIND, R>(x, id); });
 }
 
 }  // namespace stencil

@@ -1,30 +1,29 @@
 // Instantiations of the 3D split-precision kernels.  Box: r = 1 (27 points).
 #include "kernels_3d.hpp"
+#include "launch.hpp"
 #include "plan.hpp"
 
 namespace stencil {
 
 template <int KIND, int R, bool BOX>
-static hipError_t launch_split3d(const KArgs& a, dim3 grid, hipStream_t s) {
-  if (dma3d_ok<float>(a))
-    split3d_kernel<KIND, R, BOX, true><<<grid, dim3(kThreads), 0, s>>>(a);
-  else
-    split3d_kernel<KIND, R, BOX, false><<<grid, dim3(kThreads), 0, s>>>(a);
-  return hipGetLastError();
+static Kernel pick_split3d(KArgs& a, int32_t) {
+  const int64_t items = chunk3d_items(a);
+  if (dma3d_ok<float>(a)) return kernel_of<split3d_kernel<KIND, R, BOX, true>, split3d_batch<KIND, R, BOX, true>>(items);
+  return kernel_of<split3d_kernel<KIND, R, BOX, false>, split3d_batch<KIND, R, BOX, false>>(items);
 }
 
 template <int KIND>
-static LaunchFn pick(int R, bool box) {
-  if (box) return R == 1 ? launch_split3d<KIND, 1, true> : nullptr;
+static Picker pick(int R, bool box) {
+  if (box) return R == 1 ? pick_split3d<KIND, 1, true> : nullptr;
   switch (R) {
-    case 1: return launch_split3d<KIND, 1, false>;
-    case 2: return launch_split3d<KIND, 2, false>;
-    case 3: return launch_split3d<KIND, 3, false>;
-    case 4: return launch_split3d<KIND, 4, false>;
+    case 1: return pick_split3d<KIND, 1, false>;
+    case 2: return pick_split3d<KIND, 2, false>;
+    case 3: return pick_split3d<KIND, 3, false>;
+    case 4: return pick_split3d<KIND, 4, false>;
   }
   return nullptr;
 }
 
-LaunchFn find_split3d(int kind, int R, bool box) { return kind == 1 ? pick<1>(R, box) : pick<0>(R, box); }
+Picker find_split3d(int kind, int R, bool box) { return kind == 1 ? pick<1>(R, box) : pick<0>(R, box); }
 
 }  // namespace stencil

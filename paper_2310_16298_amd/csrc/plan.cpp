@@ -161,7 +161,9 @@ static int validate(const stencil_desc_t* d) {
   if (d->dtype != STENCIL_F32 && d->dtype != STENCIL_F64) return STENCIL_EINVAL;
   if (d->path < STENCIL_PATH_AUTO || d->path > STENCIL_PATH_MFMA_F16X3) return STENCIL_EINVAL;
   if (d->lines < STENCIL_LINES_AUTO || d->lines > STENCIL_LINES_HYBRID) return STENCIL_EINVAL;
-  if (d->reserved != 0) return STENCIL_EINVAL;
+  if (d->block_n != 0 && d->block_n != 4 && d->block_n != 16) return STENCIL_EINVAL;
+  if (d->chunk < 0 || d->time_block < 0) return STENCIL_EINVAL;
+  if (d->time_block > 1) return STENCIL_EUNSUPPORTED;
   int64_t total = 1;
   for (int k = 0; k < d->ndim; ++k) {
     if (d->dims[k] < 1 || d->dims[k] > (int64_t(1) << 31) - 1) return STENCIL_EINVAL;
@@ -343,8 +345,9 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
 
   int path = d.path;
   if (path == STENCIL_PATH_AUTO) {
-    path = STENCIL_PATH_MFMA;
-    if (nd == 3 && box && R > 2) path = STENCIL_PATH_GATHER;
+    // Measured on MI355X: 2D -> outer products on MFMA; 3D -> the gather
+    // kernel (HBM-bound with register blocks; the 3D MFMA kernels trail it).
+    path = nd == 2 ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
   }
   const bool split = path == STENCIL_PATH_MFMA_BF16X3 || path == STENCIL_PATH_MFMA_F16X3;
   rs->split16 = path == STENCIL_PATH_MFMA_F16X3 ? 1 : 0;
@@ -375,33 +378,29 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   if (nd == 2) {
     // Column strips of kTile2D columns, each walked in chunks of `chunk` rows
     // (a multiple of the 64-row block), sized for >= ~2048 workgroups.
-    const int64_t strips = ceil_div(d.dims[1], kTile2D);
-    int64_t chunk = d.dims[0] * strips / 2048;
-    chunk = ceil_div(chunk < kTile2D ? kTile2D : chunk, kTile2D) * kTile2D;
-    const int64_t mrows = ceil_div(d.dims[0], kTile2D) * kTile2D;
-    if (chunk > mrows) chunk = mrows;
-    const int64_t nchunks = ceil_div(d.dims[0], chunk);
-    if (strips * nchunks > (int64_t(1) << 31) - 1 || chunk > (int64_t(1) << 30)) return STENCIL_EUNSUPPORTED;
-    a.tiles0 = (int32_t)nchunks;
-    a.tiles1 = (int32_t)strips;
-    a.chunk = (int32_t)chunk;
-    a.nchunks = (int32_t)nchunks;
-    rs->grid = dim3((unsigned)(strips * nchunks));
+    // Column strips walked in row chunks; the kernel picker fixes the strip
+    // width and row block at launch (it depends on the buffers' alignment).
+    // Bound the item count of the narrowest strips and smallest chunks.
+    const int64_t strips = ceil_div(d.dims[1], 64);
+    if (strips * ceil_div(d.dims[0], 16) > (int64_t(1) << 31) - 1) return STENCIL_EUNSUPPORTED;
+    if (d.chunk > (int64_t(1) << 30)) return STENCIL_EINVAL;
+    rs->chunk_req = d.chunk;
     in.tile_rows = kTile2D;
     in.tile_cols = kTile2D;
     if (path == STENCIL_PATH_GATHER) {
       rs->family = FAM_GATHER2D;
-      rs->launch = find_gather2d(d.dtype, R, box);
+      rs->pick = find_gather2d(d.dtype, R, box);
       in.executed_flops_per_point = 2.0 * in.taps;
       lines = STENCIL_LINES_AUTO;
     } else if (path == STENCIL_PATH_MFMA) {
       rs->family = FAM_MFMA2D;
       rs->variant = box ? VAR_BOX : (lines == STENCIL_LINES_PARALLEL ? VAR_STAR_PARALLEL : VAR_STAR_ORTHO);
-      // FP32 box / parallel star: n = 4 blocks on 4x4x1 (less band padding);
-      // STENCIL_MFMA_BLOCK=16 keeps the 16x16x4 kernel (ablation).
-      const char* blk = std::getenv("STENCIL_MFMA_BLOCK");
-      const bool b4 = d.dtype == STENCIL_F32 && rs->variant != VAR_STAR_ORTHO && !(blk && std::atoi(blk) == 16);
-      rs->launch = b4 ? find_mfma2d_b4(R, box) : find_mfma2d(d.dtype, R, rs->variant);
+      // FP32 box / parallel star: n = 4 blocks on 4x4x1 by default (less band
+      // padding); block_n = 16 selects the 16x16x4 kernel.
+      const bool b4_ok = d.dtype == STENCIL_F32 && rs->variant != VAR_STAR_ORTHO;
+      if (d.block_n == 4 && !b4_ok) return STENCIL_EUNSUPPORTED;
+      const bool b4 = b4_ok && d.block_n != 16;
+      rs->pick = b4 ? find_mfma2d_b4(R, box) : find_mfma2d(d.dtype, R, rs->variant);
       std::vector<Line> col, row;
       const int fixed_r[3] = {R, R, 0};
       for (int b = 0; b < W; ++b) {
@@ -425,7 +424,7 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     } else {
       // Split precision: lines along j (C^g rows), star as a box with zero weights.
       rs->family = FAM_SPLIT2D;
-      rs->launch = find_split2d(rs->split16, R, 0);
+      rs->pick = find_split2d(rs->split16, R, 0);
       lines = STENCIL_LINES_PARALLEL;
       std::vector<Line> row;
       for (int r0 = 0; r0 < W; ++r0) {
@@ -446,6 +445,7 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     const int64_t tiles = t0 * t1;
     int64_t chunk = d.dims[0] * tiles / 1024;  // aim for >= ~1024 workgroups
     if (chunk < 16) chunk = 16;
+    if (d.chunk > 0) chunk = d.chunk;
     if (chunk > d.dims[0]) chunk = d.dims[0];
     const int64_t nch = ceil_div(d.dims[0], chunk);
     if (tiles * nch > (int64_t(1) << 31) - 1 || tiles > (int64_t(1) << 30)) return STENCIL_EUNSUPPORTED;
@@ -453,18 +453,17 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     a.tiles1 = (int32_t)t1;
     a.chunk = (int32_t)chunk;
     a.nchunks = (int32_t)nch;
-    rs->grid = dim3((unsigned)(tiles * nch));
     in.tile_rows = kTJ;
     in.tile_cols = kTK;
     if (path == STENCIL_PATH_GATHER) {
       rs->family = FAM_GATHER3D;
-      rs->launch = find_gather3d(d.dtype, R, box);
+      rs->pick = find_gather3d(d.dtype, R, box);
       in.executed_flops_per_point = 2.0 * in.taps;
       lines = STENCIL_LINES_AUTO;
     } else if (path == STENCIL_PATH_MFMA) {
       if (!box && lines != STENCIL_LINES_HYBRID) return STENCIL_EUNSUPPORTED;
       rs->family = box ? FAM_MFMA3D_BOX : FAM_MFMA3D_STAR;
-      rs->launch = find_mfma3d(d.dtype, R, box);
+      rs->pick = find_mfma3d(d.dtype, R, box);
       std::vector<Line> col, row;
       if (box) {
         for (int ap = 0; ap < W; ++ap)
@@ -491,7 +490,7 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     } else {
       if (!box && lines != STENCIL_LINES_PARALLEL) return STENCIL_EUNSUPPORTED;
       rs->family = box ? FAM_SPLIT3D_BOX : FAM_SPLIT3D_STAR;
-      rs->launch = find_split3d(rs->split16, R, box);
+      rs->pick = find_split3d(rs->split16, R, box);
       std::vector<Line> row;
       if (box) {
         for (int ap = 0; ap < W; ++ap)
@@ -519,7 +518,8 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   }
   in.path = path;
   in.lines = lines;
-  if (!rs->launch) return STENCIL_EUNSUPPORTED;
+  if (!rs->pick) return STENCIL_EUNSUPPORTED;
+  if (d.block_n != 0 && path != STENCIL_PATH_GATHER && d.block_n != in.block_n) return STENCIL_EUNSUPPORTED;
   return STENCIL_OK;
 }
 

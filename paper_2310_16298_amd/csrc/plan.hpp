@@ -9,10 +9,9 @@
 
 #include "../../include/stencil.h"
 #include "device_common.hpp"
+#include "launch.hpp"
 
 namespace stencil {
-
-typedef hipError_t (*LaunchFn)(const KArgs& args, dim3 grid, hipStream_t stream);
 
 // Kernel families.
 enum Family {
@@ -37,8 +36,8 @@ struct Resolved {
   std::vector<uint8_t> coef;  // dense C^g in the arithmetic dtype (bytes)
   float out_scale = 1.0f, lo_scale = 1.0f;
   KArgs args{};             // everything but in/out
-  dim3 grid;
-  LaunchFn launch = nullptr;
+  int32_t chunk_req = 0;    // requested rows (2D) per work item, 0 = library choice
+  Picker pick = nullptr;
 };
 
 // Validate + resolve + pack (no device calls).  Returns a stencil status.
@@ -51,13 +50,13 @@ double band_value(const double* cg2d, int R, int n, int axis, int index, int i, 
 int line_cover(const double* cg2d, int R, int* rows_out, int* cols_out);
 
 // Kernel lookups, one per family (defined next to the kernels).
-LaunchFn find_gather2d(int dtype, int R, bool box);
-LaunchFn find_mfma2d(int dtype, int R, int variant);
-LaunchFn find_mfma2d_b4(int R, bool box);
-LaunchFn find_split2d(int kind, int R, int variant);
-LaunchFn find_gather3d(int dtype, int R, bool box);
-LaunchFn find_mfma3d(int dtype, int R, bool box);
-LaunchFn find_split3d(int kind, int R, bool box);
+Picker find_gather2d(int dtype, int R, bool box);
+Picker find_mfma2d(int dtype, int R, int variant);
+Picker find_mfma2d_b4(int R, bool box);
+Picker find_split2d(int kind, int R, int variant);
+Picker find_gather3d(int dtype, int R, bool box);
+Picker find_mfma3d(int dtype, int R, bool box);
+Picker find_split3d(int kind, int R, bool box);
 
 hipError_t launch_error_norms(const void* a, int a_dtype, const double* ref, int64_t n, double* out,
                               hipStream_t s);

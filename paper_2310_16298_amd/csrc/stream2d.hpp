@@ -144,13 +144,14 @@ __device__ __forceinline__ bool strip_fast(const T* src, int64_t N, int64_t c0, 
   return (c0 + TN <= N) && (N % (16 / (int)sizeof(T)) == 0) && ((reinterpret_cast<uintptr_t>(src) & 15) == 0);
 }
 
-// Grid of (column strip x row chunk) workgroups for strips of TN columns
-// walked in blocks of BM rows; chunks are sized for about `target`
-// workgroups.  Fills a.tiles0 (chunks), a.tiles1 (strips), a.chunk (rows).
-inline dim3 strip_grid(KArgs& a, int TN, int BM, int64_t target = 1024) {
+// Work items (column strip x row chunk) for strips of TN columns walked in
+// blocks of BM rows.  Chunks hold `chunk` rows when chunk > 0 (rounded up to
+// BM), else are sized for about `target` items.  Fills a.tiles0 (chunks),
+// a.tiles1 (strips), a.chunk (rows) and returns the number of items.
+inline int64_t strip_grid(KArgs& a, int TN, int BM, int64_t target, int32_t chunk_req = 0) {
   const int64_t strips = (a.d1 + TN - 1) / TN;
   const int64_t rows = (a.d0 + BM - 1) / BM * BM;
-  int64_t chunk = a.d0 * strips / target;
+  int64_t chunk = chunk_req > 0 ? chunk_req : a.d0 * strips / target;
   chunk = (chunk < BM ? BM : chunk + BM - 1) / BM * BM;
   if (chunk > rows) chunk = rows;
   const int64_t nch = (a.d0 + chunk - 1) / chunk;
@@ -158,15 +159,14 @@ inline dim3 strip_grid(KArgs& a, int TN, int BM, int64_t target = 1024) {
   a.tiles1 = (int32_t)strips;
   a.chunk = (int32_t)chunk;
   a.nchunks = (int32_t)nch;
-  return dim3((unsigned)(strips * nch));
+  return strips * nch;
 }
 
 // Strip decomposition of a 2D grid: tiles0 = row chunks, tiles1 = column strips.
 struct Strip2D {
   int64_t i0, i1, j0;  // output rows [i0, i1), strip column origin j0
 };
-__device__ __forceinline__ Strip2D decode_strip(const KArgs& a, int TN) {
-  const int id = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ Strip2D decode_strip(const KArgs& a, int id, int TN) {
   const int chunk = id / a.tiles1;
   const int strip = id - chunk * a.tiles1;
   Strip2D s;

@@ -38,7 +38,8 @@ class Desc(ctypes.Structure):
     _fields_ = [
         ("ndim", ctypes.c_int32), ("radius", ctypes.c_int32), ("dims", ctypes.c_int64 * 3),
         ("shape", ctypes.c_int32), ("boundary", ctypes.c_int32), ("dtype", ctypes.c_int32),
-        ("path", ctypes.c_int32), ("lines", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("path", ctypes.c_int32), ("lines", ctypes.c_int32), ("block_n", ctypes.c_int32),
+        ("chunk", ctypes.c_int32), ("time_block", ctypes.c_int32),
         ("coeffs", ctypes.POINTER(ctypes.c_double)),
     ]
 
@@ -63,6 +64,7 @@ EXPORTS = [
     "stencil_version", "stencil_status_string", "stencil_desc_check", "stencil_plan_describe",
     "stencil_line_band", "stencil_line_cover", "stencil_plan", "stencil_plan_info", "stencil_plan_destroy",
     "stencil_apply", "stencil_run_steps", "stencil_error_norms",
+    "stencil_batch_create", "stencil_batch_run_steps", "stencil_batch_info", "stencil_batch_destroy",
 ]
 
 _lib = None
@@ -92,6 +94,11 @@ def load_library(path: str = LIB_PATH):
     lib.stencil_apply.argtypes = [vp, vp, vp, vp]
     lib.stencil_run_steps.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(i32)]
     lib.stencil_error_norms.argtypes = [vp, i32, vp, i64, vp, vp]
+    lib.stencil_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32,
+                                         ctypes.POINTER(vp)]
+    lib.stencil_batch_run_steps.argtypes = [vp, i64, vp, ctypes.POINTER(i32)]
+    lib.stencil_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.stencil_batch_destroy.argtypes = [vp]
     for name in EXPORTS[2:]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -112,7 +119,8 @@ def _check(status: int, where: str):
 
 
 def make_desc(dims: Sequence[int], radius: int, shape: int, coeffs, boundary: int = BC_ZERO,
-              dtype: int = F32, path: int = PATH_AUTO, lines: int = LINES_AUTO):
+              dtype: int = F32, path: int = PATH_AUTO, lines: int = LINES_AUTO, block_n: int = 0,
+              chunk: int = 0, time_block: int = 0):
     """Build a Desc; returns (desc, keepalive) -- keep the array alive while used."""
     c = np.ascontiguousarray(coeffs, dtype=np.float64)
     d = Desc()
@@ -120,8 +128,8 @@ def make_desc(dims: Sequence[int], radius: int, shape: int, coeffs, boundary: in
     d.radius = int(radius)
     for k in range(3):
         d.dims[k] = int(dims[k]) if k < len(dims) else 1
-    d.shape, d.boundary, d.dtype, d.path, d.lines, d.reserved = (
-        int(shape), int(boundary), int(dtype), int(path), int(lines), 0)
+    d.shape, d.boundary, d.dtype, d.path, d.lines = int(shape), int(boundary), int(dtype), int(path), int(lines)
+    d.block_n, d.chunk, d.time_block = int(block_n), int(chunk), int(time_block)
     d.coeffs = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return d, c
 
@@ -181,18 +189,19 @@ def _stream_ptr(stream) -> int:
 class Plan:
     """A stencil plan on the current device.
 
-    ``Plan(dims, radius, shape, coeffs, boundary, dtype, path, lines)``; grids
+    ``Plan(dims, radius, shape, coeffs, boundary, dtype, path, lines, block_n,
+    chunk, time_block)``; grids
     are torch tensors on the plan's device, contiguous, of the plan's dims and
     dtype (float32 / float64).
     """
 
     def __init__(self, dims, radius, shape, coeffs, boundary=BC_ZERO, dtype=F32,
-                 path=PATH_AUTO, lines=LINES_AUTO):
+                 path=PATH_AUTO, lines=LINES_AUTO, block_n=0, chunk=0, time_block=0):
         lib = load_library()
         self.dims = tuple(int(v) for v in dims)
         self.dtype = dtype
         d, keep = make_desc(self.dims, radius, shape, coeffs, boundary=boundary, dtype=dtype,
-                            path=path, lines=lines)
+                            path=path, lines=lines, block_n=block_n, chunk=chunk, time_block=time_block)
         h = ctypes.c_void_p()
         _check(lib.stencil_plan(ctypes.byref(d), ctypes.byref(h)), "stencil_plan")
         self._h = h
@@ -240,6 +249,56 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.stencil_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Grids of uneven sizes advanced together (``stencil_batch_*``).
+
+    ``Batch(plans, bufs0, bufs1)``: plans[i] advances the grid held in the
+    torch tensors bufs0[i] / bufs1[i].  The plans and tensors must stay alive
+    while the batch is used."""
+
+    def __init__(self, plans, bufs0, bufs1):
+        lib = load_library()
+        n = len(plans)
+        if n != len(bufs0) or n != len(bufs1):
+            raise ValueError("plans, bufs0 and bufs1 must have the same length")
+        for p, x, y in zip(plans, bufs0, bufs1):
+            p._validate(x, y)
+        vp = ctypes.c_void_p
+        hs = (vp * n)(*[p.handle for p in plans])
+        b0 = (vp * n)(*[x.data_ptr() for x in bufs0])
+        b1 = (vp * n)(*[y.data_ptr() for y in bufs1])
+        h = vp()
+        _check(lib.stencil_batch_create(hs, b0, b1, n, ctypes.byref(h)), "stencil_batch_create")
+        self._h = h
+        self._lib = lib
+        self._keep = (list(plans), list(bufs0), list(bufs1))
+
+    def run_steps(self, steps: int, stream=None) -> int:
+        """Enqueue ``steps`` steps of every grid; returns the index (0/1) of
+        the buffer set holding the final states."""
+        idx = ctypes.c_int32(0)
+        _check(self._lib.stencil_batch_run_steps(self._h, int(steps), _stream_ptr(stream), ctypes.byref(idx)),
+               "stencil_batch_run_steps")
+        return idx.value
+
+    def info(self) -> dict:
+        g, it, bl = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(self._lib.stencil_batch_info(self._h, ctypes.byref(g), ctypes.byref(it), ctypes.byref(bl)),
+               "stencil_batch_info")
+        return {"groups": g.value, "items": it.value, "blocks": bl.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.stencil_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -1,0 +1,125 @@
+"""GPU tests of the batched launch (many grids of uneven sizes per launch).
+
+A grid advanced inside a batch runs the same kernel body, with the same
+arithmetic, as the grid alone, so its result must be bitwise equal to the
+plan's own run_steps; the single runs are themselves checked against the
+CPU FP64 oracle elsewhere, and here once more for a few members."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_16298_amd import inputs
+from paper_2310_16298_amd import stencil as st
+
+from gpu_helpers import eff_coeffs, error_bound, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+BF, FH = st.PATH_MFMA_BF16X3, st.PATH_MFMA_F16X3
+
+# (dims, r, shape, bc, dtype, path): DMA-eligible and ragged extents, 2D and 3D
+MIXED = [
+    ((64, 64), 1, st.BOX, st.BC_ZERO, st.F64, st.PATH_GATHER),
+    ((100, 36), 2, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_MFMA),
+    ((77, 45), 2, st.BOX, st.BC_ZERO, st.F32, st.PATH_MFMA),
+    ((128, 128), 2, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_MFMA),
+    ((300, 260), 4, st.BOX, st.BC_ZERO, st.F32, st.PATH_MFMA),
+    ((90, 64), 3, st.STAR, st.BC_ZERO, st.F32, st.PATH_MFMA),
+    ((64, 200), 1, st.BOX, st.BC_PERIODIC, st.F32, BF),
+    ((33, 17), 2, st.BOX, st.BC_ZERO, st.F32, FH),
+    ((48, 48), 4, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_GATHER),
+    ((96, 96), 3, st.STAR, st.BC_ZERO, st.F64, st.PATH_MFMA),
+    ((8, 8, 8), 1, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_GATHER),
+    ((20, 33, 64), 2, st.STAR, st.BC_ZERO, st.F32, st.PATH_MFMA),
+    ((17, 40, 70), 1, st.BOX, st.BC_ZERO, st.F64, st.PATH_MFMA),
+    ((40, 24, 32), 4, st.STAR, st.BC_PERIODIC, st.F32, BF),
+    ((16, 16, 16), 1, st.BOX, st.BC_ZERO, st.F32, FH),
+    ((35, 30, 66), 3, st.STAR, st.BC_ZERO, st.F64, st.PATH_GATHER),
+    ((64, 64, 64), 4, st.STAR, st.BC_ZERO, st.F32, st.PATH_GATHER),
+]
+
+
+def _member(torch, spec, seed):
+    dims, r, shape, bc, dt, path = spec
+    c = inputs.coefficients(len(dims), r, shape, seed=seed, dtype=np.float64)
+    ndt = np.float64 if dt == st.F64 else np.float32
+    a0 = inputs.grid(dims, seed=seed + 1, dtype=ndt)
+    plan = st.Plan(dims, r, shape, c, boundary=bc, dtype=dt, path=path)
+    x = torch.from_numpy(a0).cuda()
+    return plan, c, a0, x, torch.empty_like(x)
+
+
+def _alone(torch, plan, a0, steps):
+    x = torch.from_numpy(a0).cuda()
+    res = plan.run_steps(x, torch.empty_like(x), steps)
+    torch.cuda.synchronize()
+    return res.cpu().numpy()
+
+
+@pytest.mark.parametrize("steps", [1, 2, 5])
+def test_mixed_batch_equals_alone(steps):
+    torch = torch_cuda()
+    ms = [_member(torch, spec, 7000 + 10 * k) for k, spec in enumerate(MIXED)]
+    batch = st.Batch([m[0] for m in ms], [m[3] for m in ms], [m[4] for m in ms])
+    info = batch.info()
+    assert 1 < info["groups"] <= len(MIXED)
+    idx = batch.run_steps(steps)
+    torch.cuda.synchronize()
+    assert idx == steps % 2
+    for k, (plan, c, a0, x, y) in enumerate(ms):
+        got = (x if idx == 0 else y).cpu().numpy()
+        want = _alone(torch, plan, a0, steps)
+        assert np.array_equal(got, want), f"member {k} {MIXED[k]}"
+    # a few members against the oracle as well
+    for k in (1, 4, 10, 13):
+        plan, c, a0, x, y = ms[k]
+        dims, r, shape, bc, dt, path = MIXED[k]
+        got = (x if idx == 0 else y).cpu().numpy().astype(np.float64)
+        ce = eff_coeffs(c, dt)
+        want = oracle.run(a0.astype(np.float64), ce, r, shape, bc, steps)
+        tol = error_bound(ce, len(dims), r, shape, dt, path, steps, np.abs(a0).max())
+        assert np.abs(got - want).max() <= tol
+    batch.close()
+
+
+def test_many_small_grids_one_group():
+    """The paper-scale case: many small FP64 grids of one stencil kind."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(7100)
+    specs = []
+    for k in range(60):
+        n0, n1 = (int(v) for v in rng.integers(24, 160, size=2))
+        specs.append(((n0, n1), 2, st.BOX, st.BC_PERIODIC, st.F64, st.PATH_MFMA))
+    ms = [_member(torch, spec, 7200 + 3 * k) for k, spec in enumerate(specs)]
+    batch = st.Batch([m[0] for m in ms], [m[3] for m in ms], [m[4] for m in ms])
+    assert batch.info()["groups"] == 1
+    idx = batch.run_steps(3)
+    torch.cuda.synchronize()
+    for plan, c, a0, x, y in ms:
+        assert np.array_equal((x if idx == 0 else y).cpu().numpy(), _alone(torch, plan, a0, 3))
+    batch.close()
+
+
+def test_repeated_runs_continue_the_trajectory():
+    """Graph replays of one batch continue from the state they left."""
+    torch = torch_cuda()
+    ms = [_member(torch, spec, 7300 + 10 * k) for k, spec in enumerate(MIXED[:6])]
+    batch = st.Batch([m[0] for m in ms], [m[3] for m in ms], [m[4] for m in ms])
+    for _ in range(3):
+        assert batch.run_steps(4) == 0
+    torch.cuda.synchronize()
+    for plan, c, a0, x, y in ms:
+        assert np.array_equal(x.cpu().numpy(), _alone(torch, plan, a0, 12))
+    batch.close()
+
+
+def test_batch_rejects_overlapping_buffers():
+    torch = torch_cuda()
+    c = inputs.coefficients(2, 1, st.BOX, seed=1, dtype=np.float64)
+    plan = st.Plan((32, 32), 1, st.BOX, c)
+    big = torch.zeros(3 * 32 * 32, device="cuda")
+    a = big[: 32 * 32].view(32, 32)
+    b = big[32 * 32: 2 * 32 * 32].view(32, 32)
+    with pytest.raises(st.StencilError) as e:
+        st.Batch([plan, plan], [a, b], [b, a])
+    assert e.value.status == st.EALIAS

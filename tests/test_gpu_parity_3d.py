@@ -100,7 +100,7 @@ def test_auto_path(shape, r):
 
 
 @pytest.mark.parametrize("path,dtype,shape,r", COMBOS)
-@pytest.mark.parametrize("dims", [(21, 45, 132), (9, 40, 64), (5, 3, 4), (34, 1, 8)])
+@pytest.mark.parametrize("dims", [(21, 45, 132), (9, 40, 64), (5, 3, 4), (34, 1, 8), (7, 20, 66)])
 def test_dma_plane_extents(path, dtype, shape, r, dims):
     """k extents that are multiples of the 16-byte vector take the
     direct-to-LDS plane windows (double-buffered across planes)."""

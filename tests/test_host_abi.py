@@ -102,6 +102,28 @@ def test_null_arguments(lib):
     assert lib.stencil_apply(None, None, None, None) == st.EINVAL
     assert lib.stencil_run_steps(None, None, None, 1, None, None) == st.EINVAL
     assert lib.stencil_plan_destroy(None) == st.OK
+    out = ctypes.c_void_p(1)
+    assert lib.stencil_batch_create(None, None, None, 1, ctypes.byref(out)) == st.EINVAL
+    assert out.value is None
+    assert lib.stencil_batch_create(None, None, None, 0, None) == st.EINVAL
+    assert lib.stencil_batch_run_steps(None, 1, None, None) == st.EINVAL
+    assert lib.stencil_batch_info(None, None, None, None) == st.EINVAL
+    assert lib.stencil_batch_destroy(None) == st.OK
+
+
+def test_tuning_fields(lib):
+    c = _box(2, 2)
+    assert st.desc_check((64, 64), 2, inputs.BOX, c, block_n=3) == st.EINVAL
+    assert st.desc_check((64, 64), 2, inputs.BOX, c, chunk=-1) == st.EINVAL
+    assert st.desc_check((64, 64), 2, inputs.BOX, c, time_block=-1) == st.EINVAL
+    # n = 4 blocks exist only for the FP32 2D box / parallel-line star MFMA kernel
+    assert st.desc_check((64, 64), 2, inputs.BOX, c, dtype=st.F64, path=st.PATH_MFMA, block_n=4) == st.EUNSUPPORTED
+    assert st.desc_check((64, 64), 2, inputs.BOX, c, path=st.PATH_MFMA_BF16X3, block_n=4) == st.EUNSUPPORTED
+    for bn, want in ((0, 4), (4, 4), (16, 16)):
+        info = st.describe((64, 64), 2, inputs.BOX, c, path=st.PATH_MFMA, block_n=bn)
+        assert info["block_n"] == want
+    assert st.describe((64, 64), 2, inputs.BOX, c, path=st.PATH_GATHER, block_n=16)["block_n"] == 0
+    assert st.desc_check((64, 64), 2, inputs.BOX, c, chunk=48) == st.OK
 
 
 # ------------------------------------------------------------ band builder
