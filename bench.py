@@ -15,6 +15,7 @@ Other configurations (their own JSON line each; not the headline):
     --workload grid3d       3D stars r=1..4 and the 27-point box, 512^3 FP32/FP64, 50 steps
     --workload mixed        BF16x3 / FP16x3 with an FP64 shadow, drift check every 50 steps
     --workload batch        many small FP64 grids (Table 3 shapes) per batched launch vs one by one
+    --workload tune         autotuner sweep: line option x MFMA block x chunk per radius
 """
 from __future__ import annotations
 
@@ -66,10 +67,10 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def time_path(st, torch, path, radius, a0_dev, coeffs, reps, warmup, stream):
+def time_path(st, torch, knobs, radius, a0_dev, coeffs, reps, warmup, stream):
     """Per-rep wall times (ms, HIP events on the launch stream) of one
-    100-step solve."""
-    plan = st.Plan(DIMS, radius, st.BOX, coeffs, boundary=st.BC_PERIODIC, dtype=st.F32, path=path)
+    100-step solve; knobs: Plan keyword arguments (path, time_block, ...)."""
+    plan = st.Plan(DIMS, radius, st.BOX, coeffs, boundary=st.BC_PERIODIC, dtype=st.F32, **knobs)
     x = a0_dev.clone()
     tmp = torch.empty_like(x)
     with torch.cuda.stream(stream):
@@ -149,8 +150,10 @@ def workload_star2d_512(args, torch, st, inputs) -> dict:
     stream = torch.cuda.Stream()
     out = {"metric": "10-step solve latency (us) and GStencil/s", "workload":
            "2D 5-point star r=1, 512x512 FP64, zero halo, 10 Jacobi steps, seed 101", "paths": {}}
-    for name, path in (("gather", st.PATH_GATHER), ("mfma", st.PATH_MFMA)):
-        plan = st.Plan(dims, 1, st.STAR, c, boundary=st.BC_ZERO, dtype=st.F64, path=path)
+    for name, knobs in (("gather", {"path": st.PATH_GATHER}), ("mfma", {"path": st.PATH_MFMA}),
+                        ("gather_tb5", {"path": st.PATH_GATHER, "time_block": 5}),
+                        ("gather_tb8", {"path": st.PATH_GATHER, "time_block": 8})):
+        plan = st.Plan(dims, 1, st.STAR, c, boundary=st.BC_ZERO, dtype=st.F64, **knobs)
         times = _time_solve(torch, plan, x0, steps, max(args.steps, 20), args.warmup, stream)
         res = plan.run_steps(x0.clone(), torch.empty_like(x0), steps)
         torch.cuda.synchronize()
@@ -159,7 +162,10 @@ def workload_star2d_512(args, torch, st, inputs) -> dict:
         out["paths"][name] = {"p50_us": float(np.percentile(times, 50)) * 1e3,
                               "p99_us": float(np.percentile(times, 99)) * 1e3,
                               "gstencil_s": dims[0] * dims[1] * steps / (np.median(times) * 1e-3) / 1e9,
-                              "max_abs_err_vs_oracle": err, "block_n": plan.info["block_n"]}
+                              "max_abs_err_vs_oracle": err, "block_n": plan.info["block_n"],
+                              "time_block": plan.info["time_block"]}
+        print(f"[bench] star2d_512 {name}: p50 {out['paths'][name]['p50_us']:.1f} us, "
+              f"p99 {out['paths'][name]['p99_us']:.1f} us, err {err:.2e}", file=sys.stderr, flush=True)
         plan.close()
     oracle.build(force=False)
     used = oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
@@ -270,6 +276,36 @@ def workload_batch(args, torch, st, inputs) -> dict:
     return out
 
 
+def workload_tune(args, torch, st, inputs) -> dict:
+    """The autotuner over line option x MFMA block x chunk, per radius: 2D
+    box/star r = 1..4 at 8192^2 FP32 (periodic), 3D star r = 1..4 and the
+    27-point box at 512^3 FP32 (zero halo), 2D box/star r = 1..3 at 512^2 FP64
+    (zero halo): every measured candidate and the winner."""
+    out = {"metric": "ms per Jacobi step of each candidate plan", "cases": {}}
+    names = {st.LINES_AUTO: "-", st.LINES_PARALLEL: "p", st.LINES_ORTHOGONAL: "o", st.LINES_HYBRID: "h"}
+    specs = [((8192, 8192), st.F32, st.BC_PERIODIC, shape, r) for shape in (st.BOX, st.STAR) for r in (1, 2, 3, 4)]
+    specs += [((512, 512, 512), st.F32, st.BC_ZERO, st.STAR, r) for r in (1, 2, 3, 4)]
+    specs += [((512, 512, 512), st.F32, st.BC_ZERO, st.BOX, 1)]
+    specs += [((512, 512), st.F64, st.BC_ZERO, shape, r) for shape in (st.BOX, st.STAR) for r in (1, 2, 3)]
+    for dims, dt, bc, shape, r in specs:
+        c = inputs.coefficients(len(dims), r, shape, seed=9500 + r, dtype=np.float64)
+        knobs, ms, rows = st.autotune(dims, r, shape, c, boundary=bc, dtype=dt, force=True)
+        pts = float(np.prod(dims))
+        key = (f"{len(dims)}d_{'box' if shape == st.BOX else 'star'}_r{r}_{'x'.join(map(str, dims))}_"
+               f"{'f64' if dt == st.F64 else 'f32'}")
+        out["cases"][key] = {
+            "winner": {"path": st.PATH_NAMES[knobs["path"]], "lines": names[knobs["lines"]],
+                       "block_n": knobs["block_n"], "chunk": knobs["chunk"], "ms_per_step": round(ms, 5),
+                       "gstencil_s": round(pts / (ms * 1e-3) / 1e9, 2)},
+            "candidates": [{"path": st.PATH_NAMES[row["path"]], "lines": names[row["lines"]],
+                            "block_n": row["block_n"], "chunk": row["chunk"],
+                            "gstencil_s": round(pts / (row["ms_per_step"] * 1e-3) / 1e9, 2)} for row in rows]}
+        w = out["cases"][key]["winner"]
+        print(f"[bench] tune {key}: {w['path']} lines={w['lines']} n={w['block_n']} chunk={w['chunk']} "
+              f"{w['gstencil_s']} GStencil/s ({len(rows)} candidates)", file=sys.stderr, flush=True)
+    return out
+
+
 def workload_mixed(args, torch, st, inputs) -> dict:
     """BF16x3 / FP16x3 outer products with FP32 state for 200 steps; an FP64
     shadow trajectory (FP64 gather path) on the GPU; rel-L2 and max-abs of the
@@ -341,13 +377,15 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed bench steps (one step = 4 solves x 100 Jacobi steps)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--headline", default="auto", choices=["auto", "mfma", "gather", "mfma_f16x3", "mfma_bf16x3"])
-    ap.add_argument("--paths", default="gather,mfma,mfma_f16x3,mfma_bf16x3,auto")
+    ap.add_argument("--headline", default="auto",
+                    choices=["auto", "mfma", "gather", "mfma_f16x3", "mfma_bf16x3", "gather_tb", "tuned"])
+    ap.add_argument("--paths", default="gather,mfma,mfma_f16x3,mfma_bf16x3,gather_tb,tuned,auto",
+                    help="gather_tb: time-blocked gather (largest time block); tuned: the autotuner's plan")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--radii", default="1,2,3,4", help="orders to run (profiling runs use a subset)")
     ap.add_argument("--jacobi-steps", type=int, default=JACOBI_STEPS,
                     help="Jacobi steps per solve (profiling runs only; the benchmark uses 100)")
-    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch"])
+    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch", "tune"])
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="first run N plain device copies of one grid (known bytes) for counter scaling")
     args = ap.parse_args()
@@ -366,13 +404,22 @@ def main() -> int:
     st.load_library()
     if args.workload != "box2d":
         fn = {"star2d_512": workload_star2d_512, "grid3d": workload_grid3d, "mixed": workload_mixed,
-              "batch": workload_batch}[args.workload]
+              "batch": workload_batch, "tune": workload_tune}[args.workload]
         res = fn(args, torch, st, inputs)
         res.update({"n_gpus": 1, "data": "synthetic"})
         print(json.dumps(res))
         return 0
     name_to_path = {"gather": st.PATH_GATHER, "mfma": st.PATH_MFMA, "mfma_f16x3": st.PATH_MFMA_F16X3,
                     "mfma_bf16x3": st.PATH_MFMA_BF16X3, "auto": st.PATH_AUTO}
+    tb_max = {1: 12, 2: 6, 3: 4, 4: 3}  # largest FP32 time block per order
+
+    def knobs_for(name, r):
+        if name == "gather_tb":
+            return {"path": st.PATH_GATHER, "time_block": tb_max[r]}
+        if name == "tuned":
+            kn, _, _ = st.autotune(DIMS, r, st.BOX, coeffs[r], boundary=st.BC_PERIODIC, dtype=st.F32)
+            return kn
+        return {"path": name_to_path[name]}
     paths = [p for p in args.paths.split(",") if p]
     if args.headline not in paths:
         paths.append(args.headline)
@@ -395,14 +442,16 @@ def main() -> int:
     for name in paths:
         per_r = {}
         for r in RADII:
-            times, info = time_path(st, torch, name_to_path[name], r, a0_dev, coeffs[r],
-                                    args.steps, args.warmup, stream)
+            knobs = knobs_for(name, r)
+            times, info = time_path(st, torch, knobs, r, a0_dev, coeffs[r], args.steps, args.warmup, stream)
             med = float(np.median(times))
             per_r[r] = {"ms_per_solve": med, "gstencil_s": pts_per_solve / (med * 1e-3) / 1e9,
                         "p50_ms": float(np.percentile(times, 50)), "p99_ms": float(np.percentile(times, 99)),
-                        "resolved_path": st.PATH_NAMES[info["path"]], "info": info, "times": times}
+                        "resolved_path": st.PATH_NAMES[info["path"]], "info": info, "times": times,
+                        "knobs": knobs}
             print(f"[bench] {name:12s} r={r}: {per_r[r]['gstencil_s']:8.1f} GStencil/s "
-                  f"({med:.2f} ms / 100 steps, path={per_r[r]['resolved_path']})", file=sys.stderr, flush=True)
+                  f"({med:.2f} ms / 100 steps, path={per_r[r]['resolved_path']}, knobs={knobs})", file=sys.stderr,
+                  flush=True)
         results[name] = per_r
 
     head = results[args.headline]
@@ -464,6 +513,7 @@ def main() -> int:
     }
     line["per_order"] = {name: {str(r): {"gstencil_s": round(v["gstencil_s"], 2), "p50_ms": round(v["p50_ms"], 3),
                                          "p99_ms": round(v["p99_ms"], 3), "path": v["resolved_path"],
+                                         "time_block": v["info"]["time_block"],
                                          "hbm_frac": round(v["gstencil_s"] * 8 / HBM_PEAK_GBS, 4)}
                                  for r, v in res.items()} for name, res in results.items()}
     if "gather" in results:

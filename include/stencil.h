@@ -101,7 +101,12 @@ typedef struct {
                            ignored by the GATHER path */
   int32_t chunk;        /* output rows (2D) or i-planes (3D) per workgroup work item: 0 = library
                            choice; rounded up to the kernel's row block and clipped to the extent */
-  int32_t time_block;   /* steps fused per launch: 0 or 1 = one step per launch */
+  int32_t time_block;   /* steps fused per launch (time blocking): 0 or 1 = one step per launch;
+                           T > 1: each launch advances T steps on overlapped tiles held in LDS
+                           (halo r*T), cutting HBM traffic per point-step about T-fold.  Built for
+                           2D grids on the GATHER path (AUTO resolves to it); the halo r*T rounded up
+                           to a multiple of 4 is at most 12 for F32 and 8 for F64 (r = 1: T <= 12 / 8;
+                           r = 2: 6 / 4; r = 3: 4 / 2; r = 4: 3 / 2), else EUNSUPPORTED */
   const double* coeffs; /* host pointer to (2r+1)^ndim gather coefficients C^g,
                            C order, index o + r for offset o; copied by the call.
                            For an F32 plan they are rounded to float first. */
@@ -122,7 +127,7 @@ typedef struct {
   double useful_flops_per_point; /* 2 * taps */
   double executed_flops_per_point; /* flops the matrix+vector units execute per output point */
   int32_t bytes_per_point;       /* algorithmic HBM bytes per point-step: read + write of one element */
-  int32_t reserved;
+  int32_t time_block;            /* steps fused per launch (1 = none) */
 } stencil_plan_info_t;
 
 typedef struct stencil_plan_s* stencil_plan_t;
@@ -185,16 +190,19 @@ stencil_status_t stencil_plan_info(stencil_plan_t plan, stencil_plan_info_t* inf
  * ensure no enqueued work still uses the plan (e.g. synchronise first). */
 stencil_status_t stencil_plan_destroy(stencil_plan_t plan);
 
-/* One Jacobi step out = S(in) on `stream` (Section 2.2).  in and out are
+/* One Jacobi step out = S(in) on `stream` (Section 2.2), also for a
+ * time-blocked plan (one launch of one step).  in and out are
  * device buffers of the plan's dims and dtype and must not overlap
  * (in == out returns STENCIL_EALIAS). */
 stencil_status_t stencil_apply(stencil_plan_t plan, const void* in, void* out, void* stream);
 
 /* `steps` Jacobi steps with two buffers used alternately: step t reads
  * buf[t % 2] and writes buf[(t+1) % 2], starting from the state in buf0
- * (Section 2.2).  *result_index (may be NULL) receives steps % 2, the buffer
- * holding the final state.  steps == 0 enqueues nothing.  Negative steps:
- * EINVAL; overlapping buffers: EALIAS.
+ * (Section 2.2).  *result_index (may be NULL) receives the index of the
+ * buffer holding the final state: steps % 2, or for a time-blocked plan
+ * (time_block T > 1) the parity of its launch count ceil(steps / T) -- each
+ * launch advances up to T steps from one buffer into the other.  steps == 0
+ * enqueues nothing.  Negative steps: EINVAL; overlapping buffers: EALIAS.
  * Launch mode: when 2 <= steps <= 4096 and `stream` is not being captured by
  * the caller, the launches are recorded once into a HIP graph, cached in the
  * plan per (buf0, buf1, steps) (four entries, least recently used replaced),
@@ -225,7 +233,7 @@ typedef struct stencil_batch_s* stencil_batch_t;
  * the batch; the plans may be shared between batches.  Errors: EINVAL (null
  * pointers, count < 1, a plan of another device), EALIAS (any two of the
  * 2 x count buffers overlap), EUNSUPPORTED (more than 2^31-1 work items in
- * one group), ENOMEM, EHIP.  On error *out is NULL. */
+ * one group, or a time-blocked plan), ENOMEM, EHIP.  On error *out is NULL. */
 stencil_status_t stencil_batch_create(const stencil_plan_t* plans, void* const* buf0, void* const* buf1,
                                       int32_t count, stencil_batch_t* out);
 
@@ -242,6 +250,56 @@ stencil_status_t stencil_batch_info(stencil_batch_t batch, int32_t* groups, int6
 
 /* Release a batch (NULL accepted); enqueued work must have completed. */
 stencil_status_t stencil_batch_destroy(stencil_batch_t batch);
+
+/* -------------------------------------------------------------- autotuner
+ * Measures candidate plans of one descriptor on the current device and
+ * returns the fastest (Section 5 compares line options and unrolling per
+ * stencil and size; this search does the same on MI355X).  Candidates, in two
+ * rounds:
+ *   1. path x line cover x MFMA block edge, the chunk left to the library:
+ *      paths GATHER and MFMA when desc->path is AUTO (plus BF16x3 / FP16x3 for
+ *      F32 grids with STENCIL_TUNE_ALLOW_SPLIT: lower precision, see
+ *      stencil_path_t), line covers PARALLEL / ORTHOGONAL / HYBRID for stars
+ *      when desc->lines is AUTO, block edges 4 and 16 for MFMA when
+ *      desc->block_n is 0 -- combinations stencil_desc_check rejects are
+ *      skipped;
+ *   2. 2D grids, path AUTO or GATHER, time_block 0: time blocks T = 2..12
+ *      (those stencil_desc_check accepts) on the gather path;
+ *   3. for the winner (unless time-blocked), chunk lengths 16..1024 rows (2D)
+ *      or 8..128 planes (3D) when desc->chunk is 0.
+ * Fields of desc other than 0 / AUTO are kept fixed.
+ * Timing: two scratch grids of desc's size (allocated here, set to zero,
+ * freed before returning) on `stream`, which must not be under capture; per
+ * candidate one warm-up run and the best of three timed runs of 24..64
+ * steps (about 2e8 point-steps).
+ * best: receives desc with the chosen path, lines, block_n, chunk and
+ *   time_block (coeffs pointer unchanged).  ms_per_step (may be NULL): the
+ *   winner's time per step.
+ * cache_path (may be NULL): a text file, one line per tuned request
+ *   ("<key> -> path=.. lines=.. block_n=.. chunk=.. time_block=.. ms=.."),
+ *   keyed by ndim,
+ *   shape, radius, dtype, boundary, dims and the requested knobs (the
+ *   coefficient values do not change the timing).  A hit returns the stored
+ *   choice without measuring (unless STENCIL_TUNE_FORCE); a new result is
+ *   appended.  An unreadable or unwritable file is treated as empty.
+ * results / capacity / count (results may be NULL when capacity is 0): every
+ *   measured candidate in order, at most `capacity` written; *count (may be
+ *   NULL) receives the number measured (0 on a cache hit).
+ * Errors: EINVAL (null desc/best, unknown flags, capacity < 0 or results NULL
+ * with capacity > 0, and anything stencil_desc_check rejects), EUNSUPPORTED
+ * (no candidate is built), ENOMEM, EHIP. */
+#define STENCIL_TUNE_ALLOW_SPLIT 1
+#define STENCIL_TUNE_FORCE 2
+
+typedef struct {
+  int32_t path, lines, block_n, chunk, time_block;
+  int32_t status;       /* stencil_status_t of the candidate */
+  double ms_per_step;   /* best timed run; negative if the candidate failed */
+} stencil_tune_result_t;
+
+stencil_status_t stencil_autotune(const stencil_desc_t* desc, const char* cache_path, int32_t flags,
+                                  stencil_desc_t* best, double* ms_per_step, void* stream,
+                                  stencil_tune_result_t* results, int32_t capacity, int32_t* count);
 
 /* Error norms of a state against a reference, for the drift check of
  * mixed-precision runs.  a: device array of n elements of a_dtype

@@ -16,18 +16,30 @@ void free_plan(stencil_plan_s* p) {
   delete p;
 }
 
-stencil_status_t launch_one(const stencil_plan_s* p, const void* in, void* out, hipStream_t s) {
+// One launch: one step, or `fused` steps of a time-blocked plan.
+stencil_status_t launch_one(const stencil_plan_s* p, const void* in, void* out, hipStream_t s, int fused = 1) {
   KArgs a;
   const Kernel k = plan_kernel(p, in, out, &a);
+  a.steps = fused;
   if (!k.launch || k.items < 1 || k.items > (int64_t(1) << 31) - 1) return STENCIL_EINTERNAL;
   return k.launch(a, (unsigned)k.items, s) == hipSuccess ? STENCIL_OK : STENCIL_EHIP;
 }
 
+// Launches of a run of `steps` steps (up to time_block steps each).
+int64_t launch_count(const stencil_plan_s* p, int64_t steps) {
+  const int64_t tb = p->rs.time_block;
+  return (steps + tb - 1) / tb;
+}
+
 stencil_status_t launch_steps(const stencil_plan_s* p, void* buf0, void* buf1, int64_t steps, hipStream_t s) {
   void* buf[2] = {buf0, buf1};
-  for (int64_t t = 0; t < steps; ++t) {
-    const stencil_status_t st = launch_one(p, buf[t & 1], buf[(t + 1) & 1], s);
+  const int64_t tb = p->rs.time_block;
+  int64_t t = 0;
+  for (int64_t k = 0; t < steps; ++k) {
+    const int fused = (int)(steps - t < tb ? steps - t : tb);
+    const stencil_status_t st = launch_one(p, buf[k & 1], buf[(k + 1) & 1], s, fused);
     if (st != STENCIL_OK) return st;
+    t += fused;
   }
   return STENCIL_OK;
 }
@@ -207,7 +219,7 @@ stencil_status_t stencil_run_steps(stencil_plan_t plan, void* buf0, void* buf1, 
     });
     if (st == STENCIL_EUNSUPPORTED) st = launch_steps(plan, buf0, buf1, steps, (hipStream_t)stream);
     if (st != STENCIL_OK) return st;
-    if (result_index) *result_index = (int32_t)(steps & 1);
+    if (result_index) *result_index = (int32_t)(launch_count(plan, steps) & 1);
     return STENCIL_OK;
   } catch (...) {
     return STENCIL_EINTERNAL;

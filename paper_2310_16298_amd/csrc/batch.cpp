@@ -96,6 +96,7 @@ stencil_status_t stencil_batch_create(const stencil_plan_t* plans, void* const* 
       const stencil_plan_s* p = plans[i];
       if (!p || !buf0[i] || !buf1[i]) return STENCIL_EINVAL;
       if (p->device != device) return STENCIL_EINVAL;
+      if (p->rs.time_block > 1) return STENCIL_EUNSUPPORTED;
       spans.push_back({(uintptr_t)buf0[i], (uintptr_t)buf0[i] + p->grid_bytes});
       spans.push_back({(uintptr_t)buf1[i], (uintptr_t)buf1[i] + p->grid_bytes});
     }

@@ -35,6 +35,8 @@ struct KArgs {
   int32_t nchunks;      // 3D: number of i-chunks
   float out_scale;      // split-precision paths: exact power-of-two rescale of the result
   float lo_scale;       // split-precision paths: weight of the cross-term accumulator
+  int32_t steps;        // time-blocked kernels: Jacobi steps fused in this launch
+  int32_t pad;
 };
 
 // Pointer to data that no lane writes during a kernel (constant address

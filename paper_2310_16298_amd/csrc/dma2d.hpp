@@ -86,6 +86,19 @@ struct DmaWindow {
   }
 };
 
+// Default rows per work item of the direct-to-LDS kernels, from a sweep on
+// MI355X (8192^2 FP32): short chunks keep many workgroups in flight, at the
+// cost of 2r re-read halo rows per chunk, so the best length grows with r.
+// Grids too small for ~2048 items of that length use shorter chunks (>= BM).
+inline int32_t dma_chunk(const KArgs& a, int TN, int R, bool box, int32_t chunk) {
+  if (chunk > 0) return chunk;
+  static const int32_t kBox[5] = {0, 16, 64, 128, 128}, kStar[5] = {0, 16, 16, 32, 64};
+  const int64_t strips = (a.d1 + TN - 1) / TN;
+  const int64_t fill = a.d0 * strips / 2048;
+  const int64_t best = box ? kBox[R] : kStar[R];
+  return (int32_t)(fill < best ? (fill < 16 ? 16 : fill) : best);
+}
+
 // Host-side condition for the direct-to-LDS kernels.
 inline bool dma2d_ok(const KArgs& a) {
   return a.d1 % 4 == 0 && (reinterpret_cast<uintptr_t>(a.in) & 15) == 0 &&

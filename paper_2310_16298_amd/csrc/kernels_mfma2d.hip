@@ -34,7 +34,7 @@ static Picker pick_var(int R, int var) {
 
 template <int R, bool BOX>
 static Kernel pick_b4(KArgs& a, int32_t chunk) {
-  if (dma2d_ok(a)) return kernel_of<mfma2d_b4_dma_kernel<R, BOX>, mfma2d_b4_dma_batch<R, BOX>>(strip_grid(a, kDmaTN, kDmaBM, 1024, chunk));
+  if (dma2d_ok(a)) return kernel_of<mfma2d_b4_dma_kernel<R, BOX>, mfma2d_b4_dma_batch<R, BOX>>(strip_grid(a, kDmaTN, kDmaBM, 1024, dma_chunk(a, kDmaTN, R, BOX, chunk)));
   return kernel_of<mfma2d_b4_kernel<R, BOX>, mfma2d_b4_batch<R, BOX>>(strip_grid(a, kTile2D, kTile2D, 2048, chunk));
 }
 

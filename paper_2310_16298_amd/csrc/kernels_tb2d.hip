@@ -1,0 +1,38 @@
+// Instantiations of the time-blocked 2D gather kernel.
+#include "kernels_tb2d.hpp"
+#include "launch.hpp"
+#include "plan.hpp"
+
+namespace stencil {
+
+template <typename T, int R, bool BOX>
+static Kernel pick_tb2d(KArgs& a, int32_t) {
+  const int64_t items = tb2d_items<T>(a);
+  if (tb2d_fast<T>(a)) return kernel_of<tb2d_kernel<T, R, BOX, true>, tb2d_batch<T, R, BOX, true>>(items);
+  return kernel_of<tb2d_kernel<T, R, BOX, false>, tb2d_batch<T, R, BOX, false>>(items);
+}
+
+template <typename T, bool BOX>
+static Picker pick(int R) {
+  switch (R) {
+    case 1: return pick_tb2d<T, 1, BOX>;
+    case 2: return pick_tb2d<T, 2, BOX>;
+    case 3: return pick_tb2d<T, 3, BOX>;
+    case 4: return pick_tb2d<T, 4, BOX>;
+  }
+  return nullptr;
+}
+
+Picker find_tb2d(int dtype, int R, bool box) {
+  if (dtype == STENCIL_F64) return box ? pick<double, true>(R) : pick<double, false>(R);
+  return box ? pick<float, true>(R) : pick<float, false>(R);
+}
+
+int tb2d_max_steps(int dtype, int R) {
+  const int hmax = dtype == STENCIL_F64 ? TbShape<double>::HMAX : TbShape<float>::HMAX;
+  int t = 1;
+  while (tb_halo(R, t + 1) <= hmax) ++t;
+  return t;
+}
+
+}  // namespace stencil

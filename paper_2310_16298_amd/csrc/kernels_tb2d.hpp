@@ -1,0 +1,198 @@
+// Time-blocked 2D gather kernel: T Jacobi steps per launch (the temporal
+// reuse the paper leaves to future work, Section 6).
+//
+// A workgroup owns a TM x TN output tile.  It stages the tile's window with a
+// halo of HW = round_up(r T, 4) on every side into LDS once, then applies T
+// steps between two LDS buffers and stores the tile: HBM traffic per
+// point-step falls about T-fold.  Step s (1-based) computes the shrinking
+// region of window points at least r s from the window edge, which depends
+// only on the region of step s-1; the tile lies HW >= r T inside the edge.  Zero halo: window points outside the
+// grid are 0 at load and reset to 0 after every step; periodic: the window
+// is the periodic extension of the grid, so no reset is needed.
+//
+// LDS layout: window element (x, y) at buf[x * P + 4 + y] (16-byte aligned
+// body); each thread computes 2 x 4 blocks from 12-wide row vectors, as the
+// other gather kernels do.
+#pragma once
+
+#include "device_common.hpp"
+
+namespace stencil {
+
+template <typename T> struct TbShape;
+template <> struct TbShape<float> {
+  static constexpr int TM = 64, TN = 64, HMAX = 12;  // LDS: 2 x 92 x 96 x 4 B = 70,656 B (2 workgroups / CU)
+};
+template <> struct TbShape<double> {
+  static constexpr int TM = 32, TN = 64, HMAX = 8;   // LDS: 2 x 52 x 88 x 8 B = 73,216 B (2 workgroups / CU)
+};
+
+__host__ __device__ constexpr int tb_halo(int R, int steps) { return round_up(R * steps, 4); }
+
+// Tiles of a time-blocked launch: tiles0 = tile rows, tiles1 = tile columns.
+template <typename T>
+inline int64_t tb2d_items(KArgs& a) {
+  typedef TbShape<T> S;
+  a.tiles0 = (int32_t)((a.d0 + S::TM - 1) / S::TM);
+  a.tiles1 = (int32_t)((a.d1 + S::TN - 1) / S::TN);
+  return (int64_t)a.tiles0 * a.tiles1;
+}
+
+template <typename T>
+inline bool tb2d_fast(const KArgs& a) {
+  return a.d1 % 4 == 0 && (reinterpret_cast<uintptr_t>(a.in) & 15) == 0 &&
+         (reinterpret_cast<uintptr_t>(a.out) & 15) == 0;
+}
+
+template <typename T, int R, bool BOX, bool FAST>
+__device__ __forceinline__ void tb2d_item(const KArgs& a, int item) {
+  typedef TbShape<T> S;
+  typedef typename Vec16<T>::type V;
+  constexpr int W = 2 * R + 1, VEC = 16 / (int)sizeof(T);
+  constexpr int WMAX = S::TM + 2 * S::HMAX + 4;  // + 4 rows: the last 2-row block may run past the window
+  constexpr int P = S::TN + 2 * S::HMAX + 8;      // columns 4 + y; 12-wide reads reach 4 past the window
+  __shared__ __attribute__((aligned(16))) T buf[2][WMAX * P];
+
+  const int steps = a.steps;
+  const int HW = tb_halo(R, steps);
+  const int WM = S::TM + 2 * HW, WN = S::TN + 2 * HW, NSEG = WN / 4;
+  const int ti = item / a.tiles1, tj = item - (item / a.tiles1) * a.tiles1;
+  const int64_t M = a.d0, N = a.d1;
+  const int64_t i0 = (int64_t)ti * S::TM - HW, j0 = (int64_t)tj * S::TN - HW;
+  const bool periodic = a.periodic != 0;
+  const T* __restrict__ in = (const T*)a.in;
+  T* __restrict__ out = (T*)a.out;
+  const ConstPtr<T> c = (ConstPtr<T>)a.coef;
+
+  // stage the window: 4-element segments
+  for (int idx = threadIdx.x; idx < WM * NSEG; idx += 256) {
+    const int x = idx / NSEG, sg = idx - (idx / NSEG) * NSEG;
+    const int64_t gi = map_index(i0 + x, M, periodic);
+    const int64_t gj = j0 + 4 * sg;
+    T v[4];
+    if (FAST && gi >= 0 && gj >= 0 && gj + 3 < N) {
+      const V* src = reinterpret_cast<const V*>(in + gi * N + gj);
+#pragma unroll
+      for (int k = 0; k < 4 / VEC; ++k) {
+        const V t = src[k];
+        const T* pt = reinterpret_cast<const T*>(&t);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) v[k * VEC + e] = pt[e];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t cj = map_index(gj + e, N, periodic);
+        v[e] = (gi >= 0 && cj >= 0) ? in[gi * N + cj] : T(0);
+      }
+    }
+    V* dst = reinterpret_cast<V*>(&buf[0][x * P + 4 + 4 * sg]);
+#pragma unroll
+    for (int k = 0; k < 4 / VEC; ++k) {
+      V t;
+      T* pt = reinterpret_cast<T*>(&t);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) pt[e] = v[k * VEC + e];
+      dst[k] = t;
+    }
+  }
+  __syncthreads();
+
+  for (int s = 0; s < steps; ++s) {
+    const T* __restrict__ src = buf[s & 1];
+    T* __restrict__ dstb = buf[(s + 1) & 1];
+    // valid after this step: rows and columns [lo, W - lo), covered by 2 x 4
+    // blocks (their extra row / columns read stale values and are never used)
+    const int lo = R * (s + 1);
+    const int sg0 = lo / 4, nseg = (WN - lo + 3) / 4 - sg0;
+    const int nblk = ((WM - 2 * lo + 1) / 2) * nseg;
+    for (int idx = threadIdx.x; idx < nblk; idx += 256) {
+      const int bx = idx / nseg, sg = sg0 + idx - (idx / nseg) * nseg;
+      const int x = lo + 2 * bx;  // window rows x, x + 1
+      T acc[2][4];
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[p][e] = T(0);
+#pragma unroll
+      for (int dx = 0; dx < 2 + 2 * R; ++dx) {
+        // window row x - r + dx, LDS columns 4 sg .. 4 sg + 11 = window columns 4 sg - 4 .. 4 sg + 7
+        const V* rp = reinterpret_cast<const V*>(src + (x - R + dx) * P + 4 * sg);
+        T v[12];
+#pragma unroll
+        for (int k = 0; k < 12 / VEC; ++k) {
+          const V t = rp[k];
+          const T* pt = reinterpret_cast<const T*>(&t);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) v[k * VEC + e] = pt[e];
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const int aa = dx - p;  // C^g row
+          if (aa < 0 || aa > 2 * R) continue;
+#pragma unroll
+          for (int b = 0; b < W; ++b) {
+            if (!BOX && aa != R && b != R) continue;
+            const T w = c[aa * W + b];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[p][e] += w * v[4 - R + e + b];
+          }
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        if (!periodic) {
+          const int64_t gi = i0 + x + p;
+          const bool row_in = gi >= 0 && gi < M;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t gj = j0 + 4 * sg + e;
+            if (!row_in || gj < 0 || gj >= N) acc[p][e] = T(0);
+          }
+        }
+        V* dv = reinterpret_cast<V*>(dstb + (x + p) * P + 4 + 4 * sg);
+#pragma unroll
+        for (int k = 0; k < 4 / VEC; ++k) {
+          V t;
+          T* pt = reinterpret_cast<T*>(&t);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) pt[e] = acc[p][k * VEC + e];
+          dv[k] = t;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // store the tile: window rows HW .., columns HW ..
+  const T* __restrict__ fin = buf[steps & 1];
+  constexpr int TSEG = S::TN / 4;
+  for (int idx = threadIdx.x; idx < S::TM * TSEG; idx += 256) {
+    const int x = idx / TSEG, sg = idx - (idx / TSEG) * TSEG;
+    const int64_t gi = (int64_t)ti * S::TM + x, gj = (int64_t)tj * S::TN + 4 * sg;
+    if (gi >= M || gj >= N) continue;
+    const T* srcp = fin + (HW + x) * P + 4 + HW + 4 * sg;
+    T* dstp = out + gi * N + gj;
+    if (FAST) {  // N % 4 == 0: the 4-element segment lies inside the row
+      const V* sv = reinterpret_cast<const V*>(srcp);
+#pragma unroll
+      for (int k = 0; k < 4 / VEC; ++k) reinterpret_cast<V*>(dstp)[k] = sv[k];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (gj + e < N) dstp[e] = srcp[e];
+    }
+  }
+}
+
+template <typename T, int R, bool BOX, bool FAST>
+__global__ __launch_bounds__(256) void tb2d_kernel(KArgs a) {
+  tb2d_item<T, R, BOX, FAST>(a, blockIdx.x);
+}
+
+template <typename T, int R, bool BOX, bool FAST>
+__global__ __launch_bounds__(256) void tb2d_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { tb2d_item<T, R, BOX, FAST>(x, id); });
+}
+
+}  // namespace stencil

@@ -163,7 +163,10 @@ static int validate(const stencil_desc_t* d) {
   if (d->lines < STENCIL_LINES_AUTO || d->lines > STENCIL_LINES_HYBRID) return STENCIL_EINVAL;
   if (d->block_n != 0 && d->block_n != 4 && d->block_n != 16) return STENCIL_EINVAL;
   if (d->chunk < 0 || d->time_block < 0) return STENCIL_EINVAL;
-  if (d->time_block > 1) return STENCIL_EUNSUPPORTED;
+  if (d->time_block > 1) {
+    if (d->ndim != 2 || (d->path != STENCIL_PATH_AUTO && d->path != STENCIL_PATH_GATHER)) return STENCIL_EUNSUPPORTED;
+    if (d->time_block > tb2d_max_steps(d->dtype, d->radius)) return STENCIL_EUNSUPPORTED;
+  }
   int64_t total = 1;
   for (int k = 0; k < d->ndim; ++k) {
     if (d->dims[k] < 1 || d->dims[k] > (int64_t(1) << 31) - 1) return STENCIL_EINVAL;
@@ -344,6 +347,8 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   const int KL = round_up(16 + 2 * R, 4);
 
   int path = d.path;
+  in.time_block = 1;
+  if (d.time_block > 1) path = STENCIL_PATH_GATHER;
   if (path == STENCIL_PATH_AUTO) {
     // Measured on MI355X: 2D -> outer products on MFMA; 3D -> the gather
     // kernel (HBM-bound with register blocks; the 3D MFMA kernels trail it).
@@ -387,7 +392,16 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     rs->chunk_req = d.chunk;
     in.tile_rows = kTile2D;
     in.tile_cols = kTile2D;
-    if (path == STENCIL_PATH_GATHER) {
+    if (path == STENCIL_PATH_GATHER && d.time_block > 1) {
+      rs->family = FAM_TB2D;
+      rs->pick = find_tb2d(d.dtype, R, box);
+      rs->time_block = d.time_block;
+      in.time_block = d.time_block;
+      in.tile_rows = d.dtype == STENCIL_F64 ? 32 : 64;
+      in.tile_cols = 64;
+      in.executed_flops_per_point = 2.0 * in.taps;
+      lines = STENCIL_LINES_AUTO;
+    } else if (path == STENCIL_PATH_GATHER) {
       rs->family = FAM_GATHER2D;
       rs->pick = find_gather2d(d.dtype, R, box);
       in.executed_flops_per_point = 2.0 * in.taps;
@@ -443,8 +457,10 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     // 3D: workgroup tile kTJ x kTK in (j, k), a chunk of planes along i.
     const int64_t t0 = ceil_div(d.dims[1], kTJ), t1 = ceil_div(d.dims[2], kTK);
     const int64_t tiles = t0 * t1;
-    int64_t chunk = d.dims[0] * tiles / 1024;  // aim for >= ~1024 workgroups
-    if (chunk < 16) chunk = 16;
+    // about 2048 work items, each at least 4r planes deep (the 2r warm-up
+    // planes of a chunk are re-read)
+    int64_t chunk = d.dims[0] * tiles / 2048;
+    if (chunk < 4 * R) chunk = 4 * R;
     if (d.chunk > 0) chunk = d.chunk;
     if (chunk > d.dims[0]) chunk = d.dims[0];
     const int64_t nch = ceil_div(d.dims[0], chunk);

@@ -22,7 +22,8 @@ enum Family {
   FAM_MFMA3D_STAR = 4, // hybrid cover, Algorithm 1 plane order
   FAM_MFMA3D_BOX = 5,
   FAM_SPLIT3D_STAR = 6,
-  FAM_SPLIT3D_BOX = 7
+  FAM_SPLIT3D_BOX = 7,
+  FAM_TB2D = 8         // time-blocked gather
 };
 
 // Everything the plan resolves on the host.
@@ -37,6 +38,7 @@ struct Resolved {
   float out_scale = 1.0f, lo_scale = 1.0f;
   KArgs args{};             // everything but in/out
   int32_t chunk_req = 0;    // requested rows (2D) per work item, 0 = library choice
+  int32_t time_block = 1;   // steps per launch
   Picker pick = nullptr;
 };
 
@@ -57,6 +59,8 @@ Picker find_split2d(int kind, int R, int variant);
 Picker find_gather3d(int dtype, int R, bool box);
 Picker find_mfma3d(int dtype, int R, bool box);
 Picker find_split3d(int kind, int R, bool box);
+Picker find_tb2d(int dtype, int R, bool box);
+int tb2d_max_steps(int dtype, int R);  // largest time_block of the time-blocked kernel
 
 hipError_t launch_error_norms(const void* a, int a_dtype, const double* ref, int64_t n, double* out,
                               hipStream_t s);

@@ -1,0 +1,259 @@
+// Autotuner (declared in stencil.h): measures candidate plans of one
+// descriptor and returns the fastest choice of path, line cover, MFMA block
+// edge and work-item chunk, with an optional text cache of results.
+#include <cerrno>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "runtime.hpp"
+
+using namespace stencil;
+
+namespace {
+
+struct Candidate {
+  int32_t path, lines, block_n, chunk, time_block;
+};
+
+std::string cache_key(const stencil_desc_t& d) {
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "nd=%d shape=%d r=%d dtype=%d bc=%d dims=%lld,%lld,%lld", d.ndim, d.shape,
+                d.radius, d.dtype, d.boundary, (long long)d.dims[0], (long long)d.dims[1],
+                (long long)(d.ndim == 3 ? d.dims[2] : 1));
+  return buf;
+}
+
+// The requested knobs are part of the key: a different request is a
+// different tuning problem.
+std::string request_key(const stencil_desc_t& d, int32_t flags) {
+  char buf[128];
+  std::snprintf(buf, sizeof(buf), " req=%d,%d,%d,%d,%d,%d", d.path, d.lines, d.block_n, d.chunk, d.time_block,
+                flags & STENCIL_TUNE_ALLOW_SPLIT);
+  return buf;
+}
+
+bool cache_lookup(const char* path, const std::string& key, Candidate* c, double* ms) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    const char* sep = std::strstr(line, " -> ");
+    if (!sep || std::strncmp(line, key.c_str(), key.size()) != 0 || (size_t)(sep - line) != key.size()) continue;
+    Candidate t;
+    double m = 0.0;
+    if (std::sscanf(sep + 4, "path=%d lines=%d block_n=%d chunk=%d time_block=%d ms=%lf", &t.path, &t.lines,
+                    &t.block_n, &t.chunk, &t.time_block, &m) == 6) {
+      *c = t;  // the last entry for a key wins
+      *ms = m;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const Candidate& c, double ms) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s -> path=%d lines=%d block_n=%d chunk=%d time_block=%d ms=%.6f\n", key.c_str(), c.path,
+               c.lines, c.block_n, c.chunk, c.time_block, ms);
+  std::fclose(f);
+}
+
+stencil_desc_t with(const stencil_desc_t& d, const Candidate& c) {
+  stencil_desc_t x = d;
+  x.path = c.path;
+  x.lines = c.lines;
+  x.block_n = c.block_n;
+  x.chunk = c.chunk;
+  x.time_block = c.time_block;
+  return x;
+}
+
+bool valid(const stencil_desc_t& d, const Candidate& c) {
+  Resolved rs;
+  stencil_desc_t x = with(d, c);
+  return resolve_plan(&x, &rs, false) == STENCIL_OK;
+}
+
+// Best of `trials` timed runs of `steps` steps, in ms per step; < 0 on error.
+double time_plan(const stencil_desc_t& d, const Candidate& c, void* b0, void* b1, int64_t steps, int trials,
+                 hipStream_t s, hipEvent_t e0, hipEvent_t e1, stencil_status_t* st) {
+  stencil_desc_t x = with(d, c);
+  stencil_plan_t p = nullptr;
+  *st = stencil_plan(&x, &p);
+  if (*st != STENCIL_OK) return -1.0;
+  double best = -1.0;
+  *st = stencil_run_steps(p, b0, b1, steps, s, nullptr);  // warm-up (records the graph)
+  if (*st == STENCIL_OK && hipStreamSynchronize(s) != hipSuccess) *st = STENCIL_EHIP;
+  for (int t = 0; t < trials && *st == STENCIL_OK; ++t) {
+    float ms = 0.0f;
+    if (hipEventRecord(e0, s) != hipSuccess) *st = STENCIL_EHIP;
+    if (*st == STENCIL_OK) *st = stencil_run_steps(p, b0, b1, steps, s, nullptr);
+    if (*st == STENCIL_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      *st = STENCIL_EHIP;
+    if (*st == STENCIL_OK) {
+      const double per = ms / (double)steps;
+      if (best < 0.0 || per < best) best = per;
+    }
+  }
+  stencil_plan_destroy(p);
+  return *st == STENCIL_OK ? best : -1.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+stencil_status_t stencil_autotune(const stencil_desc_t* desc, const char* cache_path, int32_t flags,
+                                  stencil_desc_t* best, double* ms_per_step, void* stream,
+                                  stencil_tune_result_t* results, int32_t capacity, int32_t* count) {
+  if (!desc || !best || (flags & ~(STENCIL_TUNE_ALLOW_SPLIT | STENCIL_TUNE_FORCE)) != 0 || capacity < 0 ||
+      (capacity > 0 && !results))
+    return STENCIL_EINVAL;
+  if (count) *count = 0;
+  void* b0 = nullptr;
+  void* b1 = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  try {
+    Resolved base;
+    const int vst = resolve_plan(desc, &base, false);
+    if (vst != STENCIL_OK) return (stencil_status_t)vst;
+    const stencil_desc_t& d = *desc;
+    const std::string key = cache_key(d) + request_key(d, flags);
+    Candidate win{};
+    double win_ms = -1.0;
+    if (cache_path && !(flags & STENCIL_TUNE_FORCE) && cache_lookup(cache_path, key, &win, &win_ms) &&
+        valid(d, win)) {
+      *best = with(d, win);
+      if (ms_per_step) *ms_per_step = win_ms;
+      return STENCIL_OK;
+    }
+
+    // Candidate knobs: the request's fixed fields are kept.
+    std::vector<int32_t> paths;
+    if (d.path != STENCIL_PATH_AUTO) {
+      paths.push_back(d.path);
+    } else {
+      paths = {STENCIL_PATH_GATHER, STENCIL_PATH_MFMA};
+      if ((flags & STENCIL_TUNE_ALLOW_SPLIT) && d.dtype == STENCIL_F32) {
+        paths.push_back(STENCIL_PATH_MFMA_BF16X3);
+        paths.push_back(STENCIL_PATH_MFMA_F16X3);
+      }
+    }
+    std::vector<Candidate> first;
+    for (int32_t p : paths) {
+      std::vector<int32_t> lines = {d.lines};
+      if (d.lines == STENCIL_LINES_AUTO && p != STENCIL_PATH_GATHER && d.shape == STENCIL_STAR)
+        lines = {STENCIL_LINES_PARALLEL, STENCIL_LINES_ORTHOGONAL, STENCIL_LINES_HYBRID};
+      std::vector<int32_t> blocks = {d.block_n};
+      if (d.block_n == 0 && p == STENCIL_PATH_MFMA) blocks = {4, 16};
+      for (int32_t l : lines)
+        for (int32_t b : blocks) {
+          const Candidate c{p, l, b, d.chunk, d.time_block};
+          if (valid(d, c)) first.push_back(c);
+        }
+    }
+    if (first.empty()) return STENCIL_EUNSUPPORTED;
+
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return STENCIL_EHIP;
+    const size_t bytes = (size_t)base.info.bytes_per_point / 2 *
+                         (size_t)(d.dims[0] * d.dims[1] * (d.ndim == 3 ? d.dims[2] : 1));
+    if (hipMalloc(&b0, bytes) != hipSuccess || hipMalloc(&b1, bytes) != hipSuccess) {
+      if (b0) (void)hipFree(b0);
+      return STENCIL_ENOMEM;
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    stencil_status_t st = STENCIL_OK;
+    if (hipMemsetAsync(b0, 0, bytes, s) != hipSuccess || hipMemsetAsync(b1, 0, bytes, s) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      st = STENCIL_EHIP;
+    // steps per trial: about 2e8 point-steps, between 24 (two launches of the
+    // deepest time block) and 64
+    const double pts = (double)bytes / (base.info.bytes_per_point / 2);
+    int64_t steps = (int64_t)(2e8 / pts);
+    steps = steps < 24 ? 24 : (steps > 64 ? 64 : steps);
+    int32_t n = 0;
+    auto record = [&](const Candidate& c, double ms, stencil_status_t cst) {
+      if (n < capacity) {
+        stencil_tune_result_t& r = results[n];
+        std::memset(&r, 0, sizeof(r));
+        r.path = c.path;
+        r.lines = c.lines;
+        r.block_n = c.block_n;
+        r.chunk = c.chunk;
+        r.time_block = c.time_block;
+        r.ms_per_step = ms;
+        r.status = cst;
+      }
+      ++n;
+    };
+    auto consider = [&](const Candidate& c) {
+      stencil_status_t cst = STENCIL_OK;
+      const double ms = time_plan(d, c, b0, b1, steps, 3, s, e0, e1, &cst);
+      record(c, ms, cst);
+      if (cst == STENCIL_EHIP) st = cst;  // a device error ends the search
+      if (cst == STENCIL_OK && (win_ms < 0.0 || ms < win_ms)) {
+        win = c;
+        win_ms = ms;
+      }
+    };
+    // 1) path x lines x block edge with the library's chunk
+    for (const Candidate& c : first) {
+      if (st != STENCIL_OK) break;
+      consider(c);
+    }
+    // 2) time blocking (2D gather form) when the request leaves it open
+    if (st == STENCIL_OK && d.ndim == 2 && d.time_block == 0 &&
+        (d.path == STENCIL_PATH_AUTO || d.path == STENCIL_PATH_GATHER)) {
+      for (int32_t t = 2; t <= 12; ++t) {
+        const Candidate c{STENCIL_PATH_GATHER, STENCIL_LINES_AUTO, 0, 0, t};
+        if (!valid(d, c)) continue;
+        consider(c);
+        if (st != STENCIL_OK) break;
+      }
+    }
+    // 3) chunk length for the winner (coordinate search; not used by time blocks)
+    if (st == STENCIL_OK && win_ms >= 0.0 && d.chunk == 0 && win.time_block <= 1) {
+      const int32_t opts2[] = {16, 32, 64, 128, 256, 512, 1024};
+      const int32_t opts3[] = {8, 16, 32, 64, 128};
+      const int32_t* opts = d.ndim == 2 ? opts2 : opts3;
+      const int nopt = d.ndim == 2 ? 7 : 5;
+      const Candidate head = win;
+      for (int k = 0; k < nopt && st == STENCIL_OK; ++k) {
+        if (opts[k] > d.dims[0]) break;
+        Candidate c = head;
+        c.chunk = opts[k];
+        if (valid(d, c)) consider(c);
+      }
+    }
+    if (count) *count = n;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    e0 = e1 = nullptr;
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(b0);
+    (void)hipFree(b1);
+    b0 = b1 = nullptr;
+    if (st != STENCIL_OK) return st;
+    if (win_ms < 0.0) return STENCIL_EUNSUPPORTED;
+    *best = with(d, win);
+    if (ms_per_step) *ms_per_step = win_ms;
+    if (cache_path) cache_store(cache_path, key, win, win_ms);
+    return STENCIL_OK;
+  } catch (...) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (b0) (void)hipFree(b0);
+    if (b1) (void)hipFree(b1);
+    return STENCIL_EINTERNAL;
+  }
+}
+
+}  // extern "C"

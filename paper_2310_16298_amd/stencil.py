@@ -53,11 +53,11 @@ class PlanInfo(ctypes.Structure):
         ("block_n", ctypes.c_int32), ("mfma_lines", ctypes.c_int32), ("valu_lines", ctypes.c_int32),
         ("k_rows", ctypes.c_int32), ("rank1_per_block", ctypes.c_int64),
         ("useful_flops_per_point", ctypes.c_double), ("executed_flops_per_point", ctypes.c_double),
-        ("bytes_per_point", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("bytes_per_point", ctypes.c_int32), ("time_block", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 EXPORTS = [
@@ -65,7 +65,17 @@ EXPORTS = [
     "stencil_line_band", "stencil_line_cover", "stencil_plan", "stencil_plan_info", "stencil_plan_destroy",
     "stencil_apply", "stencil_run_steps", "stencil_error_norms",
     "stencil_batch_create", "stencil_batch_run_steps", "stencil_batch_info", "stencil_batch_destroy",
+    "stencil_autotune",
 ]
+
+TUNE_ALLOW_SPLIT, TUNE_FORCE = 1, 2
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [
+        ("path", ctypes.c_int32), ("lines", ctypes.c_int32), ("block_n", ctypes.c_int32), ("chunk", ctypes.c_int32),
+        ("time_block", ctypes.c_int32), ("status", ctypes.c_int32), ("ms_per_step", ctypes.c_double),
+    ]
 
 _lib = None
 
@@ -99,6 +109,9 @@ def load_library(path: str = LIB_PATH):
     lib.stencil_batch_run_steps.argtypes = [vp, i64, vp, ctypes.POINTER(i32)]
     lib.stencil_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.stencil_batch_destroy.argtypes = [vp]
+    lib.stencil_autotune.argtypes = [ctypes.POINTER(Desc), ctypes.c_char_p, i32, ctypes.POINTER(Desc),
+                                     ctypes.POINTER(ctypes.c_double), vp, ctypes.POINTER(TuneResult), i32,
+                                     ctypes.POINTER(i32)]
     for name in EXPORTS[2:]:
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -256,6 +269,34 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def autotune(dims, radius, shape, coeffs, boundary=BC_ZERO, dtype=F32, path=PATH_AUTO, lines=LINES_AUTO,
+             block_n=0, chunk=0, cache: Optional[str] = None, allow_split=False, force=False, stream=None,
+             capacity=64):
+    """Measure candidate plans on the current device (``stencil_autotune``).
+
+    stream=None measures on the device's null stream.  Returns (knobs,
+    ms_per_step, results): knobs is a dict of path, lines,
+    block_n, chunk and time_block for ``Plan(..., **knobs)``; results lists every measured
+    candidate (empty on a cache hit)."""
+    lib = load_library()
+    d, keep = make_desc(dims, radius, shape, coeffs, boundary=boundary, dtype=dtype, path=path, lines=lines,
+                        block_n=block_n, chunk=chunk)
+    best = Desc()
+    ms = ctypes.c_double(0.0)
+    res = (TuneResult * capacity)()
+    cnt = ctypes.c_int32(0)
+    flags = (TUNE_ALLOW_SPLIT if allow_split else 0) | (TUNE_FORCE if force else 0)
+    _check(lib.stencil_autotune(ctypes.byref(d), cache.encode() if cache else None, flags, ctypes.byref(best),
+                                ctypes.byref(ms), _stream_ptr(stream) if stream is not None else None, res,
+                                capacity, ctypes.byref(cnt)),
+           "stencil_autotune")
+    knobs = {"path": best.path, "lines": best.lines, "block_n": best.block_n, "chunk": best.chunk,
+             "time_block": best.time_block}
+    rows = [{"path": r.path, "lines": r.lines, "block_n": r.block_n, "chunk": r.chunk, "time_block": r.time_block,
+             "ms_per_step": r.ms_per_step, "status": r.status} for r in res[:min(cnt.value, capacity)]]
+    return knobs, ms.value, rows
 
 
 class Batch:

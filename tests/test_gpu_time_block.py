@@ -1,0 +1,106 @@
+"""GPU parity of time-blocked plans (T Jacobi steps per launch on overlapped
+tiles in LDS) against the CPU FP64 oracle: every radius, both shapes, both
+boundaries and dtypes, time blocks from 2 to the largest built, step counts
+that leave a partial last launch, ragged and tiny extents, integer data
+bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2310_16298_amd import inputs
+from paper_2310_16298_amd import stencil as st
+
+from gpu_helpers import eff_coeffs, error_bound, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TMAX = {(st.F32, 1): 12, (st.F32, 2): 6, (st.F32, 3): 4, (st.F32, 4): 3,
+        (st.F64, 1): 8, (st.F64, 2): 4, (st.F64, 3): 2, (st.F64, 4): 2}
+
+
+def _run(a0, c, r, shape, bc, dtype, tb, steps):
+    torch = torch_cuda()
+    plan = st.Plan(a0.shape, r, shape, c, boundary=bc, dtype=dtype, time_block=tb)
+    assert plan.info["time_block"] == max(tb, 1)
+    x = torch.from_numpy(a0).cuda()
+    y = torch.empty_like(x)
+    res = plan.run_steps(x, y, steps)
+    torch.cuda.synchronize()
+    launches = -(-steps // max(tb, 1))
+    assert (res is x) == (launches % 2 == 0)
+    out = res.cpu().numpy().astype(np.float64)
+    plan.close()
+    return out
+
+
+def _case(dims, r, shape, bc, dtype, tb, steps, seed):
+    c = inputs.coefficients(2, r, shape, seed=seed, dtype=np.float64)
+    ce = eff_coeffs(c, dtype)
+    a0 = inputs.grid(dims, seed=seed + 1, dtype=np.float32 if dtype == st.F32 else np.float64)
+    want = oracle.run(a0, ce, r, shape, bc, steps)
+    got = _run(a0, c, r, shape, bc, dtype, tb, steps)
+    tol = error_bound(ce, 2, r, shape, dtype, st.PATH_GATHER, steps, np.abs(a0).max())
+    err = np.abs(got - want).max()
+    assert err <= tol, f"max err {err:.3e} > bound {tol:.3e}"
+
+
+@pytest.mark.parametrize("dtype", [st.F32, st.F64])
+@pytest.mark.parametrize("shape", [st.BOX, st.STAR])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("bc", [st.BC_ZERO, st.BC_PERIODIC])
+@pytest.mark.parametrize("dims", [(100, 77), (96, 132)])
+def test_time_block_parity(dtype, shape, r, bc, dims):
+    tmax = TMAX[(dtype, r)]
+    for tb in sorted({2, tmax}):
+        _case(dims, r, shape, bc, dtype, tb, 2 * tb + 1, seed=1000 + 10 * r + bc)
+
+
+@pytest.mark.parametrize("dims", [(1, 1), (5, 3), (3, 70), (70, 2), (9, 9)])
+@pytest.mark.parametrize("r", [1, 3])
+def test_time_block_small_extents(dims, r):
+    """Windows much larger than the grid: periodic wraps many times, zero
+    halo keeps re-zeroing almost the whole window."""
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        for dtype in (st.F32, st.F64):
+            _case(dims, r, st.BOX, bc, dtype, TMAX[(dtype, r)], 5, seed=1100 + r)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("dtype", [st.F32, st.F64])
+def test_time_block_integer_bit_exact(r, dtype):
+    c = inputs.int_coefficients(2, r, st.BOX, seed=1200 + r)
+    s = float(np.abs(c).sum())
+    tb = TMAX[(dtype, r)]
+    limit = 2.0 ** 24 if dtype == st.F32 else 2.0 ** 53
+    steps = 1
+    while steps < tb + 1 and 8 * s ** (steps + 1) < limit:
+        steps += 1
+    a0 = inputs.int_grid((70, 132), seed=1210 + r, dtype=np.float32 if dtype == st.F32 else np.float64)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        want = oracle.run(a0, c, r, st.BOX, bc, steps)
+        got = _run(a0, c, r, st.BOX, bc, dtype, tb, steps)
+        assert np.array_equal(got, want)
+
+
+def test_time_block_apply_is_one_step():
+    torch = torch_cuda()
+    c = inputs.coefficients(2, 2, st.BOX, seed=1300, dtype=np.float64)
+    a0 = inputs.grid((64, 64), seed=1301)
+    plan = st.Plan((64, 64), 2, st.BOX, c, time_block=4)
+    x = torch.from_numpy(a0).cuda()
+    y = torch.empty_like(x)
+    plan.apply(x, y)
+    torch.cuda.synchronize()
+    want = oracle.run(a0, eff_coeffs(c, st.F32), 2, st.BOX, st.BC_ZERO, 1)
+    tol = error_bound(eff_coeffs(c, st.F32), 2, 2, st.BOX, st.F32, st.PATH_GATHER, 1, 1.0)
+    assert np.abs(y.cpu().numpy().astype(np.float64) - want).max() <= tol
+
+
+def test_batch_rejects_time_blocked_plan():
+    torch = torch_cuda()
+    c = inputs.coefficients(2, 1, st.BOX, seed=1400, dtype=np.float64)
+    plan = st.Plan((32, 32), 1, st.BOX, c, time_block=2)
+    x, y = torch.zeros(32, 32, device="cuda"), torch.zeros(32, 32, device="cuda")
+    with pytest.raises(st.StencilError) as e:
+        st.Batch([plan], [x], [y])
+    assert e.value.status == st.EUNSUPPORTED

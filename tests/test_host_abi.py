@@ -126,6 +126,21 @@ def test_tuning_fields(lib):
     assert st.desc_check((64, 64), 2, inputs.BOX, c, chunk=48) == st.OK
 
 
+@pytest.mark.parametrize("r,f32max,f64max", [(1, 12, 8), (2, 6, 4), (3, 4, 2), (4, 3, 2)])
+def test_time_block_limits(lib, r, f32max, f64max):
+    """Time blocks: 2D gather form only; the halo r*T rounded up to 4 fits
+    the kernel's LDS window (12 for FP32, 8 for FP64)."""
+    c = _box(2, r)
+    for dt, tmax in ((st.F32, f32max), (st.F64, f64max)):
+        assert st.desc_check((100, 100), r, inputs.BOX, c, dtype=dt, time_block=tmax) == st.OK
+        assert st.desc_check((100, 100), r, inputs.BOX, c, dtype=dt, time_block=tmax + 1) == st.EUNSUPPORTED
+        info = st.describe((100, 100), r, inputs.BOX, c, dtype=dt, time_block=tmax)
+        assert info["time_block"] == tmax and info["path"] == st.PATH_GATHER
+    assert st.desc_check((100, 100), r, inputs.BOX, c, path=st.PATH_MFMA, time_block=2) == st.EUNSUPPORTED
+    assert st.desc_check((20, 20, 20), r, inputs.BOX, _box(3, r), time_block=2) == st.EUNSUPPORTED
+    assert st.describe((100, 100), r, inputs.BOX, c, time_block=1)["time_block"] == 1
+
+
 # ------------------------------------------------------------ band builder
 
 def _golden(name):
@@ -295,3 +310,33 @@ def test_line_cover_is_minimum(lib, seed):
     for i, j in zip(*np.nonzero(nz)):
         assert i in rl or j in cl
     assert len(rl) + len(cl) == _brute_cover(nz)
+
+
+# ------------------------------------------------------------ autotuner (host part)
+
+def test_autotune_rejects(lib):
+    c = _box(2, 2)
+    d, keep = st.make_desc((64, 64), 2, inputs.BOX, c)
+    best = st.Desc()
+    assert lib.stencil_autotune(None, None, 0, ctypes.byref(best), None, None, None, 0, None) == st.EINVAL
+    assert lib.stencil_autotune(ctypes.byref(d), None, 0, None, None, None, None, 0, None) == st.EINVAL
+    assert lib.stencil_autotune(ctypes.byref(d), None, 8, ctypes.byref(best), None, None, None, 0, None) == st.EINVAL
+    assert lib.stencil_autotune(ctypes.byref(d), None, 0, ctypes.byref(best), None, None, None, 4, None) == st.EINVAL
+    bad, keep2 = st.make_desc((64, 64), 5, inputs.BOX, _box(2, 4))
+    assert lib.stencil_autotune(ctypes.byref(bad), None, 0, ctypes.byref(best), None, None, None, 0, None) == st.EINVAL
+
+
+def test_autotune_cache_hit_needs_no_device(lib, tmp_path):
+    """A cached entry is returned without measuring (the last entry of a key
+    wins; other keys and malformed lines are skipped)."""
+    cache = tmp_path / "tune.txt"
+    key = "nd=2 shape=1 r=2 dtype=0 bc=1 dims=64,80,1 req=0,0,0,0,0,0"
+    cache.write_text(
+        "garbage line\n"
+        f"{key} -> path=2 lines=1 block_n=16 chunk=0 time_block=0 ms=0.250000\n"
+        "nd=2 shape=1 r=2 dtype=0 bc=1 dims=64,81,1 req=0,0,0,0,0,0 -> path=1 lines=0 block_n=0 chunk=0 "
+        "time_block=3 ms=0.1\n"
+        f"{key} -> path=2 lines=1 block_n=4 chunk=32 time_block=0 ms=0.125000\n")
+    knobs, ms, rows = st.autotune((64, 80), 2, inputs.BOX, _box(2, 2), boundary=st.BC_PERIODIC, cache=str(cache))
+    assert knobs == {"path": st.PATH_MFMA, "lines": st.LINES_PARALLEL, "block_n": 4, "chunk": 32, "time_block": 0}
+    assert ms == 0.125 and rows == []
