@@ -251,6 +251,77 @@ stencil_status_t stencil_batch_info(stencil_batch_t batch, int32_t* groups, int6
 /* Release a batch (NULL accepted); enqueued work must have completed. */
 stencil_status_t stencil_batch_destroy(stencil_batch_t batch);
 
+/* ---------------------------------------------------------------- serving
+ * A serving loop with continuous batching.  Requests -- a descriptor, an
+ * input and an output grid buffer, a step count -- wait in a FIFO.  Each call
+ * of stencil_server_tick
+ *   1. admits requests from the head of the queue while their device
+ *      footprint (two grids plus operand fragments, coefficients and a zero
+ *      line, each rounded up to 256 bytes) fits the server's arena and, if
+ *      max_active > 0, while fewer than max_active are resident;
+ *   2. advances every resident request by one Jacobi step with one persistent
+ *      batched launch per kernel group (as stencil_batch_run_steps; requests
+ *      admitted at different ticks advance together);
+ *   3. copies each request that has done its steps to its output buffer and
+ *      releases its arena block.
+ * The arena is one device allocation made at creation, with a first-fit
+ * allocator; ticks make no device allocation or free (hipFree would
+ * synchronise the device), except that the two work tables (pinned host and
+ * device) grow when more requests are resident than ever before.  All work
+ * runs on the server's own stream (stencil_server_stream), in order.  A
+ * request's result equals the result of a plan of the same descriptor run
+ * alone (same kernel, same arithmetic).  Not thread-safe: one thread drives a
+ * server.  Time-blocked descriptors (time_block > 1) are rejected
+ * (EUNSUPPORTED). */
+typedef struct stencil_server_s* stencil_server_t;
+
+typedef struct {
+  int64_t arena_bytes;         /* device memory for resident requests (>= 256) */
+  int32_t max_active;          /* 0 = limited by the arena only */
+  int32_t max_inflight_ticks;  /* ticks enqueued ahead of the GPU before tick() waits; 0 = 4 */
+} stencil_server_config_t;
+
+typedef struct {
+  int64_t tick;                /* ticks so far */
+  int64_t arena_in_use;        /* bytes of the arena held by resident requests */
+  int32_t active;              /* resident requests after this tick */
+  int32_t queued;              /* waiting requests */
+  int32_t groups;              /* kernel groups launched this tick */
+  int32_t retired;             /* requests whose results were enqueued this tick */
+} stencil_server_stats_t;
+
+/* Create a server on the current device (allocates the arena, 64 pinned
+ * staging buffers of 64 KiB and a stream).  Errors: EINVAL, ENOMEM, EHIP. */
+stencil_status_t stencil_server_create(const stencil_server_config_t* config, stencil_server_t* out);
+
+/* The server's stream (hipStream_t): work the caller enqueues on it before a
+ * submit is ordered before that request's admission (e.g. writing its input). */
+stencil_status_t stencil_server_stream(stencil_server_t server, void** stream);
+
+/* Queue a request: `steps` Jacobi steps of the grid in `input` (device, the
+ * descriptor's dims and dtype) written to `output` (device, same size, not
+ * overlapping input).  The descriptor is resolved and its coefficients copied
+ * now; input must stay valid and unchanged, and output valid, until
+ * stencil_server_poll reports the request.  *id (may be NULL) receives its id
+ * (1, 2, ... in submission order).  Errors: EINVAL (null arguments, negative
+ * steps, anything stencil_desc_check rejects), EALIAS, EUNSUPPORTED
+ * (time-blocked descriptor), ENOMEM (footprint larger than the arena). */
+stencil_status_t stencil_server_submit(stencil_server_t server, const stencil_desc_t* desc, const void* input,
+                                       void* output, int64_t steps, int64_t* id);
+
+/* One tick (see above); stats (may be NULL) receives the server's counters.
+ * Blocks only to keep at most max_inflight_ticks ticks in flight. */
+stencil_status_t stencil_server_tick(stencil_server_t server, stencil_server_stats_t* stats);
+
+/* Ids of requests whose results are complete in their output buffers, in
+ * completion order; at most `capacity` (whole ticks at a time), *count
+ * receives the number written.  Non-blocking. */
+stencil_status_t stencil_server_poll(stencil_server_t server, int64_t* ids, int32_t capacity, int32_t* count);
+
+/* Wait for the server's stream and release everything (NULL accepted);
+ * requests not yet finished are dropped. */
+stencil_status_t stencil_server_destroy(stencil_server_t server);
+
 /* -------------------------------------------------------------- autotuner
  * Measures candidate plans of one descriptor on the current device and
  * returns the fastest (Section 5 compares line options and unrolling per

@@ -66,7 +66,19 @@ EXPORTS = [
     "stencil_apply", "stencil_run_steps", "stencil_error_norms",
     "stencil_batch_create", "stencil_batch_run_steps", "stencil_batch_info", "stencil_batch_destroy",
     "stencil_autotune",
+    "stencil_server_create", "stencil_server_stream", "stencil_server_submit", "stencil_server_tick",
+    "stencil_server_poll", "stencil_server_destroy",
 ]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32),
+                ("max_inflight_ticks", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("tick", ctypes.c_int64), ("arena_in_use", ctypes.c_int64), ("active", ctypes.c_int32),
+                ("queued", ctypes.c_int32), ("groups", ctypes.c_int32), ("retired", ctypes.c_int32)]
 
 TUNE_ALLOW_SPLIT, TUNE_FORCE = 1, 2
 
@@ -109,6 +121,12 @@ def load_library(path: str = LIB_PATH):
     lib.stencil_batch_run_steps.argtypes = [vp, i64, vp, ctypes.POINTER(i32)]
     lib.stencil_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.stencil_batch_destroy.argtypes = [vp]
+    lib.stencil_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.stencil_server_stream.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.stencil_server_submit.argtypes = [vp, ctypes.POINTER(Desc), vp, vp, i64, ctypes.POINTER(i64)]
+    lib.stencil_server_tick.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.stencil_server_poll.argtypes = [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32)]
+    lib.stencil_server_destroy.argtypes = [vp]
     lib.stencil_autotune.argtypes = [ctypes.POINTER(Desc), ctypes.c_char_p, i32, ctypes.POINTER(Desc),
                                      ctypes.POINTER(ctypes.c_double), vp, ctypes.POINTER(TuneResult), i32,
                                      ctypes.POINTER(i32)]
@@ -341,6 +359,72 @@ class Batch:
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.stencil_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop with continuous batching (``stencil_server_*``).
+
+    ``Server(arena_bytes, max_active=0, max_inflight_ticks=0)``; requests are
+    submitted with their input and output tensors (kept alive here until the
+    request is polled), advanced by ``tick()`` and reported by ``poll()``."""
+
+    def __init__(self, arena_bytes: int, max_active: int = 0, max_inflight_ticks: int = 0):
+        lib = load_library()
+        cfg = ServerConfig(int(arena_bytes), int(max_active), int(max_inflight_ticks))
+        h = ctypes.c_void_p()
+        _check(lib.stencil_server_create(ctypes.byref(cfg), ctypes.byref(h)), "stencil_server_create")
+        self._h = h
+        self._lib = lib
+        self._live = {}
+        sp = ctypes.c_void_p()
+        _check(lib.stencil_server_stream(h, ctypes.byref(sp)), "stencil_server_stream")
+        self.stream_handle = sp.value
+
+    def stream(self):
+        """The server's stream as a torch stream object."""
+        return _torch().cuda.ExternalStream(self.stream_handle)
+
+    def submit(self, x, out, steps: int, radius: int, shape: int, coeffs, boundary=BC_ZERO, path=PATH_AUTO,
+               lines=LINES_AUTO, block_n=0, chunk=0) -> int:
+        torch = _torch()
+        if not (x.is_cuda and out.is_cuda and x.is_contiguous() and out.is_contiguous()):
+            raise ValueError("input and output must be contiguous GPU tensors")
+        if x.shape != out.shape or x.dtype != out.dtype or x.dtype not in (torch.float32, torch.float64):
+            raise ValueError("input and output must have the same shape and a float32/float64 dtype")
+        dtype = F64 if x.dtype == torch.float64 else F32
+        d, keep = make_desc(tuple(x.shape), radius, shape, coeffs, boundary=boundary, dtype=dtype, path=path,
+                            lines=lines, block_n=block_n, chunk=chunk)
+        rid = ctypes.c_int64(0)
+        _check(self._lib.stencil_server_submit(self._h, ctypes.byref(d), x.data_ptr(), out.data_ptr(), int(steps),
+                                               ctypes.byref(rid)), "stencil_server_submit")
+        self._live[rid.value] = (x, out)
+        return rid.value
+
+    def tick(self) -> dict:
+        stats = ServerStats()
+        _check(self._lib.stencil_server_tick(self._h, ctypes.byref(stats)), "stencil_server_tick")
+        return {name: getattr(stats, name) for name, _ in ServerStats._fields_}
+
+    def poll(self, capacity: int = 4096):
+        ids = (ctypes.c_int64 * capacity)()
+        cnt = ctypes.c_int32(0)
+        _check(self._lib.stencil_server_poll(self._h, ids, capacity, ctypes.byref(cnt)), "stencil_server_poll")
+        done = [ids[k] for k in range(cnt.value)]
+        for rid in done:
+            self._live.pop(rid, None)
+        return done
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.stencil_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._live.clear()
 
     def __del__(self):
         try:

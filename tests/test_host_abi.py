@@ -109,6 +109,17 @@ def test_null_arguments(lib):
     assert lib.stencil_batch_run_steps(None, 1, None, None) == st.EINVAL
     assert lib.stencil_batch_info(None, None, None, None) == st.EINVAL
     assert lib.stencil_batch_destroy(None) == st.OK
+    h = ctypes.c_void_p(1)
+    assert lib.stencil_server_create(None, ctypes.byref(h)) == st.EINVAL
+    assert h.value is None
+    bad = st.ServerConfig(16, 0, 0)  # arena below 256 bytes
+    assert lib.stencil_server_create(ctypes.byref(bad), ctypes.byref(h)) == st.EINVAL
+    assert lib.stencil_server_stream(None, None) == st.EINVAL
+    assert lib.stencil_server_submit(None, None, None, None, 1, None) == st.EINVAL
+    assert lib.stencil_server_tick(None, None) == st.EINVAL
+    cnt = ctypes.c_int32(0)
+    assert lib.stencil_server_poll(None, None, 0, ctypes.byref(cnt)) == st.EINVAL
+    assert lib.stencil_server_destroy(None) == st.OK
 
 
 def test_tuning_fields(lib):
