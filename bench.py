@@ -16,6 +16,7 @@ Other configurations (their own JSON line each; not the headline):
     --workload mixed        BF16x3 / FP16x3 with an FP64 shadow, drift check every 50 steps
     --workload batch        many small FP64 grids (Table 3 shapes) per batched launch vs one by one
     --workload tune         autotuner sweep: line option x MFMA block x chunk per radius
+    --workload serve        serving loop, Poisson arrivals at 0.5 / 0.8 load: p50/p99 latency
 """
 from __future__ import annotations
 
@@ -306,6 +307,116 @@ def workload_tune(args, torch, st, inputs) -> dict:
     return out
 
 
+def _serve_requests(n, st):
+    """Seeded request stream (stream seed 501): 2D/3D 50/50, square/cube side
+    log-uniform on [64, 4096] (2D) or [32, 512] (3D), r uniform on 1..4,
+    star/box 50/50, steps uniform on 1..200, zero/periodic 50/50, FP32."""
+    rng = np.random.default_rng(501)
+    reqs = []
+    for k in range(n):
+        nd = 2 if rng.random() < 0.5 else 3
+        lo, hi = (64, 4096) if nd == 2 else (32, 512)
+        side = int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
+        reqs.append({"id": k, "dims": (side,) * nd, "r": int(rng.integers(1, 5)),
+                     "shape": st.STAR if rng.random() < 0.5 else st.BOX, "steps": int(rng.integers(1, 201)),
+                     "bc": st.BC_ZERO if rng.random() < 0.5 else st.BC_PERIODIC})
+    return reqs
+
+
+def _serve_run(torch, st, inputs, srv, reqs, arrivals, keep_ids=()):
+    """Drive the server: submit each request at its arrival time (seconds
+    from the start), tick while work is resident or queued, record completion
+    times at poll.  Returns (latency_s by id, wall seconds, outputs kept)."""
+    stream = srv.stream()
+    t0 = time.perf_counter()
+    nxt, busy = 0, 0
+    by_rid, lat, kept = {}, {}, {}
+    total = len(reqs)
+    last_note = 0.0
+    while len(lat) < total:
+        now = time.perf_counter() - t0
+        if now - last_note > 10.0:
+            print(f"[serve] t={now:.0f}s submitted={nxt} done={len(lat)} of {total}", file=sys.stderr, flush=True)
+            last_note = now
+        while nxt < total and arrivals[nxt] <= now:
+            q = reqs[nxt]
+            g = torch.Generator(device="cuda")
+            g.manual_seed(5000 + q["id"])
+            with torch.cuda.stream(stream):
+                x = torch.rand(q["dims"], generator=g, device="cuda", dtype=torch.float32) * 2 - 1
+                out = torch.empty_like(x)
+            c = inputs.coefficients(len(q["dims"]), q["r"], q["shape"], seed=5000 + q["id"], dtype=np.float64)
+            rid = srv.submit(x, out, q["steps"], q["r"], q["shape"], c, boundary=q["bc"])
+            by_rid[rid] = (q, out, arrivals[nxt], c, x if q["id"] in keep_ids else None)
+            nxt += 1
+            busy += 1
+        if busy:
+            srv.tick()
+        elif nxt < total:
+            time.sleep(max(0.0, min(arrivals[nxt] - now, 0.0005)))
+        for rid in srv.poll():
+            q, out, arr, c, x = by_rid.pop(rid)
+            lat[q["id"]] = time.perf_counter() - t0 - arr
+            busy -= 1
+            if q["id"] in keep_ids:
+                kept[q["id"]] = (q, c, x.cpu().numpy(), out.cpu().numpy())
+    torch.cuda.synchronize()
+    return lat, time.perf_counter() - t0, kept
+
+
+def workload_serve(args, torch, st, inputs) -> dict:
+    """Serving: Poisson arrivals of the seeded request stream at offered
+    loads 0.5 and 0.8 of the server's calibrated closed-loop throughput;
+    p50/p99 of completion - arrival, aggregate GStencil/s, and results of
+    sampled requests equal (bitwise) to the same request run alone."""
+    n_warm, n_meas = args.serve_warmup, args.serve_requests
+    reqs = _serve_requests(n_warm + n_meas, st)
+    pts = {q["id"]: float(np.prod(q["dims"])) * q["steps"] for q in reqs}
+    out = {"metric": "completion - arrival latency p50/p99 (ms) and aggregate GStencil/s",
+           "workload": f"{n_warm} warm-up + {n_meas} measured requests per load; 2D side log-uniform[64,4096], "
+                       "3D side log-uniform[32,512], r 1..4, star/box, steps 1..200, zero/periodic, FP32",
+           "arena_gib": args.serve_arena_gib, "loads": {}}
+    srv = st.Server(args.serve_arena_gib << 30, max_inflight_ticks=4)
+    # closed loop: everything arrives at once
+    cal = reqs[:min(len(reqs), 150)]
+    lat, wall, _ = _serve_run(torch, st, inputs, srv, cal, [0.0] * len(cal))
+    thr_req = len(cal) / wall
+    thr_pts = sum(pts[q["id"]] for q in cal) / wall
+    out["closed_loop"] = {"requests": len(cal), "requests_per_s": round(thr_req, 2),
+                          "gstencil_s": round(thr_pts / 1e9, 2)}
+    print(f"[bench] serve closed loop: {thr_req:.1f} req/s, {thr_pts / 1e9:.1f} GStencil/s", file=sys.stderr,
+          flush=True)
+    rng = np.random.default_rng(502)
+    for rho in (0.5, 0.8):
+        lam = rho * thr_req
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
+        arrivals -= arrivals[0]
+        sample = [q["id"] for q in reqs[n_warm:] if np.prod(q["dims"]) <= 300 * 300][:6]
+        lat, wall, kept = _serve_run(torch, st, inputs, srv, reqs, arrivals, keep_ids=set(sample))
+        meas = [q["id"] for q in reqs[n_warm:]]
+        ms = np.array([lat[i] for i in meas]) * 1e3
+        t_first = arrivals[n_warm]
+        t_last = max(arrivals[i] + lat[i] for i in meas)
+        g = sum(pts[i] for i in meas) / (t_last - t_first) / 1e9
+        equal = []
+        for rid, (q, c, x, got) in kept.items():
+            plan = st.Plan(q["dims"], q["r"], q["shape"], c, boundary=q["bc"], dtype=st.F32)
+            xd = torch.from_numpy(x).cuda()
+            res = plan.run_steps(xd, torch.empty_like(xd), q["steps"])
+            torch.cuda.synchronize()
+            equal.append(bool(np.array_equal(res.cpu().numpy(), got)))
+            plan.close()
+        out["loads"][str(rho)] = {"offered_requests_per_s": round(lam, 2), "p50_ms": round(float(np.percentile(ms, 50)), 3),
+                                  "p99_ms": round(float(np.percentile(ms, 99)), 3),
+                                  "mean_ms": round(float(ms.mean()), 3), "gstencil_s": round(g, 2),
+                                  "hbm_frac_1step_equiv": round(g * 8 / HBM_PEAK_GBS, 4),
+                                  "alone_equals_mix": {"checked": len(equal), "equal": int(sum(equal))}}
+        print(f"[bench] serve rho={rho}: p50 {np.percentile(ms, 50):.2f} ms, p99 {np.percentile(ms, 99):.2f} ms, "
+              f"{g:.1f} GStencil/s, alone==mix {sum(equal)}/{len(equal)}", file=sys.stderr, flush=True)
+    srv.close()
+    return out
+
+
 def workload_mixed(args, torch, st, inputs) -> dict:
     """BF16x3 / FP16x3 outer products with FP32 state for 200 steps; an FP64
     shadow trajectory (FP64 gather path) on the GPU; rel-L2 and max-abs of the
@@ -385,7 +496,10 @@ def main() -> int:
     ap.add_argument("--radii", default="1,2,3,4", help="orders to run (profiling runs use a subset)")
     ap.add_argument("--jacobi-steps", type=int, default=JACOBI_STEPS,
                     help="Jacobi steps per solve (profiling runs only; the benchmark uses 100)")
-    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch", "tune"])
+    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch", "tune", "serve"])
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per offered load")
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-arena-gib", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="first run N plain device copies of one grid (known bytes) for counter scaling")
     args = ap.parse_args()
@@ -404,7 +518,7 @@ def main() -> int:
     st.load_library()
     if args.workload != "box2d":
         fn = {"star2d_512": workload_star2d_512, "grid3d": workload_grid3d, "mixed": workload_mixed,
-              "batch": workload_batch, "tune": workload_tune}[args.workload]
+              "batch": workload_batch, "tune": workload_tune, "serve": workload_serve}[args.workload]
         res = fn(args, torch, st, inputs)
         res.update({"n_gpus": 1, "data": "synthetic"})
         print(json.dumps(res))

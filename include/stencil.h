@@ -259,9 +259,13 @@ stencil_status_t stencil_batch_destroy(stencil_batch_t batch);
  *      footprint (two grids plus operand fragments, coefficients and a zero
  *      line, each rounded up to 256 bytes) fits the server's arena and, if
  *      max_active > 0, while fewer than max_active are resident;
- *   2. advances every resident request by one Jacobi step with one persistent
- *      batched launch per kernel group (as stencil_batch_run_steps; requests
- *      admitted at different ticks advance together);
+ *   2. advances every resident request with persistent batched launches, k
+ *      per kernel group (the kernels of stencil_batch_run_steps; requests
+ *      admitted at different ticks advance together): k is chosen from an
+ *      estimate of each group's cost per step (HBM bytes and executed flops
+ *      of its plans) so that the costliest group does one step and cheaper
+ *      groups up to 64 in about the same time; a request takes part in the
+ *      first min(k, steps left) launches of its group;
  *   3. copies each request that has done its steps to its output buffer and
  *      releases its arena block.
  * The arena is one device allocation made at creation, with a first-fit

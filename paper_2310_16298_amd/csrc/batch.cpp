@@ -47,7 +47,7 @@ stencil_status_t launch_group(const Group& g, int parity, hipStream_t s) {
   b.table = g.d_table;
   b.ngrids = (int32_t)g.grids.size();
   b.total = (int32_t)g.total;
-  b.parity = parity & 1;
+  b.launch = parity & 1;
   b.pad = 0;
   return g.k.launch_batch(b, g.blocks, s) == hipSuccess ? STENCIL_OK : STENCIL_EHIP;
 }
@@ -128,6 +128,7 @@ stencil_status_t stencil_batch_create(const stencil_plan_t* plans, void* const* 
       e.args = a;
       e.first = (int32_t)g.total;
       e.phase = 0;
+      e.limit = 2;  // launches 0 and 1 (the step parity) always advance every grid
       g.grids.push_back(e);
       g.total += k.items;
       if (g.total > (int64_t(1) << 31) - 1) {

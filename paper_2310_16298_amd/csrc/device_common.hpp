@@ -148,21 +148,24 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
 }
 
 // Several grids in one launch.  Grid g of a table owns the work items
-// (workgroup tiles) [table[g].first, table[g+1].first); table[ngrids].first is
-// the total.  Its args hold buffer 0 in `in` and buffer 1 in `out`; a launch
-// whose step parity p has (p ^ phase) odd reads buffer 1 and writes buffer 0,
-// so grids that joined a batch at different steps advance together.
+// (workgroup tiles) [table[g].first, table[g+1].first); the last grid's end
+// is `total`.  Its args hold buffer 0 in `in` and buffer 1 in `out`.  Launch
+// number `launch` of a sequence advances the grids with launch < limit by one
+// step: a grid with (launch + phase) even reads buffer 0 and writes buffer 1,
+// odd the reverse, so grids that joined at different steps advance together.
 struct BatchGrid {
   KArgs args;
   int32_t first;  // first work item of this grid
-  int32_t phase;  // step parity offset of this grid
+  int32_t phase;  // steps the grid had done before launch 0, mod 2
+  int32_t limit;  // launches of the sequence that advance this grid
+  int32_t pad;
 };
 
 struct BatchArgs {
-  const BatchGrid* table;  // nullptr: one grid, described by the kernel's own KArgs
+  const BatchGrid* table;
   int32_t ngrids;
   int32_t total;           // work items over all grids
-  int32_t parity;          // step parity of this launch
+  int32_t launch;          // index of this launch in its sequence
   int32_t pad;
 };
 
@@ -192,8 +195,9 @@ __device__ __forceinline__ void for_each_batch_item(const BatchArgs& b, F item) 
       else hi = mid - 1;
     }
     const BatchGrid e = uniform_load(&b.table[lo]);
+    if (b.launch >= e.limit) continue;  // this grid has done its steps
     KArgs g = e.args;
-    if ((b.parity ^ e.phase) & 1) {
+    if ((b.launch + e.phase) & 1) {
       g.in = e.args.out;
       g.out = const_cast<void*>(e.args.in);
     }

@@ -3,14 +3,17 @@
 // Requests (a descriptor, an input and an output buffer, a step count) wait
 // in a FIFO.  Each tick admits requests from the head of the queue while their
 // device footprint fits the server's arena, then advances every resident
-// request by one Jacobi step: one persistent batched launch per kernel group
-// (the kernels of stencil_batch_*), each grid reading buffer (t - t0) % 2 of
-// its own pair through the per-grid phase t0 % 2.  A request that has done
-// its steps is copied to its output buffer and leaves; its arena block is
-// reused by later requests (stream order keeps the reuse behind the copy).
+// request: each kernel group (the batched kernels of stencil_batch_*) gets k
+// persistent launches, k chosen so that cheap groups do several steps in the
+// time the costliest group does one (estimated from the plans' bytes and
+// flops per point), and a grid takes part in its first min(k, steps left)
+// launches.  A request that has done its steps is copied to its output buffer
+// and leaves; its arena block is reused by later requests (stream order keeps
+// the reuse behind the copy).
 // No device allocation or free happens after creation: hipFree synchronises
 // the device and would stall the pipeline.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -88,10 +91,11 @@ struct Request {
   int64_t id = 0;
   Resolved rs;
   size_t grid_bytes = 0;
+  double step_cost = 0.0;  // estimated seconds per step
   const void* input = nullptr;
   void* output = nullptr;
   int64_t steps = 0, done = 0;
-  int64_t t0 = 0;          // tick of admission
+  int32_t limit = 0;       // steps in the current tick
   size_t arena_off = SIZE_MAX;
   KArgs args{};            // buffers 0 / 1 in in / out
   Kernel kernel;
@@ -118,17 +122,18 @@ struct stencil_server_s {
   int64_t tick = 0;
   std::deque<Request*> queue;
   std::vector<Request*> active;
-  bool dirty = true;                    // membership changed since the tables were built
   struct Group {
     Kernel k;
     int32_t first_entry = 0, ngrids = 0;
     int64_t total = 0;
     unsigned blocks = 0;
+    int32_t launches = 1;
   };
   std::vector<Group> groups;
-  void* d_tables[2] = {nullptr, nullptr};
-  BatchGrid* h_tables[2] = {nullptr, nullptr};  // pinned
-  hipEvent_t table_free[2] = {nullptr, nullptr};
+  static constexpr int kTables = 8;     // ring of work tables, one per tick in flight
+  void* d_tables[kTables] = {};
+  BatchGrid* h_tables[kTables] = {};    // pinned
+  hipEvent_t table_free[kTables] = {};
   size_t table_cap = 0;                 // entries per table buffer
   int cur_table = 0;
   std::vector<Slot> slots;
@@ -151,7 +156,7 @@ struct stencil_server_s {
       if (s.host) (void)hipHostFree(s.host);
       if (s.ready) (void)hipEventDestroy(s.ready);
     }
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kTables; ++k) {
       if (d_tables[k]) (void)hipFree(d_tables[k]);
       if (h_tables[k]) (void)hipHostFree(h_tables[k]);
       if (table_free[k]) (void)hipEventDestroy(table_free[k]);
@@ -217,7 +222,9 @@ stencil_status_t admit(stencil_server_s* s, Request* r) {
   r->kernel = r->rs.pick(a, r->rs.chunk_req);
   if (!r->kernel.launch_batch || r->kernel.items < 1) return STENCIL_EINTERNAL;
   r->args = a;
-  r->t0 = s->tick;
+  // rough cost model: HBM bytes at 5 TB/s plus executed flops at 50 TFLOP/s
+  const double pts = (double)r->grid_bytes / (r->rs.info.dtype == STENCIL_F64 ? 8.0 : 4.0);
+  r->step_cost = pts * (r->rs.info.bytes_per_point / 5.0e12 + r->rs.info.executed_flops_per_point / 50.0e12);
   return STENCIL_OK;
 }
 
@@ -237,10 +244,10 @@ stencil_status_t rebuild_tables(stencil_server_s* s) {
   }
   const size_t n = s->active.size();
   if (n > s->table_cap) {
-    // grow both table buffers (after all work that read them)
+    // grow the table buffers (after all work that read them)
     if (hipStreamSynchronize(s->stream) != hipSuccess) return STENCIL_EHIP;
     size_t cap = std::max<size_t>(n, 2 * s->table_cap);
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < stencil_server_s::kTables; ++k) {
       if (s->d_tables[k]) (void)hipFree(s->d_tables[k]);
       if (s->h_tables[k]) (void)hipHostFree(s->h_tables[k]);
       s->d_tables[k] = nullptr;
@@ -251,8 +258,15 @@ stencil_status_t rebuild_tables(stencil_server_s* s) {
     }
     s->table_cap = cap;
   }
-  const int k = s->cur_table ^ 1;
+  const int k = (s->cur_table + 1) % stencil_server_s::kTables;
   if (hipEventSynchronize(s->table_free[k]) != hipSuccess) return STENCIL_EHIP;
+  // launches per group: the costliest group does one step per tick (at least
+  // 100 us of estimated work), cheaper groups up to 64
+  std::vector<double> cost(s->groups.size(), 4.0e-6);
+  for (size_t g = 0; g < s->groups.size(); ++g)
+    for (Request* r : members[g]) cost[g] += r->step_cost;
+  double tau = 100.0e-6;
+  for (double c : cost) tau = std::max(tau, c);
   BatchGrid* h = s->h_tables[k];
   int32_t e = 0;
   for (size_t g = 0; g < s->groups.size(); ++g) {
@@ -260,14 +274,20 @@ stencil_status_t rebuild_tables(stencil_server_s* s) {
     G.first_entry = e;
     G.ngrids = (int32_t)members[g].size();
     G.total = 0;
+    G.launches = (int32_t)std::min(64.0, std::max(1.0, std::floor(tau / cost[g])));
+    int32_t most = 1;
     for (Request* r : members[g]) {
+      r->limit = (int32_t)std::min<int64_t>(G.launches, r->steps - r->done);
+      most = std::max(most, r->limit);
       std::memset(&h[e], 0, sizeof(BatchGrid));
       h[e].args = r->args;
       h[e].first = (int32_t)G.total;
-      h[e].phase = (int32_t)(r->t0 & 1);
+      h[e].phase = (int32_t)(r->done & 1);
+      h[e].limit = r->limit;
       G.total += r->kernel.items;
       ++e;
     }
+    G.launches = most;
     if (G.total > (int64_t(1) << 31) - 1) return STENCIL_EUNSUPPORTED;
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, G.k.batch_id, 256, 0) != hipSuccess || occ < 1) occ = 1;
@@ -285,7 +305,6 @@ stencil_status_t rebuild_tables(stencil_server_s* s) {
     if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return STENCIL_EHIP;
     s->join.push_back(ev);
   }
-  s->dirty = false;
   return STENCIL_OK;
 }
 
@@ -300,13 +319,15 @@ stencil_status_t launch_tick(stencil_server_s* s) {
   }
   for (size_t g = 0; g < ng; ++g) {
     const auto& G = s->groups[g];
-    BatchArgs b;
-    b.table = table + G.first_entry;
-    b.ngrids = G.ngrids;
-    b.total = (int32_t)G.total;
-    b.parity = (int32_t)(s->tick & 1);
-    b.pad = 0;
-    if (G.k.launch_batch(b, G.blocks, g == 0 ? s->stream : s->side[g - 1]) != hipSuccess) return STENCIL_EHIP;
+    for (int32_t j = 0; j < G.launches; ++j) {
+      BatchArgs b;
+      b.table = table + G.first_entry;
+      b.ngrids = G.ngrids;
+      b.total = (int32_t)G.total;
+      b.launch = j;
+      b.pad = 0;
+      if (G.k.launch_batch(b, G.blocks, g == 0 ? s->stream : s->side[g - 1]) != hipSuccess) return STENCIL_EHIP;
+    }
   }
   for (size_t g = 1; g < ng; ++g) {
     if (hipEventRecord(s->join[g - 1], s->side[g - 1]) != hipSuccess) return STENCIL_EHIP;
@@ -352,7 +373,7 @@ stencil_status_t stencil_server_create(const stencil_server_config_t* cfg, stenc
         return STENCIL_EHIP;
       }
     }
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < stencil_server_s::kTables; ++k)
       if (hipEventCreateWithFlags(&s->table_free[k], hipEventDisableTiming) != hipSuccess) {
         delete s;
         return STENCIL_EHIP;
@@ -438,22 +459,18 @@ stencil_status_t stencil_server_tick(stencil_server_t s, stencil_server_stats_t*
         continue;
       }
       s->active.push_back(r);
-      s->dirty = true;
     }
-    // 2) one step of every resident request
-    if (s->dirty) {
-      const stencil_status_t st = rebuild_tables(s);
-      if (st != STENCIL_OK) return st;
-    }
+    // 2) advance every resident request (a fresh work table each tick)
     if (!s->active.empty()) {
-      const stencil_status_t st = launch_tick(s);
+      stencil_status_t st = rebuild_tables(s);
+      if (st == STENCIL_OK) st = launch_tick(s);
       if (st != STENCIL_OK) return st;
     }
     // 3) retire finished requests
     std::vector<Request*> keep;
     keep.reserve(s->active.size());
     for (Request* r : s->active) {
-      ++r->done;
+      r->done += r->limit;
       if (r->done < r->steps) {
         keep.push_back(r);
         continue;
@@ -464,7 +481,6 @@ stencil_status_t stencil_server_tick(stencil_server_t s, stencil_server_stats_t*
       retired.push_back(r->id);
       s->arena.release(r->arena_off);
       delete r;
-      s->dirty = true;
     }
     s->active.swap(keep);
     ++s->tick;

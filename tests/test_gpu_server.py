@@ -28,6 +28,9 @@ SPECS = [  # dims, r, shape, bc, dtype, path, steps
     ((9, 9), 1, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_GATHER, 9),
     ((40, 24, 32), 4, st.STAR, st.BC_ZERO, st.F32, BF, 3),
     ((256, 64), 2, st.BOX, st.BC_ZERO, st.F32, st.PATH_MFMA, 8),
+    ((64, 64), 2, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_AUTO, 137),  # many launches per tick
+    ((24, 40, 48), 1, st.STAR, st.BC_ZERO, st.F64, st.PATH_GATHER, 70),
+    ((512, 512), 1, st.STAR, st.BC_PERIODIC, st.F32, st.PATH_MFMA, 65),
 ]
 
 
@@ -88,7 +91,7 @@ def test_server_results_equal_alone(arena_mib, max_active):
         c, a0 = data[k]
         got = outs[k].cpu().numpy()
         assert np.array_equal(got, _alone(torch, SPECS[k], c, a0)), f"request {k} {SPECS[k]}"
-    for k in (0, 2, 4, 9):
+    for k in (0, 2, 4, 9, 12, 13):
         dims, r, shape, bc, dt, path, steps = SPECS[k]
         c, a0 = data[k]
         ce = eff_coeffs(c, dt)
