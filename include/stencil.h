@@ -56,7 +56,14 @@ typedef enum {
   STENCIL_EINTERNAL = -6     /* unexpected internal error */
 } stencil_status_t;
 
-typedef enum { STENCIL_STAR = 0, STENCIL_BOX = 1 } stencil_shape_t;
+/* STAR: only on-axis weights may be nonzero (2rd+1 taps); BOX: any weights,
+ * all (2r+1)^d taps computed; GENERAL: any weights, 2D outer-product plans
+ * cover the nonzero weights with a minimum set of axis-parallel coefficient
+ * lines (Section 3.5, see stencil_line_cover) -- at most 2r+1 lines of either
+ * direction, a weight on a column line and a row line being carried by the
+ * column line only; other paths and 3D treat GENERAL as BOX.  The line
+ * option (lines) must be AUTO for GENERAL. */
+typedef enum { STENCIL_STAR = 0, STENCIL_BOX = 1, STENCIL_GENERAL = 2 } stencil_shape_t;
 
 /* Boundary rule (the paper states none):
  *   ZERO     -- every grid point is updated; values outside the grid read as 0;

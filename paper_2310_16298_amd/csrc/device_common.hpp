@@ -36,7 +36,8 @@ struct KArgs {
   float out_scale;      // split-precision paths: exact power-of-two rescale of the result
   float lo_scale;       // split-precision paths: weight of the cross-term accumulator
   int32_t steps;        // time-blocked kernels: Jacobi steps fused in this launch
-  int32_t pad;
+  int32_t lcode0;       // line-cover kernel: slots 0..5, 5 bits each (bit 4: line along j, bits 0..3: index)
+  int32_t lcode1;       // slots 6..8 in bits 0..14, number of lines in bits 27..30
 };
 
 // Pointer to data that no lane writes during a kernel (constant address

@@ -12,7 +12,7 @@
 
 namespace stencil {
 
-enum Variant2D { VAR_BOX = 0, VAR_STAR_PARALLEL = 1, VAR_STAR_ORTHO = 2 };
+enum Variant2D { VAR_BOX = 0, VAR_STAR_PARALLEL = 1, VAR_STAR_ORTHO = 2, VAR_COVER = 3 };
 
 constexpr int kTile2D = 64;   // output tile edge of one workgroup
 constexpr int kThreads = 256; // four waves
@@ -129,14 +129,19 @@ __global__ __launch_bounds__(kThreads) void gather2d_batch(BatchArgs b) {
 //                    (C^g row r, centre excluded) in the transposed form
 //                    D[p][q] += sum_y H[p + r][y] * S[y][q], S[y][q] = C^g[r][y-q]
 //                    (Eq. (14)): the input column segment is the A operand.
+// VAR_COVER:         any C^g (Section 3.5): up to 2r+1 lines of a minimum
+//                    axis-parallel cover, each along i (C^g column b, first
+//                    form) or along j (C^g row a, second form); the slot
+//                    kinds and indices come from KArgs.lcode0 / lcode1.
 // K is padded to a multiple of 4 per line; padded rows carry zero weights.
 // ---------------------------------------------------------------------------
 template <typename T, int R, int VAR>
 struct Mfma2DShape {
   static constexpr int KL = round_up(16 + 2 * R, 4);   // K rows per line incl. padding
   static constexpr int CPL = KL / 4;                    // MFMA chunks per line
-  static constexpr int NLC = VAR == VAR_BOX ? 2 * R + 1 : 1;
+  static constexpr int NLC = (VAR == VAR_BOX || VAR == VAR_COVER) ? 2 * R + 1 : 1;
   static constexpr int NLR = VAR == VAR_STAR_ORTHO ? 1 : 0;
+  static constexpr bool ROWREAD = VAR == VAR_STAR_ORTHO || VAR == VAR_COVER;  // lines along j read columns
   static constexpr int NCH = (NLC + NLR) * CPL;         // band fragments per lane
   static constexpr int TM = kTile2D, TN = kTile2D;
   static constexpr int WROWS = TM + 2 * R;
@@ -144,8 +149,8 @@ struct Mfma2DShape {
   static constexpr int COL0 = lds_col0<T, R>();
   static constexpr int WEND = COL0 + TN + 2 * R;        // one past the window's last column
   static constexpr int REND = COL0 + (TN - 16) + KL;    // one past the row-line reads' last column
-  static constexpr int LCOLS = cmax(WEND, NLR ? REND : 0);
-  static constexpr int PITCH = pick_pitch<T, VAR == VAR_STAR_ORTHO>(LCOLS);
+  static constexpr int LCOLS = cmax(WEND, ROWREAD ? REND : 0);
+  static constexpr int PITCH = pick_pitch<T, ROWREAD>(LCOLS);
 };
 
 template <typename T, int R, int VAR>
@@ -196,16 +201,44 @@ __device__ __forceinline__ void mfma2d_item(const KArgs& a, int item) {
     acc_t acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[t] = acc_t{};
+    if constexpr (VAR != VAR_COVER) {
 #pragma unroll
-    for (int li = 0; li < S::NLC; ++li) {
-      const int b = VAR == VAR_BOX ? li : R;
+      for (int li = 0; li < S::NLC; ++li) {
+        const int b = VAR == VAR_BOX ? li : R;
 #pragma unroll
-      for (int cc = 0; cc < S::CPL; ++cc) {
-        const T av = af[li * S::CPL + cc];
+        for (int cc = 0; cc < S::CPL; ++cc) {
+          const T av = af[li * S::CPL + cc];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const T bv = colbase[(4 * cc) * S::PITCH + 16 * t + b];
-          acc[t] = MM::mma(av, bv, acc[t]);
+          for (int t = 0; t < 4; ++t) {
+            const T bv = colbase[(4 * cc) * S::PITCH + 16 * t + b];
+            acc[t] = MM::mma(av, bv, acc[t]);
+          }
+        }
+      }
+    } else {
+      const int nlines = (a.lcode1 >> 27) & 15;
+#pragma unroll
+      for (int k = 0; k < S::NLC; ++k) {
+        if (k >= nlines) break;
+        const int code = k < 6 ? (a.lcode0 >> (5 * k)) & 31 : (a.lcode1 >> (5 * (k - 6))) & 31;
+        const int idx = code & 15;
+        if ((code & 16) == 0) {
+          // line along i, C^g column idx: A = band, B = input row segment shifted by idx
+#pragma unroll
+          for (int cc = 0; cc < S::CPL; ++cc) {
+            const T av = af[k * S::CPL + cc];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = MM::mma(av, colbase[(4 * cc) * S::PITCH + 16 * t + idx], acc[t]);
+          }
+        } else {
+          // line along j, C^g row idx: A = input column segment of rows shifted by idx, B = band
+          const T* rb = lds + (16 * w + idx + q) * S::PITCH + S::COL0 + g;
+#pragma unroll
+          for (int cc = 0; cc < S::CPL; ++cc) {
+            const T sv = af[k * S::CPL + cc];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = MM::mma(rb[16 * t + 4 * cc], sv, acc[t]);
+          }
         }
       }
     }

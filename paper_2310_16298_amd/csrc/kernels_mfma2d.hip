@@ -28,6 +28,7 @@ static Picker pick_var(int R, int var) {
     case VAR_BOX: return pick<T, VAR_BOX>(R);
     case VAR_STAR_PARALLEL: return pick<T, VAR_STAR_PARALLEL>(R);
     case VAR_STAR_ORTHO: return pick<T, VAR_STAR_ORTHO>(R);
+    case VAR_COVER: return pick<T, VAR_COVER>(R);
   }
   return nullptr;
 }

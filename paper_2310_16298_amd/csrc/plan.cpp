@@ -156,7 +156,7 @@ static int validate(const stencil_desc_t* d) {
   if (!d || !d->coeffs) return STENCIL_EINVAL;
   if (d->ndim != 2 && d->ndim != 3) return STENCIL_EINVAL;
   if (d->radius < 1 || d->radius > 4) return STENCIL_EINVAL;
-  if (d->shape != STENCIL_STAR && d->shape != STENCIL_BOX) return STENCIL_EINVAL;
+  if (d->shape != STENCIL_STAR && d->shape != STENCIL_BOX && d->shape != STENCIL_GENERAL) return STENCIL_EINVAL;
   if (d->boundary != STENCIL_BC_ZERO && d->boundary != STENCIL_BC_PERIODIC) return STENCIL_EINVAL;
   if (d->dtype != STENCIL_F32 && d->dtype != STENCIL_F64) return STENCIL_EINVAL;
   if (d->path < STENCIL_PATH_AUTO || d->path > STENCIL_PATH_MFMA_F16X3) return STENCIL_EINVAL;
@@ -190,6 +190,7 @@ static int validate(const stencil_desc_t* d) {
   }
   const bool split = d->path == STENCIL_PATH_MFMA_BF16X3 || d->path == STENCIL_PATH_MFMA_F16X3;
   if (split && d->dtype != STENCIL_F32) return STENCIL_EUNSUPPORTED;
+  if (d->shape == STENCIL_GENERAL && d->lines != STENCIL_LINES_AUTO) return STENCIL_EUNSUPPORTED;
   if (d->shape == STENCIL_BOX && d->lines != STENCIL_LINES_AUTO && d->lines != STENCIL_LINES_PARALLEL)
     return STENCIL_EUNSUPPORTED;
   if (d->shape == STENCIL_STAR && d->ndim == 2 && d->lines == STENCIL_LINES_HYBRID)
@@ -339,8 +340,15 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   in.shape = d.shape;
   in.boundary = d.boundary;
   in.dtype = d.dtype;
-  const bool box = d.shape == STENCIL_BOX;
+  // GENERAL (any C^g) runs on the box kernels, except for the 2D outer-product
+  // form, which takes a minimum line cover (Section 3.5).
+  const bool general = d.shape == STENCIL_GENERAL;
+  const bool box = d.shape == STENCIL_BOX || general;
   in.taps = box ? (nd == 2 ? W * W : W * W * W) : 2 * R * nd + 1;
+  if (general) {
+    in.taps = 0;
+    for (int t = 0; t < ncoef; ++t) in.taps += cg[t] != 0.0;
+  }
   in.useful_flops_per_point = 2.0 * in.taps;
   in.bytes_per_point = 2 * dtype_size(d.dtype);
   const int n = 16;
@@ -408,23 +416,61 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       lines = STENCIL_LINES_AUTO;
     } else if (path == STENCIL_PATH_MFMA) {
       rs->family = FAM_MFMA2D;
-      rs->variant = box ? VAR_BOX : (lines == STENCIL_LINES_PARALLEL ? VAR_STAR_PARALLEL : VAR_STAR_ORTHO);
+      rs->variant = general ? VAR_COVER
+                            : (box ? VAR_BOX : (lines == STENCIL_LINES_PARALLEL ? VAR_STAR_PARALLEL : VAR_STAR_ORTHO));
       // FP32 box / parallel star: n = 4 blocks on 4x4x1 by default (less band
       // padding); block_n = 16 selects the 16x16x4 kernel.
-      const bool b4_ok = d.dtype == STENCIL_F32 && rs->variant != VAR_STAR_ORTHO;
+      const bool b4_ok = d.dtype == STENCIL_F32 && (rs->variant == VAR_BOX || rs->variant == VAR_STAR_PARALLEL);
       if (d.block_n == 4 && !b4_ok) return STENCIL_EUNSUPPORTED;
       const bool b4 = b4_ok && d.block_n != 16;
       rs->pick = b4 ? find_mfma2d_b4(R, box) : find_mfma2d(d.dtype, R, rs->variant);
       std::vector<Line> col, row;
       const int fixed_r[3] = {R, R, 0};
+      if (rs->variant == VAR_COVER) {
+        // Minimum cover: lines along i (C^g columns) first, then lines along j
+        // (C^g rows, with the cover's columns zeroed so each weight is counted
+        // once), padded with zero lines to 2r+1 fragment slots.
+        int rows[9], cols[9];
+        const int ncov = line_cover(cg.data(), R, rows, cols);
+        int64_t code = 0;
+        int k = 0;
+        for (int b = 0; b < W; ++b)
+          if (cols[b]) {
+            const int fx[3] = {0, b, 0};
+            col.push_back(line_of(cg, 2, R, 0, fx, false));
+            code |= (int64_t)b << (5 * k++);
+          }
+        for (int a0 = 0; a0 < W; ++a0)
+          if (rows[a0]) {
+            Line w(W);
+            for (int y = 0; y < W; ++y) w[y] = cols[y] ? 0.0 : cg[(size_t)a0 * W + y];
+            col.push_back(w);
+            code |= (int64_t)(16 | a0) << (5 * k++);
+          }
+        while ((int)col.size() < W) col.push_back(Line(W, 0.0));
+        a.lcode0 = (int32_t)(code & ((int64_t(1) << 30) - 1));
+        a.lcode1 = (int32_t)((code >> 30) | ((int64_t)ncov << 27));
+        in.block_n = n;
+        if (pack) pack_mfma(rs, R, d.dtype, col, row);
+        in.mfma_lines = ncov;
+        in.valu_lines = 0;
+        in.k_rows = ncov * KL;
+        in.rank1_per_block = (int64_t)ncov * (2 * R + n);
+        in.executed_flops_per_point = 2.0 * in.k_rows;
+        lines = STENCIL_LINES_AUTO;
+        col.clear();
+      }
       for (int b = 0; b < W; ++b) {
+        if (rs->variant == VAR_COVER) break;
         if (rs->variant != VAR_BOX && b != R) continue;
         const int fx[3] = {0, b, 0};
         col.push_back(line_of(cg, 2, R, 0, fx, false));  // C^g column b
       }
       if (rs->variant == VAR_STAR_ORTHO) row.push_back(line_of(cg, 2, R, 1, fixed_r, true));  // C^g row r
-      fill_2d_counts(rs, R, rs->variant, false);
-      if (b4) {
+      if (rs->variant != VAR_COVER) fill_2d_counts(rs, R, rs->variant, false);
+      if (rs->variant == VAR_COVER) {
+        // packed above
+      } else if (b4) {
         if (pack) pack_mfma_b4(rs, R, col);
         else in.k_rows = (int)col.size() * (4 + 2 * R);
         in.block_n = 4;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libstencil.so")
 
 # enums (mirror include/stencil.h)
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, EALIAS, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
-STAR, BOX = 0, 1
+STAR, BOX, GENERAL = 0, 1, 2
 BC_ZERO, BC_PERIODIC = 0, 1
 F32, F64 = 0, 1
 PATH_AUTO, PATH_GATHER, PATH_MFMA, PATH_MFMA_BF16X3, PATH_MFMA_F16X3 = 0, 1, 2, 3, 4

@@ -351,3 +351,31 @@ def test_autotune_cache_hit_needs_no_device(lib, tmp_path):
     knobs, ms, rows = st.autotune((64, 80), 2, inputs.BOX, _box(2, 2), boundary=st.BC_PERIODIC, cache=str(cache))
     assert knobs == {"path": st.PATH_MFMA, "lines": st.LINES_PARALLEL, "block_n": 4, "chunk": 32, "time_block": 0}
     assert ms == 0.125 and rows == []
+
+
+# ------------------------------------------------------------ general shapes (Section 3.5)
+
+def _pattern_cg(r, mask, seed):
+    rng = np.random.default_rng(seed)
+    return np.where(mask, rng.uniform(0.1, 1.0, size=mask.shape), 0.0)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_general_plan_uses_minimum_cover(lib, seed):
+    rng = np.random.default_rng(900 + seed)
+    r = int(rng.integers(1, 5))
+    w = 2 * r + 1
+    mask = rng.random((w, w)) < rng.uniform(0.1, 0.6)
+    c = _pattern_cg(r, mask, seed)
+    rows, cols = st.line_cover(c, r)
+    info = st.describe((64, 64), r, st.GENERAL, c, path=st.PATH_MFMA)
+    assert info["mfma_lines"] == len(rows) + len(cols) <= w
+    assert info["taps"] == int(mask.sum())
+    assert info["block_n"] == 16 and info["valu_lines"] == 0
+    kl = -(-(16 + 2 * r) // 4) * 4
+    assert info["k_rows"] == info["mfma_lines"] * kl
+    assert st.desc_check((64, 64), r, st.GENERAL, c, lines=st.LINES_PARALLEL) == st.EUNSUPPORTED
+    assert st.desc_check((64, 64), r, st.GENERAL, c, path=st.PATH_MFMA, block_n=4) == st.EUNSUPPORTED
+    # other paths take GENERAL as a box
+    assert st.describe((64, 64), r, st.GENERAL, c, path=st.PATH_GATHER)["path"] == st.PATH_GATHER
+    assert st.describe((16, 16, 16), r, st.GENERAL, _box(3, r))["path"] == st.PATH_GATHER
