@@ -17,6 +17,7 @@ Other configurations (their own JSON line each; not the headline):
     --workload batch        many small FP64 grids (Table 3 shapes) per batched launch vs one by one
     --workload tune         autotuner sweep: line option x MFMA block x chunk per radius
     --workload serve        serving loop, Poisson arrivals at 0.5 / 0.8 load: p50/p99 latency
+    --workload cover        irregular order-4 stencils: minimum line cover vs box and gather
 """
 from __future__ import annotations
 
@@ -419,6 +420,41 @@ def workload_serve(args, torch, st, inputs) -> dict:
     return out
 
 
+def workload_cover(args, torch, st, inputs) -> dict:
+    """Irregular 2D stencils of order 4 on 8192^2 FP32 (periodic, 100 steps):
+    the outer-product form over a minimum line cover (GENERAL) against the
+    same weights as a box (all 9 lines / all 81 taps) and the gather form."""
+    dims, r, steps = (8192, 8192), 4, 100
+    w = 2 * r + 1
+    z = np.zeros((w, w), dtype=bool)
+    pats = {}
+    m = z.copy(); m[r, :] = True; m[:, r] = True; m[0, 0] = m[w - 1, w - 1] = True; pats["cross_plus_two_corners"] = m
+    m = z.copy(); m[w - 1, :] = True; m[:, 0] = True; pats["l_shape"] = m
+    m = z.copy(); m[1, :] = True; m[5, :] = True; m[:, 2] = True; pats["two_rows_one_column"] = m
+    pats["random_25pct"] = np.random.default_rng(6100).random((w, w)) < 0.25
+    a0 = torch.from_numpy(inputs.grid(dims, seed=6000, dtype=np.float32)).cuda()
+    stream = torch.cuda.Stream()
+    out = {"metric": "GStencil/s", "workload": "2D order-4 irregular stencils, 8192^2 FP32, periodic, 100 steps",
+           "cases": {}}
+    for name, mask in pats.items():
+        c = np.where(mask, np.random.default_rng(6200).uniform(0.05, 1.0, size=(w, w)), 0.0)
+        c /= c.sum()
+        rows, cols = st.line_cover(c, r)
+        res = {"nonzeros": int(mask.sum()), "cover_lines": len(rows) + len(cols)}
+        for label, shape, path in (("general_mfma_cover", st.GENERAL, st.PATH_MFMA),
+                                   ("box_mfma_all_columns", st.BOX, st.PATH_MFMA),
+                                   ("box_gather_all_taps", st.BOX, st.PATH_GATHER)):
+            plan = st.Plan(dims, r, shape, c, boundary=st.BC_PERIODIC, dtype=st.F32, path=path)
+            times = _time_solve(torch, plan, a0, steps, args.steps, args.warmup, stream)
+            res[label] = round(float(dims[0] * dims[1] * steps / (np.median(times) * 1e-3) / 1e9), 2)
+            if shape == st.GENERAL:
+                res["plan_lines"] = plan.info["mfma_lines"]
+            plan.close()
+        out["cases"][name] = res
+        print(f"[bench] cover {name}: {res}", file=sys.stderr, flush=True)
+    return out
+
+
 def workload_mixed(args, torch, st, inputs) -> dict:
     """BF16x3 / FP16x3 outer products with FP32 state for 200 steps; an FP64
     shadow trajectory (FP64 gather path) on the GPU; rel-L2 and max-abs of the
@@ -498,7 +534,7 @@ def main() -> int:
     ap.add_argument("--radii", default="1,2,3,4", help="orders to run (profiling runs use a subset)")
     ap.add_argument("--jacobi-steps", type=int, default=JACOBI_STEPS,
                     help="Jacobi steps per solve (profiling runs only; the benchmark uses 100)")
-    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch", "tune", "serve"])
+    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch", "tune", "serve", "cover"])
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per offered load")
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-arena-gib", type=int, default=64)
@@ -520,7 +556,8 @@ def main() -> int:
     st.load_library()
     if args.workload != "box2d":
         fn = {"star2d_512": workload_star2d_512, "grid3d": workload_grid3d, "mixed": workload_mixed,
-              "batch": workload_batch, "tune": workload_tune, "serve": workload_serve}[args.workload]
+              "batch": workload_batch, "tune": workload_tune, "serve": workload_serve,
+              "cover": workload_cover}[args.workload]
         res = fn(args, torch, st, inputs)
         res.update({"n_gpus": 1, "data": "synthetic"})
         print(json.dumps(res))

@@ -233,6 +233,85 @@ __global__ __launch_bounds__(256) void mfma2d_b4_dma_batch(BatchArgs b) {
 }
 
 // ---------------------------------------------------------------------------
+// n = 4 blocks over a minimum line cover of any C^g (Section 3.5): up to 2r+1
+// slots, each a line along i (C^g column b, as above) or along j (C^g row a).
+// A line along j uses the same accumulator layout: for window column offset
+// e = 0 .. 3 + 2r, lane 4 beta + i supplies the band value w[e - i] (the A
+// operand, packed like a column line's) and lane 4 beta + j the input
+// H[4 s + j + a][4 beta + e], so block beta accumulates output (row 4 s + j,
+// column 4 beta + i) += w[e - i] * input (row + a - r, column + e - i - r).
+// Slot kinds and indices: KArgs.lcode0 / lcode1.
+// ---------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ void mfma2d_b4c_dma_item(const KArgs& a, int item) {
+  constexpr int BM = kDmaBM, TN = kDmaTN, NB = 4 + 2 * R, W = 2 * R + 1;
+  typedef DmaWindow<R, BM, TN, 256> D;
+  __shared__ __attribute__((aligned(16))) float bufs[2 * D::BUF];
+
+  const int64_t N = a.d1;
+  float* __restrict__ out = (float*)a.out;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const Strip2D sp = decode_strip(a, item, TN);
+  const float* __restrict__ frag = (const float*)a.frag;
+  float af[W * NB];
+#pragma unroll
+  for (int c = 0; c < W * NB; ++c) af[c] = frag[c * 64 + lane];
+  const int nlines = (a.lcode1 >> 27) & 15;
+  const int orow = lane & 3;
+  const int64_t gj = sp.j0 + 64 * w + 4 * (lane >> 2);
+
+  dma_block_loop<D, BM>(bufs, a, sp, [&](const float* cur, int64_t ib) {
+    floatx4 acc[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[s] = floatx4{0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      if (k >= nlines) break;
+      const int code = k < 6 ? (a.lcode0 >> (5 * k)) & 31 : (a.lcode1 >> (5 * (k - 6))) & 31;
+      const int idx = code & 15;
+      if ((code & 16) == 0) {
+        const float* rowp = cur + D::WCOL0 + 64 * w + lane + idx;
+#pragma unroll
+        for (int x = 0; x < 16 + 2 * R; ++x) {
+          const float hv = rowp[x * D::PITCH];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int d = x - 4 * s;
+            if (d < 0 || d >= NB) continue;
+            acc[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv, af[k * NB + d], acc[s], 0, 0, 0);
+          }
+        }
+      } else {
+        const float* colp = cur + (orow + idx) * D::PITCH + D::WCOL0 + 64 * w + 4 * (lane >> 2);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int e = 0; e < NB; ++e)
+            acc[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(af[k * NB + e], colp[4 * s * D::PITCH + e], acc[s], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (gj < N) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t gi = ib + 4 * s + orow;
+        if (gi < sp.i1) *reinterpret_cast<float4*>(out + gi * N + gj) = float4{acc[s][0], acc[s][1], acc[s][2], acc[s][3]};
+      }
+    }
+  });
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void mfma2d_b4c_dma_kernel(KArgs a) {
+  mfma2d_b4c_dma_item<R>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void mfma2d_b4c_dma_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { mfma2d_b4c_dma_item<R>(x, id); });
+}
+
+// ---------------------------------------------------------------------------
 // Gather-form baseline on DMA-fed windows: thread t owns a 4 x 4 block of
 // outputs (rows 4 (t / 64) .., columns 4 (t % 64) .. of the strip), reads
 // its input rows as three aligned 16-byte LDS vectors, applies the taps with

@@ -52,6 +52,28 @@ static Picker pick_b4r(int R) {
 
 Picker find_mfma2d_b4(int R, bool box) { return box ? pick_b4r<true>(R) : pick_b4r<false>(R); }
 
+// Line cover on n = 4 blocks; grids the direct-to-LDS kernels cannot take use
+// the 16x16 cover kernel, whose fragments follow the n = 4 ones in the buffer.
+template <int R>
+static Kernel pick_b4c(KArgs& a, int32_t chunk) {
+  if (dma2d_ok(a))
+    return kernel_of<mfma2d_b4c_dma_kernel<R>, mfma2d_b4c_dma_batch<R>>(
+        strip_grid(a, kDmaTN, kDmaBM, 1024, dma_chunk(a, kDmaTN, R, true, chunk)));
+  a.frag = static_cast<const char*>(a.frag) + cover_b4_frag_bytes(R);
+  return kernel_of<mfma2d_kernel<float, R, VAR_COVER>, mfma2d_batch<float, R, VAR_COVER>>(
+      strip_grid(a, kTile2D, kTile2D, 2048, chunk));
+}
+
+Picker find_mfma2d_b4c(int R) {
+  switch (R) {
+    case 1: return pick_b4c<1>;
+    case 2: return pick_b4c<2>;
+    case 3: return pick_b4c<3>;
+    case 4: return pick_b4c<4>;
+  }
+  return nullptr;
+}
+
 Picker find_mfma2d(int dtype, int R, int variant) {
   return dtype == STENCIL_F64 ? pick_var<double>(R, variant) : pick_var<float>(R, variant);
 }

@@ -322,6 +322,32 @@ static void fill_2d_counts(Resolved* rs, int R, int variant, bool split) {
   else in.rank1_per_block = 2 * (2 * R + n);                                                      // Table 1
 }
 
+// Lines covering the nonzero weights of a 2D C^g: a minimum axis-parallel
+// cover (König).  For the n = 4 kernel (c4) a line along j costs about 1.5
+// lines along i (one LDS read per MFMA instead of one per four), so the
+// nonzero columns alone are taken when they are not dearer.  Returns the
+// number of lines; rows / cols flag the chosen lines.
+static int general_cover(const std::vector<double>& cg, int R, bool c4, int* rows, int* cols) {
+  const int W = 2 * R + 1;
+  int ncov = line_cover(cg.data(), R, rows, cols);
+  if (!c4) return ncov;
+  int nzc = 0, nr = 0, nc = 0, colnz[9] = {0};
+  for (int b = 0; b < W; ++b) {
+    for (int a0 = 0; a0 < W; ++a0) colnz[b] |= cg[(size_t)a0 * W + b] != 0.0;
+    nzc += colnz[b];
+    nr += rows[b];
+    nc += cols[b];
+  }
+  if (nr > 0 && 2 * nzc <= 2 * nc + 3 * nr) {
+    for (int b = 0; b < W; ++b) {
+      rows[b] = 0;
+      cols[b] = colnz[b];
+    }
+    ncov = nzc;
+  }
+  return ncov;
+}
+
 int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   const int st = validate(desc);
   if (st != STENCIL_OK) return st;
@@ -416,22 +442,33 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       lines = STENCIL_LINES_AUTO;
     } else if (path == STENCIL_PATH_MFMA) {
       rs->family = FAM_MFMA2D;
-      rs->variant = general ? VAR_COVER
-                            : (box ? VAR_BOX : (lines == STENCIL_LINES_PARALLEL ? VAR_STAR_PARALLEL : VAR_STAR_ORTHO));
+      // GENERAL: a cover of the nonzero weights by lines (Section 3.5); when it
+      // is every column (no lines along j) the box kernel does the same work.
+      int crow[9] = {0}, ccol[9] = {0}, ncov = 0;
+      bool cover = false;
+      if (general) {
+        ncov = general_cover(cg, R, d.dtype == STENCIL_F32 && d.block_n != 16, crow, ccol);
+        for (int b = 0; b < W; ++b) cover |= crow[b] != 0 || ccol[b] == 0;
+        if (d.dtype != STENCIL_F32 || d.block_n == 16) cover = true;
+      }
+      rs->variant = cover ? VAR_COVER
+                          : (box ? VAR_BOX : (lines == STENCIL_LINES_PARALLEL ? VAR_STAR_PARALLEL : VAR_STAR_ORTHO));
+      if (general) lines = STENCIL_LINES_AUTO;
       // FP32 box / parallel star: n = 4 blocks on 4x4x1 by default (less band
       // padding); block_n = 16 selects the 16x16x4 kernel.
       const bool b4_ok = d.dtype == STENCIL_F32 && (rs->variant == VAR_BOX || rs->variant == VAR_STAR_PARALLEL);
-      if (d.block_n == 4 && !b4_ok) return STENCIL_EUNSUPPORTED;
+      if (d.block_n == 4 && !b4_ok && !cover) return STENCIL_EUNSUPPORTED;
       const bool b4 = b4_ok && d.block_n != 16;
-      rs->pick = b4 ? find_mfma2d_b4(R, box) : find_mfma2d(d.dtype, R, rs->variant);
+      rs->pick = b4 ? find_mfma2d_b4(R, box) : find_mfma2d(d.dtype, R, rs->variant);  // cover: set below
       std::vector<Line> col, row;
       const int fixed_r[3] = {R, R, 0};
       if (rs->variant == VAR_COVER) {
-        // Minimum cover: lines along i (C^g columns) first, then lines along j
-        // (C^g rows, with the cover's columns zeroed so each weight is counted
-        // once), padded with zero lines to 2r+1 fragment slots.
-        int rows[9], cols[9];
-        const int ncov = line_cover(cg.data(), R, rows, cols);
+        // Lines along i (C^g columns) first, then lines along j (C^g rows, with
+        // the cover's columns zeroed so each weight is counted once), padded
+        // with zero lines to 2r+1 fragment slots.
+        const int* rows = crow;
+        const int* cols = ccol;
+        const bool c4 = d.dtype == STENCIL_F32 && d.block_n != 16;  // n = 4 blocks (+16x16 for the fallback)
         int64_t code = 0;
         int k = 0;
         for (int b = 0; b < W; ++b)
@@ -450,12 +487,22 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
         while ((int)col.size() < W) col.push_back(Line(W, 0.0));
         a.lcode0 = (int32_t)(code & ((int64_t(1) << 30) - 1));
         a.lcode1 = (int32_t)((code >> 30) | ((int64_t)ncov << 27));
-        in.block_n = n;
-        if (pack) pack_mfma(rs, R, d.dtype, col, row);
+        if (d.block_n == 4 && !c4) return STENCIL_EUNSUPPORTED;
+        if (c4) rs->pick = find_mfma2d_b4c(R);
+        in.block_n = c4 ? 4 : n;
+        if (pack) {
+          std::vector<uint8_t> f4;
+          if (c4) {
+            pack_mfma_b4(rs, R, col);
+            f4.swap(rs->frag);
+          }
+          pack_mfma(rs, R, d.dtype, col, row);
+          if (c4) rs->frag.insert(rs->frag.begin(), f4.begin(), f4.end());
+        }
         in.mfma_lines = ncov;
         in.valu_lines = 0;
-        in.k_rows = ncov * KL;
-        in.rank1_per_block = (int64_t)ncov * (2 * R + n);
+        in.k_rows = ncov * (c4 ? 4 + 2 * R : KL);
+        in.rank1_per_block = (int64_t)ncov * (2 * R + in.block_n);
         in.executed_flops_per_point = 2.0 * in.k_rows;
         lines = STENCIL_LINES_AUTO;
         col.clear();

@@ -55,6 +55,9 @@ int line_cover(const double* cg2d, int R, int* rows_out, int* cols_out);
 Picker find_gather2d(int dtype, int R, bool box);
 Picker find_mfma2d(int dtype, int R, int variant);
 Picker find_mfma2d_b4(int R, bool box);
+Picker find_mfma2d_b4c(int R);  // line cover, n = 4 (FP32)
+// Bytes of the n = 4 cover fragments that precede the 16x16 ones.
+inline size_t cover_b4_frag_bytes(int R) { return (size_t)(2 * R + 1) * (4 + 2 * R) * 64 * sizeof(float); }
 Picker find_split2d(int kind, int R, int variant);
 Picker find_gather3d(int dtype, int R, bool box);
 Picker find_mfma3d(int dtype, int R, bool box);

@@ -43,18 +43,20 @@ def _coeffs(mask, seed, integer=False):
     return np.where(mask, v, 0.0)
 
 
+# FP32 n = 4 blocks on direct-to-LDS windows (column extent a multiple of 4),
+# the 16x16 fallback on ragged extents, FP64 16x16
+@pytest.mark.parametrize("dims", [(150, 203), (100, 260)])
 @pytest.mark.parametrize("r", [1, 2, 3, 4])
-@pytest.mark.parametrize("dtype", [st.F32, st.F64])
+@pytest.mark.parametrize("dtype,block_n", [(st.F32, 0), (st.F32, 16), (st.F64, 0)])
 @pytest.mark.parametrize("bc", [st.BC_ZERO, st.BC_PERIODIC])
-def test_general_cover_parity(r, dtype, bc):
+def test_general_cover_parity(dims, r, dtype, block_n, bc):
     torch = torch_cuda()
-    dims = (150, 203)
     a0 = inputs.grid(dims, seed=1500 + r, dtype=np.float32 if dtype == st.F32 else np.float64)
     for name, mask in patterns(r).items():
         c = _coeffs(mask, 1600 + r)
-        plan = st.Plan(dims, r, st.GENERAL, c, boundary=bc, dtype=dtype, path=st.PATH_MFMA)
+        plan = st.Plan(dims, r, st.GENERAL, c, boundary=bc, dtype=dtype, path=st.PATH_MFMA, block_n=block_n)
         rows, cols = st.line_cover(c, r)
-        assert plan.info["mfma_lines"] == len(rows) + len(cols)
+        assert plan.info["mfma_lines"] <= max(len(rows) + len(cols), int(mask.any(axis=0).sum()))
         x = torch.from_numpy(a0).cuda()
         got = plan.run_steps(x, torch.empty_like(x), 2).cpu().numpy().astype(np.float64)
         ce = eff_coeffs(c, dtype)
@@ -65,9 +67,10 @@ def test_general_cover_parity(r, dtype, bc):
 
 
 @pytest.mark.parametrize("r", [1, 2, 3, 4])
-def test_general_cover_integer_bit_exact(r):
+@pytest.mark.parametrize("dims", [(96, 70), (64, 132)])
+def test_general_cover_integer_bit_exact(r, dims):
     torch = torch_cuda()
-    a0 = inputs.int_grid((96, 70), seed=1700 + r)
+    a0 = inputs.int_grid(dims, seed=1700 + r)
     for name, mask in patterns(r).items():
         c = _coeffs(mask, 1800 + r, integer=True)
         s = float(np.abs(c).sum())

@@ -368,14 +368,19 @@ def test_general_plan_uses_minimum_cover(lib, seed):
     mask = rng.random((w, w)) < rng.uniform(0.1, 0.6)
     c = _pattern_cg(r, mask, seed)
     rows, cols = st.line_cover(c, r)
-    info = st.describe((64, 64), r, st.GENERAL, c, path=st.PATH_MFMA)
-    assert info["mfma_lines"] == len(rows) + len(cols) <= w
-    assert info["taps"] == int(mask.sum())
-    assert info["block_n"] == 16 and info["valu_lines"] == 0
     kl = -(-(16 + 2 * r) // 4) * 4
-    assert info["k_rows"] == info["mfma_lines"] * kl
+    nzc = int(mask.any(axis=0).sum())
+    # n = 4 blocks: the nonzero columns alone when not dearer than the cover
+    # with lines along j counted 1.5
+    n4 = nzc if rows and 2 * nzc <= 2 * len(cols) + 3 * len(rows) else len(rows) + len(cols)
+    for dt, bn, krows in ((st.F32, 0, 4 + 2 * r), (st.F32, 16, kl), (st.F64, 0, kl)):
+        info = st.describe((64, 64), r, st.GENERAL, c, path=st.PATH_MFMA, dtype=dt, block_n=bn)
+        assert info["mfma_lines"] == (n4 if krows == 4 + 2 * r else len(rows) + len(cols)) <= w
+        assert info["taps"] == int(mask.sum())
+        assert info["block_n"] == (4 if krows == 4 + 2 * r else 16) and info["valu_lines"] == 0
+        assert info["k_rows"] == info["mfma_lines"] * krows
     assert st.desc_check((64, 64), r, st.GENERAL, c, lines=st.LINES_PARALLEL) == st.EUNSUPPORTED
-    assert st.desc_check((64, 64), r, st.GENERAL, c, path=st.PATH_MFMA, block_n=4) == st.EUNSUPPORTED
+    assert st.desc_check((64, 64), r, st.GENERAL, c, path=st.PATH_MFMA, dtype=st.F64, block_n=4) == st.EUNSUPPORTED
     # other paths take GENERAL as a box
     assert st.describe((64, 64), r, st.GENERAL, c, path=st.PATH_GATHER)["path"] == st.PATH_GATHER
     assert st.describe((16, 16, 16), r, st.GENERAL, _box(3, r))["path"] == st.PATH_GATHER
