@@ -215,7 +215,9 @@ def workload_batch(args, torch, st, inputs) -> dict:
     """Many small FP64 grids of the paper's Table 3 shapes (2D box/star r = 1..3
     at 64^2..512^2, 3D box r = 1, 2 and star r = 1..3 at 8^3..64^3), zero halo,
     10 Jacobi steps: one batched launch per step over 2^24 points of grids of
-    one size (a shared plan), against launching the grids one by one."""
+    one size (a shared plan), for the outer-product (MFMA) and the gather
+    path -- their ratio is the MI355X counterpart of Table 3's speedups --
+    and, for the AUTO plan, against launching the grids one by one."""
     steps = 10
     total_pts = 1 << 24
     stream = torch.cuda.Stream()
@@ -223,6 +225,21 @@ def workload_batch(args, torch, st, inputs) -> dict:
            "zero halo, 10 Jacobi steps", "cases": {}}
     cases = [(2, st.BOX, r) for r in (1, 2, 3)] + [(2, st.STAR, r) for r in (1, 2, 3)]
     cases += [(3, st.BOX, r) for r in (1, 2)] + [(3, st.STAR, r) for r in (1, 2, 3)]
+
+    def timed(batch):
+        for _ in range(max(args.warmup, 1)):
+            batch.run_steps(steps, stream=stream)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(max(args.steps, 3)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            batch.run_steps(steps, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return total_pts * steps / (np.median(times) * 1e-3) / 1e9
+
     for nd, shape, r in cases:
         sizes = (64, 128, 256, 512) if nd == 2 else (8, 16, 32, 64)
         for n in sizes:
@@ -230,52 +247,48 @@ def workload_batch(args, torch, st, inputs) -> dict:
             pts = n ** nd
             count = total_pts // pts
             c = inputs.coefficients(nd, r, shape, seed=8000 + 10 * nd + r + 100 * shape, dtype=np.float64)
-            plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=st.F64)
             a0 = torch.from_numpy(inputs.grid((count,) + dims, seed=8001, dtype=np.float64)).cuda()
-            b0 = a0.clone()
-            b1 = torch.empty_like(b0)
-            batch = st.Batch([plan] * count, list(b0.unbind(0)), list(b1.unbind(0)))
-            for _ in range(max(args.warmup, 1)):
-                batch.run_steps(steps, stream=stream)
-            torch.cuda.synchronize()
-            times = []
-            for _ in range(max(args.steps, 3)):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                batch.run_steps(steps, stream=stream)
-                e1.record(stream)
-                torch.cuda.synchronize()
-                times.append(e0.elapsed_time(e1))
-            g_batch = total_pts * steps / (np.median(times) * 1e-3) / 1e9
-            # one by one: a sample of the grids, each launched eagerly step by step
-            ns = min(count, 64)
-            x = a0[:ns].clone()
-            y = torch.empty_like(x)
-            os.environ["STENCIL_NO_GRAPH"] = "1"
-            try:
-                for k in range(ns):
-                    plan.run_steps(x[k], y[k], steps, stream=stream)
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                for k in range(ns):
-                    plan.run_steps(x[k], y[k], steps, stream=stream)
-                e1.record(stream)
-                torch.cuda.synchronize()
-            finally:
-                del os.environ["STENCIL_NO_GRAPH"]
-            g_single = ns * pts * steps / (e0.elapsed_time(e1) * 1e-3) / 1e9
             key = f"{nd}d_{'box' if shape == st.BOX else 'star'}_r{r}_{n}"
-            info = batch.info()
-            out["cases"][key] = {"grids": count, "batched_gstencil_s": round(g_batch, 2),
-                                 "one_by_one_gstencil_s": round(g_single, 2),
-                                 "speedup": round(g_batch / g_single, 2), "path": st.PATH_NAMES[plan.info["path"]],
-                                 "items": info["items"], "workgroups": info["blocks"]}
-            print(f"[bench] batch {key}: {g_batch:.1f} GStencil/s batched, {g_single:.2f} one by one "
-                  f"({count} grids)", file=sys.stderr, flush=True)
-            batch.close()
-            plan.close()
-            del a0, b0, b1, x, y
+            entry = {"grids": count}
+            for name, path in (("mfma", st.PATH_MFMA), ("gather", st.PATH_GATHER), ("auto", st.PATH_AUTO)):
+                plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=st.F64, path=path)
+                b0 = a0.clone()
+                b1 = torch.empty_like(b0)
+                batch = st.Batch([plan] * count, list(b0.unbind(0)), list(b1.unbind(0)))
+                entry[f"{name}_batched_gstencil_s"] = round(timed(batch), 2)
+                if name == "auto":
+                    info = batch.info()
+                    entry.update({"auto_path": st.PATH_NAMES[plan.info["path"]], "items": info["items"],
+                                  "workgroups": info["blocks"]})
+                    # one by one: a sample of the grids, each launched eagerly step by step
+                    ns = min(count, 64)
+                    x = a0[:ns].clone()
+                    y = torch.empty_like(x)
+                    os.environ["STENCIL_NO_GRAPH"] = "1"
+                    try:
+                        for k in range(ns):
+                            plan.run_steps(x[k], y[k], steps, stream=stream)
+                        torch.cuda.synchronize()
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record(stream)
+                        for k in range(ns):
+                            plan.run_steps(x[k], y[k], steps, stream=stream)
+                        e1.record(stream)
+                        torch.cuda.synchronize()
+                    finally:
+                        del os.environ["STENCIL_NO_GRAPH"]
+                    entry["auto_one_by_one_gstencil_s"] = round(ns * pts * steps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 3)
+                    del x, y
+                batch.close()
+                plan.close()
+                del b0, b1
+            entry["mfma_vs_gather"] = round(entry["mfma_batched_gstencil_s"] / entry["gather_batched_gstencil_s"], 3)
+            entry["batched_vs_one_by_one"] = round(entry["auto_batched_gstencil_s"] / entry["auto_one_by_one_gstencil_s"], 1)
+            out["cases"][key] = entry
+            print(f"[bench] batch {key}: mfma {entry['mfma_batched_gstencil_s']:.1f}, gather "
+                  f"{entry['gather_batched_gstencil_s']:.1f} GStencil/s batched (x{entry['mfma_vs_gather']}); auto one by "
+                  f"one {entry['auto_one_by_one_gstencil_s']:.2f} ({count} grids)", file=sys.stderr, flush=True)
+            del a0
             torch.cuda.empty_cache()
     return out
 

@@ -6,14 +6,10 @@
 // LDS with its in-plane halo and scattered into the 2r+1 output planes it
 // reaches, whose accumulators form a ring in registers (the i-direction
 // unrolling of Section 4.2: an input element is loaded once and used by all
-// its neighbours along i).  When input plane i has been scattered, output
-// plane i - r is complete: it is stored and its ring slot reset.
-//
-// Ring slot of output plane o: (o - ib + 2r) mod (2r+1).  With the input
-// counter u = i - ib + r unrolled in groups of 2r+1 (u = G (2r+1) + uu), the
-// slot reached through coefficient plane a (o = i - a + r) is
-// (uu + 2r - a) mod (2r+1) and the completed plane sits in slot uu: all slot
-// indices are compile-time constants.
+// its neighbours along i).  While input plane i is scattered, ring slot z
+// holds output plane i - r + z, so coefficient plane a (output plane
+// i - a + r) goes to the compile-time slot 2r - a; afterwards output plane
+// i - r is complete in slot 0: it is stored and the ring shifts down by one.
 //
 // Staging: with DMA = true the window of plane i+1 is loaded straight into
 // LDS (dma3d.hpp) while plane i is computed; otherwise (extents or pointers
@@ -53,11 +49,7 @@ __device__ __forceinline__ Chunk3D decode_chunk(const KArgs& a, int id) {
 
 // Walk the input planes of a chunk.  LROWS window rows (global j0 - r ..) of
 // each plane are staged into a buffer of pitch PITCH, window column y at LDS
-// column COL0 + y; body(win, uu, valid) scatters the plane (win = window base,
-// uu = compile-time ring phase, valid = false for a zero-halo plane outside
-// the grid); store(uu, o, live) writes completed output plane o from slot uu
-// when live (o >= ib; warm-up planes reach outputs below the chunk) and always
-// resets the slot for the output plane that reuses it.
+// column COL0 + y.
 template <typename T, int R, int LROWS, bool DMA, bool BODY4 = false>
 struct PlaneWalk {
   static constexpr int W = 2 * R + 1;
@@ -69,57 +61,11 @@ struct PlaneWalk {
   static constexpr int BUF = DMA ? D::BUF : LROWS * PITCH;  // elements per buffer
   static constexpr int NBUF = DMA ? 2 : 1;
 
-  template <class Body, class Store>
-  static __device__ __forceinline__ void run(T* bufs, const KArgs& a, const Chunk3D& ch, Body body, Store store) {
-    const int64_t Ni = a.d0, Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
-    const bool periodic = a.periodic != 0;
-    const T* __restrict__ in = (const T*)a.in;
-    const T* __restrict__ zeros = (const T*)a.zeros;
-    const int nu = (int)(ch.iend - ch.ib) + 2 * R;
-    typename D::Lines lines;
-    if constexpr (DMA) {
-      D::prepare(lines, Nj, Nk, ch.j0 - R, ch.k0, periodic);
-      const int64_t g0 = map_index(ch.ib - R, Ni, periodic);
-      D::issue(bufs, g0 >= 0 ? in + g0 * plane : nullptr, zeros, lines);
-    } else {
-      // rows and columns past the window (K padding of the MFMA kernels) carry zero weights
-      zero_region<T, kThreads>(bufs, LROWS, PITCH, PITCH, 0, 0);
-    }
-    for (int ug = 0; ug < nu; ug += W) {
-#pragma unroll
-      for (int uu = 0; uu < W; ++uu) {
-        const int u = ug + uu;
-        if (u >= nu) break;
-        const int64_t gi = map_index(ch.ib - R + u, Ni, periodic);
-        const T* win;
-        if constexpr (DMA) {
-          win = bufs + (u & 1) * BUF;
-          if (u + 1 < nu) {
-            const int64_t g1 = map_index(ch.ib - R + u + 1, Ni, periodic);
-            D::issue(bufs + ((u + 1) & 1) * BUF, g1 >= 0 ? in + g1 * plane : nullptr, zeros, lines);
-            D::template wait_vm<D::NPW>();
-          } else {
-            D::template wait_vm<0>();
-          }
-          __syncthreads();
-        } else {
-          win = bufs;
-          __syncthreads();
-          if (gi >= 0)
-            stage_window<T, R, kTJ + 2 * R, kTK, PITCH, kThreads, COL0>(bufs, in + gi * plane, Nj, Nk, ch.j0 - R,
-                                                                       ch.k0, periodic);
-          __syncthreads();
-        }
-        body(win, uu, gi >= 0);
-        store(uu, ch.ib + u - 2 * R, u >= 2 * R);
-        if constexpr (DMA) __syncthreads();
-      }
-    }
-  }
-
-  // The same walk without the ring-phase unrolling: body(win, valid) then
-  // finish(o, live) once per input plane; the caller keeps its ring in a
-  // fixed order and rotates it in finish.
+  // body(win, valid) scatters input plane i (win = its window; valid = false
+  // for a zero-halo plane outside the grid), then finish(o, live) completes
+  // output plane o = i - r (live = o lies in the chunk; warm-up planes reach
+  // outputs below it): the caller stores its ring's slot 0 when live and
+  // shifts the ring down by one.
   template <class Body, class Finish>
   static __device__ __forceinline__ void walk(T* bufs, const KArgs& a, const Chunk3D& ch, Body body, Finish finish) {
     const int64_t Ni = a.d0, Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
@@ -132,6 +78,10 @@ struct PlaneWalk {
       D::prepare(lines, Nj, Nk, ch.j0 - R, ch.k0, periodic);
       const int64_t g0 = map_index(ch.ib - R, Ni, periodic);
       D::issue(bufs, g0 >= 0 ? in + g0 * plane : nullptr, zeros, lines);
+    } else {
+      // rows and columns past the window (K padding of the MFMA kernels) are
+      // read with zero weights: keep them finite
+      zero_region<T, kThreads>(bufs, LROWS, PITCH, PITCH, 0, 0);
     }
     for (int u = 0; u < nu; ++u) {
       const int64_t gi = map_index(ch.ib - R + u, Ni, periodic);
@@ -383,16 +333,19 @@ __device__ __forceinline__ void mfma3d_item(const KArgs& a, int item) {
     ring[z][0] = acc_t{};
     ring[z][1] = acc_t{};
   }
-  PW::run(
+  // ring[z] accumulates output plane i - r + z while input plane i is
+  // scattered (coefficient plane a reaches z = 2r - a); then ring[0] is
+  // complete and the ring shifts down by one.
+  PW::walk(
       bufs, a, ch,
-      [&](const T* win, int uu, bool valid) {
+      [&](const T* win, bool valid) {
         if (!valid) return;
         const T* colbase = win + (16 * wj + g) * PW::PITCH + PW::COL0 + 32 * wk + q;
         const T* rowbase = win + (16 * wj + R + q) * PW::PITCH + PW::COL0 + 32 * wk + g;
         if constexpr (BOX) {
 #pragma unroll
           for (int ap = 0; ap < W; ++ap) {
-            const int slot = (uu + 2 * R - ap) % W;
+            const int slot = 2 * R - ap;
 #pragma unroll
             for (int cs = 0; cs < W; ++cs) {
 #pragma unroll
@@ -407,7 +360,7 @@ __device__ __forceinline__ void mfma3d_item(const KArgs& a, int item) {
             }
           }
         } else {
-          const int slot = (uu + R) % W;
+          const int slot = R;
 #pragma unroll
           for (int cc = 0; cc < S::CPL; ++cc) {
             const T av = af[cc];
@@ -436,24 +389,31 @@ __device__ __forceinline__ void mfma3d_item(const KArgs& a, int item) {
 #pragma unroll
               for (int ap = 0; ap < W; ++ap) {
                 if (ap == R) continue;
-                ring[(uu + 2 * R - ap) % W][t][v] += ci[ap] * ctr;
+                ring[2 * R - ap][t][v] += ci[ap] * ctr;
               }
             }
           }
         }
       },
-      [&](int uu, int64_t o, bool live) {
+      [&](int64_t o, bool live) {
+        if (live) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t gj = ch.j0 + 16 * wj + MM::row(lane, v);
+          for (int v = 0; v < 4; ++v) {
+            const int64_t gj = ch.j0 + 16 * wj + MM::row(lane, v);
 #pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            const int64_t gk = ch.k0 + 32 * wk + 16 * t + MM::col(lane);
-            if (live && gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = ring[uu][t][v];
+            for (int t = 0; t < 2; ++t) {
+              const int64_t gk = ch.k0 + 32 * wk + 16 * t + MM::col(lane);
+              if (gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = ring[0][t][v];
+            }
           }
         }
-        ring[uu][0] = acc_t{};
-        ring[uu][1] = acc_t{};
+#pragma unroll
+        for (int z = 0; z < 2 * R; ++z) {
+          ring[z][0] = ring[z + 1][0];
+          ring[z][1] = ring[z + 1][1];
+        }
+        ring[2 * R][0] = acc_t{};
+        ring[2 * R][1] = acc_t{};
       });
 }
 
@@ -526,17 +486,24 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
   const float lo_mul = 1.0f / a.lo_scale;
   const float ls = a.lo_scale, os = a.out_scale;
 
-  floatx4 acc[W][2], acx[W][2];
+  // Box: every ring slot takes MFMA products, so the cross terms (hi*lo +
+  // lo*hi) keep a ring of their own.  Star: only the centre plane's slot takes
+  // the k line's products, so its cross terms are folded into acc at once.
+  constexpr int WX = BOX ? W : 1;
+  floatx4 acc[W][2], acx[WX][2];
 #pragma unroll
   for (int z = 0; z < W; ++z)
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      acc[z][t] = floatx4{0, 0, 0, 0};
-      acx[z][t] = floatx4{0, 0, 0, 0};
-    }
-  PW::run(
+    for (int t = 0; t < 2; ++t) acc[z][t] = floatx4{0, 0, 0, 0};
+#pragma unroll
+  for (int z = 0; z < WX; ++z)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acx[z][t] = floatx4{0, 0, 0, 0};
+  // ring slot z holds output plane i - r + z while input plane i is
+  // scattered; slot 0 is stored after the plane and the ring shifts down
+  PW::walk(
       bufs, a, ch,
-      [&](const float* win, int uu, bool valid) {
+      [&](const float* win, bool valid) {
         if (!valid) return;
         // split the FP32 window into hi/lo planes
         constexpr int HALF = S::WEND / 2;
@@ -553,7 +520,7 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
 #pragma unroll
         for (int ap = 0; ap < W; ++ap) {
           if (!BOX && ap != R) continue;
-          const int slot = (uu + 2 * R - ap) % W;
+          const int slot = 2 * R - ap;
 #pragma unroll
           for (int b = 0; b < W; ++b) {
             if (!BOX && b != R) continue;
@@ -564,10 +531,18 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
             for (int t = 0; t < 2; ++t) {
               const u16x8 ah = *reinterpret_cast<const u16x8*>(ph + 16 * t);
               const u16x8 al = *reinterpret_cast<const u16x8*>(pl + 16 * t);
+              const int xs = BOX ? slot : 0;
               acc[slot][t] = Split16<KIND>::mma(ah, bh[l], acc[slot][t]);
-              acx[slot][t] = Split16<KIND>::mma(ah, bl[l], acx[slot][t]);
-              acx[slot][t] = Split16<KIND>::mma(al, bh[l], acx[slot][t]);
+              acx[xs][t] = Split16<KIND>::mma(ah, bl[l], acx[xs][t]);
+              acx[xs][t] = Split16<KIND>::mma(al, bh[l], acx[xs][t]);
             }
+          }
+        }
+        if constexpr (!BOX) {
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            acc[R][t] += ls * acx[0][t];
+            acx[0][t] = floatx4{0, 0, 0, 0};
           }
         }
         if constexpr (!BOX) {
@@ -582,31 +557,41 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
                 if (b == R) continue;
                 sj += cj[b] * cp[b * PW::PITCH + 16 * t];
               }
-              acc[(uu + R) % W][t][v] += sj;
+              acc[R][t][v] += sj;
               const float ctr = cp[R * PW::PITCH + 16 * t];
 #pragma unroll
               for (int ap = 0; ap < W; ++ap) {
                 if (ap == R) continue;
-                acc[(uu + 2 * R - ap) % W][t][v] += ci[ap] * ctr;
+                acc[2 * R - ap][t][v] += ci[ap] * ctr;
               }
             }
           }
         }
       },
-      [&](int uu, int64_t o, bool live) {
+      [&](int64_t o, bool live) {
+        if (live) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t gj = ch.j0 + 16 * wj + 4 * g + v;
+          for (int v = 0; v < 4; ++v) {
+            const int64_t gj = ch.j0 + 16 * wj + 4 * g + v;
 #pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            const int64_t gk = ch.k0 + 32 * wk + 16 * t + q;
-            if (live && gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = (acc[uu][t][v] + ls * acx[uu][t][v]) * os;
+            for (int t = 0; t < 2; ++t) {
+              const int64_t gk = ch.k0 + 32 * wk + 16 * t + q;
+              const float v0 = BOX ? acc[0][t][v] + ls * acx[0][t][v] : acc[0][t][v];
+              if (gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = v0 * os;
+            }
           }
         }
 #pragma unroll
+        for (int z = 0; z < 2 * R; ++z)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            acc[z][t] = acc[z + 1][t];
+            if constexpr (BOX) acx[z][t] = acx[z + 1][t];
+          }
+#pragma unroll
         for (int t = 0; t < 2; ++t) {
-          acc[uu][t] = floatx4{0, 0, 0, 0};
-          acx[uu][t] = floatx4{0, 0, 0, 0};
+          acc[2 * R][t] = floatx4{0, 0, 0, 0};
+          if constexpr (BOX) acx[2 * R][t] = floatx4{0, 0, 0, 0};
         }
       });
 }
