@@ -428,6 +428,130 @@ __global__ __launch_bounds__(kThreads) void mfma3d_batch(BatchArgs b) {
 }
 
 // ---------------------------------------------------------------------------
+// Outer-product form on n = 4 blocks (v_mfma_f32_4x4x1_16b_f32, FP32), as the
+// 2D kernel of dma2d.hpp: wave w owns tile rows 8 w .. 8 w + 7 (two 4-row
+// blocks s) and all 64 columns; block beta of an instruction holds output
+// (row 4 s + j, column 4 beta + i), lane 4 beta + j owning four consecutive
+// columns.  Lines along j (CLS(a, *, c)): A = input row segment of window
+// row x (column lane + c), B = band value w[x - 4 s - j].  Line along k
+// (CLS(r, r, *), centre excluded): A = band value w[e - i], B = input
+// H[4 s + j + r][4 beta + e].  Star: the j and k lines through the centre on
+// MFMA, the i arm as vector FMAs into the other ring slots.  Box: the 27-point
+// box (r = 1), all nine lines along j.
+// ---------------------------------------------------------------------------
+template <int R, bool BOX, bool DMA>
+__device__ __forceinline__ void mfma3d_b4_item(const KArgs& a, int item) {
+  constexpr int W = 2 * R + 1, NB = 4 + 2 * R, NL = BOX ? W * W : 2;
+  typedef PlaneWalk<float, R, kTJ + 2 * R, DMA, true> PW;
+  static_assert(PW::COL0 + R == 4, "tile body at LDS column 4");
+  __shared__ __attribute__((aligned(16))) float bufs[PW::NBUF * PW::BUF];
+
+  const Chunk3D ch = decode_chunk(a, item);
+  const int64_t Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
+  float* __restrict__ out = (float*)a.out;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int orow = lane & 3, beta = lane >> 2;
+
+  const float* __restrict__ frag = (const float*)a.frag;
+  float af[NL * NB];
+#pragma unroll
+  for (int c = 0; c < NL * NB; ++c) af[c] = frag[c * 64 + lane];
+  float ci[W];  // star: i-arm weights C^g[a][r][r]
+  if constexpr (!BOX) {
+    const float* __restrict__ c = (const float*)a.coef;
+#pragma unroll
+    for (int ap = 0; ap < W; ++ap) ci[ap] = c[(ap * W + R) * W + R];
+  }
+
+  // ring[z][s]: output plane i - r + z while input plane i is scattered
+  floatx4 ring[W][2];
+#pragma unroll
+  for (int z = 0; z < W; ++z)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) ring[z][t] = floatx4{0, 0, 0, 0};
+
+  PW::walk(
+      bufs, a, ch,
+      [&](const float* win, bool valid) {
+        if (!valid) return;
+        // lines along j: CLS(ap, *, cs) into slot 2r - ap
+#pragma unroll
+        for (int l = 0; l < (BOX ? W * W : 1); ++l) {
+          const int ap = BOX ? l / W : R, cs = BOX ? l % W : R;
+          const float* rowp = win + (8 * w) * PW::PITCH + PW::COL0 + lane + cs;
+#pragma unroll
+          for (int x = 0; x < 8 + 2 * R; ++x) {
+            const float hv = rowp[x * PW::PITCH];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+              const int d = x - 4 * s;
+              if (d < 0 || d >= NB) continue;
+              ring[2 * R - ap][s] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv, af[l * NB + d], ring[2 * R - ap][s], 0, 0, 0);
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (!BOX) {
+          // line along k through the centre (row offset r), centre excluded
+          const float* colp = win + (8 * w + orow + R) * PW::PITCH + PW::COL0 + 4 * beta;
+#pragma unroll
+          for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int e = 0; e < NB; ++e)
+              ring[R][s] = __builtin_amdgcn_mfma_f32_4x4x1f32(af[NB + e], colp[4 * s * PW::PITCH + e], ring[R][s], 0, 0, 0);
+          // i arm: this plane's centre values reach output plane i - ap + r
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const float4 ctr =
+                *reinterpret_cast<const float4*>(win + (8 * w + 4 * s + orow + R) * PW::PITCH + 4 + 4 * beta);
+#pragma unroll
+            for (int ap = 0; ap < W; ++ap) {
+              if (ap == R) continue;
+              ring[2 * R - ap][s][0] += ci[ap] * ctr.x;
+              ring[2 * R - ap][s][1] += ci[ap] * ctr.y;
+              ring[2 * R - ap][s][2] += ci[ap] * ctr.z;
+              ring[2 * R - ap][s][3] += ci[ap] * ctr.w;
+            }
+          }
+        }
+      },
+      [&](int64_t o, bool live) {
+        if (live) {
+          const int64_t gk = ch.k0 + 4 * beta;
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const int64_t gj = ch.j0 + 8 * w + 4 * s + orow;
+            if (gj >= Nj) continue;
+            float* dst = out + o * plane + gj * Nk + gk;
+            if constexpr (DMA) {  // k extent a multiple of 4, output 16-byte aligned
+              if (gk < Nk) *reinterpret_cast<float4*>(dst) = float4{ring[0][s][0], ring[0][s][1], ring[0][s][2], ring[0][s][3]};
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (gk + e < Nk) dst[e] = ring[0][s][e];
+            }
+          }
+        }
+#pragma unroll
+        for (int z = 0; z < 2 * R; ++z)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) ring[z][t] = ring[z + 1][t];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) ring[2 * R][t] = floatx4{0, 0, 0, 0};
+      });
+}
+
+template <int R, bool BOX, bool DMA>
+__global__ __launch_bounds__(kThreads) void mfma3d_b4_kernel(KArgs a) {
+  mfma3d_b4_item<R, BOX, DMA>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <int R, bool BOX, bool DMA>
+__global__ __launch_bounds__(kThreads) void mfma3d_b4_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { mfma3d_b4_item<R, BOX, DMA>(x, id); });
+}
+
+// ---------------------------------------------------------------------------
 // Outer-product form with 16-bit split operands (see kernels_split2d.hpp) in
 // the plane order of Algorithm 1.  Lines run along k: CLS(a, b, *) adds
 // D[p][q] += sum_y H[p + b][y] * S_{a,b}[y][q], S_{a,b}[y][q] = C^g[a][b][y - q],

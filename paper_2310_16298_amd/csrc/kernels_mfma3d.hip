@@ -31,6 +31,25 @@ static Picker pick(int R, bool box) {
   return nullptr;
 }
 
+// n = 4 blocks (FP32): stars r = 1..4 and the 27-point box
+template <int R, bool BOX>
+static Kernel pick_mfma3d_b4(KArgs& a, int32_t) {
+  const int64_t items = chunk3d_items(a);
+  if (dma3d_ok<float>(a)) return kernel_of<mfma3d_b4_kernel<R, BOX, true>, mfma3d_b4_batch<R, BOX, true>>(items);
+  return kernel_of<mfma3d_b4_kernel<R, BOX, false>, mfma3d_b4_batch<R, BOX, false>>(items);
+}
+
+Picker find_mfma3d_b4(int R, bool box) {
+  if (box) return R == 1 ? pick_mfma3d_b4<1, true> : nullptr;
+  switch (R) {
+    case 1: return pick_mfma3d_b4<1, false>;
+    case 2: return pick_mfma3d_b4<2, false>;
+    case 3: return pick_mfma3d_b4<3, false>;
+    case 4: return pick_mfma3d_b4<4, false>;
+  }
+  return nullptr;
+}
+
 Picker find_mfma3d(int dtype, int R, bool box) {
   return dtype == STENCIL_F64 ? pick<double>(R, box) : pick<float>(R, box);
 }

@@ -592,9 +592,23 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
         in.valu_lines = 2 * R;
         in.rank1_per_block = 2 * (2 * R + n) + (int64_t)2 * R * n;  // Table 2, hybrid
       }
-      if (pack) pack_mfma(rs, R, d.dtype, col, row);
-      else in.k_rows = (int)(col.size() + row.size()) * KL;
-      in.block_n = n;
+      // FP32 stars and the 27-point box: n = 4 blocks by default (block_n = 16:
+      // the 16x16x4 kernel)
+      const bool b4 = d.dtype == STENCIL_F32 && (!box || R == 1) && d.block_n != 16;
+      if (d.block_n == 4 && !b4) return STENCIL_EUNSUPPORTED;
+      if (b4) {
+        rs->pick = find_mfma3d_b4(R, box);
+        std::vector<Line> lines4(col);
+        lines4.insert(lines4.end(), row.begin(), row.end());
+        if (pack) pack_mfma_b4(rs, R, lines4);
+        in.k_rows = (int)lines4.size() * (4 + 2 * R);
+        in.block_n = 4;
+        in.rank1_per_block = box ? (int64_t)W * W * (2 * R + 4) : 2 * (2 * R + 4) + (int64_t)2 * R * 4;
+      } else {
+        if (pack) pack_mfma(rs, R, d.dtype, col, row);
+        else in.k_rows = (int)(col.size() + row.size()) * KL;
+        in.block_n = n;
+      }
       in.executed_flops_per_point = 2.0 * in.k_rows + 2.0 * in.valu_lines;
     } else {
       if (!box && lines != STENCIL_LINES_PARALLEL) return STENCIL_EUNSUPPORTED;

@@ -61,6 +61,7 @@ inline size_t cover_b4_frag_bytes(int R) { return (size_t)(2 * R + 1) * (4 + 2 *
 Picker find_split2d(int kind, int R, int variant);
 Picker find_gather3d(int dtype, int R, bool box);
 Picker find_mfma3d(int dtype, int R, bool box);
+Picker find_mfma3d_b4(int R, bool box);  // FP32 n = 4 blocks: stars, 27-point box
 Picker find_split3d(int kind, int R, bool box);
 Picker find_tb2d(int dtype, int R, bool box);
 int tb2d_max_steps(int dtype, int R);  // largest time_block of the time-blocked kernel

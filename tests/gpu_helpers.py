@@ -44,14 +44,15 @@ def error_bound(c_eff, ndim, r, shape, dtype, path, steps, amax):
     return 2.0 * steps * (gamma + u + eps_p) * s ** steps * amax + 1e-300
 
 
-def run_gpu(a0, coeffs, radius, shape, bc, dtype, path, steps, lines=st.LINES_AUTO, check_info=True):
-    """Final state after `steps` Jacobi steps on the GPU (numpy FP64)."""
+def run_gpu(a0, coeffs, radius, shape, bc, dtype, path, steps, lines=st.LINES_AUTO, check_info=True, **plan_kw):
+    """Final state after `steps` Jacobi steps on the GPU (numpy FP64);
+    plan_kw: further Plan knobs (block_n, chunk, ...)."""
     torch = torch_cuda()
     tdt = torch.float64 if dtype == st.F64 else torch.float32
     ndt = np.float64 if dtype == st.F64 else np.float32
     x = torch.from_numpy(np.ascontiguousarray(a0, dtype=ndt)).cuda()
     tmp = torch.empty_like(x)
-    plan = st.Plan(a0.shape, radius, shape, coeffs, boundary=bc, dtype=dtype, path=path, lines=lines)
+    plan = st.Plan(a0.shape, radius, shape, coeffs, boundary=bc, dtype=dtype, path=path, lines=lines, **plan_kw)
     if check_info and path != st.PATH_AUTO:
         assert plan.info["path"] == path
     res = plan.run_steps(x, tmp, steps)

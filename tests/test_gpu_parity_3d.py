@@ -118,3 +118,19 @@ def test_dma_plane_integer_bit_exact(path, dtype, shape, r):
     for bc in (st.BC_ZERO, st.BC_PERIODIC):
         assert np.array_equal(run_gpu(a0, c, r, shape, bc, dtype, path, steps),
                               oracle.run(a0, c, r, shape, bc, steps))
+
+
+@pytest.mark.parametrize("shape,r", [(st.STAR, 1), (st.STAR, 2), (st.STAR, 3), (st.STAR, 4), (st.BOX, 1), (st.BOX, 2)])
+@pytest.mark.parametrize("dims", [(37, 45, 77), (21, 45, 132)])
+def test_mfma_fp32_block_edges(shape, r, dims):
+    """FP32 outer products on n = 4 blocks (default) and on 16x16 blocks
+    (block_n = 16), synchronous and direct-to-LDS staging (k extent 77 / 132)."""
+    c = inputs.coefficients(3, r, shape, seed=700 + r, dtype=np.float64)
+    ce = eff_coeffs(c, st.F32)
+    a0 = inputs.grid(dims, seed=701 + r)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        want = oracle.run(a0, ce, r, shape, bc, 3)
+        tol = error_bound(ce, 3, r, shape, st.F32, st.PATH_MFMA, 3, np.abs(a0).max())
+        for bn in ((0, 16) if shape == st.STAR or r == 1 else (16,)):
+            got = run_gpu(a0, c, r, shape, bc, st.F32, st.PATH_MFMA, 3, block_n=bn)
+            assert np.abs(got - want).max() <= tol, (bn, bc, np.abs(got - want).max(), tol)

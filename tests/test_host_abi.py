@@ -384,3 +384,20 @@ def test_general_plan_uses_minimum_cover(lib, seed):
     # other paths take GENERAL as a box
     assert st.describe((64, 64), r, st.GENERAL, c, path=st.PATH_GATHER)["path"] == st.PATH_GATHER
     assert st.describe((16, 16, 16), r, st.GENERAL, _box(3, r))["path"] == st.PATH_GATHER
+
+
+
+def test_3d_mfma_block_edge(lib):
+    """FP32 3D outer products default to n = 4 blocks for stars and the
+    27-point box (executed flops 2 (2r+4) per line and point), FP64 and the
+    r = 2 box use 16x16 blocks."""
+    for r in (1, 2, 3, 4):
+        s = inputs.coefficients(3, r, inputs.STAR, seed=5, dtype=np.float64)
+        info = st.describe((20, 20, 20), r, inputs.STAR, s, path=st.PATH_MFMA)
+        assert info["block_n"] == 4 and info["k_rows"] == 2 * (2 * r + 4) and info["valu_lines"] == 2 * r
+        assert st.describe((20, 20, 20), r, inputs.STAR, s, path=st.PATH_MFMA, block_n=16)["block_n"] == 16
+        assert st.describe((20, 20, 20), r, inputs.STAR, s, path=st.PATH_MFMA, dtype=st.F64)["block_n"] == 16
+    b1 = st.describe((20, 20, 20), 1, inputs.BOX, _box(3, 1), path=st.PATH_MFMA)
+    assert b1["block_n"] == 4 and b1["k_rows"] == 9 * 6
+    assert st.describe((20, 20, 20), 2, inputs.BOX, _box(3, 2), path=st.PATH_MFMA)["block_n"] == 16
+    assert st.desc_check((20, 20, 20), 2, inputs.BOX, _box(3, 2), path=st.PATH_MFMA, block_n=4) == st.EUNSUPPORTED
