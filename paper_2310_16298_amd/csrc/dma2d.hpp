@@ -1,4 +1,4 @@
-// Asynchronous window loads for the FP32 2D kernels (gfx950 direct-to-LDS).
+// Asynchronous window loads for the 2D kernels (gfx950 direct-to-LDS).
 //
 // A workgroup walks a strip of TN columns in blocks of BM rows.  The input
 // window of a block -- rows [ib - r, ib + BM + r), columns [j0 - 4, j0 + TN + 4)
@@ -6,8 +6,9 @@
 // global_load_lds_dwordx4 (16 bytes per lane, 1 KiB per wave instruction, no
 // registers), into one of two buffers, while the previous block is computed
 // from the other buffer.  Wide strips keep every row segment a workgroup
-// reads long and contiguous (TN = 256: 1 KiB), which HBM serves far better
-// than short scattered segments.
+// reads long and contiguous (TN = 256 FP32 or 128 FP64 columns: 1 KiB),
+// which HBM serves far better than short scattered segments.  A 16-byte line
+// holds 4 FP32 or 2 FP64 values.
 //
 // Every wave issues the same number of load instructions per window with all
 // lanes active (lanes past the window end read a 16-byte zero line into slack
@@ -33,11 +34,13 @@ namespace stencil {
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-template <int R, int BM, int TN, int NT>
+template <typename T, int R, int BM, int TN, int NT>
 struct DmaWindow {
+  typedef T elem_t;
   static constexpr int RAD = R;
-  static constexpr int PITCH = TN + 8;          // floats per LDS row: columns j0-4 .. j0+TN+3
-  static constexpr int LPR = PITCH / 4;         // 16-byte lines per row
+  static constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte line
+  static constexpr int PITCH = TN + 8;          // elements per LDS row: columns j0-4 .. j0+TN+3
+  static constexpr int LPR = PITCH / VEC;       // 16-byte lines per row
   static constexpr int WCOL0 = 4 - R;           // LDS column of window column 0 (global j0 - r)
   static constexpr int ROWS = BM + 2 * R;
   static constexpr int NWAVES = NT / 64;
@@ -47,9 +50,9 @@ struct DmaWindow {
   static constexpr int npw(int rows) { return ((rows * LPR + 63) / 64 + NWAVES - 1) / NWAVES; }
   static constexpr int NPW_FULL = npw(ROWS);
   static constexpr int NPW_NEW = npw(BM);
-  // floats per buffer, incl. slack: the first window's loads start at row 0,
+  // elements per buffer, incl. slack: the first window's loads start at row 0,
   // later windows' loads at row 2r
-  static constexpr int BUF = cmax(NPW_FULL * NWAVES * 256, 2 * R * PITCH + NPW_NEW * NWAVES * 256);
+  static constexpr int BUF = cmax(NPW_FULL * NWAVES * 64 * VEC, 2 * R * PITCH + NPW_NEW * NWAVES * 64 * VEC);
   static_assert(R <= 4, "window covers at most 4 halo columns");
   static_assert(NPW_FULL < 64, "vmcnt range");
   static_assert(BM >= 2 * R, "carried halo rows must come from one buffer");
@@ -58,8 +61,8 @@ struct DmaWindow {
   // starting at `dst` (a row boundary of a buffer).  Every wave issues exactly
   // npw(NROWS) instructions with all lanes active.
   template <int NROWS>
-  static __device__ __forceinline__ void issue(float* dst, const float* __restrict__ src,
-                                               const float* __restrict__ zeros, int64_t M, int64_t N,
+  static __device__ __forceinline__ void issue(T* dst, const T* __restrict__ src,
+                                               const T* __restrict__ zeros, int64_t M, int64_t N,
                                                int64_t grow0, int64_t j0, bool periodic) {
     constexpr int LINES = NROWS * LPR, NP = npw(NROWS);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -67,14 +70,14 @@ struct DmaWindow {
     for (int k = 0; k < NP; ++k) {
       const int inst = k * NWAVES + w;
       const int line = inst * 64 + lane;
-      const float* s = zeros;
+      const T* s = zeros;
       if (line < LINES) {
         const int row = line / LPR, lc = line - (line / LPR) * LPR;
         const int64_t g = map_index(grow0 + row, M, periodic);
-        const int64_t c = map_index(j0 - 4 + 4 * lc, N, periodic);
+        const int64_t c = map_index(j0 - 4 + VEC * lc, N, periodic);
         if (g >= 0 && c >= 0) s = src + g * N + c;
       }
-      __builtin_amdgcn_global_load_lds(s, (lds_void_t*)(dst + inst * 256), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)s, (lds_void_t*)(dst + inst * 64 * VEC), 16, 0, 0);
     }
   }
 
@@ -111,17 +114,18 @@ inline bool dma2d_ok(const KArgs& a) {
 // loads of window b+1 (its BM new rows) are issued before block b is
 // computed, and block b's last 2r rows are copied to the top of window b+1.
 template <class D, int BM, class Body>
-__device__ __forceinline__ void dma_block_loop(float* bufs, const KArgs& a, const Strip2D& sp, Body body) {
+__device__ __forceinline__ void dma_block_loop(typename D::elem_t* bufs, const KArgs& a, const Strip2D& sp, Body body) {
+  typedef typename D::elem_t T;
   constexpr int R = D::RAD;
-  const float* __restrict__ in = (const float*)a.in;
-  const float* __restrict__ zeros = (const float*)a.zeros;
+  const T* __restrict__ in = (const T*)a.in;
+  const T* __restrict__ zeros = (const T*)a.zeros;
   const bool periodic = a.periodic != 0;
   const int nb = (int)((sp.i1 - sp.i0 + BM - 1) / BM);
   D::template issue<D::ROWS>(bufs, in, zeros, a.d0, a.d1, sp.i0 - R, sp.j0, periodic);
   for (int bi = 0; bi < nb; ++bi) {
     const int64_t ib = sp.i0 + (int64_t)bi * BM;
-    float* cur = bufs + (bi & 1) * D::BUF;
-    float* nxt = bufs + ((bi + 1) & 1) * D::BUF;
+    T* cur = bufs + (bi & 1) * D::BUF;
+    T* nxt = bufs + ((bi + 1) & 1) * D::BUF;
     if (bi + 1 < nb) {
       D::template issue<BM>(nxt + 2 * R * D::PITCH, in, zeros, a.d0, a.d1, ib + BM + R, sp.j0, periodic);
       D::template wait_vm<D::NPW_NEW>();
@@ -131,8 +135,8 @@ __device__ __forceinline__ void dma_block_loop(float* bufs, const KArgs& a, cons
     __syncthreads();
     if (bi + 1 < nb) {
       // carry window rows BM .. BM + 2r - 1 to rows 0 .. 2r - 1 of the next window
-      constexpr int N4 = 2 * R * D::PITCH / 4;
-      for (int idx = threadIdx.x; idx < N4; idx += 256)
+      constexpr int N4 = 2 * R * D::PITCH / D::VEC;
+      for (int idx = threadIdx.x; idx < N4; idx += D::NWAVES * 64)
         reinterpret_cast<float4*>(nxt)[idx] = reinterpret_cast<const float4*>(cur + BM * D::PITCH)[idx];
     }
     body(cur, ib);
@@ -154,7 +158,7 @@ constexpr int kDmaTN = 256, kDmaBM = 16;
 template <int R, bool BOX>
 __device__ __forceinline__ void mfma2d_b4_dma_item(const KArgs& a, int item) {
   constexpr int BM = kDmaBM, TN = kDmaTN, NB = 4 + 2 * R, NL = BOX ? 2 * R + 1 : 1;
-  typedef DmaWindow<R, BM, TN, 256> D;
+  typedef DmaWindow<float, R, BM, TN, 256> D;
   __shared__ __attribute__((aligned(16))) float bufs[2 * D::BUF];
 
   const int64_t N = a.d1;
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(256) void mfma2d_b4_dma_batch(BatchArgs b) {
 template <int R>
 __device__ __forceinline__ void mfma2d_b4c_dma_item(const KArgs& a, int item) {
   constexpr int BM = kDmaBM, TN = kDmaTN, NB = 4 + 2 * R, W = 2 * R + 1;
-  typedef DmaWindow<R, BM, TN, 256> D;
+  typedef DmaWindow<float, R, BM, TN, 256> D;
   __shared__ __attribute__((aligned(16))) float bufs[2 * D::BUF];
 
   const int64_t N = a.d1;
@@ -312,67 +316,106 @@ __global__ __launch_bounds__(256) void mfma2d_b4c_dma_batch(BatchArgs b) {
 }
 
 // ---------------------------------------------------------------------------
-// Gather-form baseline on DMA-fed windows: thread t owns a 4 x 4 block of
-// outputs (rows 4 (t / 64) .., columns 4 (t % 64) .. of the strip), reads
-// its input rows as three aligned 16-byte LDS vectors, applies the taps with
-// wave-uniform coefficients and stores 16-byte rows.
+// Gather-form baseline on DMA-fed windows: strips of 256 (FP32) or 128 (FP64)
+// columns; thread t owns a block of 4 (FP32) or 2 (FP64) rows x 4 columns,
+// reads each input row it needs as 12 values (three 16-byte LDS vectors FP32,
+// six FP64) covering the column offsets -r .. r of its four columns, applies
+// the taps with wave-uniform coefficients and stores 16-byte rows.
 // ---------------------------------------------------------------------------
-template <int R, bool BOX>
+template <typename T> struct Gather2DDma;
+template <> struct Gather2DDma<float> { static constexpr int TN = 256; };
+template <> struct Gather2DDma<double> { static constexpr int TN = 128; };
+
+template <typename T, int R, bool BOX>
 __device__ __forceinline__ void gather2d_dma_item(const KArgs& a, int item) {
-  constexpr int BM = kDmaBM, TN = kDmaTN, W = 2 * R + 1;
-  typedef DmaWindow<R, BM, TN, 256> D;
-  __shared__ __attribute__((aligned(16))) float bufs[2 * D::BUF];
+  constexpr int BM = kDmaBM, TN = Gather2DDma<T>::TN, W = 2 * R + 1;
+  constexpr int CT = TN / 4, NRG = 256 / CT, PR = BM / NRG;  // column groups, row groups, rows per thread
+  typedef DmaWindow<T, R, BM, TN, 256> D;
+  typedef typename Vec16<T>::type V;
+  constexpr int VEC = D::VEC;
+  constexpr int XU = BOX && (sizeof(T) == 8 || R >= 3) ? 2 : 0;  // unroll of the middle rows (0: all)
+  __shared__ __attribute__((aligned(16))) T bufs[2 * D::BUF];
 
   const int64_t N = a.d1;
-  float* __restrict__ out = (float*)a.out;
-  const float* __restrict__ c = (const float*)a.coef;
-  const int rg = threadIdx.x >> 6, c4 = 4 * (threadIdx.x & 63);
+  T* __restrict__ out = (T*)a.out;
+  const ConstPtr<T> c = (ConstPtr<T>)a.coef;  // uniform reads: scalar loads
+  const int rg = threadIdx.x / CT, c4 = 4 * (threadIdx.x % CT);
   const Strip2D sp = decode_strip(a, item, TN);
   const int64_t gj = sp.j0 + c4;
 
-  dma_block_loop<D, BM>(bufs, a, sp, [&](const float* cur, int64_t ib) {
-    float acc[4][4];
+  dma_block_loop<D, BM>(bufs, a, sp, [&](const T* cur, int64_t ib) {
+    T acc[PR][4];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < PR; ++p)
 #pragma unroll
-      for (int qq = 0; qq < 4; ++qq) acc[p][qq] = 0.0f;
-#pragma unroll
-    for (int x = 0; x < 4 + 2 * R; ++x) {
+      for (int qq = 0; qq < 4; ++qq) acc[p][qq] = T(0);
+    // window row x feeds output rows p with coefficient row x - p; `edge`
+    // rows (the first and last PR - 1) have some p out of range
+    auto row = [&](int x, auto edge) {
       // LDS columns c4 .. c4 + 11 hold window columns c4 - 4 + r .. c4 + 7 + r
-      const float4* rp = reinterpret_cast<const float4*>(cur + (4 * rg + x) * D::PITCH + c4);
-      const float4 v0 = rp[0], v1 = rp[1], v2 = rp[2];
-      const float vv[12] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w, v2.x, v2.y, v2.z, v2.w};
+      const V* rp = reinterpret_cast<const V*>(cur + (PR * rg + x) * D::PITCH + c4);
+      T vv[12];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
+      for (int k = 0; k < 12 / VEC; ++k) {
+        const V t = rp[k];
+        const T* pt = reinterpret_cast<const T*>(&t);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) vv[k * VEC + e] = pt[e];
+      }
+#pragma unroll
+      for (int p = 0; p < PR; ++p) {
         const int aa = x - p;
-        if (aa < 0 || aa > 2 * R) continue;
+        if constexpr (decltype(edge)::value) {
+          if (aa < 0 || aa > 2 * R) continue;
+        }
 #pragma unroll
         for (int b = 0; b < W; ++b) {
           if (!BOX && aa != R && b != R) continue;
-          const float cf = c[aa * W + b];
+          const T cf = c[aa * W + b];
 #pragma unroll
           for (int qq = 0; qq < 4; ++qq) acc[p][qq] += cf * vv[D::WCOL0 + qq + b];
         }
       }
-    }
-    if (gj < N) {
+    };
+    if constexpr (XU == 0) {  // fully unrolled: every row index a constant
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const int64_t gi = ib + 4 * rg + p;
-        if (gi < sp.i1) *reinterpret_cast<float4*>(out + gi * N + gj) = float4{acc[p][0], acc[p][1], acc[p][2], acc[p][3]};
+      for (int x = 0; x < PR + 2 * R; ++x) row(x, std::true_type{});
+    } else {  // large boxes: a rolled middle keeps registers and scalar coefficients in budget
+      static_assert(PR - 1 <= 2 * R + 1, "edge rows overlap");
+#pragma unroll
+      for (int x = 0; x < PR - 1; ++x) row(x, std::true_type{});
+#pragma unroll XU
+      for (int x = PR - 1; x <= 2 * R; ++x) row(x, std::false_type{});
+#pragma unroll
+      for (int x = 2 * R + 1; x < PR + 2 * R; ++x) row(x, std::true_type{});
+    }
+    if (gj < N) {  // column extent a multiple of 4: the four columns lie inside the row
+#pragma unroll
+      for (int p = 0; p < PR; ++p) {
+        const int64_t gi = ib + PR * rg + p;
+        if (gi >= sp.i1) continue;
+        V* dst = reinterpret_cast<V*>(out + gi * N + gj);
+#pragma unroll
+        for (int k = 0; k < 4 / VEC; ++k) {
+          V t;
+          T* pt = reinterpret_cast<T*>(&t);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) pt[e] = acc[p][k * VEC + e];
+          dst[k] = t;
+        }
       }
     }
   });
 }
 
-template <int R, bool BOX>
+template <typename T, int R, bool BOX>
 __global__ __launch_bounds__(256) void gather2d_dma_kernel(KArgs a) {
-  gather2d_dma_item<R, BOX>(a, xcd_remap(blockIdx.x, gridDim.x));
+  gather2d_dma_item<T, R, BOX>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-template <int R, bool BOX>
+template <typename T, int R, bool BOX>
 __global__ __launch_bounds__(256) void gather2d_dma_batch(BatchArgs b) {
-  for_each_batch_item(b, [&](const KArgs& x, int id) { gather2d_dma_item<R, BOX>(x, id); });
+  for_each_batch_item(b, [&](const KArgs& x, int id) { gather2d_dma_item<T, R, BOX>(x, id); });
 }
 
 // ---------------------------------------------------------------------------
@@ -391,7 +434,7 @@ __device__ __forceinline__ void split2d_dma_item(const KArgs& a, int item) {
   constexpr int WROWS = BM + 2 * R, WEND = TN + 2 * R;
   constexpr int P = 152;  // 16-bit pitch: multiple of 8, odd number of 16-byte units, >= 96 + 16 + 32
   static_assert(WEND <= P && 32 * 3 + 16 + 32 <= P, "pitch too small");
-  typedef DmaWindow<R, BM, TN, 256> D;
+  typedef DmaWindow<float, R, BM, TN, 256> D;
   __shared__ __attribute__((aligned(16))) float bufs[2 * D::BUF];
   __shared__ __attribute__((aligned(16))) uint16_t lhi[WROWS * P];
   __shared__ __attribute__((aligned(16))) uint16_t llo[WROWS * P];

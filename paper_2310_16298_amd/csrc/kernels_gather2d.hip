@@ -8,9 +8,10 @@ namespace stencil {
 
 template <typename T, int R, bool BOX>
 static Kernel pick_gather2d(KArgs& a, int32_t chunk) {
-  if constexpr (sizeof(T) == 4) {
-    if (dma2d_ok(a)) return kernel_of<gather2d_dma_kernel<R, BOX>, gather2d_dma_batch<R, BOX>>(strip_grid(a, kDmaTN, kDmaBM, 1024, dma_chunk(a, kDmaTN, R, BOX, chunk)));
-  }
+  constexpr int TN = Gather2DDma<T>::TN;
+  if (dma2d_ok(a))
+    return kernel_of<gather2d_dma_kernel<T, R, BOX>, gather2d_dma_batch<T, R, BOX>>(
+        strip_grid(a, TN, kDmaBM, 1024, dma_chunk(a, TN, R, BOX, chunk)));
   return kernel_of<gather2d_kernel<T, R, BOX>, gather2d_batch<T, R, BOX>>(strip_grid(a, kTile2D, kTile2D, 2048, chunk));
 }
 

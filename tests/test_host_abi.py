@@ -386,6 +386,19 @@ def test_general_plan_uses_minimum_cover(lib, seed):
     assert st.describe((16, 16, 16), r, st.GENERAL, _box(3, r))["path"] == st.PATH_GATHER
 
 
+@pytest.mark.parametrize("shape", [inputs.STAR, inputs.BOX])
+def test_auto_path_choice(lib, shape):
+    """AUTO: 2D FP32 -> outer products on MFMA; 2D FP64 -> the gather kernel
+    when the column extent allows its direct-to-LDS windows (a multiple of
+    4), MFMA otherwise; 3D -> gather."""
+    c = inputs.coefficients(2, 2, shape, seed=3, dtype=np.float64)
+    assert st.describe((64, 64), 2, shape, c, dtype=st.F32)["path"] == st.PATH_MFMA
+    assert st.describe((64, 64), 2, shape, c, dtype=st.F64)["path"] == st.PATH_GATHER
+    assert st.describe((64, 66), 2, shape, c, dtype=st.F64)["path"] == st.PATH_MFMA
+    c3 = inputs.coefficients(3, 2, shape, seed=3, dtype=np.float64)
+    for dt in (st.F32, st.F64):
+        assert st.describe((16, 16, 16), 2, shape, c3, dtype=dt)["path"] == st.PATH_GATHER
+
 
 def test_3d_mfma_block_edge(lib):
     """FP32 3D outer products default to n = 4 blocks for stars and the
