@@ -384,13 +384,17 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   in.time_block = 1;
   if (d.time_block > 1) path = STENCIL_PATH_GATHER;
   if (path == STENCIL_PATH_AUTO) {
-    // Measured on MI355X: 2D FP32 -> outer products on MFMA; 3D -> the
-    // gather kernel (HBM-bound with register blocks; the 3D MFMA kernels
-    // trail it).  2D FP64: the FP64 matrix rate equals the FP64 vector rate,
-    // and the gather kernel on direct-to-LDS windows (column extent a
-    // multiple of 4) beats the FP64 outer products at every radius.
+    // Measured on MI355X.  3D: the gather kernel (HBM-bound with register
+    // blocks; the 3D outer products trail it).  2D on direct-to-LDS windows
+    // (column extent a multiple of 4): outer products on MFMA where the
+    // arithmetic outgrows the memory traffic -- FP32 boxes of radius >= 3 and
+    // GENERAL line covers -- and the gather kernel elsewhere (stars and small
+    // boxes stay HBM-bound there; the FP64 matrix rate equals the FP64
+    // vector rate).  Other 2D extents: outer products.
+    const bool dma_cols = d.dims[1] % 4 == 0;
+    const bool heavy = d.dtype == STENCIL_F32 && (general || (box && R >= 3));
     if (nd == 3) path = STENCIL_PATH_GATHER;
-    else if (d.dtype == STENCIL_F64 && d.dims[1] % 4 == 0) path = STENCIL_PATH_GATHER;
+    else if (dma_cols && !heavy) path = STENCIL_PATH_GATHER;
     else path = STENCIL_PATH_MFMA;
   }
   const bool split = path == STENCIL_PATH_MFMA_BF16X3 || path == STENCIL_PATH_MFMA_F16X3;

@@ -388,16 +388,23 @@ def test_general_plan_uses_minimum_cover(lib, seed):
 
 @pytest.mark.parametrize("shape", [inputs.STAR, inputs.BOX])
 def test_auto_path_choice(lib, shape):
-    """AUTO: 2D FP32 -> outer products on MFMA; 2D FP64 -> the gather kernel
-    when the column extent allows its direct-to-LDS windows (a multiple of
-    4), MFMA otherwise; 3D -> gather."""
-    c = inputs.coefficients(2, 2, shape, seed=3, dtype=np.float64)
-    assert st.describe((64, 64), 2, shape, c, dtype=st.F32)["path"] == st.PATH_MFMA
-    assert st.describe((64, 64), 2, shape, c, dtype=st.F64)["path"] == st.PATH_GATHER
-    assert st.describe((64, 66), 2, shape, c, dtype=st.F64)["path"] == st.PATH_MFMA
-    c3 = inputs.coefficients(3, 2, shape, seed=3, dtype=np.float64)
-    for dt in (st.F32, st.F64):
-        assert st.describe((16, 16, 16), 2, shape, c3, dtype=dt)["path"] == st.PATH_GATHER
+    """AUTO in 2D: outer products on MFMA for FP32 boxes of radius >= 3 and
+    GENERAL covers, the gather kernel for the rest when the column extent
+    allows direct-to-LDS windows (a multiple of 4), MFMA on other extents;
+    3D: gather."""
+    for r in (1, 2, 3, 4):
+        c = inputs.coefficients(2, r, shape, seed=3, dtype=np.float64)
+        heavy = shape == inputs.BOX and r >= 3
+        assert st.describe((64, 64), r, shape, c, dtype=st.F32)["path"] == (st.PATH_MFMA if heavy else st.PATH_GATHER)
+        assert st.describe((64, 64), r, shape, c, dtype=st.F64)["path"] == st.PATH_GATHER
+        for dt in (st.F32, st.F64):
+            assert st.describe((64, 66), r, shape, c, dtype=dt)["path"] == st.PATH_MFMA
+        g = c.copy()
+        g[0, 0] = 0.0  # not a full box: a GENERAL stencil
+        assert st.describe((64, 64), r, st.GENERAL, g, dtype=st.F32)["path"] == st.PATH_MFMA
+        c3 = inputs.coefficients(3, r, shape, seed=3, dtype=np.float64)
+        for dt in (st.F32, st.F64):
+            assert st.describe((16, 16, 16), r, shape, c3, dtype=dt)["path"] == st.PATH_GATHER
 
 
 def test_3d_mfma_block_edge(lib):
