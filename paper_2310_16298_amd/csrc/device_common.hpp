@@ -49,6 +49,15 @@ __host__ __device__ constexpr int round_up(int v, int m) { return (v + m - 1) / 
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
+// Workgroup barrier over LDS only: waits for this wave's LDS operations
+// (lgkmcnt(0)) and joins the barrier, leaving vector-memory operations in
+// flight.  __syncthreads() also waits for those (vmcnt(0)) -- the compiler
+// treats pending direct-to-LDS loads as LDS writes -- which would make every
+// block wait for the prefetch of the next window as well.  Direct-to-LDS
+// windows are published by each wave's own vmcnt wait before this barrier.
+// The memory clobber keeps the compiler from moving memory accesses across.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Index of global coordinate g under the boundary rule, or -1 for a zero-halo
 // point outside [0, n).  The modulo branch is taken only at grid faces.
 __device__ __forceinline__ int64_t map_index(int64_t g, int64_t n, bool periodic) {

@@ -14,10 +14,10 @@
 // lanes active (lanes past the window end read a 16-byte zero line into slack
 // at the end of the buffer), so "s_waitcnt vmcnt(n)" with n = the loads just
 // issued for window b+1 guarantees that this wave's loads of window b (and
-// its older stores) have completed; a barrier then makes all waves' loads
-// visible.  Only the first window of a strip is loaded whole; later windows
-// load their BM new rows and receive the 2r halo rows from the previous
-// window by an LDS copy.
+// its older stores) have completed; an LDS-only barrier then makes all
+// waves' loads visible while window b+1 stays in flight.  Every window is
+// loaded whole (BM + 2r rows); its 2r halo rows were read for the previous
+// block moments before and come from L2, not HBM.
 //
 // Requirements (checked on the host before choosing these kernels): the
 // column extent is a multiple of 4 and both grid pointers are 16-byte
@@ -44,18 +44,13 @@ struct DmaWindow {
   static constexpr int WCOL0 = 4 - R;           // LDS column of window column 0 (global j0 - r)
   static constexpr int ROWS = BM + 2 * R;
   static constexpr int NWAVES = NT / 64;
-  // Loads per wave for `rows` window rows; the first window of a strip loads
-  // all BM + 2r rows, later windows only the BM new rows (the 2r halo rows
-  // are carried over in LDS).
+  // Loads per wave for `rows` window rows.
   static constexpr int npw(int rows) { return ((rows * LPR + 63) / 64 + NWAVES - 1) / NWAVES; }
   static constexpr int NPW_FULL = npw(ROWS);
-  static constexpr int NPW_NEW = npw(BM);
-  // elements per buffer, incl. slack: the first window's loads start at row 0,
-  // later windows' loads at row 2r
-  static constexpr int BUF = cmax(NPW_FULL * NWAVES * 64 * VEC, 2 * R * PITCH + NPW_NEW * NWAVES * 64 * VEC);
+  // elements per buffer, incl. slack for the lanes past the window end
+  static constexpr int BUF = NPW_FULL * NWAVES * 64 * VEC;
   static_assert(R <= 4, "window covers at most 4 halo columns");
   static_assert(NPW_FULL < 64, "vmcnt range");
-  static_assert(BM >= 2 * R, "carried halo rows must come from one buffer");
 
   // Issue the loads of NROWS window rows, global rows grow0 .., into LDS rows
   // starting at `dst` (a row boundary of a buffer).  Every wave issues exactly
@@ -110,9 +105,11 @@ inline bool dma2d_ok(const KArgs& a) {
 
 // Block loop shared by the DMA kernels: body(cur, ib) computes and stores the
 // block of rows [ib, min(ib + BM, i1)) from the window in `cur` (window row 0
-// = global row ib - r).  The first window is loaded whole; afterwards the
-// loads of window b+1 (its BM new rows) are issued before block b is
-// computed, and block b's last 2r rows are copied to the top of window b+1.
+// = global row ib - r).  The loads of window b+1 (all BM + 2r rows; its 2r
+// halo rows were just read for window b and come from L2) are issued before
+// block b is computed.  Nothing else writes LDS inside the loop, so the
+// compiler has no LDS store to order behind the loads in flight and the LDS
+// barriers leave them outstanding across the compute of block b.
 template <class D, int BM, class Body>
 __device__ __forceinline__ void dma_block_loop(typename D::elem_t* bufs, const KArgs& a, const Strip2D& sp, Body body) {
   typedef typename D::elem_t T;
@@ -127,20 +124,14 @@ __device__ __forceinline__ void dma_block_loop(typename D::elem_t* bufs, const K
     T* cur = bufs + (bi & 1) * D::BUF;
     T* nxt = bufs + ((bi + 1) & 1) * D::BUF;
     if (bi + 1 < nb) {
-      D::template issue<BM>(nxt + 2 * R * D::PITCH, in, zeros, a.d0, a.d1, ib + BM + R, sp.j0, periodic);
-      D::template wait_vm<D::NPW_NEW>();
+      D::template issue<D::ROWS>(nxt, in, zeros, a.d0, a.d1, ib + BM - R, sp.j0, periodic);
+      D::template wait_vm<D::NPW_FULL>();
     } else {
       D::template wait_vm<0>();
     }
-    __syncthreads();
-    if (bi + 1 < nb) {
-      // carry window rows BM .. BM + 2r - 1 to rows 0 .. 2r - 1 of the next window
-      constexpr int N4 = 2 * R * D::PITCH / D::VEC;
-      for (int idx = threadIdx.x; idx < N4; idx += D::NWAVES * 64)
-        reinterpret_cast<float4*>(nxt)[idx] = reinterpret_cast<const float4*>(cur + BM * D::PITCH)[idx];
-    }
+    lds_barrier();
     body(cur, ib);
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -152,12 +143,28 @@ __device__ __forceinline__ void dma_block_loop(typename D::elem_t* bufs, const K
 // of the instruction holds D[i][j] = input column 4 beta + i times the weight
 // for block row j: lane 4 beta + j then owns four consecutive columns of one
 // output row and stores them with one 16-byte write.
+//
+// Every block of the instruction uses the same B vector, so one VGPR carries
+// four of them, one per 16-lane group, and the instruction's B lane-group
+// broadcast (blgp = 4 + g: lanes 16 g .. 16 g + 15 feed all 16 blocks)
+// selects one: the coefficient fragments take NL NB / 4 registers, not NL NB.
 // ---------------------------------------------------------------------------
 constexpr int kDmaTN = 256, kDmaBM = 16;
+
+// v_mfma_f32_4x4x1_16b_f32 with the B operand taken from lane group g.
+__device__ __forceinline__ floatx4 mfma4_group(float a, float b, floatx4 c, int g) {
+  switch (g) {
+    case 0: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 4);
+    case 1: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 5);
+    case 2: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 6);
+    default: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 7);
+  }
+}
 
 template <int R, bool BOX>
 __device__ __forceinline__ void mfma2d_b4_dma_item(const KArgs& a, int item) {
   constexpr int BM = kDmaBM, TN = kDmaTN, NB = 4 + 2 * R, NL = BOX ? 2 * R + 1 : 1;
+  constexpr int NC = NL * NB, NP = (NC + 3) / 4;  // coefficient vectors, packed registers
   typedef DmaWindow<float, R, BM, TN, 256> D;
   __shared__ __attribute__((aligned(16))) float bufs[2 * D::BUF];
 
@@ -166,17 +173,22 @@ __device__ __forceinline__ void mfma2d_b4_dma_item(const KArgs& a, int item) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const Strip2D sp = decode_strip(a, item, TN);
 
+  // vector c's value for lane l sits at frag[64 c + l] (it depends on l mod 4
+  // only); register k holds vector 4 k + g in lane group g
   const float* __restrict__ frag = (const float*)a.frag;
-  float af[NL * NB];
+  float af[NP];
 #pragma unroll
-  for (int c = 0; c < NL * NB; ++c) af[c] = frag[c * 64 + lane];
+  for (int k = 0; k < NP; ++k) {
+    const int c = 4 * k + (lane >> 4);
+    af[k] = c < NC ? frag[c * 64 + lane] : 0.0f;
+  }
   float cw[2 * R + 1];
   if constexpr (!BOX) {
     const float* __restrict__ c = (const float*)a.coef;
 #pragma unroll
     for (int b = 0; b <= 2 * R; ++b) cw[b] = c[R * (2 * R + 1) + b];
   }
-  const int orow = lane & 3;                      // block row owned by this lane
+  const int orow = lane & 3;                            // block row owned by this lane
   const int64_t gj = sp.j0 + 64 * w + 4 * (lane >> 2);  // first of its four columns
 
   dma_block_loop<D, BM>(bufs, a, sp, [&](const float* cur, int64_t ib) {
@@ -192,9 +204,9 @@ __device__ __forceinline__ void mfma2d_b4_dma_item(const KArgs& a, int item) {
         const float hv = rowp[x * D::PITCH + b];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          const int d = x - 4 * s;
+          const int d = x - 4 * s, c = li * NB + d;
           if (d < 0 || d >= NB) continue;
-          acc[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv, af[li * NB + d], acc[s], 0, 0, 0);
+          acc[s] = mfma4_group(hv, af[c >> 2], acc[s], c & 3);
         }
       }
       __builtin_amdgcn_sched_barrier(0);  // keep each line's LDS reads next to its MFMAs
@@ -469,7 +481,7 @@ __device__ __forceinline__ void split2d_dma_item(const KArgs& a, int item) {
       *reinterpret_cast<uint32_t*>(lhi + row * P + y) = (uint32_t)h0 | ((uint32_t)h1 << 16);
       *reinterpret_cast<uint32_t*>(llo + row * P + y) = (uint32_t)l0 | ((uint32_t)l1 << 16);
     }
-    __syncthreads();
+    lds_barrier();
     floatx4 acc[2], acx[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {

@@ -95,7 +95,7 @@ struct PlaneWalk {
         } else {
           D::template wait_vm<0>();
         }
-        __syncthreads();
+        lds_barrier();
       } else {
         win = bufs;
         __syncthreads();
@@ -106,7 +106,7 @@ struct PlaneWalk {
       }
       body(win, gi >= 0);
       finish(ch.ib + u - 2 * R, u >= 2 * R);
-      if constexpr (DMA) __syncthreads();
+      if constexpr (DMA) lds_barrier();
     }
   }
 };
@@ -640,7 +640,7 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
           *reinterpret_cast<uint32_t*>(lhi + row * S::P + y) = (uint32_t)h0 | ((uint32_t)h1 << 16);
           *reinterpret_cast<uint32_t*>(llo + row * S::P + y) = (uint32_t)l0 | ((uint32_t)l1 << 16);
         }
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int ap = 0; ap < W; ++ap) {
           if (!BOX && ap != R) continue;
