@@ -312,14 +312,14 @@ def workload_tune(args, torch, st, inputs) -> dict:
                f"{'f64' if dt == st.F64 else 'f32'}")
         out["cases"][key] = {
             "winner": {"path": st.PATH_NAMES[knobs["path"]], "lines": names[knobs["lines"]],
-                       "block_n": knobs["block_n"], "chunk": knobs["chunk"], "ms_per_step": round(ms, 5),
-                       "gstencil_s": round(pts / (ms * 1e-3) / 1e9, 2)},
+                       "block_n": knobs["block_n"], "chunk": knobs["chunk"], "time_block": knobs["time_block"],
+                       "ms_per_step": round(ms, 5), "gstencil_s": round(pts / (ms * 1e-3) / 1e9, 2)},
             "candidates": [{"path": st.PATH_NAMES[row["path"]], "lines": names[row["lines"]],
-                            "block_n": row["block_n"], "chunk": row["chunk"],
+                            "block_n": row["block_n"], "chunk": row["chunk"], "time_block": row["time_block"],
                             "gstencil_s": round(pts / (row["ms_per_step"] * 1e-3) / 1e9, 2)} for row in rows]}
         w = out["cases"][key]["winner"]
         print(f"[bench] tune {key}: {w['path']} lines={w['lines']} n={w['block_n']} chunk={w['chunk']} "
-              f"{w['gstencil_s']} GStencil/s ({len(rows)} candidates)", file=sys.stderr, flush=True)
+              f"T={w['time_block']} {w['gstencil_s']} GStencil/s ({len(rows)} candidates)", file=sys.stderr, flush=True)
     return out
 
 
