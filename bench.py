@@ -196,8 +196,9 @@ def workload_grid3d(args, torch, st, inputs) -> dict:
             key = f"{'f32' if dt == st.F32 else 'f64'}_{'box' if shape == st.BOX else 'star'}_r{r}"
             out["cases"][key] = {}
             for name, path in paths:
-                if shape == st.BOX and r > 1 and (path != st.PATH_GATHER and not (path == st.PATH_MFMA and r == 2)):
-                    continue  # 3D boxes beyond r = 1 run on the gather path (and MFMA at r = 2)
+                if shape == st.BOX and r > 1 and path != st.PATH_GATHER and (path != st.PATH_MFMA or
+                                                                           (dt == st.F64 and r > 2)):
+                    continue  # 3D boxes beyond r = 1: gather and outer products (FP64: r <= 2)
                 plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=dt, path=path)
                 times = _time_solve(torch, plan, x0, steps, args.steps, args.warmup, stream)
                 g = dims[0] * dims[1] * dims[2] * steps / (np.median(times) * 1e-3) / 1e9

@@ -58,6 +58,19 @@ __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 // The memory clobber keeps the compiler from moving memory accesses across.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
+// v_mfma_f32_4x4x1_16b_f32 with the B operand taken from lane group g (the
+// B lane-group broadcast, blgp = 4 + g: lanes 16 g .. 16 g + 15 feed all 16
+// blocks).  A register can then carry four B vectors, one per lane group;
+// g must fold to a constant after unrolling.
+__device__ __forceinline__ floatx4 mfma4_group(float a, float b, floatx4 c, int g) {
+  switch (g) {
+    case 0: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 4);
+    case 1: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 5);
+    case 2: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 6);
+    default: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 7);
+  }
+}
+
 // Index of global coordinate g under the boundary rule, or -1 for a zero-halo
 // point outside [0, n).  The modulo branch is taken only at grid faces.
 __device__ __forceinline__ int64_t map_index(int64_t g, int64_t n, bool periodic) {

@@ -151,16 +151,6 @@ __device__ __forceinline__ void dma_block_loop(typename D::elem_t* bufs, const K
 // ---------------------------------------------------------------------------
 constexpr int kDmaTN = 256, kDmaBM = 16;
 
-// v_mfma_f32_4x4x1_16b_f32 with the B operand taken from lane group g.
-__device__ __forceinline__ floatx4 mfma4_group(float a, float b, floatx4 c, int g) {
-  switch (g) {
-    case 0: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 4);
-    case 1: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 5);
-    case 2: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 6);
-    default: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 7);
-  }
-}
-
 template <int R, bool BOX>
 __device__ __forceinline__ void mfma2d_b4_dma_item(const KArgs& a, int item) {
   constexpr int BM = kDmaBM, TN = kDmaTN, NB = 4 + 2 * R, NL = BOX ? 2 * R + 1 : 1;

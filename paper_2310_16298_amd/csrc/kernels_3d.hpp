@@ -552,6 +552,112 @@ __global__ __launch_bounds__(kThreads) void mfma3d_b4_batch(BatchArgs b) {
 }
 
 // ---------------------------------------------------------------------------
+// 3D boxes of radius >= 2 on n = 4 blocks.  The (2r+1)^2 lines along j,
+// CLS(a, *, c), scatter input plane i into output plane i - a + r (ring slot
+// 2r - a).  For one column offset c the lines of all 2r+1 planes a read the
+// same input column, so each window row value is read from LDS once and feeds
+// (2r+1) x 2 MFMAs.  The (2r+1)^2 (4 + 2r) band vectors (972 at r = 4) do not
+// fit in registers: a table in LDS holds them in the packed lane order (four
+// vectors per register, one per 16-lane group, selected with the B lane-group
+// broadcast), and the 2r+1 planes' vectors of one column offset are loaded
+// before its rows.  Ring and tile layout as mfma3d_b4_item.
+// ---------------------------------------------------------------------------
+template <int R, bool DMA>
+__device__ __forceinline__ void mfma3d_b4box_item(const KArgs& a, int item) {
+  constexpr int W = 2 * R + 1, NB = 4 + 2 * R;
+  constexpr int NQ = W * NB, NPC = (NQ + 3) / 4;  // vectors and packed registers per column offset
+  typedef PlaneWalk<float, R, kTJ + 2 * R, DMA, true> PW;
+  static_assert(PW::COL0 + R == 4, "tile body at LDS column 4");
+  __shared__ __attribute__((aligned(16))) float bufs[PW::NBUF * PW::BUF];
+  // ptab[((c NPC + k) 16 + 4 g + j]: vector q = 4 k + g of column offset c
+  // (plane a = q / NB, band row d = q % NB) for block row j
+  __shared__ __attribute__((aligned(16))) float ptab[W * NPC * 16];
+
+  const Chunk3D ch = decode_chunk(a, item);
+  const int64_t Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
+  float* __restrict__ out = (float*)a.out;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int orow = lane & 3, beta = lane >> 2;
+
+  // the plan's fragments: line l = a (2r+1) + c, vector l NB + d, lane value
+  // for block row j at frag[64 (l NB + d) + j]
+  const float* __restrict__ frag = (const float*)a.frag;
+  for (int e = threadIdx.x; e < W * NPC * 16; e += kThreads) {
+    const int j = e & 3, g = (e >> 2) & 3, k = (e >> 4) % NPC, c = (e >> 4) / NPC;
+    const int q = 4 * k + g;
+    ptab[e] = q < NQ ? frag[(((q / NB) * W + c) * NB + q % NB) * 64 + j] : 0.0f;
+  }
+  __syncthreads();
+  const float* lanetab = ptab + 4 * (lane >> 4) + (lane & 3);
+
+  floatx4 ring[W][2];
+#pragma unroll
+  for (int z = 0; z < W; ++z)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) ring[z][t] = floatx4{0, 0, 0, 0};
+
+  PW::walk(
+      bufs, a, ch,
+      [&](const float* win, bool valid) {
+        if (!valid) return;
+#pragma unroll
+        for (int cs = 0; cs < W; ++cs) {
+          float pf[NPC];
+#pragma unroll
+          for (int k = 0; k < NPC; ++k) pf[k] = lanetab[(cs * NPC + k) * 16];
+          const float* rowp = win + (8 * w) * PW::PITCH + PW::COL0 + lane + cs;
+#pragma unroll
+          for (int x = 0; x < 8 + 2 * R; ++x) {
+            const float hv = rowp[x * PW::PITCH];
+#pragma unroll
+            for (int ap = 0; ap < W; ++ap)
+#pragma unroll
+              for (int s = 0; s < 2; ++s) {
+                const int d = x - 4 * s, q = ap * NB + d;
+                if (d < 0 || d >= NB) continue;
+                ring[2 * R - ap][s] = mfma4_group(hv, pf[q >> 2], ring[2 * R - ap][s], q & 3);
+              }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      },
+      [&](int64_t o, bool live) {
+        if (live) {
+          const int64_t gk = ch.k0 + 4 * beta;
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const int64_t gj = ch.j0 + 8 * w + 4 * s + orow;
+            if (gj >= Nj) continue;
+            float* dst = out + o * plane + gj * Nk + gk;
+            if constexpr (DMA) {  // k extent a multiple of 4, output 16-byte aligned
+              if (gk < Nk) *reinterpret_cast<float4*>(dst) = float4{ring[0][s][0], ring[0][s][1], ring[0][s][2], ring[0][s][3]};
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (gk + e < Nk) dst[e] = ring[0][s][e];
+            }
+          }
+        }
+#pragma unroll
+        for (int z = 0; z < 2 * R; ++z)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) ring[z][t] = ring[z + 1][t];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) ring[2 * R][t] = floatx4{0, 0, 0, 0};
+      });
+}
+
+template <int R, bool DMA>
+__global__ __launch_bounds__(kThreads) void mfma3d_b4box_kernel(KArgs a) {
+  mfma3d_b4box_item<R, DMA>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <int R, bool DMA>
+__global__ __launch_bounds__(kThreads) void mfma3d_b4box_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { mfma3d_b4box_item<R, DMA>(x, id); });
+}
+
+// ---------------------------------------------------------------------------
 // Outer-product form with 16-bit split operands (see kernels_split2d.hpp) in
 // the plane order of Algorithm 1.  Lines run along k: CLS(a, b, *) adds
 // D[p][q] += sum_y H[p + b][y] * S_{a,b}[y][q], S_{a,b}[y][q] = C^g[a][b][y - q],

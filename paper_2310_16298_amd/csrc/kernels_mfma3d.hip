@@ -39,8 +39,23 @@ static Kernel pick_mfma3d_b4(KArgs& a, int32_t) {
   return kernel_of<mfma3d_b4_kernel<R, BOX, false>, mfma3d_b4_batch<R, BOX, false>>(items);
 }
 
+template <int R>
+static Kernel pick_mfma3d_b4box(KArgs& a, int32_t) {
+  const int64_t items = chunk3d_items(a);
+  if (dma3d_ok<float>(a)) return kernel_of<mfma3d_b4box_kernel<R, true>, mfma3d_b4box_batch<R, true>>(items);
+  return kernel_of<mfma3d_b4box_kernel<R, false>, mfma3d_b4box_batch<R, false>>(items);
+}
+
 Picker find_mfma3d_b4(int R, bool box) {
-  if (box) return R == 1 ? pick_mfma3d_b4<1, true> : nullptr;
+  if (box) {
+    switch (R) {
+      case 1: return pick_mfma3d_b4<1, true>;
+      case 2: return pick_mfma3d_b4box<2>;
+      case 3: return pick_mfma3d_b4box<3>;
+      case 4: return pick_mfma3d_b4box<4>;
+    }
+    return nullptr;
+  }
   switch (R) {
     case 1: return pick_mfma3d_b4<1, false>;
     case 2: return pick_mfma3d_b4<2, false>;

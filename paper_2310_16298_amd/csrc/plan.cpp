@@ -384,18 +384,20 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   in.time_block = 1;
   if (d.time_block > 1) path = STENCIL_PATH_GATHER;
   if (path == STENCIL_PATH_AUTO) {
-    // Measured on MI355X.  3D: the gather kernel (HBM-bound with register
-    // blocks; the 3D outer products trail it).  2D on direct-to-LDS windows
-    // (column extent a multiple of 4): outer products on MFMA where the
-    // arithmetic outgrows the memory traffic -- FP32 boxes of radius >= 3 and
-    // GENERAL line covers -- and the gather kernel elsewhere (stars and small
-    // boxes stay HBM-bound there; the FP64 matrix rate equals the FP64
-    // vector rate).  Other 2D extents: outer products.
-    const bool dma_cols = d.dims[1] % 4 == 0;
-    const bool heavy = d.dtype == STENCIL_F32 && (general || (box && R >= 3));
-    if (nd == 3) path = STENCIL_PATH_GATHER;
-    else if (dma_cols && !heavy) path = STENCIL_PATH_GATHER;
-    else path = STENCIL_PATH_MFMA;
+    // Measured on MI355X: outer products on MFMA where the arithmetic
+    // outgrows the memory traffic -- FP32 boxes of radius >= 3 (2D and 3D)
+    // and 2D GENERAL line covers -- and the gather kernel elsewhere (stars and
+    // small boxes stay HBM-bound, where the gather kernel ties or wins; the
+    // FP64 matrix rate equals the FP64 vector rate).  2D extents whose column
+    // count is not a multiple of 4 (no direct-to-LDS windows): outer products.
+    const bool f32 = d.dtype == STENCIL_F32;
+    if (nd == 3) {
+      path = f32 && box && R >= 3 ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
+    } else {
+      const bool dma_cols = d.dims[1] % 4 == 0;
+      const bool heavy = f32 && (general || (box && R >= 3));
+      path = dma_cols && !heavy ? STENCIL_PATH_GATHER : STENCIL_PATH_MFMA;
+    }
   }
   const bool split = path == STENCIL_PATH_MFMA_BF16X3 || path == STENCIL_PATH_MFMA_F16X3;
   rs->split16 = path == STENCIL_PATH_MFMA_F16X3 ? 1 : 0;
@@ -601,9 +603,9 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
         in.valu_lines = 2 * R;
         in.rank1_per_block = 2 * (2 * R + n) + (int64_t)2 * R * n;  // Table 2, hybrid
       }
-      // FP32 stars and the 27-point box: n = 4 blocks by default (block_n = 16:
-      // the 16x16x4 kernel)
-      const bool b4 = d.dtype == STENCIL_F32 && (!box || R == 1) && d.block_n != 16;
+      // FP32 stars and boxes: n = 4 blocks by default (block_n = 16: the
+      // 16x16x4 kernel)
+      const bool b4 = d.dtype == STENCIL_F32 && d.block_n != 16;
       if (d.block_n == 4 && !b4) return STENCIL_EUNSUPPORTED;
       if (b4) {
         rs->pick = find_mfma3d_b4(R, box);

@@ -11,7 +11,7 @@ import oracle
 from paper_2310_16298_amd import inputs
 from paper_2310_16298_amd import stencil as st
 
-from gpu_helpers import eff_coeffs, error_bound, run_gpu
+from gpu_helpers import eff_coeffs, error_bound, run_gpu, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
@@ -25,7 +25,7 @@ def combos():
             out.append((st.PATH_GATHER, dt, st.BOX, r))
             out.append((st.PATH_GATHER, dt, st.STAR, r))
             out.append((st.PATH_MFMA, dt, st.STAR, r))
-            if r <= 2:
+            if r <= 2 or dt == st.F32:
                 out.append((st.PATH_MFMA, dt, st.BOX, r))
         for p in (BF, FH):
             out.append((p, st.F32, st.STAR, r))
@@ -120,7 +120,8 @@ def test_dma_plane_integer_bit_exact(path, dtype, shape, r):
                               oracle.run(a0, c, r, shape, bc, steps))
 
 
-@pytest.mark.parametrize("shape,r", [(st.STAR, 1), (st.STAR, 2), (st.STAR, 3), (st.STAR, 4), (st.BOX, 1), (st.BOX, 2)])
+@pytest.mark.parametrize("shape,r", [(st.STAR, 1), (st.STAR, 2), (st.STAR, 3), (st.STAR, 4),
+                                     (st.BOX, 1), (st.BOX, 2), (st.BOX, 3), (st.BOX, 4)])
 @pytest.mark.parametrize("dims", [(37, 45, 77), (21, 45, 132)])
 def test_mfma_fp32_block_edges(shape, r, dims):
     """FP32 outer products on n = 4 blocks (default) and on 16x16 blocks
@@ -131,6 +132,55 @@ def test_mfma_fp32_block_edges(shape, r, dims):
     for bc in (st.BC_ZERO, st.BC_PERIODIC):
         want = oracle.run(a0, ce, r, shape, bc, 3)
         tol = error_bound(ce, 3, r, shape, st.F32, st.PATH_MFMA, 3, np.abs(a0).max())
-        for bn in ((0, 16) if shape == st.STAR or r == 1 else (16,)):
+        for bn in ((0, 16) if shape == st.STAR or r <= 2 else (0,)):
             got = run_gpu(a0, c, r, shape, bc, st.F32, st.PATH_MFMA, 3, block_n=bn)
             assert np.abs(got - want).max() <= tol, (bn, bc, np.abs(got - want).max(), tol)
+
+
+@pytest.mark.parametrize("r,dims", [(2, (11, 20, 68)), (2, (9, 13, 70)), (3, (12, 18, 64)), (4, (13, 21, 72))])
+def test_mfma_box_pure_shift(r, dims):
+    """FP32 3D box outer products (n = 4 blocks, band vectors from the LDS
+    table) with a single weight 1 at C^g[a][b][c]: the result is the grid
+    shifted by (a - r, b - r, c - r), bit for bit.  r = 2 visits every offset,
+    r = 3 and 4 a seeded sample; k extents 68 / 64 / 72 use direct-to-LDS
+    planes, 70 the synchronous staging."""
+    torch = torch_cuda()
+    a0 = inputs.grid(dims, seed=820 + r)
+    w = 2 * r + 1
+    offs = [(a, b, c) for a in range(w) for b in range(w) for c in range(w)]
+    if r > 2:
+        rng = np.random.default_rng(830 + r)
+        offs = [offs[i] for i in rng.choice(len(offs), size=40, replace=False)]
+    x = torch.from_numpy(a0).cuda()
+    for a, b, c in offs:
+        cg = np.zeros((w, w, w))
+        cg[a, b, c] = 1.0
+        plan = st.Plan(dims, r, st.BOX, cg, boundary=st.BC_PERIODIC, dtype=st.F32, path=st.PATH_MFMA)
+        assert plan.info["block_n"] == 4
+        got = plan.run_steps(x, torch.empty_like(x), 1).cpu().numpy()
+        assert np.array_equal(got, np.roll(a0, shift=(r - a, r - b, r - c), axis=(0, 1, 2))), (a, b, c)
+        plan.close()
+
+
+@pytest.mark.parametrize("r", [3, 4])
+@pytest.mark.parametrize("density", [0.1, 0.5])
+def test_general_3d_auto(r, density):
+    """Irregular 3D stencils under AUTO (outer products on n = 4 blocks from
+    r = 3, all (2r+1)^2 lines) against the oracle's full (2r+1)^3 sum."""
+    torch = torch_cuda()
+    rng = np.random.default_rng(840 + r + int(10 * density))
+    w = 2 * r + 1
+    mask = rng.random((w, w, w)) < density
+    cg = np.where(mask, rng.uniform(-1.0, 1.0, size=mask.shape), 0.0)
+    cg /= max(1e-30, float(np.abs(cg).sum()))
+    a0 = inputs.grid((14, 22, 76), seed=850 + r)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        plan = st.Plan(a0.shape, r, st.GENERAL, cg, boundary=bc, dtype=st.F32)
+        assert plan.info["path"] == st.PATH_MFMA
+        x = torch.from_numpy(a0).cuda()
+        got = plan.run_steps(x, torch.empty_like(x), 2).cpu().numpy().astype(np.float64)
+        ce = eff_coeffs(cg, st.F32)
+        want = oracle.run(a0, ce, r, st.BOX, bc, 2)
+        tol = error_bound(ce, 3, r, st.BOX, st.F32, st.PATH_MFMA, 2, np.abs(a0).max())
+        assert np.abs(got - want).max() <= tol, (bc, np.abs(got - want).max(), tol)
+        plan.close()

@@ -381,17 +381,18 @@ def test_general_plan_uses_minimum_cover(lib, seed):
         assert info["k_rows"] == info["mfma_lines"] * krows
     assert st.desc_check((64, 64), r, st.GENERAL, c, lines=st.LINES_PARALLEL) == st.EUNSUPPORTED
     assert st.desc_check((64, 64), r, st.GENERAL, c, path=st.PATH_MFMA, dtype=st.F64, block_n=4) == st.EUNSUPPORTED
-    # other paths take GENERAL as a box
+    # other paths take GENERAL as a box; so does AUTO in 3D (outer products from r = 3)
     assert st.describe((64, 64), r, st.GENERAL, c, path=st.PATH_GATHER)["path"] == st.PATH_GATHER
-    assert st.describe((16, 16, 16), r, st.GENERAL, _box(3, r))["path"] == st.PATH_GATHER
+    want3 = st.PATH_MFMA if r >= 3 else st.PATH_GATHER
+    assert st.describe((16, 16, 16), r, st.GENERAL, _box(3, r))["path"] == want3
 
 
 @pytest.mark.parametrize("shape", [inputs.STAR, inputs.BOX])
 def test_auto_path_choice(lib, shape):
-    """AUTO in 2D: outer products on MFMA for FP32 boxes of radius >= 3 and
-    GENERAL covers, the gather kernel for the rest when the column extent
-    allows direct-to-LDS windows (a multiple of 4), MFMA on other extents;
-    3D: gather."""
+    """AUTO: outer products on MFMA for FP32 boxes of radius >= 3 (2D and 3D)
+    and 2D GENERAL covers, the gather kernel for the rest when the column
+    extent allows direct-to-LDS windows (a multiple of 4; 2D), MFMA on other
+    2D extents."""
     for r in (1, 2, 3, 4):
         c = inputs.coefficients(2, r, shape, seed=3, dtype=np.float64)
         heavy = shape == inputs.BOX and r >= 3
@@ -403,21 +404,24 @@ def test_auto_path_choice(lib, shape):
         g[0, 0] = 0.0  # not a full box: a GENERAL stencil
         assert st.describe((64, 64), r, st.GENERAL, g, dtype=st.F32)["path"] == st.PATH_MFMA
         c3 = inputs.coefficients(3, r, shape, seed=3, dtype=np.float64)
-        for dt in (st.F32, st.F64):
-            assert st.describe((16, 16, 16), r, shape, c3, dtype=dt)["path"] == st.PATH_GATHER
+        assert st.describe((16, 16, 16), r, shape, c3, dtype=st.F32)["path"] == (st.PATH_MFMA if heavy else st.PATH_GATHER)
+        assert st.describe((16, 16, 16), r, shape, c3, dtype=st.F64)["path"] == st.PATH_GATHER
 
 
 def test_3d_mfma_block_edge(lib):
-    """FP32 3D outer products default to n = 4 blocks for stars and the
-    27-point box (executed flops 2 (2r+4) per line and point), FP64 and the
-    r = 2 box use 16x16 blocks."""
+    """FP32 3D outer products default to n = 4 blocks for stars and boxes
+    (executed flops 2 (2r+4) per line and point); FP64 uses 16x16 blocks, and
+    the 16x16 form of a box exists up to r = 2."""
     for r in (1, 2, 3, 4):
         s = inputs.coefficients(3, r, inputs.STAR, seed=5, dtype=np.float64)
         info = st.describe((20, 20, 20), r, inputs.STAR, s, path=st.PATH_MFMA)
         assert info["block_n"] == 4 and info["k_rows"] == 2 * (2 * r + 4) and info["valu_lines"] == 2 * r
         assert st.describe((20, 20, 20), r, inputs.STAR, s, path=st.PATH_MFMA, block_n=16)["block_n"] == 16
         assert st.describe((20, 20, 20), r, inputs.STAR, s, path=st.PATH_MFMA, dtype=st.F64)["block_n"] == 16
-    b1 = st.describe((20, 20, 20), 1, inputs.BOX, _box(3, 1), path=st.PATH_MFMA)
-    assert b1["block_n"] == 4 and b1["k_rows"] == 9 * 6
-    assert st.describe((20, 20, 20), 2, inputs.BOX, _box(3, 2), path=st.PATH_MFMA)["block_n"] == 16
-    assert st.desc_check((20, 20, 20), 2, inputs.BOX, _box(3, 2), path=st.PATH_MFMA, block_n=4) == st.EUNSUPPORTED
+    for r in (1, 2, 3, 4):
+        w = 2 * r + 1
+        b = st.describe((20, 20, 20), r, inputs.BOX, _box(3, r), path=st.PATH_MFMA)
+        assert b["block_n"] == 4 and b["k_rows"] == w * w * (2 * r + 4) and b["mfma_lines"] == w * w
+    assert st.describe((20, 20, 20), 2, inputs.BOX, _box(3, 2), path=st.PATH_MFMA, block_n=16)["block_n"] == 16
+    assert st.desc_check((20, 20, 20), 3, inputs.BOX, _box(3, 3), path=st.PATH_MFMA, block_n=16) == st.EUNSUPPORTED
+    assert st.describe((20, 20, 20), 2, inputs.BOX, _box(3, 2), path=st.PATH_MFMA, dtype=st.F64)["block_n"] == 16
