@@ -437,9 +437,12 @@ __device__ __forceinline__ void split2d_dma_item(const KArgs& a, int item) {
   constexpr int P = 152;  // 16-bit pitch: multiple of 8, odd number of 16-byte units, >= 96 + 16 + 32
   static_assert(WEND <= P && 32 * 3 + 16 + 32 <= P, "pitch too small");
   typedef DmaWindow<float, R, BM, TN, 256> D;
-  __shared__ __attribute__((aligned(16))) float bufs[2 * D::BUF];
-  __shared__ __attribute__((aligned(16))) uint16_t lhi[WROWS * P];
-  __shared__ __attribute__((aligned(16))) uint16_t llo[WROWS * P];
+  // one LDS object (separate ones make the compiler wait for the window in
+  // flight before LDS accesses): the two windows, then the hi and lo planes
+  constexpr int PLANE = (WROWS * P * 2 + 15) / 16 * 4;  // floats per 16-bit plane, 16-byte multiple
+  __shared__ __attribute__((aligned(16))) float bufs[2 * D::BUF + 2 * PLANE];
+  uint16_t* lhi = reinterpret_cast<uint16_t*>(bufs + 2 * D::BUF);
+  uint16_t* llo = reinterpret_cast<uint16_t*>(bufs + 2 * D::BUF + PLANE);
 
   const int64_t N = a.d1;
   float* __restrict__ out = (float*)a.out;
@@ -461,8 +464,11 @@ __device__ __forceinline__ void split2d_dma_item(const KArgs& a, int item) {
 
   dma_block_loop<D, BM>(bufs, a, sp, [&](const float* cur, int64_t ib) {
     // split the window into hi/lo planes, two columns per thread and step
-    constexpr int HALF = WEND / 2;
-    for (int idx = threadIdx.x; idx < WROWS * HALF; idx += 256) {
+    constexpr int HALF = WEND / 2, NIT = (WROWS * HALF + 255) / 256;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int idx = threadIdx.x + 256 * it;
+      if (idx >= WROWS * HALF) break;
       const int row = idx / HALF, y = 2 * (idx - (idx / HALF) * HALF);
       const float* src = cur + row * D::PITCH + D::WCOL0 + y;
       uint16_t h0, l0, h1, l1;

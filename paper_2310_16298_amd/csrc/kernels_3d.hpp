@@ -568,10 +568,12 @@ __device__ __forceinline__ void mfma3d_b4box_item(const KArgs& a, int item) {
   constexpr int NQ = W * NB, NPC = (NQ + 3) / 4;  // vectors and packed registers per column offset
   typedef PlaneWalk<float, R, kTJ + 2 * R, DMA, true> PW;
   static_assert(PW::COL0 + R == 4, "tile body at LDS column 4");
-  __shared__ __attribute__((aligned(16))) float bufs[PW::NBUF * PW::BUF];
-  // ptab[((c NPC + k) 16 + 4 g + j]: vector q = 4 k + g of column offset c
-  // (plane a = q / NB, band row d = q % NB) for block row j
-  __shared__ __attribute__((aligned(16))) float ptab[W * NPC * 16];
+  // one LDS object (separate ones make the compiler wait for the plane in
+  // flight before LDS accesses): the plane buffers, then ptab[(c NPC + k) 16 +
+  // 4 g + j], vector q = 4 k + g of column offset c (plane a = q / NB, band
+  // row d = q % NB) for block row j
+  __shared__ __attribute__((aligned(16))) float bufs[PW::NBUF * PW::BUF + W * NPC * 16];
+  float* ptab = bufs + PW::NBUF * PW::BUF;
 
   const Chunk3D ch = decode_chunk(a, item);
   const int64_t Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
@@ -683,9 +685,12 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
   typedef Split3DShape<R, BOX> S;
   typedef PlaneWalk<float, R, S::WROWS, DMA> PW;
   constexpr int W = S::W;
-  __shared__ __attribute__((aligned(16))) float bufs[PW::NBUF * PW::BUF];
-  __shared__ __attribute__((aligned(16))) uint16_t lhi[S::WROWS * S::P];
-  __shared__ __attribute__((aligned(16))) uint16_t llo[S::WROWS * S::P];
+  // one LDS object (separate ones make the compiler wait for the plane in
+  // flight before LDS accesses): the plane buffers, then the hi and lo planes
+  constexpr int PLANE = (S::WROWS * S::P * 2 + 15) / 16 * 4;  // floats per 16-bit plane
+  __shared__ __attribute__((aligned(16))) float bufs[PW::NBUF * PW::BUF + 2 * PLANE];
+  uint16_t* lhi = reinterpret_cast<uint16_t*>(bufs + PW::NBUF * PW::BUF);
+  uint16_t* llo = reinterpret_cast<uint16_t*>(bufs + PW::NBUF * PW::BUF + PLANE);
 
   const Chunk3D ch = decode_chunk(a, item);
   const int64_t Nj = a.d1, Nk = a.d2, plane = Nj * Nk;

@@ -12,6 +12,7 @@
 // agree for stencils symmetric in j, the case of the paper's examples).
 #include "plan.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -564,6 +565,10 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     // about 2048 work items, each at least 4r planes deep (the 2r warm-up
     // planes of a chunk are re-read)
     int64_t chunk = d.dims[0] * tiles / 2048;
+    // boxes of radius >= 2 spend most of their time in arithmetic, which the
+    // 2r warm-up planes repeat: deeper chunks while ~1024 items remain
+    // (measured on 512^3: +5-10 % at 64 planes)
+    if (box && R >= 2) chunk = std::max(chunk, std::min<int64_t>(64, d.dims[0] * tiles / 1024));
     if (chunk < 4 * R) chunk = 4 * R;
     if (d.chunk > 0) chunk = d.chunk;
     if (chunk > d.dims[0]) chunk = d.dims[0];
