@@ -581,13 +581,13 @@ __device__ __forceinline__ void mfma3d_b4box_item(const KArgs& a, int item) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int orow = lane & 3, beta = lane >> 2;
 
-  // the plan's fragments: line l = a (2r+1) + c, vector l NB + d, lane value
-  // for block row j at frag[64 (l NB + d) + j]
+  // the plan's compact fragments: line l = a (2r+1) + c, vector l NB + d,
+  // its value for block row j at frag[4 (l NB + d) + j]
   const float* __restrict__ frag = (const float*)a.frag;
   for (int e = threadIdx.x; e < W * NPC * 16; e += kThreads) {
     const int j = e & 3, g = (e >> 2) & 3, k = (e >> 4) % NPC, c = (e >> 4) / NPC;
     const int q = 4 * k + g;
-    ptab[e] = q < NQ ? frag[(((q / NB) * W + c) * NB + q % NB) * 64 + j] : 0.0f;
+    ptab[e] = q < NQ ? frag[(((q / NB) * W + c) * NB + q % NB) * 4 + j] : 0.0f;
   }
   __syncthreads();
   const float* lanetab = ptab + 4 * (lane >> 4) + (lane & 3);

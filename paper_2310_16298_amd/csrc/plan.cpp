@@ -252,6 +252,23 @@ static void pack_mfma_b4(Resolved* rs, int R, const std::vector<Line>& col) {
   rs->info.k_rows = NF;
 }
 
+// Compact n = 4 fragments: vector li NB + dd holds only its four distinct
+// values (block row j = lane mod 4) at 4 (li NB + dd) + j; kernels that build
+// the packed lane order themselves (the 3D box table) read this form.
+static void pack_mfma_b4_compact(Resolved* rs, int R, const std::vector<Line>& col) {
+  const int NB = 4 + 2 * R;
+  const int NF = (int)col.size() * NB;
+  rs->frag.assign((size_t)NF * 4 * 4, 0);
+  for (int li = 0; li < (int)col.size(); ++li)
+    for (int dd = 0; dd < NB; ++dd)
+      for (int j = 0; j < 4; ++j) {
+        const int e = dd - j;
+        const double v = (e >= 0 && e <= 2 * R) ? col[li][e] : 0.0;
+        put<float>(rs->frag, (size_t)(li * NB + dd) * 4 + j, (float)v);
+      }
+  rs->info.k_rows = NF;
+}
+
 // 16-bit split fragments for row lines on 16x16x32 (B operand: lane l,
 // element e holds S[y = 8 (l / 16) + e][q = l % 16]); hi and lo parts.  For
 // FP16 the coefficients are scaled by 2^e (max weight in [2^14, 2^15)) and the
@@ -616,7 +633,10 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
         rs->pick = find_mfma3d_b4(R, box);
         std::vector<Line> lines4(col);
         lines4.insert(lines4.end(), row.begin(), row.end());
-        if (pack) pack_mfma_b4(rs, R, lines4);
+        if (pack) {
+          if (box && R >= 2) pack_mfma_b4_compact(rs, R, lines4);
+          else pack_mfma_b4(rs, R, lines4);
+        }
         in.k_rows = (int)lines4.size() * (4 + 2 * R);
         in.block_n = 4;
         in.rank1_per_block = box ? (int64_t)W * W * (2 * R + 4) : 2 * (2 * R + 4) + (int64_t)2 * R * 4;

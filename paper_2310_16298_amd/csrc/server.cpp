@@ -196,21 +196,32 @@ stencil_status_t admit(stencil_server_s* s, Request* r) {
   char* frag = b1 + up(r->grid_bytes);
   char* coef = frag + up(r->rs.frag.size());
   char* zeros = coef + up(r->rs.coef.size());
-  // operands and the zero line through a pinned staging slot
+  // operands and the zero line through a pinned staging slot; operands larger
+  // than a slot go straight from the request's own (pageable) host copies,
+  // which the request keeps until it retires
   const size_t fb = r->rs.frag.size(), cb = r->rs.coef.size();
-  if (fb + cb + kAlign > kSlotBytes) return STENCIL_EUNSUPPORTED;
+  const bool staged = fb + cb + kAlign <= kSlotBytes;
   Slot& sl = s->slots[s->next_slot];
   s->next_slot = (s->next_slot + 1) % kSlots;
   if (hipEventSynchronize(sl.ready) != hipSuccess) return STENCIL_EHIP;
   char* h = static_cast<char*>(sl.host);
-  if (fb) std::memcpy(h, r->rs.frag.data(), fb);
-  std::memcpy(h + fb, r->rs.coef.data(), cb);
-  std::memset(h + fb + cb, 0, kAlign);
-  if ((fb && hipMemcpyAsync(frag, h, fb, hipMemcpyHostToDevice, s->stream) != hipSuccess) ||
-      hipMemcpyAsync(coef, h + fb, cb, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-      hipMemcpyAsync(zeros, h + fb + cb, kAlign, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
-      hipEventRecord(sl.ready, s->stream) != hipSuccess)
-    return STENCIL_EHIP;
+  if (staged) {
+    if (fb) std::memcpy(h, r->rs.frag.data(), fb);
+    std::memcpy(h + fb, r->rs.coef.data(), cb);
+    std::memset(h + fb + cb, 0, kAlign);
+    if ((fb && hipMemcpyAsync(frag, h, fb, hipMemcpyHostToDevice, s->stream) != hipSuccess) ||
+        hipMemcpyAsync(coef, h + fb, cb, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(zeros, h + fb + cb, kAlign, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipEventRecord(sl.ready, s->stream) != hipSuccess)
+      return STENCIL_EHIP;
+  } else {
+    std::memset(h, 0, kAlign);
+    if ((fb && hipMemcpyAsync(frag, r->rs.frag.data(), fb, hipMemcpyHostToDevice, s->stream) != hipSuccess) ||
+        hipMemcpyAsync(coef, r->rs.coef.data(), cb, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(zeros, h, kAlign, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipEventRecord(sl.ready, s->stream) != hipSuccess)
+      return STENCIL_EHIP;
+  }
   if (hipMemcpyAsync(b0, r->input, r->grid_bytes, hipMemcpyDeviceToDevice, s->stream) != hipSuccess)
     return STENCIL_EHIP;
   KArgs a = r->rs.args;

@@ -36,6 +36,8 @@ MIXED = [
     ((16, 16, 16), 1, st.BOX, st.BC_ZERO, st.F32, FH),
     ((35, 30, 66), 3, st.STAR, st.BC_ZERO, st.F64, st.PATH_GATHER),
     ((64, 64, 64), 4, st.STAR, st.BC_ZERO, st.F32, st.PATH_GATHER),
+    ((14, 30, 64), 3, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_AUTO),
+    ((11, 19, 70), 4, st.BOX, st.BC_ZERO, st.F32, st.PATH_MFMA),
 ]
 
 
@@ -71,7 +73,7 @@ def test_mixed_batch_equals_alone(steps):
         want = _alone(torch, plan, a0, steps)
         assert np.array_equal(got, want), f"member {k} {MIXED[k]}"
     # a few members against the oracle as well
-    for k in (1, 4, 10, 13):
+    for k in (1, 4, 10, 13, 17, 18):
         plan, c, a0, x, y = ms[k]
         dims, r, shape, bc, dt, path = MIXED[k]
         got = (x if idx == 0 else y).cpu().numpy().astype(np.float64)

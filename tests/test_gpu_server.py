@@ -31,6 +31,7 @@ SPECS = [  # dims, r, shape, bc, dtype, path, steps
     ((64, 64), 2, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_AUTO, 137),  # many launches per tick
     ((24, 40, 48), 1, st.STAR, st.BC_ZERO, st.F64, st.PATH_GATHER, 70),
     ((512, 512), 1, st.STAR, st.BC_PERIODIC, st.F32, st.PATH_MFMA, 65),
+    ((12, 26, 64), 4, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_AUTO, 3),
 ]
 
 
