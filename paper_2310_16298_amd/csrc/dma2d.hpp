@@ -464,11 +464,8 @@ __device__ __forceinline__ void split2d_dma_item(const KArgs& a, int item) {
 
   dma_block_loop<D, BM>(bufs, a, sp, [&](const float* cur, int64_t ib) {
     // split the window into hi/lo planes, two columns per thread and step
-    constexpr int HALF = WEND / 2, NIT = (WROWS * HALF + 255) / 256;
-#pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-      const int idx = threadIdx.x + 256 * it;
-      if (idx >= WROWS * HALF) break;
+    constexpr int HALF = WEND / 2;
+    for (int idx = threadIdx.x; idx < WROWS * HALF; idx += 256) {
       const int row = idx / HALF, y = 2 * (idx - (idx / HALF) * HALF);
       const float* src = cur + row * D::PITCH + D::WCOL0 + y;
       uint16_t h0, l0, h1, l1;
