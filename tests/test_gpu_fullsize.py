@@ -58,3 +58,62 @@ def test_fullsize_windows_time_blocked(grid0, r, tb):
         got = res[lo[0]:lo[0] + 16, lo[1]:lo[1] + 16].cpu().numpy().astype(np.float64)
         assert np.abs(got - want).max() <= tol, (lo, np.abs(got - want).max(), tol)
     plan.close()
+
+
+# ---------------------------------------------------------------- 3D, 512^3
+DIMS3 = (512, 512, 512)
+STEPS3 = 3
+WINDOWS3 = [(0, 0, 0), (0, 504, 0), (504, 0, 504), (504, 504, 504), (250, 17, 300), (33, 260, 8)]
+
+
+@pytest.fixture(scope="module")
+def grid3():
+    return inputs.grid(DIMS3, seed=301, dtype=np.float64)
+
+
+@pytest.mark.parametrize("dtype", [st.F32, st.F64])
+@pytest.mark.parametrize("shape,r", [(st.STAR, 1), (st.STAR, 2), (st.STAR, 3), (st.STAR, 4), (st.BOX, 1),
+                                     (st.BOX, 3), (st.BOX, 4)])
+@pytest.mark.parametrize("path", [st.PATH_AUTO, st.PATH_GATHER, st.PATH_MFMA])
+def test_fullsize_3d_windows(grid3, dtype, shape, r, path):
+    """512^3, zero halo, the configuration of the 3D benchmark (stars r = 1..4,
+    the 27-point box) and the serving mix's large boxes, on sampled 8^3
+    windows including corners and faces."""
+    if dtype == st.F64 and shape == st.BOX and r > 2 and path != st.PATH_GATHER:
+        pytest.skip("FP64 3D boxes beyond r = 2 run on the gather kernel only")
+    torch = torch_cuda()
+    c = inputs.coefficients(3, r, shape, seed=3100 + 10 * shape + r, dtype=np.float64)
+    ce = eff_coeffs(c, dtype)
+    a0 = grid3 if dtype == st.F64 else grid3.astype(np.float32)
+    plan = st.Plan(DIMS3, r, shape, c, boundary=st.BC_ZERO, dtype=dtype, path=path)
+    x = torch.from_numpy(a0).cuda()
+    res = plan.run_steps(x, torch.empty_like(x), STEPS3)
+    torch.cuda.synchronize()
+    tol = error_bound(ce, 3, r, shape, dtype, plan.info["path"], STEPS3, 1.0)
+    for lo in WINDOWS3:
+        want = oracle.window(a0, ce, r, shape, st.BC_ZERO, STEPS3, lo, (8, 8, 8))
+        got = res[lo[0]:lo[0] + 8, lo[1]:lo[1] + 8, lo[2]:lo[2] + 8].cpu().numpy().astype(np.float64)
+        assert np.abs(got - want).max() <= tol, (lo, np.abs(got - want).max(), tol)
+    plan.close()
+    del x, res
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("path,tb", [(st.PATH_AUTO, 0), (st.PATH_GATHER, 0), (st.PATH_MFMA, 0),
+                                     (st.PATH_GATHER, 5), (st.PATH_GATHER, 8)])
+def test_fullsize_512_fp64_star(path, tb):
+    """The 512^2 FP64 five-point star (centre 0.5, neighbours 0.125, zero halo,
+    10 steps) on every path the latency benchmark times, against the oracle
+    on the whole grid."""
+    torch = torch_cuda()
+    c = np.zeros((3, 3))
+    c[1, 1] = 0.5
+    c[0, 1] = c[2, 1] = c[1, 0] = c[1, 2] = 0.125
+    a0 = inputs.grid((512, 512), seed=101, dtype=np.float64)
+    plan = st.Plan((512, 512), 1, st.STAR, c, boundary=st.BC_ZERO, dtype=st.F64, path=path, time_block=tb)
+    x = torch.from_numpy(a0).cuda()
+    got = plan.run_steps(x, torch.empty_like(x), 10).cpu().numpy()
+    want = oracle.run(a0, c, 1, st.STAR, st.BC_ZERO, 10)
+    tol = error_bound(c, 2, 1, st.STAR, st.F64, st.PATH_GATHER, 10, 1.0)
+    assert np.abs(got - want).max() <= tol
+    plan.close()
