@@ -76,7 +76,10 @@ typedef enum { STENCIL_BC_ZERO = 0, STENCIL_BC_PERIODIC = 1 } stencil_boundary_t
 typedef enum { STENCIL_F32 = 0, STENCIL_F64 = 1 } stencil_dtype_t;
 
 typedef enum {
-  STENCIL_PATH_AUTO = 0,        /* library picks (see stencil_plan_info) */
+  STENCIL_PATH_AUTO = 0,        /* library picks, from measurements on MI355X: MFMA for F32 boxes of
+                                   order >= 3 (2D and 3D) and 2D GENERAL stencils, GATHER otherwise;
+                                   2D grids whose column extent is not a multiple of 4 take MFMA;
+                                   stencil_plan_info reports the choice */
   STENCIL_PATH_GATHER = 1,      /* gather-form vector kernel, Eq. (1) */
   STENCIL_PATH_MFMA = 2,        /* outer-product form on MFMA in the grid dtype (FP32 or FP64) */
   STENCIL_PATH_MFMA_BF16X3 = 3, /* outer-product form, BF16 hi/lo split operands (3 products), FP32 accumulate; F32 grids */
@@ -105,9 +108,10 @@ typedef struct {
   int32_t path;         /* stencil_path_t */
   int32_t lines;        /* stencil_lines_t */
   int32_t block_n;      /* edge n of the MFMA output block: 0 = library choice; 4 selects
-                           v_mfma_f32_4x4x1_16b blocks (FP32 2D box and parallel-line star only),
-                           16 the 16x16 instructions; any other resolved block edge: EUNSUPPORTED;
-                           ignored by the GATHER path */
+                           v_mfma_f32_4x4x1_16b blocks (F32 only: 2D boxes, parallel-line and
+                           GENERAL covers; 3D stars and boxes; the default there), 16 the 16x16
+                           instructions (F64, 2D orthogonal stars, 3D boxes up to order 2); any
+                           other resolved block edge: EUNSUPPORTED; ignored by the GATHER path */
   int32_t chunk;        /* output rows (2D) or i-planes (3D) per workgroup work item: 0 = library
                            choice; rounded up to the kernel's row block and clipped to the extent */
   int32_t time_block;   /* steps fused per launch (time blocking): 0 or 1 = one step per launch;
@@ -128,7 +132,7 @@ typedef struct {
   int32_t taps;          /* nonzero-capable taps: (2r+1)^d box, 2rd+1 star (Section 3.4) */
   int32_t tile_rows;     /* output tile of one workgroup: rows (2D) or j-rows (3D) */
   int32_t tile_cols;     /* ... contiguous columns */
-  int32_t block_n;       /* edge n of one MFMA output block (16); 0 for GATHER */
+  int32_t block_n;       /* edge n of one MFMA output block (4 or 16); 0 for GATHER */
   int32_t mfma_lines;    /* coefficient lines issued on the matrix cores */
   int32_t valu_lines;    /* single-weight lines issued as vector FMAs */
   int32_t k_rows;        /* rank-1 updates per n x n block as issued, incl. MFMA K padding */
