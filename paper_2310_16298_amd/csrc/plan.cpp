@@ -580,8 +580,14 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     const int64_t t0 = ceil_div(d.dims[1], kTJ), t1 = ceil_div(d.dims[2], kTK);
     const int64_t tiles = t0 * t1;
     // about 2048 work items, each at least 4r planes deep (the 2r warm-up
-    // planes of a chunk are re-read)
-    int64_t chunk = d.dims[0] * tiles / 2048;
+    // planes of a chunk are re-read, from HBM when the previous chunk's
+    // workgroup read them long before); fewer, deeper items where a sweep on
+    // 512^3 measured them faster: FP64 stars and 27-point box (larger windows,
+    // fewer workgroups per CU) and low-order FP32 stars on the gather kernel
+    int64_t items = 2048;
+    if (d.dtype == STENCIL_F64 && (!box || R == 1)) items = (!box && R == 4) ? 256 : 512;
+    else if (d.dtype == STENCIL_F32 && !box && R <= 3 && path == STENCIL_PATH_GATHER) items = R == 1 ? 512 : 1024;
+    int64_t chunk = d.dims[0] * tiles / items;
     // boxes of radius >= 2 spend most of their time in arithmetic, which the
     // 2r warm-up planes repeat: deeper chunks while ~1024 items remain
     // (measured on 512^3: +5-10 % at 64 planes)
