@@ -44,26 +44,30 @@ struct DmaWindow {
   static constexpr int WCOL0 = 4 - R;           // LDS column of window column 0 (global j0 - r)
   static constexpr int ROWS = BM + 2 * R;
   static constexpr int NWAVES = NT / 64;
-  // Loads per wave for `rows` window rows.
-  static constexpr int npw(int rows) { return ((rows * LPR + 63) / 64 + NWAVES - 1) / NWAVES; }
-  static constexpr int NPW_FULL = npw(ROWS);
-  // elements per buffer, incl. slack for the lanes past the window end
-  static constexpr int BUF = NPW_FULL * NWAVES * 64 * VEC;
+  // Load instructions per window (1 KiB each, all lanes active; lanes past
+  // the window end read the zero line into the last instruction's tail),
+  // spread round-robin over the waves: waves 0 .. NREM-1 issue NPW_FULL of
+  // them, the others NPW_FULL - 1.  The buffer holds exactly NI instructions,
+  // which keeps two of the largest windows (FP32 r = 4: 25 KiB each) small
+  // enough for three workgroups per CU.
+  static constexpr int NI = (ROWS * LPR + 63) / 64;
+  static constexpr int NPW_FULL = (NI + NWAVES - 1) / NWAVES;
+  static constexpr int NREM = NI - (NPW_FULL - 1) * NWAVES;
+  static constexpr int BUF = NI * 64 * VEC;  // elements per buffer
   static_assert(R <= 4, "window covers at most 4 halo columns");
-  static_assert(NPW_FULL < 64, "vmcnt range");
+  static_assert(NPW_FULL < 64 && NPW_FULL >= 2, "vmcnt range");
 
-  // Issue the loads of NROWS window rows, global rows grow0 .., into LDS rows
-  // starting at `dst` (a row boundary of a buffer).  Every wave issues exactly
-  // npw(NROWS) instructions with all lanes active.
-  template <int NROWS>
+  // Issue the loads of one window, global rows grow0 .. grow0 + ROWS - 1,
+  // into the buffer at `dst`.
   static __device__ __forceinline__ void issue(T* dst, const T* __restrict__ src,
                                                const T* __restrict__ zeros, int64_t M, int64_t N,
                                                int64_t grow0, int64_t j0, bool periodic) {
-    constexpr int LINES = NROWS * LPR, NP = npw(NROWS);
+    constexpr int LINES = ROWS * LPR;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
+    for (int k = 0; k < NPW_FULL; ++k) {
       const int inst = k * NWAVES + w;
+      if (inst >= NI) break;  // wave-uniform
       const int line = inst * 64 + lane;
       const T* s = zeros;
       if (line < LINES) {
@@ -74,6 +78,13 @@ struct DmaWindow {
       }
       __builtin_amdgcn_global_load_lds((const void*)s, (lds_void_t*)(dst + inst * 64 * VEC), 16, 0, 0);
     }
+  }
+
+  // After issuing window b+1: wait until this wave's loads of window b (and
+  // everything older) have completed.
+  static __device__ __forceinline__ void wait_previous() {
+    if ((threadIdx.x >> 6) < NREM) wait_vm<NPW_FULL>();
+    else wait_vm<NPW_FULL - 1>();
   }
 
   // s_waitcnt vmcnt(n): vmcnt[3:0] in bits 3:0, vmcnt[5:4] in bits 15:14;
@@ -118,14 +129,14 @@ __device__ __forceinline__ void dma_block_loop(typename D::elem_t* bufs, const K
   const T* __restrict__ zeros = (const T*)a.zeros;
   const bool periodic = a.periodic != 0;
   const int nb = (int)((sp.i1 - sp.i0 + BM - 1) / BM);
-  D::template issue<D::ROWS>(bufs, in, zeros, a.d0, a.d1, sp.i0 - R, sp.j0, periodic);
+  D::issue(bufs, in, zeros, a.d0, a.d1, sp.i0 - R, sp.j0, periodic);
   for (int bi = 0; bi < nb; ++bi) {
     const int64_t ib = sp.i0 + (int64_t)bi * BM;
     T* cur = bufs + (bi & 1) * D::BUF;
     T* nxt = bufs + ((bi + 1) & 1) * D::BUF;
     if (bi + 1 < nb) {
-      D::template issue<D::ROWS>(nxt, in, zeros, a.d0, a.d1, ib + BM - R, sp.j0, periodic);
-      D::template wait_vm<D::NPW_FULL>();
+      D::issue(nxt, in, zeros, a.d0, a.d1, ib + BM - R, sp.j0, periodic);
+      D::wait_previous();
     } else {
       D::template wait_vm<0>();
     }
