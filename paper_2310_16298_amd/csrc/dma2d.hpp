@@ -101,7 +101,7 @@ struct DmaWindow {
 // Grids too small for ~2048 items of that length use shorter chunks (>= BM).
 inline int32_t dma_chunk(const KArgs& a, int TN, int R, bool box, int32_t chunk) {
   if (chunk > 0) return chunk;
-  static const int32_t kBox[5] = {0, 16, 64, 128, 128}, kStar[5] = {0, 16, 16, 32, 64};
+  static const int32_t kBox[5] = {0, 16, 64, 64, 64}, kStar[5] = {0, 16, 16, 32, 64};
   const int64_t strips = (a.d1 + TN - 1) / TN;
   const int64_t fill = a.d0 * strips / 2048;
   const int64_t best = box ? kBox[R] : kStar[R];
