@@ -9,7 +9,9 @@ namespace stencil {
 template <typename T, int R, bool BOX>
 static Kernel pick_gather2d(KArgs& a, int32_t chunk) {
   constexpr int TN = Gather2DDma<T>::TN;
-  if (dma2d_ok(a))
+  // FP32 grids at most one 64-column tile wide: the 64 x 64 tiled kernel
+  // (a 256-column window would leave three quarters of its lanes idle)
+  if (dma2d_ok(a) && !(sizeof(T) == 4 && a.d1 <= kTile2D))
     return kernel_of<gather2d_dma_kernel<T, R, BOX>, gather2d_dma_batch<T, R, BOX>>(
         strip_grid(a, TN, kDmaBM, 1024, dma_chunk(a, TN, R, BOX, chunk)));
   return kernel_of<gather2d_kernel<T, R, BOX>, gather2d_batch<T, R, BOX>>(strip_grid(a, kTile2D, kTile2D, 2048, chunk));

@@ -412,9 +412,12 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     if (nd == 3) {  // also the r = 4 stars: the hybrid outer products lead by 4 % (FP32) / 10 % (FP64)
       path = (f32 && box && R >= 3) || (!box && R == 4) ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
     } else {
+      // grids at most 64 columns wide (the paper's smallest Table 3 shapes):
+      // outer products for FP64 and for FP32 stars, measured ahead there
       const bool dma_cols = d.dims[1] % 4 == 0;
       const bool heavy = f32 && (general || (box && R >= 3));
-      path = dma_cols && !heavy ? STENCIL_PATH_GATHER : STENCIL_PATH_MFMA;
+      const bool narrow = d.dims[1] <= 64 && (!f32 || !box);
+      path = dma_cols && !heavy && !narrow ? STENCIL_PATH_GATHER : STENCIL_PATH_MFMA;
     }
   }
   const bool split = path == STENCIL_PATH_MFMA_BF16X3 || path == STENCIL_PATH_MFMA_F16X3;

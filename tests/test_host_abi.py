@@ -396,8 +396,12 @@ def test_auto_path_choice(lib, shape):
     for r in (1, 2, 3, 4):
         c = inputs.coefficients(2, r, shape, seed=3, dtype=np.float64)
         heavy = shape == inputs.BOX and r >= 3
-        assert st.describe((64, 64), r, shape, c, dtype=st.F32)["path"] == (st.PATH_MFMA if heavy else st.PATH_GATHER)
-        assert st.describe((64, 64), r, shape, c, dtype=st.F64)["path"] == st.PATH_GATHER
+        assert st.describe((96, 96), r, shape, c, dtype=st.F32)["path"] == (st.PATH_MFMA if heavy else st.PATH_GATHER)
+        assert st.describe((96, 96), r, shape, c, dtype=st.F64)["path"] == st.PATH_GATHER
+        # at most 64 columns: FP64 and FP32 stars take the outer products
+        narrow = shape == inputs.STAR or heavy
+        assert st.describe((64, 64), r, shape, c, dtype=st.F32)["path"] == (st.PATH_MFMA if narrow else st.PATH_GATHER)
+        assert st.describe((64, 64), r, shape, c, dtype=st.F64)["path"] == st.PATH_MFMA
         for dt in (st.F32, st.F64):
             assert st.describe((64, 66), r, shape, c, dtype=dt)["path"] == st.PATH_MFMA
         g = c.copy()
