@@ -79,7 +79,8 @@ typedef enum {
   STENCIL_PATH_AUTO = 0,        /* library picks, from measurements on MI355X: MFMA for F32 boxes of
                                    order >= 3 (2D and 3D), 3D stars of order 4 and 2D GENERAL
                                    stencils, GATHER otherwise; 2D grids whose column extent is not
-                                   a multiple of 4, or at most 64 (F64, F32 stars), take MFMA;
+                                   a multiple of 4, or at most 64 (stars, the F64 9-point box),
+                                   take MFMA;
                                    stencil_plan_info reports the choice */
   STENCIL_PATH_GATHER = 1,      /* gather-form vector kernel, Eq. (1) */
   STENCIL_PATH_MFMA = 2,        /* outer-product form on MFMA in the grid dtype (FP32 or FP64) */

@@ -413,10 +413,10 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       path = (f32 && box && R >= 3) || (!box && R == 4) ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
     } else {
       // grids at most 64 columns wide (the paper's smallest Table 3 shapes):
-      // outer products for FP64 and for FP32 stars, measured ahead there
+      // outer products for stars and the FP64 9-point box, measured ahead there
       const bool dma_cols = d.dims[1] % 4 == 0;
       const bool heavy = f32 && (general || (box && R >= 3));
-      const bool narrow = d.dims[1] <= 64 && (!f32 || !box);
+      const bool narrow = d.dims[1] <= 64 && (!box || (!f32 && R == 1));
       path = dma_cols && !heavy && !narrow ? STENCIL_PATH_GATHER : STENCIL_PATH_MFMA;
     }
   }

@@ -398,10 +398,11 @@ def test_auto_path_choice(lib, shape):
         heavy = shape == inputs.BOX and r >= 3
         assert st.describe((96, 96), r, shape, c, dtype=st.F32)["path"] == (st.PATH_MFMA if heavy else st.PATH_GATHER)
         assert st.describe((96, 96), r, shape, c, dtype=st.F64)["path"] == st.PATH_GATHER
-        # at most 64 columns: FP64 and FP32 stars take the outer products
+        # at most 64 columns: stars and the FP64 9-point box take the outer products
         narrow = shape == inputs.STAR or heavy
         assert st.describe((64, 64), r, shape, c, dtype=st.F32)["path"] == (st.PATH_MFMA if narrow else st.PATH_GATHER)
-        assert st.describe((64, 64), r, shape, c, dtype=st.F64)["path"] == st.PATH_MFMA
+        narrow64 = shape == inputs.STAR or r == 1
+        assert st.describe((64, 64), r, shape, c, dtype=st.F64)["path"] == (st.PATH_MFMA if narrow64 else st.PATH_GATHER)
         for dt in (st.F32, st.F64):
             assert st.describe((64, 66), r, shape, c, dtype=dt)["path"] == st.PATH_MFMA
         g = c.copy()
