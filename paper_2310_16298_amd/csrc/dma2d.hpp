@@ -99,12 +99,14 @@ struct DmaWindow {
 // MI355X (8192^2 FP32): short chunks keep many workgroups in flight, at the
 // cost of 2r re-read halo rows per chunk, so the best length grows with r.
 // Grids too small for ~2048 items of that length use shorter chunks (>= BM).
-inline int32_t dma_chunk(const KArgs& a, int TN, int R, bool box, int32_t chunk) {
+// kind: 0 star, 1 box (outer products and gather), 2 split-precision kernel
+// (128-column strips: its per-block split pass favours long chunks).
+inline int32_t dma_chunk(const KArgs& a, int TN, int R, int kind, int32_t chunk) {
   if (chunk > 0) return chunk;
   static const int32_t kBox[5] = {0, 16, 64, 64, 64}, kStar[5] = {0, 16, 16, 32, 64};
   const int64_t strips = (a.d1 + TN - 1) / TN;
   const int64_t fill = a.d0 * strips / 2048;
-  const int64_t best = box ? kBox[R] : kStar[R];
+  const int64_t best = kind == 2 ? 128 : kind == 1 ? kBox[R] : kStar[R];
   return (int32_t)(fill < best ? (fill < 16 ? 16 : fill) : best);
 }
 

@@ -8,7 +8,7 @@ namespace stencil {
 
 template <int KIND, int R>
 static Kernel pick_split2d(KArgs& a, int32_t chunk) {
-  if (dma2d_ok(a)) return kernel_of<split2d_dma_kernel<KIND, R>, split2d_dma_batch<KIND, R>>(strip_grid(a, kSplitTN, kDmaBM, 1024, dma_chunk(a, kSplitTN, R, true, chunk)));
+  if (dma2d_ok(a)) return kernel_of<split2d_dma_kernel<KIND, R>, split2d_dma_batch<KIND, R>>(strip_grid(a, kSplitTN, kDmaBM, 1024, dma_chunk(a, kSplitTN, R, 2, chunk)));
   return kernel_of<split2d_kernel<KIND, R>, split2d_batch<KIND, R>>(strip_grid(a, 64, 64, 2048, chunk));
 }
 
