@@ -71,6 +71,18 @@ __device__ __forceinline__ floatx4 mfma4_group(float a, float b, floatx4 c, int 
   }
 }
 
+// v_mfma_f32_4x4x1_16b_f32 with the A operand of block 4 g (lanes 16 g ..
+// 16 g + 3) broadcast to all 16 blocks (cbsz = 4, abid = 4 g): with the same
+// packing as mfma4_group, a register's lane group g holds one A vector.
+__device__ __forceinline__ floatx4 mfma4_agroup(float a, float b, floatx4 c, int g) {
+  switch (g) {
+    case 0: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 0, 0);
+    case 1: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 4, 0);
+    case 2: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 8, 0);
+    default: return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, 12, 0);
+  }
+}
+
 // Index of global coordinate g under the boundary rule, or -1 for a zero-halo
 // point outside [0, n).  The modulo branch is taken only at grid faces.
 __device__ __forceinline__ int64_t map_index(int64_t g, int64_t n, bool periodic) {

@@ -271,10 +271,17 @@ __device__ __forceinline__ void mfma2d_b4c_dma_item(const KArgs& a, int item) {
   float* __restrict__ out = (float*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const Strip2D sp = decode_strip(a, item, TN);
+  // band vectors packed four to a register (lane group g holds vector 4 k + g),
+  // selected by the B lane-group broadcast (lines along i) or the A block
+  // broadcast (lines along j)
+  constexpr int NC = W * NB, NP = (NC + 3) / 4;
   const float* __restrict__ frag = (const float*)a.frag;
-  float af[W * NB];
+  float af[NP];
 #pragma unroll
-  for (int c = 0; c < W * NB; ++c) af[c] = frag[c * 64 + lane];
+  for (int k = 0; k < NP; ++k) {
+    const int c = 4 * k + (lane >> 4);
+    af[k] = c < NC ? frag[c * 64 + lane] : 0.0f;
+  }
   const int nlines = (a.lcode1 >> 27) & 15;
   const int orow = lane & 3;
   const int64_t gj = sp.j0 + 64 * w + 4 * (lane >> 2);
@@ -297,7 +304,8 @@ __device__ __forceinline__ void mfma2d_b4c_dma_item(const KArgs& a, int item) {
           for (int s = 0; s < 4; ++s) {
             const int d = x - 4 * s;
             if (d < 0 || d >= NB) continue;
-            acc[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv, af[k * NB + d], acc[s], 0, 0, 0);
+            const int c = k * NB + d;
+            acc[s] = mfma4_group(hv, af[c >> 2], acc[s], c & 3);
           }
         }
       } else {
@@ -306,7 +314,7 @@ __device__ __forceinline__ void mfma2d_b4c_dma_item(const KArgs& a, int item) {
         for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int e = 0; e < NB; ++e)
-            acc[s] = __builtin_amdgcn_mfma_f32_4x4x1f32(af[k * NB + e], colp[4 * s * D::PITCH + e], acc[s], 0, 0, 0);
+            acc[s] = mfma4_agroup(af[(k * NB + e) >> 2], colp[4 * s * D::PITCH + e], acc[s], (k * NB + e) & 3);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
