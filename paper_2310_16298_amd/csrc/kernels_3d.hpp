@@ -452,10 +452,15 @@ __device__ __forceinline__ void mfma3d_b4_item(const KArgs& a, int item) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int orow = lane & 3, beta = lane >> 2;
 
+  // band vectors packed four to a register (lane group g holds vector 4 k + g)
+  constexpr int NC = NL * NB, NP = (NC + 3) / 4;
   const float* __restrict__ frag = (const float*)a.frag;
-  float af[NL * NB];
+  float af[NP];
 #pragma unroll
-  for (int c = 0; c < NL * NB; ++c) af[c] = frag[c * 64 + lane];
+  for (int k = 0; k < NP; ++k) {
+    const int c = 4 * k + (lane >> 4);
+    af[k] = c < NC ? frag[c * 64 + lane] : 0.0f;
+  }
   float ci[W];  // star: i-arm weights C^g[a][r][r]
   if constexpr (!BOX) {
     const float* __restrict__ c = (const float*)a.coef;
@@ -486,7 +491,8 @@ __device__ __forceinline__ void mfma3d_b4_item(const KArgs& a, int item) {
             for (int s = 0; s < 2; ++s) {
               const int d = x - 4 * s;
               if (d < 0 || d >= NB) continue;
-              ring[2 * R - ap][s] = __builtin_amdgcn_mfma_f32_4x4x1f32(hv, af[l * NB + d], ring[2 * R - ap][s], 0, 0, 0);
+              const int c = l * NB + d;
+              ring[2 * R - ap][s] = mfma4_group(hv, af[c >> 2], ring[2 * R - ap][s], c & 3);
             }
           }
           __builtin_amdgcn_sched_barrier(0);
@@ -498,7 +504,7 @@ __device__ __forceinline__ void mfma3d_b4_item(const KArgs& a, int item) {
           for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int e = 0; e < NB; ++e)
-              ring[R][s] = __builtin_amdgcn_mfma_f32_4x4x1f32(af[NB + e], colp[4 * s * PW::PITCH + e], ring[R][s], 0, 0, 0);
+              ring[R][s] = mfma4_agroup(af[(NB + e) >> 2], colp[4 * s * PW::PITCH + e], ring[R][s], (NB + e) & 3);
           // i arm: this plane's centre values reach output plane i - ap + r
 #pragma unroll
           for (int s = 0; s < 2; ++s) {
