@@ -446,6 +446,8 @@ def workload_cover(args, torch, st, inputs) -> dict:
     m = z.copy(); m[w - 1, :] = True; m[:, 0] = True; pats["l_shape"] = m
     m = z.copy(); m[1, :] = True; m[5, :] = True; m[:, 2] = True; pats["two_rows_one_column"] = m
     pats["random_25pct"] = np.random.default_rng(6100).random((w, w)) < 0.25
+    m = z.copy(); np.fill_diagonal(m, True); pats["diagonal"] = m
+    m = z.copy(); np.fill_diagonal(m, True); m[np.arange(w), w - 1 - np.arange(w)] = True; pats["both_diagonals"] = m
     a0 = torch.from_numpy(inputs.grid(dims, seed=6000, dtype=np.float32)).cuda()
     stream = torch.cuda.Stream()
     out = {"metric": "GStencil/s", "workload": "2D order-4 irregular stencils, 8192^2 FP32, periodic, 100 steps",
@@ -456,13 +458,17 @@ def workload_cover(args, torch, st, inputs) -> dict:
         rows, cols = st.line_cover(c, r)
         res = {"nonzeros": int(mask.sum()), "cover_lines": len(rows) + len(cols)}
         for label, shape, path in (("general_mfma_cover", st.GENERAL, st.PATH_MFMA),
+                                   ("general_gather_nonzero_taps", st.GENERAL, st.PATH_GATHER),
+                                   ("general_auto", st.GENERAL, st.PATH_AUTO),
                                    ("box_mfma_all_columns", st.BOX, st.PATH_MFMA),
                                    ("box_gather_all_taps", st.BOX, st.PATH_GATHER)):
             plan = st.Plan(dims, r, shape, c, boundary=st.BC_PERIODIC, dtype=st.F32, path=path)
             times = _time_solve(torch, plan, a0, steps, args.steps, args.warmup, stream)
             res[label] = round(float(dims[0] * dims[1] * steps / (np.median(times) * 1e-3) / 1e9), 2)
-            if shape == st.GENERAL:
+            if shape == st.GENERAL and path == st.PATH_MFMA:
                 res["plan_lines"] = plan.info["mfma_lines"]
+            if path == st.PATH_AUTO:
+                res["auto_path"] = st.PATH_NAMES[plan.info["path"]]
             plan.close()
         out["cases"][name] = res
         print(f"[bench] cover {name}: {res}", file=sys.stderr, flush=True)

@@ -63,8 +63,10 @@ typedef enum {
  * direction, a weight on a column line and a row line being carried by the
  * column line only (on FP32 n = 4 blocks, where a line along j costs about
  * 1.5 lines along i, the nonzero columns alone are used when they are not
- * dearer); other paths and 3D treat GENERAL as BOX.  The line option (lines)
- * must be AUTO for GENERAL. */
+ * dearer); the 2D GATHER path computes only the nonzero weights (a tap list
+ * in the plan) when at most half the box is nonzero, every tap otherwise;
+ * other paths and 3D treat GENERAL as BOX.  The line option (lines) must be
+ * AUTO for GENERAL. */
 typedef enum { STENCIL_STAR = 0, STENCIL_BOX = 1, STENCIL_GENERAL = 2 } stencil_shape_t;
 
 /* Boundary rule (the paper states none):
@@ -78,7 +80,11 @@ typedef enum { STENCIL_F32 = 0, STENCIL_F64 = 1 } stencil_dtype_t;
 typedef enum {
   STENCIL_PATH_AUTO = 0,        /* library picks, from measurements on MI355X: MFMA for F32 boxes of
                                    order >= 3 (2D and 3D), 3D stars of order 4 and 2D GENERAL
-                                   stencils, GATHER otherwise; 2D grids whose column extent is not
+                                   stencils (FP32 grids wider than 64 columns: the line cover or
+                                   the nonzero-tap gather, whichever a cost fitted on MI355X
+                                   prefers -- 12290 + 403 n per point for n nonzero taps against
+                                   12910 + 1530 L (2r+4)/12 for L lines), GATHER otherwise; 2D
+                                   grids whose column extent is not
                                    a multiple of 4, or at most 64 (stars, the F64 9-point box),
                                    take MFMA;
                                    stencil_plan_info reports the choice */

@@ -415,8 +415,17 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       // grids at most 64 columns wide (the paper's smallest Table 3 shapes):
       // outer products for stars and the FP64 9-point box, measured ahead there
       const bool dma_cols = d.dims[1] % 4 == 0;
-      const bool heavy = f32 && (general || (box && R >= 3));
+      bool heavy = f32 && (general || (box && R >= 3));
       const bool narrow = d.dims[1] <= 64 && (!box || (!f32 && R == 1));
+      if (general && f32 && dma_cols && d.dims[1] > 64) {
+        // GENERAL: the nonzero-tap gather against the line cover.  Time per
+        // point fitted on MI355X (order 4, 8192^2 FP32), in units of 1e-7 us:
+        // 12290 + 403 n for n nonzero taps, 12910 + 1530 L for L lines, the
+        // line term scaled by the band length (2r + 4) / 12 for other orders.
+        int rr[9] = {0}, cc[9] = {0};
+        const int L = general_cover(cg, R, d.block_n != 16, rr, cc);
+        if (12 * 403 * in.taps < 12 * 620 + 1530 * L * (4 + 2 * R)) heavy = false;
+      }
       path = dma_cols && !heavy && !narrow ? STENCIL_PATH_GATHER : STENCIL_PATH_MFMA;
     }
   }
@@ -469,8 +478,24 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       lines = STENCIL_LINES_AUTO;
     } else if (path == STENCIL_PATH_GATHER) {
       rs->family = FAM_GATHER2D;
-      rs->pick = find_gather2d(d.dtype, R, box);
-      in.executed_flops_per_point = 2.0 * in.taps;
+      // GENERAL with at most half the box nonzero: the nonzero-tap gather
+      // (Section 3.5: weights left to vector units); denser ones: every tap
+      const bool sparse = general && 2 * in.taps <= W * W;
+      rs->pick = sparse ? find_sparse2d(d.dtype, R) : find_gather2d(d.dtype, R, box);
+      in.executed_flops_per_point = 2.0 * (sparse || !general ? in.taps : W * W);
+      if (sparse) {  // table of the nonzero taps
+        const size_t es = dtype_size(d.dtype);
+        rs->frag.assign(kSparseWeightOffset + (size_t)kSparseTapMax * es, 0);
+        int nt = 0;
+        for (int t = 0; t < ncoef; ++t) {
+          if (cg[t] == 0.0) continue;
+          put<int32_t>(rs->frag, 1 + nt, (int32_t)((t / W) << 8 | (t % W)));
+          if (d.dtype == STENCIL_F64) put<double>(rs->frag, kSparseWeightOffset / 8 + nt, cg[t]);
+          else put<float>(rs->frag, kSparseWeightOffset / 4 + nt, (float)cg[t]);
+          ++nt;
+        }
+        put<int32_t>(rs->frag, 0, nt);
+      }
       lines = STENCIL_LINES_AUTO;
     } else if (path == STENCIL_PATH_MFMA) {
       rs->family = FAM_MFMA2D;

@@ -53,6 +53,11 @@ int line_cover(const double* cg2d, int R, int* rows_out, int* cols_out);
 
 // Kernel lookups, one per family (defined next to the kernels).
 Picker find_gather2d(int dtype, int R, bool box);
+// Nonzero-tap gather of GENERAL 2D stencils.  Its table in the fragment
+// buffer: int32 tap count at byte 0, int32 codes (row << 8 | column) from
+// byte 4, weights in the arithmetic dtype from byte kSparseWeightOffset.
+constexpr int kSparseTapMax = 81, kSparseWeightOffset = 512;
+Picker find_sparse2d(int dtype, int R);
 Picker find_mfma2d(int dtype, int R, int variant);
 Picker find_mfma2d_b4(int R, bool box);
 Picker find_mfma2d_b4c(int R);  // line cover, n = 4 (FP32)

@@ -125,3 +125,32 @@ def test_batch_rejects_overlapping_buffers():
     with pytest.raises(st.StencilError) as e:
         st.Batch([plan, plan], [a, b], [b, a])
     assert e.value.status == st.EALIAS
+
+
+def test_batch_general_nonzero_tap_gather():
+    """GENERAL members on the nonzero-tap gather in one batch with a box member:
+    each equals its own launch and the oracle."""
+    torch = torch_cuda()
+    specs = [((130, 264), 4, np.float32, st.F32, np.eye(9)),
+             ((70, 132), 2, np.float64, st.F64, np.eye(5)[::-1] * 0.3),
+             ((96, 516), 3, np.float32, st.F32, None)]
+    ms = []
+    for k, (dims, r, ndt, dt, c) in enumerate(specs):
+        shape = st.BOX if c is None else st.GENERAL
+        if c is None:
+            c = inputs.coefficients(2, r, st.BOX, seed=7300, dtype=np.float64)
+        a0 = inputs.grid(dims, seed=7310 + k, dtype=ndt)
+        plan = st.Plan(dims, r, shape, c, boundary=st.BC_PERIODIC, dtype=dt, path=st.PATH_GATHER)
+        x = torch.from_numpy(a0).cuda()
+        ms.append((plan, c, a0, x, torch.empty_like(x), r, dt))
+    batch = st.Batch([m[0] for m in ms], [m[3] for m in ms], [m[4] for m in ms])
+    idx = batch.run_steps(3)
+    torch.cuda.synchronize()
+    for plan, c, a0, x, y, r, dt in ms:
+        got = (x if idx == 0 else y).cpu().numpy()
+        assert np.array_equal(got, _alone(torch, plan, a0, 3))
+        ce = eff_coeffs(c, dt)
+        want = oracle.run(a0.astype(np.float64), ce, r, st.BOX, st.BC_PERIODIC, 3)
+        tol = error_bound(ce, 2, r, st.BOX, dt, st.PATH_GATHER, 3, np.abs(a0).max())
+        assert np.abs(got.astype(np.float64) - want).max() <= tol
+    batch.close()

@@ -100,3 +100,55 @@ def test_general_pure_shift_every_offset(r):
             got = plan.run_steps(x, torch.empty_like(x), 1).cpu().numpy()
             assert np.array_equal(got, np.roll(a0, shift=(r - a, r - b), axis=(0, 1))), (a, b)
             plan.close()
+
+
+# The gather path of GENERAL stencils walks the nonzero taps only (direct-to-
+# LDS windows: column extent a multiple of 4 and wider than 64 FP32 columns;
+# other extents take the tiled all-tap gather kernel).
+@pytest.mark.parametrize("dims", [(150, 260), (37, 516), (100, 203), (48, 64)])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("dtype", [st.F32, st.F64])
+@pytest.mark.parametrize("bc", [st.BC_ZERO, st.BC_PERIODIC])
+def test_general_sparse_gather_parity(dims, r, dtype, bc):
+    torch = torch_cuda()
+    a0 = inputs.grid(dims, seed=2000 + r, dtype=np.float32 if dtype == st.F32 else np.float64)
+    for name, mask in patterns(r).items():
+        c = _coeffs(mask, 2100 + r)
+        plan = st.Plan(dims, r, st.GENERAL, c, boundary=bc, dtype=dtype, path=st.PATH_GATHER)
+        assert plan.info["taps"] == int(mask.sum())
+        x = torch.from_numpy(a0).cuda()
+        got = plan.run_steps(x, torch.empty_like(x), 2).cpu().numpy().astype(np.float64)
+        ce = eff_coeffs(c, dtype)
+        want = oracle.run(a0, ce, r, st.BOX, bc, 2)
+        tol = error_bound(ce, 2, r, st.BOX, dtype, st.PATH_GATHER, 2, np.abs(a0).max())
+        assert np.abs(got - want).max() <= tol, (name, np.abs(got - want).max(), tol)
+        plan.close()
+
+
+@pytest.mark.parametrize("r", [1, 4])
+def test_general_sparse_gather_shift_and_integer(r):
+    """Single weight 1 at C^g[a][b]: the nonzero-tap gather shifts the grid by
+    (a - r, b - r) exactly; integer patterns match the oracle bit for bit."""
+    torch = torch_cuda()
+    a0 = inputs.grid((40, 264), seed=2200 + r)
+    w = 2 * r + 1
+    for a in range(w):
+        for b in range(w):
+            c = np.zeros((w, w))
+            c[a, b] = 1.0
+            plan = st.Plan(a0.shape, r, st.GENERAL, c, boundary=st.BC_PERIODIC, dtype=st.F32, path=st.PATH_GATHER)
+            x = torch.from_numpy(a0).cuda()
+            got = plan.run_steps(x, torch.empty_like(x), 1).cpu().numpy()
+            assert np.array_equal(got, np.roll(a0, shift=(r - a, r - b), axis=(0, 1))), (a, b)
+            plan.close()
+    ai = inputs.int_grid((96, 260), seed=2300 + r)
+    for name, mask in patterns(r).items():
+        c = _coeffs(mask, 2400 + r, integer=True)
+        s = float(np.abs(c).sum())
+        steps = 2 if 8 * s * s < 2.0 ** 24 else 1
+        for bc in (st.BC_ZERO, st.BC_PERIODIC):
+            plan = st.Plan(ai.shape, r, st.GENERAL, c, boundary=bc, dtype=st.F32, path=st.PATH_GATHER)
+            x = torch.from_numpy(ai).cuda()
+            got = plan.run_steps(x, torch.empty_like(x), steps).cpu().numpy().astype(np.float64)
+            assert np.array_equal(got, oracle.run(ai, c, r, st.BOX, bc, steps)), (name, bc)
+            plan.close()

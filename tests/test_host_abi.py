@@ -431,3 +431,39 @@ def test_3d_mfma_block_edge(lib):
     assert st.describe((20, 20, 20), 2, inputs.BOX, _box(3, 2), path=st.PATH_MFMA, block_n=16)["block_n"] == 16
     assert st.desc_check((20, 20, 20), 3, inputs.BOX, _box(3, 3), path=st.PATH_MFMA, block_n=16) == st.EUNSUPPORTED
     assert st.describe((20, 20, 20), 2, inputs.BOX, _box(3, 2), path=st.PATH_MFMA, dtype=st.F64)["block_n"] == 16
+
+
+def test_general_gather_choice(lib):
+    """GENERAL 2D: the gather path walks the nonzero taps when at most half the
+    box is nonzero (every tap otherwise); AUTO on FP32 direct-to-LDS grids wider
+    than 64 columns takes that gather when its fitted cost (12290 + 403 n per
+    point, n nonzero taps) is below the line cover's (12910 + 1530 L (2r+4)/12,
+    L lines), and the cover otherwise."""
+    for r in (1, 2, 3, 4):
+        w = 2 * r + 1
+        diag = np.eye(w)
+        info = st.describe((256, 256), r, st.GENERAL, diag, path=st.PATH_GATHER, dtype=st.F32)
+        assert info["taps"] == w and info["executed_flops_per_point"] == 2.0 * w
+        full = np.ones((w, w))
+        full[0, 0] = 0.0
+        info = st.describe((256, 256), r, st.GENERAL, full, path=st.PATH_GATHER, dtype=st.F64)
+        assert info["taps"] == w * w - 1 and info["executed_flops_per_point"] == 2.0 * w * w
+        for mask in (np.eye(w, dtype=bool), np.eye(w, dtype=bool) | np.eye(w, dtype=bool)[::-1],
+                     np.ones((w, w), dtype=bool), np.pad(np.ones((1, w), dtype=bool), ((w - 1, 0), (0, 0)))):
+            c = np.where(mask, 0.5, 0.0)
+            c[-1, 0] = 0.5  # plus one corner
+            n = int((c != 0).sum())
+            rows, cols = st.line_cover(c, r)
+            nzc = int((c != 0).any(axis=0).sum())
+            L = nzc if rows and 2 * nzc <= 2 * len(cols) + 3 * len(rows) else len(rows) + len(cols)
+            want = st.PATH_GATHER if 12 * 403 * n < 12 * 620 + 1530 * L * (4 + 2 * r) else st.PATH_MFMA
+            assert st.describe((256, 256), r, st.GENERAL, c, dtype=st.F32)["path"] == want, (r, n, L)
+            # narrow or ragged grids keep the cover; FP64 the gather
+            assert st.describe((64, 64), r, st.GENERAL, c, dtype=st.F32)["path"] == st.PATH_MFMA
+            assert st.describe((256, 258), r, st.GENERAL, c, dtype=st.F32)["path"] == st.PATH_MFMA
+            assert st.describe((256, 256), r, st.GENERAL, c, dtype=st.F64)["path"] == st.PATH_GATHER
+    # the measured order-4 cases: diagonals to the gather, short covers to MFMA
+    w = 9
+    assert st.describe((8192, 8192), 4, st.GENERAL, np.eye(w), dtype=st.F32)["path"] == st.PATH_GATHER
+    ell = np.zeros((w, w)); ell[w - 1, :] = 1.0; ell[:, 0] = 1.0
+    assert st.describe((8192, 8192), 4, st.GENERAL, ell, dtype=st.F32)["path"] == st.PATH_MFMA
