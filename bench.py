@@ -436,8 +436,9 @@ def workload_serve(args, torch, st, inputs) -> dict:
 
 def workload_cover(args, torch, st, inputs) -> dict:
     """Irregular 2D stencils of order 4 on 8192^2 FP32 (periodic, 100 steps):
-    the outer-product form over a minimum line cover (GENERAL) against the
-    same weights as a box (all 9 lines / all 81 taps) and the gather form."""
+    the outer-product form over a minimum line cover (GENERAL), the gather
+    over the nonzero taps, the AUTO choice between them, and the same weights
+    as a box (all 9 lines on MFMA / all 81 taps gathered)."""
     dims, r, steps = (8192, 8192), 4, 100
     w = 2 * r + 1
     z = np.zeros((w, w), dtype=bool)
@@ -448,6 +449,8 @@ def workload_cover(args, torch, st, inputs) -> dict:
     pats["random_25pct"] = np.random.default_rng(6100).random((w, w)) < 0.25
     m = z.copy(); np.fill_diagonal(m, True); pats["diagonal"] = m
     m = z.copy(); np.fill_diagonal(m, True); m[np.arange(w), w - 1 - np.arange(w)] = True; pats["both_diagonals"] = m
+    if args.patterns:
+        pats = {k: v for k, v in pats.items() if k in args.patterns.split(",")}
     a0 = torch.from_numpy(inputs.grid(dims, seed=6000, dtype=np.float32)).cuda()
     stream = torch.cuda.Stream()
     out = {"metric": "GStencil/s", "workload": "2D order-4 irregular stencils, 8192^2 FP32, periodic, 100 steps",
@@ -555,6 +558,7 @@ def main() -> int:
     ap.add_argument("--jacobi-steps", type=int, default=JACOBI_STEPS,
                     help="Jacobi steps per solve (profiling runs only; the benchmark uses 100)")
     ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch", "tune", "serve", "cover"])
+    ap.add_argument("--patterns", default="", help="cover workload: comma-separated pattern names (default all)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per offered load")
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-arena-gib", type=int, default=64)
