@@ -478,6 +478,50 @@ def workload_cover(args, torch, st, inputs) -> dict:
     return out
 
 
+def workload_cover_sweep(args, torch, st, inputs) -> dict:
+    """GENERAL 2D stencils of orders 1..4, FP32 and FP64, 8192^2 periodic, 50
+    steps: the nonzero-tap gather, the all-tap gather (the same weights as a
+    box), the line cover on MFMA and the AUTO choice, on four patterns of
+    growing density (one diagonal, ~25 % and ~45 % random, one row plus one
+    column)."""
+    dims, steps = (8192, 8192), 50
+    stream = torch.cuda.Stream()
+    out = {"metric": "GStencil/s", "workload": "2D GENERAL stencils r=1..4, 8192^2 FP32/FP64, periodic, 50 steps",
+           "cases": {}}
+    for dt, ndt, tag in ((st.F32, np.float32, "f32"), (st.F64, np.float64, "f64")):
+        x0 = torch.from_numpy(inputs.grid(dims, seed=6200, dtype=ndt)).cuda()
+        for r in (1, 2, 3, 4):
+            w = 2 * r + 1
+            rng = np.random.default_rng(6300 + r)
+            rc = np.zeros((w, w), dtype=bool)
+            rc[0, :] = True
+            rc[:, w - 1] = True
+            pats = {"diagonal": np.eye(w, dtype=bool), "random_25pct": rng.random((w, w)) < 0.25,
+                    "random_45pct": rng.random((w, w)) < 0.45, "row_and_column": rc}
+            for name, m in pats.items():
+                c = np.where(m, 1.0 / max(1, int(m.sum())), 0.0)
+                res = {"nonzeros": int(m.sum())}
+                for label, shape, path in (("nonzero_tap_gather", st.GENERAL, st.PATH_GATHER),
+                                           ("all_tap_gather", st.BOX, st.PATH_GATHER),
+                                           ("line_cover_mfma", st.GENERAL, st.PATH_MFMA),
+                                           ("auto", st.GENERAL, st.PATH_AUTO)):
+                    plan = st.Plan(dims, r, shape, c, boundary=st.BC_PERIODIC, dtype=dt, path=path)
+                    times = _time_solve(torch, plan, x0, steps, args.steps, args.warmup, stream)
+                    res[label] = round(float(dims[0] * dims[1] * steps / (np.median(times) * 1e-3) / 1e9), 1)
+                    if label == "nonzero_tap_gather":
+                        res["gather_taps_run"] = int(plan.info["executed_flops_per_point"] // 2)
+                    if label == "line_cover_mfma":
+                        res["lines"] = plan.info["mfma_lines"]
+                    if label == "auto":
+                        res["auto_path"] = st.PATH_NAMES[plan.info["path"]]
+                    plan.close()
+                key = f"{tag}_r{r}_{name}"
+                out["cases"][key] = res
+                print(f"[bench] cover_sweep {key}: {res}", file=sys.stderr, flush=True)
+        del x0
+    return out
+
+
 def workload_mixed(args, torch, st, inputs) -> dict:
     """BF16x3 / FP16x3 outer products with FP32 state for 200 steps; an FP64
     shadow trajectory (FP64 gather path) on the GPU; rel-L2 and max-abs of the
@@ -557,7 +601,7 @@ def main() -> int:
     ap.add_argument("--radii", default="1,2,3,4", help="orders to run (profiling runs use a subset)")
     ap.add_argument("--jacobi-steps", type=int, default=JACOBI_STEPS,
                     help="Jacobi steps per solve (profiling runs only; the benchmark uses 100)")
-    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch", "tune", "serve", "cover"])
+    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch", "tune", "serve", "cover", "cover_sweep"])
     ap.add_argument("--patterns", default="", help="cover workload: comma-separated pattern names (default all)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per offered load")
     ap.add_argument("--serve-warmup", type=int, default=200)
@@ -581,7 +625,7 @@ def main() -> int:
     if args.workload != "box2d":
         fn = {"star2d_512": workload_star2d_512, "grid3d": workload_grid3d, "mixed": workload_mixed,
               "batch": workload_batch, "tune": workload_tune, "serve": workload_serve,
-              "cover": workload_cover}[args.workload]
+              "cover": workload_cover, "cover_sweep": workload_cover_sweep}[args.workload]
         res = fn(args, torch, st, inputs)
         res.update({"n_gpus": 1, "data": "synthetic"})
         print(json.dumps(res))

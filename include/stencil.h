@@ -64,7 +64,9 @@ typedef enum {
  * column line only (on FP32 n = 4 blocks, where a line along j costs about
  * 1.5 lines along i, the nonzero columns alone are used when they are not
  * dearer); the 2D GATHER path computes only the nonzero weights (a tap list
- * in the plan) when at most half the box is nonzero, every tap otherwise;
+ * in the plan) when there are at most 3 / 10 / 27 / 43 of them (FP32, order
+ * 1 / 2 / 3 / 4; FP64 5 / 10 / 27 / 31: where the all-tap gather catches up
+ * on MI355X), every tap otherwise;
  * other paths and 3D treat GENERAL as BOX.  The line option (lines) must be
  * AUTO for GENERAL. */
 typedef enum { STENCIL_STAR = 0, STENCIL_BOX = 1, STENCIL_GENERAL = 2 } stencil_shape_t;

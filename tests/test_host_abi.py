@@ -434,13 +434,20 @@ def test_3d_mfma_block_edge(lib):
 
 
 def test_general_gather_choice(lib):
-    """GENERAL 2D: the gather path walks the nonzero taps when at most half the
-    box is nonzero (every tap otherwise); AUTO on FP32 direct-to-LDS grids wider
+    """GENERAL 2D: the gather path walks the nonzero taps up to a measured count
+    per order and dtype (every tap beyond it); AUTO on FP32 direct-to-LDS grids wider
     than 64 columns takes that gather when its fitted cost (12290 + 403 n per
     point, n nonzero taps) is below the line cover's (12910 + 1530 L (2r+4)/12,
     L lines), and the cover otherwise."""
+    limit = {st.F32: (0, 3, 10, 27, 43), st.F64: (0, 5, 10, 27, 31)}
     for r in (1, 2, 3, 4):
         w = 2 * r + 1
+        for dt in (st.F32, st.F64):
+            for n in range(1, w * w + 1):
+                c = np.zeros(w * w); c[:n] = 0.1
+                info = st.describe((256, 256), r, st.GENERAL, c.reshape(w, w), path=st.PATH_GATHER, dtype=dt)
+                want = 2.0 * (n if n <= limit[dt][r] else w * w)
+                assert info["taps"] == n and info["executed_flops_per_point"] == want, (r, dt, n)
         diag = np.eye(w)
         info = st.describe((256, 256), r, st.GENERAL, diag, path=st.PATH_GATHER, dtype=st.F32)
         assert info["taps"] == w and info["executed_flops_per_point"] == 2.0 * w
