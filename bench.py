@@ -522,6 +522,51 @@ def workload_cover_sweep(args, torch, st, inputs) -> dict:
     return out
 
 
+def workload_general3d(args, torch, st, inputs) -> dict:
+    """GENERAL 3D stencils of orders 1..4, FP32 and FP64, 256^3 periodic, 20
+    steps: the nonzero-tap gather, the all-tap gather (the same weights as a
+    box), the outer products over every line (MFMA) and the AUTO choice, for
+    n random nonzero taps (n = 2r+1 on the space diagonal, then 16, 32, 64,
+    128 where the box holds them)."""
+    dims, steps = (256, 256, 256), 20
+    stream = torch.cuda.Stream()
+    out = {"metric": "GStencil/s", "workload": "3D GENERAL stencils r=1..4, 256^3 FP32/FP64, periodic, 20 steps",
+           "cases": {}}
+    for dt, ndt, tag in ((st.F32, np.float32, "f32"), (st.F64, np.float64, "f64")):
+        x0 = torch.from_numpy(inputs.grid(dims, seed=6400, dtype=ndt)).cuda()
+        for r in (1, 2, 3, 4):
+            w = 2 * r + 1
+            rng = np.random.default_rng(6500 + r)
+            pats = {"space_diagonal": np.zeros((w, w, w), dtype=bool)}
+            pats["space_diagonal"][np.arange(w), np.arange(w), np.arange(w)] = True
+            for n in (16, 32, 64, 128):
+                if n < w ** 3:
+                    m = np.zeros(w ** 3, dtype=bool)
+                    m[rng.choice(w ** 3, size=n, replace=False)] = True
+                    pats[f"random_{n}"] = m.reshape(w, w, w)
+            for name, m in pats.items():
+                c = np.where(m, 1.0 / max(1, int(m.sum())), 0.0)
+                res = {"nonzeros": int(m.sum())}
+                cols = [("nonzero_tap_gather", st.GENERAL, st.PATH_GATHER), ("all_tap_gather", st.BOX, st.PATH_GATHER),
+                        ("auto", st.GENERAL, st.PATH_AUTO)]
+                if dt == st.F32 or r <= 2:  # FP64 3D boxes have outer products up to r = 2
+                    cols.insert(2, ("box_mfma", st.BOX, st.PATH_MFMA))
+                for label, shape, path in cols:
+                    plan = st.Plan(dims, r, shape, c, boundary=st.BC_PERIODIC, dtype=dt, path=path)
+                    times = _time_solve(torch, plan, x0, steps, args.steps, args.warmup, stream)
+                    res[label] = round(float(np.prod(dims) * steps / (np.median(times) * 1e-3) / 1e9), 1)
+                    if label == "nonzero_tap_gather":
+                        res["gather_taps_run"] = int(plan.info["executed_flops_per_point"] // 2)
+                    if label == "auto":
+                        res["auto_path"] = st.PATH_NAMES[plan.info["path"]]
+                    plan.close()
+                key = f"{tag}_r{r}_{name}"
+                out["cases"][key] = res
+                print(f"[bench] general3d {key}: {res}", file=sys.stderr, flush=True)
+        del x0
+    return out
+
+
 def workload_mixed(args, torch, st, inputs) -> dict:
     """BF16x3 / FP16x3 outer products with FP32 state for 200 steps; an FP64
     shadow trajectory (FP64 gather path) on the GPU; rel-L2 and max-abs of the
@@ -601,7 +646,7 @@ def main() -> int:
     ap.add_argument("--radii", default="1,2,3,4", help="orders to run (profiling runs use a subset)")
     ap.add_argument("--jacobi-steps", type=int, default=JACOBI_STEPS,
                     help="Jacobi steps per solve (profiling runs only; the benchmark uses 100)")
-    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch", "tune", "serve", "cover", "cover_sweep"])
+    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch", "tune", "serve", "cover", "cover_sweep", "general3d"])
     ap.add_argument("--patterns", default="", help="cover workload: comma-separated pattern names (default all)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per offered load")
     ap.add_argument("--serve-warmup", type=int, default=200)
@@ -625,7 +670,8 @@ def main() -> int:
     if args.workload != "box2d":
         fn = {"star2d_512": workload_star2d_512, "grid3d": workload_grid3d, "mixed": workload_mixed,
               "batch": workload_batch, "tune": workload_tune, "serve": workload_serve,
-              "cover": workload_cover, "cover_sweep": workload_cover_sweep}[args.workload]
+              "cover": workload_cover, "cover_sweep": workload_cover_sweep,
+              "general3d": workload_general3d}[args.workload]
         res = fn(args, torch, st, inputs)
         res.update({"n_gpus": 1, "data": "synthetic"})
         print(json.dumps(res))

@@ -366,6 +366,11 @@ static int general_cover(const std::vector<double>& cg, int R, bool c4, int* row
   return ncov;
 }
 
+// Largest nonzero-tap count of a GENERAL 3D stencil on the nonzero-tap
+// gather; beyond it the all-tap gather is as fast (measured on MI355X,
+// 256^3; FP32 / FP64, orders 1..4).
+static const int kSparse3DMax[2][5] = {{0, 4, 32, 120, 128}, {0, 3, 28, 112, 128}};
+
 int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   const int st = validate(desc);
   if (st != STENCIL_OK) return st;
@@ -410,7 +415,11 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     // count is not a multiple of 4 (no direct-to-LDS windows): outer products.
     const bool f32 = d.dtype == STENCIL_F32;
     if (nd == 3) {  // also the r = 4 stars: the hybrid outer products lead by 4 % (FP32) / 10 % (FP64)
-      path = (f32 && box && R >= 3) || (!box && R == 4) ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
+      // GENERAL with few nonzero taps: the nonzero-tap gather beats the box
+      // outer products up to 64 (r = 3) / 90 (r = 4) taps (256^3 FP32)
+      static const int kSparse3DAuto[5] = {0, 0, 0, 64, 90};
+      const bool few = general && in.taps <= kSparse3DAuto[R];
+      path = (f32 && box && R >= 3 && !few) || (!box && R == 4) ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
     } else {
       // grids at most 64 columns wide (the paper's smallest Table 3 shapes):
       // outer products for stars and the FP64 9-point box, measured ahead there
@@ -635,8 +644,29 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     in.tile_cols = kTK;
     if (path == STENCIL_PATH_GATHER) {
       rs->family = FAM_GATHER3D;
-      rs->pick = find_gather3d(d.dtype, R, box);
-      in.executed_flops_per_point = 2.0 * in.taps;
+      // GENERAL: the nonzero-tap gather up to the tap count where the all-tap
+      // gather catches up (measured on MI355X; FP32 / FP64, orders 1..4)
+      const bool sparse = general && in.taps <= kSparse3DMax[d.dtype == STENCIL_F64 ? 1 : 0][R];
+      rs->pick = sparse ? find_sparse3d(d.dtype, R) : find_gather3d(d.dtype, R, box);
+      in.executed_flops_per_point = 2.0 * (sparse || !general ? in.taps : W * W * W);
+      if (sparse) {  // taps grouped by coefficient plane
+        const size_t es = dtype_size(d.dtype);
+        rs->frag.assign(kSparse3DWeightOffset + (size_t)kSparse3DTapMax * es, 0);
+        int nt = 0;
+        for (int ap = 0; ap < W; ++ap) {
+          put<int32_t>(rs->frag, 1 + ap, nt);
+          for (int t = ap * W * W; t < (ap + 1) * W * W; ++t) {
+            if (cg[t] == 0.0) continue;
+            const int rem = t - ap * W * W;
+            put<int32_t>(rs->frag, kSparse3DCodeIndex + nt, (int32_t)((rem / W) << 8 | (rem % W)));
+            if (d.dtype == STENCIL_F64) put<double>(rs->frag, kSparse3DWeightOffset / 8 + nt, cg[t]);
+            else put<float>(rs->frag, kSparse3DWeightOffset / 4 + nt, (float)cg[t]);
+            ++nt;
+          }
+        }
+        put<int32_t>(rs->frag, 1 + W, nt);
+        put<int32_t>(rs->frag, 0, nt);
+      }
       lines = STENCIL_LINES_AUTO;
     } else if (path == STENCIL_PATH_MFMA) {
       if (!box && lines != STENCIL_LINES_HYBRID) return STENCIL_EUNSUPPORTED;

@@ -58,6 +58,12 @@ Picker find_gather2d(int dtype, int R, bool box);
 // byte 4, weights in the arithmetic dtype from byte kSparseWeightOffset.
 constexpr int kSparseTapMax = 81, kSparseWeightOffset = 512;
 Picker find_sparse2d(int dtype, int R);
+// 3D: int32 tap count at index 0, the first tap of each coefficient plane
+// a = 0 .. 2r at index 1 + a (index 2r + 2: the count), int32 codes
+// (j row << 8 | k column) from index kSparse3DCodeIndex, taps ordered by a,
+// weights from byte kSparse3DWeightOffset; at most kSparse3DTapMax taps.
+constexpr int kSparse3DTapMax = 128, kSparse3DCodeIndex = 16, kSparse3DWeightOffset = 1024;
+Picker find_sparse3d(int dtype, int R);
 Picker find_mfma2d(int dtype, int R, int variant);
 Picker find_mfma2d_b4(int R, bool box);
 Picker find_mfma2d_b4c(int R);  // line cover, n = 4 (FP32)

@@ -166,7 +166,8 @@ def test_mfma_box_pure_shift(r, dims):
 @pytest.mark.parametrize("density", [0.1, 0.5])
 def test_general_3d_auto(r, density):
     """Irregular 3D stencils under AUTO (outer products on n = 4 blocks from
-    r = 3, all (2r+1)^2 lines) against the oracle's full (2r+1)^3 sum."""
+    r = 3, all (2r+1)^2 lines; the nonzero-tap gather for at most 64 / 90
+    nonzero taps at r = 3 / 4) against the oracle's full (2r+1)^3 sum."""
     torch = torch_cuda()
     rng = np.random.default_rng(840 + r + int(10 * density))
     w = 2 * r + 1
@@ -176,11 +177,69 @@ def test_general_3d_auto(r, density):
     a0 = inputs.grid((14, 22, 76), seed=850 + r)
     for bc in (st.BC_ZERO, st.BC_PERIODIC):
         plan = st.Plan(a0.shape, r, st.GENERAL, cg, boundary=bc, dtype=st.F32)
-        assert plan.info["path"] == st.PATH_MFMA
+        want_path = st.PATH_GATHER if int(mask.sum()) <= {3: 64, 4: 90}[r] else st.PATH_MFMA
+        assert plan.info["path"] == want_path
         x = torch.from_numpy(a0).cuda()
         got = plan.run_steps(x, torch.empty_like(x), 2).cpu().numpy().astype(np.float64)
         ce = eff_coeffs(cg, st.F32)
         want = oracle.run(a0, ce, r, st.BOX, bc, 2)
-        tol = error_bound(ce, 3, r, st.BOX, st.F32, st.PATH_MFMA, 2, np.abs(a0).max())
+        tol = error_bound(ce, 3, r, st.BOX, st.F32, want_path, 2, np.abs(a0).max())
         assert np.abs(got - want).max() <= tol, (bc, np.abs(got - want).max(), tol)
         plan.close()
+
+
+def _sparse3d_patterns(r, seed):
+    w = 2 * r + 1
+    rng = np.random.default_rng(seed)
+    z = np.zeros((w, w, w), dtype=bool)
+    pats = {}
+    m = z.copy(); m[np.arange(w), np.arange(w), np.arange(w)] = True; pats["space_diagonal"] = m
+    m = z.copy(); m[0, 2 * r, 1] = True; pats["single"] = m
+    m = z.copy(); m[r] = np.eye(w, dtype=bool); m[:, r, r] = True; pats["plane_diagonal_plus_i_arm"] = m
+    pats["random"] = rng.random((w, w, w)) < min(0.5, 40.0 / w ** 3)
+    pats["empty"] = z
+    return pats
+
+
+# The gather path of 3D GENERAL stencils walks the nonzero taps (at most
+# 128): direct-to-LDS windows when the k extent allows 16-byte lines, the
+# staged windows otherwise (k = 70 FP32, 75 FP64).
+@pytest.mark.parametrize("dims", [(13, 40, 64), (9, 35, 70), (6, 33, 75)])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("dtype", [st.F32, st.F64])
+def test_general_3d_nonzero_tap_gather(dims, r, dtype):
+    torch = torch_cuda()
+    ndt = np.float32 if dtype == st.F32 else np.float64
+    a0 = inputs.grid(dims, seed=860 + r, dtype=ndt)
+    for name, mask in _sparse3d_patterns(r, 870 + r).items():
+        rng = np.random.default_rng(880 + r)
+        cg = np.where(mask, rng.uniform(-1.0, 1.0, size=mask.shape), 0.0)
+        cg /= max(1e-30, float(np.abs(cg).sum()))
+        for bc in (st.BC_ZERO, st.BC_PERIODIC):
+            plan = st.Plan(dims, r, st.GENERAL, cg, boundary=bc, dtype=dtype, path=st.PATH_GATHER)
+            assert plan.info["taps"] == int(mask.sum())
+            x = torch.from_numpy(a0).cuda()
+            got = plan.run_steps(x, torch.empty_like(x), 2).cpu().numpy().astype(np.float64)
+            ce = eff_coeffs(cg, dtype)
+            want = oracle.run(a0.astype(np.float64), ce, r, st.BOX, bc, 2)
+            tol = error_bound(ce, 3, r, st.BOX, dtype, st.PATH_GATHER, 2, np.abs(a0).max())
+            assert np.abs(got - want).max() <= tol, (name, bc, np.abs(got - want).max(), tol)
+            plan.close()
+
+
+@pytest.mark.parametrize("r", [1, 4])
+def test_general_3d_nonzero_tap_gather_shift(r):
+    """One weight 1 at C^g[a][b][c]: the 3D nonzero-tap gather shifts the grid
+    by (a - r, b - r, c - r) exactly, for every plane a."""
+    torch = torch_cuda()
+    a0 = inputs.grid((11, 36, 64), seed=890 + r)
+    w = 2 * r + 1
+    for a in range(w):
+        for b, c in ((0, 0), (w - 1, 1), (r, r), (1, w - 1)):
+            cg = np.zeros((w, w, w))
+            cg[a, b, c] = 1.0
+            plan = st.Plan(a0.shape, r, st.GENERAL, cg, boundary=st.BC_PERIODIC, dtype=st.F32, path=st.PATH_GATHER)
+            x = torch.from_numpy(a0).cuda()
+            got = plan.run_steps(x, torch.empty_like(x), 1).cpu().numpy()
+            assert np.array_equal(got, np.roll(a0, shift=(r - a, r - b, r - c), axis=(0, 1, 2))), (a, b, c)
+            plan.close()

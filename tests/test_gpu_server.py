@@ -32,12 +32,19 @@ SPECS = [  # dims, r, shape, bc, dtype, path, steps
     ((24, 40, 48), 1, st.STAR, st.BC_ZERO, st.F64, st.PATH_GATHER, 70),
     ((512, 512), 1, st.STAR, st.BC_PERIODIC, st.F32, st.PATH_MFMA, 65),
     ((12, 26, 64), 4, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_AUTO, 3),
+    ((130, 264), 4, st.GENERAL, st.BC_PERIODIC, st.F32, st.PATH_GATHER, 4),  # nonzero-tap gather
+    ((70, 132), 2, st.GENERAL, st.BC_ZERO, st.F64, st.PATH_AUTO, 3),
 ]
 
 
 def _inputs(k, spec):
     dims, r, shape, bc, dt, path, steps = spec
-    c = inputs.coefficients(len(dims), r, shape, seed=9700 + 10 * k, dtype=np.float64)
+    if shape == st.GENERAL:  # both diagonals with random weights
+        w = 2 * r + 1
+        m = np.eye(w, dtype=bool) | np.eye(w, dtype=bool)[::-1]
+        c = np.where(m, np.random.default_rng(9700 + 10 * k).uniform(0.02, 0.1, (w, w)), 0.0)
+    else:
+        c = inputs.coefficients(len(dims), r, shape, seed=9700 + 10 * k, dtype=np.float64)
     a0 = inputs.grid(dims, seed=9701 + 10 * k, dtype=np.float64 if dt == st.F64 else np.float32)
     return c, a0
 
@@ -92,10 +99,11 @@ def test_server_results_equal_alone(arena_mib, max_active):
         c, a0 = data[k]
         got = outs[k].cpu().numpy()
         assert np.array_equal(got, _alone(torch, SPECS[k], c, a0)), f"request {k} {SPECS[k]}"
-    for k in (0, 2, 4, 9, 12, 13):
+    for k in (0, 2, 4, 9, 12, 13, 15, 16):
         dims, r, shape, bc, dt, path, steps = SPECS[k]
         c, a0 = data[k]
         ce = eff_coeffs(c, dt)
+        shape = st.BOX if shape == st.GENERAL else shape  # the oracle sums every tap
         want = oracle.run(a0.astype(np.float64), ce, r, shape, bc, steps)
         tol = error_bound(ce, len(dims), r, shape, dt, path, steps, np.abs(a0).max())
         assert np.abs(outs[k].cpu().numpy().astype(np.float64) - want).max() <= tol
