@@ -66,8 +66,8 @@ typedef enum {
  * dearer); the 2D GATHER path computes only the nonzero weights (a tap list
  * in the plan) when there are at most 3 / 10 / 27 / 43 of them (FP32, order
  * 1 / 2 / 3 / 4; FP64 5 / 10 / 27 / 31: where the all-tap gather catches up
- * on MI355X), every tap otherwise; the 3D GATHER path likewise up to 4 / 32 /
- * 120 / 128 nonzero taps (FP32; FP64 3 / 28 / 112 / 128); other paths treat
+ * on MI355X), every tap otherwise; the 3D GATHER path likewise up to 5 / 44 /
+ * 128 / 128 nonzero taps (FP32; FP64 3 / 40 / 128 / 128); other paths treat
  * GENERAL as BOX.  The line option (lines) must be
  * AUTO for GENERAL. */
 typedef enum { STENCIL_STAR = 0, STENCIL_BOX = 1, STENCIL_GENERAL = 2 } stencil_shape_t;
@@ -82,7 +82,7 @@ typedef enum { STENCIL_F32 = 0, STENCIL_F64 = 1 } stencil_dtype_t;
 
 typedef enum {
   STENCIL_PATH_AUTO = 0,        /* library picks, from measurements on MI355X: MFMA for F32 boxes of
-                                   order >= 3 (2D and 3D; 3D GENERAL stencils with at most 64 / 90
+                                   order >= 3 (2D and 3D; 3D GENERAL stencils with at most 88 / 124
                                    nonzero taps at order 3 / 4 take GATHER), 3D stars of order 4
                                    and 2D GENERAL
                                    stencils (FP32 grids wider than 64 columns: the line cover or

@@ -59,15 +59,38 @@ __device__ __forceinline__ void sparse3d_item(const KArgs& a, int item) {
         // output (j row PR w + p, k column l), tap (b, c) of plane a: window
         // row PR w + p + b, LDS column 4 - r + l + c
         const T* base = win + PR * w * PW::PITCH + (4 - R) + lane;
+        // ACC: each plane's taps sum into acc, added to its ring slot once, so
+        // the tap loop carries no slot index (the compiler otherwise merges
+        // the plane loops and picks the slot per tap); FP64 at r >= 3 keeps
+        // the direct form, whose smaller register set measured faster there
+        constexpr bool ACC = sizeof(T) == 4 || R <= 2;
 #pragma unroll
         for (int ap = 0; ap < W; ++ap) {
-          for (int t = start[ap]; t < start[ap + 1]; ++t) {
-            const int c = t < 64 ? __builtin_amdgcn_readlane(code[0], t) : __builtin_amdgcn_readlane(code[1], t - 64);
-            const T f = t < 64 ? lane_value(cf[0], t) : lane_value(cf[1], t - 64);
+          const int t0 = start[ap], t1 = start[ap + 1];
+          if constexpr (!ACC) {
+            for (int t = t0; t < t1; ++t) {
+              const int c = __builtin_amdgcn_readlane(t < 64 ? code[0] : code[1], t & 63);
+              const T f = lane_value(t < 64 ? cf[0] : cf[1], t & 63);
+              const T* p0 = base + (c >> 8) * PW::PITCH + (c & 255);
+#pragma unroll
+              for (int p = 0; p < PR; ++p) ring[2 * R - ap][p] += f * p0[p * PW::PITCH];
+            }
+            continue;
+          }
+          if (t0 == t1) continue;
+          T acc[PR];
+#pragma unroll
+          for (int p = 0; p < PR; ++p) acc[p] = T(0);
+#pragma unroll 2
+          for (int t = t0; t < t1; ++t) {
+            const int c = __builtin_amdgcn_readlane(t < 64 ? code[0] : code[1], t & 63);
+            const T f = lane_value(t < 64 ? cf[0] : cf[1], t & 63);
             const T* p0 = base + (c >> 8) * PW::PITCH + (c & 255);
 #pragma unroll
-            for (int p = 0; p < PR; ++p) ring[2 * R - ap][p] += f * p0[p * PW::PITCH];
+            for (int p = 0; p < PR; ++p) acc[p] += f * p0[p * PW::PITCH];
           }
+#pragma unroll
+          for (int p = 0; p < PR; ++p) ring[2 * R - ap][p] += acc[p];
         }
       },
       [&](int64_t o, bool live) {

@@ -369,7 +369,7 @@ static int general_cover(const std::vector<double>& cg, int R, bool c4, int* row
 // Largest nonzero-tap count of a GENERAL 3D stencil on the nonzero-tap
 // gather; beyond it the all-tap gather is as fast (measured on MI355X,
 // 256^3; FP32 / FP64, orders 1..4).
-static const int kSparse3DMax[2][5] = {{0, 4, 32, 120, 128}, {0, 3, 28, 112, 128}};
+static const int kSparse3DMax[2][5] = {{0, 5, 44, 128, 128}, {0, 3, 40, 128, 128}};
 
 int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   const int st = validate(desc);
@@ -416,8 +416,8 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     const bool f32 = d.dtype == STENCIL_F32;
     if (nd == 3) {  // also the r = 4 stars: the hybrid outer products lead by 4 % (FP32) / 10 % (FP64)
       // GENERAL with few nonzero taps: the nonzero-tap gather beats the box
-      // outer products up to 64 (r = 3) / 90 (r = 4) taps (256^3 FP32)
-      static const int kSparse3DAuto[5] = {0, 0, 0, 64, 90};
+      // outer products up to 88 (r = 3) / 124 (r = 4) taps (256^3 FP32)
+      static const int kSparse3DAuto[5] = {0, 0, 0, 88, 124};
       const bool few = general && in.taps <= kSparse3DAuto[R];
       path = (f32 && box && R >= 3 && !few) || (!box && R == 4) ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
     } else {

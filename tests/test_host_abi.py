@@ -477,15 +477,15 @@ def test_general_gather_choice(lib):
 
 
 def test_general_3d_gather_choice(lib):
-    """GENERAL 3D: the gather path walks the nonzero taps up to 4 / 32 / 120 /
-    128 of them (FP32, orders 1..4; FP64 3 / 28 / 112 / 128), every tap beyond;
-    AUTO on FP32 takes that gather over the box outer products up to 64 (r = 3)
-    and 90 (r = 4) nonzero taps."""
-    limit = {st.F32: (0, 4, 32, 120, 128), st.F64: (0, 3, 28, 112, 128)}
+    """GENERAL 3D: the gather path walks the nonzero taps up to 5 / 44 / 128 /
+    128 of them (FP32, orders 1..4; FP64 3 / 40 / 128 / 128), every tap beyond;
+    AUTO on FP32 takes that gather over the box outer products up to 88 (r = 3)
+    and 124 (r = 4) nonzero taps."""
+    limit = {st.F32: (0, 5, 44, 128, 128), st.F64: (0, 3, 40, 128, 128)}
     for r in (1, 2, 3, 4):
         w = 2 * r + 1
         for dt in (st.F32, st.F64):
-            for n in sorted({1, 2, 3, 4, 5, 27, 28, 29, 32, 33, 64, 90, 91, 112, 113, 120, 121, 128, 129, w ** 3}):
+            for n in sorted({1, 2, 3, 4, 5, 6, 16, 27, 40, 41, 44, 45, 64, 65, 88, 89, 124, 125, 128, 129, w ** 3}):
                 if n > w ** 3:
                     continue
                 c = np.zeros(w ** 3); c[:n] = 0.01
@@ -494,5 +494,5 @@ def test_general_3d_gather_choice(lib):
                 want = 2.0 * (n if n <= limit[dt][r] else w ** 3)
                 assert info["taps"] == n and info["executed_flops_per_point"] == want, (r, dt, n)
                 auto = st.describe((32, 32, 64), r, st.GENERAL, c, dtype=dt)["path"]
-                mfma = dt == st.F32 and r >= 3 and n > {3: 64, 4: 90}[r]
+                mfma = dt == st.F32 and r >= 3 and n > {3: 88, 4: 124}[r]
                 assert auto == (st.PATH_MFMA if mfma else st.PATH_GATHER), (r, dt, n)
