@@ -128,17 +128,19 @@ def test_batch_rejects_overlapping_buffers():
 
 
 def test_batch_general_nonzero_tap_gather():
-    """GENERAL members on the nonzero-tap gather in one batch with a box member:
+    """GENERAL members (2D and 3D) on the nonzero-tap gather in one batch with a box member:
     each equals its own launch and the oracle."""
     torch = torch_cuda()
+    d3 = np.zeros((9, 9, 9)); d3[np.arange(9), np.arange(9), np.arange(9)] = 0.1
     specs = [((130, 264), 4, np.float32, st.F32, np.eye(9)),
              ((70, 132), 2, np.float64, st.F64, np.eye(5)[::-1] * 0.3),
-             ((96, 516), 3, np.float32, st.F32, None)]
+             ((96, 516), 3, np.float32, st.F32, None),
+             ((14, 40, 64), 4, np.float32, st.F32, d3)]
     ms = []
     for k, (dims, r, ndt, dt, c) in enumerate(specs):
         shape = st.BOX if c is None else st.GENERAL
         if c is None:
-            c = inputs.coefficients(2, r, st.BOX, seed=7300, dtype=np.float64)
+            c = inputs.coefficients(len(dims), r, st.BOX, seed=7300, dtype=np.float64)
         a0 = inputs.grid(dims, seed=7310 + k, dtype=ndt)
         plan = st.Plan(dims, r, shape, c, boundary=st.BC_PERIODIC, dtype=dt, path=st.PATH_GATHER)
         x = torch.from_numpy(a0).cuda()
@@ -151,6 +153,6 @@ def test_batch_general_nonzero_tap_gather():
         assert np.array_equal(got, _alone(torch, plan, a0, 3))
         ce = eff_coeffs(c, dt)
         want = oracle.run(a0.astype(np.float64), ce, r, st.BOX, st.BC_PERIODIC, 3)
-        tol = error_bound(ce, 2, r, st.BOX, dt, st.PATH_GATHER, 3, np.abs(a0).max())
+        tol = error_bound(ce, a0.ndim, r, st.BOX, dt, st.PATH_GATHER, 3, np.abs(a0).max())
         assert np.abs(got.astype(np.float64) - want).max() <= tol
     batch.close()
