@@ -81,8 +81,26 @@ __device__ __forceinline__ void sparse3d_item(const KArgs& a, int item) {
           T acc[PR];
 #pragma unroll
           for (int p = 0; p < PR; ++p) acc[p] = T(0);
-#pragma unroll 2
-          for (int t = t0; t < t1; ++t) {
+          // two taps per step: all 2 PR reads issue before the first FMA
+          int t = t0;
+          for (; t + 1 < t1; t += 2) {
+            const int c0 = __builtin_amdgcn_readlane(t < 64 ? code[0] : code[1], t & 63);
+            const int c1 = __builtin_amdgcn_readlane(t + 1 < 64 ? code[0] : code[1], (t + 1) & 63);
+            const T f0 = lane_value(t < 64 ? cf[0] : cf[1], t & 63);
+            const T f1 = lane_value(t + 1 < 64 ? cf[0] : cf[1], (t + 1) & 63);
+            const T* p0 = base + (c0 >> 8) * PW::PITCH + (c0 & 255);
+            const T* p1 = base + (c1 >> 8) * PW::PITCH + (c1 & 255);
+            T v0[PR], v1[PR];
+#pragma unroll
+            for (int p = 0; p < PR; ++p) v0[p] = p0[p * PW::PITCH];
+#pragma unroll
+            for (int p = 0; p < PR; ++p) v1[p] = p1[p * PW::PITCH];
+#pragma unroll
+            for (int p = 0; p < PR; ++p) acc[p] += f0 * v0[p];
+#pragma unroll
+            for (int p = 0; p < PR; ++p) acc[p] += f1 * v1[p];
+          }
+          if (t < t1) {
             const int c = __builtin_amdgcn_readlane(t < 64 ? code[0] : code[1], t & 63);
             const T f = lane_value(t < 64 ? cf[0] : cf[1], t & 63);
             const T* p0 = base + (c >> 8) * PW::PITCH + (c & 255);

@@ -416,8 +416,8 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     const bool f32 = d.dtype == STENCIL_F32;
     if (nd == 3) {  // also the r = 4 stars: the hybrid outer products lead by 4 % (FP32) / 10 % (FP64)
       // GENERAL with few nonzero taps: the nonzero-tap gather beats the box
-      // outer products up to 88 (r = 3) / 124 (r = 4) taps (256^3 FP32)
-      static const int kSparse3DAuto[5] = {0, 0, 0, 88, 124};
+      // outer products up to 88 (r = 3) / 128 (r = 4) taps (256^3 FP32)
+      static const int kSparse3DAuto[5] = {0, 0, 0, 88, 128};
       const bool few = general && in.taps <= kSparse3DAuto[R];
       path = (f32 && box && R >= 3 && !few) || (!box && R == 4) ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
     } else {

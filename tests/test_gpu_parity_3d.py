@@ -166,7 +166,7 @@ def test_mfma_box_pure_shift(r, dims):
 @pytest.mark.parametrize("density", [0.1, 0.5])
 def test_general_3d_auto(r, density):
     """Irregular 3D stencils under AUTO (outer products on n = 4 blocks from
-    r = 3, all (2r+1)^2 lines; the nonzero-tap gather for at most 88 / 124
+    r = 3, all (2r+1)^2 lines; the nonzero-tap gather for at most 88 / 128
     nonzero taps at r = 3 / 4) against the oracle's full (2r+1)^3 sum."""
     torch = torch_cuda()
     rng = np.random.default_rng(840 + r + int(10 * density))
@@ -177,7 +177,7 @@ def test_general_3d_auto(r, density):
     a0 = inputs.grid((14, 22, 76), seed=850 + r)
     for bc in (st.BC_ZERO, st.BC_PERIODIC):
         plan = st.Plan(a0.shape, r, st.GENERAL, cg, boundary=bc, dtype=st.F32)
-        want_path = st.PATH_GATHER if int(mask.sum()) <= {3: 88, 4: 124}[r] else st.PATH_MFMA
+        want_path = st.PATH_GATHER if int(mask.sum()) <= {3: 88, 4: 128}[r] else st.PATH_MFMA
         assert plan.info["path"] == want_path
         x = torch.from_numpy(a0).cuda()
         got = plan.run_steps(x, torch.empty_like(x), 2).cpu().numpy().astype(np.float64)

@@ -480,7 +480,7 @@ def test_general_3d_gather_choice(lib):
     """GENERAL 3D: the gather path walks the nonzero taps up to 5 / 44 / 128 /
     128 of them (FP32, orders 1..4; FP64 3 / 40 / 128 / 128), every tap beyond;
     AUTO on FP32 takes that gather over the box outer products up to 88 (r = 3)
-    and 124 (r = 4) nonzero taps."""
+    and 128 (r = 4) nonzero taps."""
     limit = {st.F32: (0, 5, 44, 128, 128), st.F64: (0, 3, 40, 128, 128)}
     for r in (1, 2, 3, 4):
         w = 2 * r + 1
@@ -494,5 +494,5 @@ def test_general_3d_gather_choice(lib):
                 want = 2.0 * (n if n <= limit[dt][r] else w ** 3)
                 assert info["taps"] == n and info["executed_flops_per_point"] == want, (r, dt, n)
                 auto = st.describe((32, 32, 64), r, st.GENERAL, c, dtype=dt)["path"]
-                mfma = dt == st.F32 and r >= 3 and n > {3: 88, 4: 124}[r]
+                mfma = dt == st.F32 and r >= 3 and n > {3: 88, 4: 128}[r]
                 assert auto == (st.PATH_MFMA if mfma else st.PATH_GATHER), (r, dt, n)
