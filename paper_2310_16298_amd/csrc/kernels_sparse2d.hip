@@ -26,7 +26,7 @@ namespace stencil {
 template <typename T, int R>
 __device__ __forceinline__ void sparse2d_dma_item(const KArgs& a, int item) {
   constexpr int BM = kDmaBM, TN = Gather2DDma<T>::TN, CPT = TN / 64, PR = BM / 4;
-  static_assert(2 * kSparseTapMax <= 256 && (2 * R + 1) * (2 * R + 1) <= kSparseTapMax, "tap table");
+  static_assert(kSparseTapMax <= 128 && (2 * R + 1) * (2 * R + 1) <= kSparseTapMax, "taps fit two registers");
   typedef DmaWindow<T, R, BM, TN, 256> D;
   __shared__ __attribute__((aligned(16))) T bufs[2 * D::BUF];
 

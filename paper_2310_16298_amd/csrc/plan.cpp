@@ -491,7 +491,9 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       // units) up to the tap count where the all-tap gather catches up
       // (measured on MI355X, 8192^2; FP32 / FP64, orders 1..4)
       static const int kSparseMax[2][5] = {{0, 3, 10, 27, 43}, {0, 5, 10, 27, 31}};
-      const bool sparse = general && in.taps <= kSparseMax[d.dtype == STENCIL_F64 ? 1 : 0][R];
+      // (grids that cannot take direct-to-LDS windows run every tap anyway)
+      const bool dma_shape = d.dims[1] % 4 == 0 && !(d.dtype == STENCIL_F32 && d.dims[1] <= kTile2D);
+      const bool sparse = general && dma_shape && in.taps <= kSparseMax[d.dtype == STENCIL_F64 ? 1 : 0][R];
       rs->pick = sparse ? find_sparse2d(d.dtype, R) : find_gather2d(d.dtype, R, box);
       in.executed_flops_per_point = 2.0 * (sparse || !general ? in.taps : W * W);
       if (sparse) {  // table of the nonzero taps

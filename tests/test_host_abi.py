@@ -469,6 +469,11 @@ def test_general_gather_choice(lib):
             assert st.describe((64, 64), r, st.GENERAL, c, dtype=st.F32)["path"] == st.PATH_MFMA
             assert st.describe((256, 258), r, st.GENERAL, c, dtype=st.F32)["path"] == st.PATH_MFMA
             assert st.describe((256, 256), r, st.GENERAL, c, dtype=st.F64)["path"] == st.PATH_GATHER
+    # extents without direct-to-LDS windows run (and report) every tap
+    for dims, dt in (((256, 258), st.F64), ((64, 64), st.F32), ((80, 62), st.F64)):
+        info = st.describe(dims, 2, st.GENERAL, np.eye(5), path=st.PATH_GATHER, dtype=dt)
+        assert info["executed_flops_per_point"] == 2.0 * 25, dims
+    assert st.describe((80, 64), 2, st.GENERAL, np.eye(5), path=st.PATH_GATHER, dtype=st.F64)["executed_flops_per_point"] == 10.0
     # the measured order-4 cases: diagonals to the gather, short covers to MFMA
     w = 9
     assert st.describe((8192, 8192), 4, st.GENERAL, np.eye(w), dtype=st.F32)["path"] == st.PATH_GATHER
