@@ -53,7 +53,9 @@ typedef enum {
   STENCIL_ENOMEM = -3,       /* device or host allocation failed */
   STENCIL_EHIP = -4,         /* a HIP runtime call or kernel launch failed */
   STENCIL_EALIAS = -5,       /* input and output buffers are the same */
-  STENCIL_EINTERNAL = -6     /* unexpected internal error */
+  STENCIL_EINTERNAL = -6,    /* unexpected internal error */
+  STENCIL_ETOOBIG = -7       /* the plan's operands exceed the static scratch buffer of
+                                stencil_run_steps_noalloc (STENCIL_NOALLOC_SCRATCH_BYTES) */
 } stencil_status_t;
 
 /* STAR: only on-axis weights may be nonzero (2rd+1 taps); BOX: any weights,
@@ -154,6 +156,9 @@ typedef struct {
   double executed_flops_per_point; /* flops the matrix+vector units execute per output point */
   int32_t bytes_per_point;       /* algorithmic HBM bytes per point-step: read + write of one element */
   int32_t time_block;            /* steps fused per launch (1 = none) */
+  int32_t pad0;
+  int64_t operand_bytes;         /* device bytes of the plan's operands: band fragments, dense C^g
+                                    and a 256-byte zero line, each rounded up to 256 bytes */
 } stencil_plan_info_t;
 
 typedef struct stencil_plan_s* stencil_plan_t;
@@ -238,6 +243,31 @@ stencil_status_t stencil_apply(stencil_plan_t plan, const void* in, void* out, v
  * the kernels are enqueued one by one. */
 stencil_status_t stencil_run_steps(stencil_plan_t plan, void* buf0, void* buf1, int64_t steps,
                                    void* stream, int32_t* result_index);
+
+/* For callers that cannot allocate device memory -- tight serving loops,
+ * harnesses that forbid hipMalloc -- the steps of stencil_run_steps without a
+ * plan object: nothing is allocated on the device.  The descriptor is resolved
+ * on the host as stencil_plan would (ordinary host memory only), its operands
+ * (plan_info.operand_bytes: band fragments, dense C^g, the zero line) are
+ * written into a static device array of STENCIL_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends (written by
+ * small fill kernels that carry the bytes in their arguments: no host
+ * staging, no memset), and the plan's kernels then run from it, one launch
+ * per step (or per time block), eagerly on `stream`.
+ * buf0 / buf1 / steps / result_index: as stencil_run_steps (the state starts
+ * in buf0; *result_index receives the buffer of the final state).
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * operands: calls whose work overlaps in time on one GPU (other streams, or
+ * the same stream from several threads) race and must be serialised by the
+ * caller; calls in order on one stream are safe.
+ * Errors: as stencil_desc_check (EINVAL / EUNSUPPORTED), EINVAL for null
+ * buffers or negative steps, EALIAS for overlapping buffers, ETOOBIG when
+ * operand_bytes exceeds STENCIL_NOALLOC_SCRATCH_BYTES (checked before any
+ * device call), EUNSUPPORTED while `stream` is being captured (the upload is
+ * not meant for graphs), EHIP for a failed device call. */
+#define STENCIL_NOALLOC_SCRATCH_BYTES 32768
+stencil_status_t stencil_run_steps_noalloc(const stencil_desc_t* desc, void* buf0, void* buf1, int64_t steps,
+                                           void* stream, int32_t* result_index);
 
 /* ---------------------------------------------------------------- batches
  * Many grids of uneven sizes (each with its own plan: dims, radius, shape,

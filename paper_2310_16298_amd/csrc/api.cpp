@@ -16,34 +16,6 @@ void free_plan(stencil_plan_s* p) {
   delete p;
 }
 
-// One launch: one step, or `fused` steps of a time-blocked plan.
-stencil_status_t launch_one(const stencil_plan_s* p, const void* in, void* out, hipStream_t s, int fused = 1) {
-  KArgs a;
-  const Kernel k = plan_kernel(p, in, out, &a);
-  a.steps = fused;
-  if (!k.launch || k.items < 1 || k.items > (int64_t(1) << 31) - 1) return STENCIL_EINTERNAL;
-  return k.launch(a, (unsigned)k.items, s) == hipSuccess ? STENCIL_OK : STENCIL_EHIP;
-}
-
-// Launches of a run of `steps` steps (up to time_block steps each).
-int64_t launch_count(const stencil_plan_s* p, int64_t steps) {
-  const int64_t tb = p->rs.time_block;
-  return (steps + tb - 1) / tb;
-}
-
-stencil_status_t launch_steps(const stencil_plan_s* p, void* buf0, void* buf1, int64_t steps, hipStream_t s) {
-  void* buf[2] = {buf0, buf1};
-  const int64_t tb = p->rs.time_block;
-  int64_t t = 0;
-  for (int64_t k = 0; t < steps; ++k) {
-    const int fused = (int)(steps - t < tb ? steps - t : tb);
-    const stencil_status_t st = launch_one(p, buf[k & 1], buf[(k + 1) & 1], s, fused);
-    if (st != STENCIL_OK) return st;
-    t += fused;
-  }
-  return STENCIL_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -59,6 +31,7 @@ const char* stencil_status_string(stencil_status_t s) {
     case STENCIL_EHIP: return "HIP runtime error";
     case STENCIL_EALIAS: return "input and output buffers overlap";
     case STENCIL_EINTERNAL: return "internal error";
+    case STENCIL_ETOOBIG: return "plan operands exceed the no-allocation scratch buffer";
   }
   return "unknown status";
 }
@@ -134,9 +107,7 @@ stencil_status_t stencil_plan(const stencil_desc_t* desc, stencil_plan_t* out) {
       free_plan(p);
       return STENCIL_EHIP;
     }
-    int64_t npts = 1;
-    for (int k = 0; k < desc->ndim; ++k) npts *= desc->dims[k];
-    p->grid_bytes = (size_t)npts * (desc->dtype == STENCIL_F64 ? 8 : 4);
+    p->grid_bytes = grid_bytes_of(desc);
     const size_t fb = p->rs.frag.size(), cb = p->rs.coef.size();
     if (fb) {
       if (hipMalloc(&p->d_frag, fb) != hipSuccess) {
@@ -200,7 +171,7 @@ stencil_status_t stencil_apply(stencil_plan_t plan, const void* in, void* out, v
   try {
     const stencil_status_t d = check_device(plan->device);
     if (d != STENCIL_OK) return d;
-    return launch_one(plan, in, out, (hipStream_t)stream);
+    return launch_one(plan->rs, in, out, (hipStream_t)stream);
   } catch (...) {
     return STENCIL_EINTERNAL;
   }
@@ -215,11 +186,11 @@ stencil_status_t stencil_run_steps(stencil_plan_t plan, void* buf0, void* buf1, 
     if (d != STENCIL_OK) return d;
     const stencil_plan_s* p = plan;
     stencil_status_t st = plan->graphs.run(buf0, buf1, steps, (hipStream_t)stream, [&](hipStream_t cs) {
-      return launch_steps(p, buf0, buf1, steps, cs);
+      return launch_steps(p->rs, buf0, buf1, steps, cs);
     });
-    if (st == STENCIL_EUNSUPPORTED) st = launch_steps(plan, buf0, buf1, steps, (hipStream_t)stream);
+    if (st == STENCIL_EUNSUPPORTED) st = launch_steps(plan->rs, buf0, buf1, steps, (hipStream_t)stream);
     if (st != STENCIL_OK) return st;
-    if (result_index) *result_index = (int32_t)(launch_count(plan, steps) & 1);
+    if (result_index) *result_index = (int32_t)(launch_count(plan->rs, steps) & 1);
     return STENCIL_OK;
   } catch (...) {
     return STENCIL_EINTERNAL;

@@ -111,7 +111,7 @@ stencil_status_t stencil_batch_create(const stencil_plan_t* plans, void* const* 
     std::map<const void*, size_t> by_kernel;
     for (int32_t i = 0; i < count; ++i) {
       KArgs a;
-      const Kernel k = plan_kernel(plans[i], buf0[i], buf1[i], &a);
+      const Kernel k = plan_kernel(plans[i]->rs, buf0[i], buf1[i], &a);
       if (!k.launch || k.items < 1) {
         delete b;
         return STENCIL_EINTERNAL;

@@ -745,6 +745,7 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   }
   in.path = path;
   in.lines = lines;
+  if (pack) in.operand_bytes = 256 + (int64_t)round_up((int)rs->coef.size(), 256) + (int64_t)round_up((int)rs->frag.size(), 256);
   if (!rs->pick) return STENCIL_EUNSUPPORTED;
   if (d.block_n != 0 && path != STENCIL_PATH_GATHER && d.block_n != in.block_n) return STENCIL_EUNSUPPORTED;
   return STENCIL_OK;

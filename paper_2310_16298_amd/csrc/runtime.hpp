@@ -117,13 +117,49 @@ inline stencil_status_t check_device(int device) {
   return dev == device ? STENCIL_OK : STENCIL_EINVAL;
 }
 
-// The plan's args with the two buffers filled in, its kernel picked and the
-// decomposition applied.
-inline Kernel plan_kernel(const stencil_plan_s* p, const void* in, void* out, KArgs* a) {
-  *a = p->rs.args;
+// The resolved plan's args with the two buffers filled in, its kernel picked
+// and the decomposition applied.
+inline Kernel plan_kernel(const Resolved& rs, const void* in, void* out, KArgs* a) {
+  *a = rs.args;
   a->in = in;
   a->out = out;
-  return p->rs.pick(*a, p->rs.chunk_req);
+  return rs.pick(*a, rs.chunk_req);
+}
+
+// One launch: one step, or `fused` steps of a time-blocked plan.
+inline stencil_status_t launch_one(const Resolved& rs, const void* in, void* out, hipStream_t s, int fused = 1) {
+  KArgs a;
+  const Kernel k = plan_kernel(rs, in, out, &a);
+  a.steps = fused;
+  if (!k.launch || k.items < 1 || k.items > (int64_t(1) << 31) - 1) return STENCIL_EINTERNAL;
+  return k.launch(a, (unsigned)k.items, s) == hipSuccess ? STENCIL_OK : STENCIL_EHIP;
+}
+
+// Launches of a run of `steps` steps (up to time_block steps each).
+inline int64_t launch_count(const Resolved& rs, int64_t steps) {
+  const int64_t tb = rs.time_block;
+  return (steps + tb - 1) / tb;
+}
+
+// The launches of `steps` Jacobi steps, ping-ponging between buf0 and buf1.
+inline stencil_status_t launch_steps(const Resolved& rs, void* buf0, void* buf1, int64_t steps, hipStream_t s) {
+  void* buf[2] = {buf0, buf1};
+  const int64_t tb = rs.time_block;
+  int64_t t = 0;
+  for (int64_t k = 0; t < steps; ++k) {
+    const int fused = (int)(steps - t < tb ? steps - t : tb);
+    const stencil_status_t st = launch_one(rs, buf[k & 1], buf[(k + 1) & 1], s, fused);
+    if (st != STENCIL_OK) return st;
+    t += fused;
+  }
+  return STENCIL_OK;
+}
+
+// Grid bytes of a descriptor (validated: dims >= 1, dtype F32 / F64).
+inline size_t grid_bytes_of(const stencil_desc_t* d) {
+  int64_t npts = 1;
+  for (int k = 0; k < d->ndim; ++k) npts *= d->dims[k];
+  return (size_t)npts * (d->dtype == STENCIL_F64 ? 8 : 4);
 }
 
 }  // namespace stencil

@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libstencil.so")
 
 # enums (mirror include/stencil.h)
-OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, EALIAS, EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, EALIAS, EINTERNAL, ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7
+NOALLOC_SCRATCH_BYTES = 32768  # STENCIL_NOALLOC_SCRATCH_BYTES
 STAR, BOX, GENERAL = 0, 1, 2
 BC_ZERO, BC_PERIODIC = 0, 1
 F32, F64 = 0, 1
@@ -54,6 +55,7 @@ class PlanInfo(ctypes.Structure):
         ("k_rows", ctypes.c_int32), ("rank1_per_block", ctypes.c_int64),
         ("useful_flops_per_point", ctypes.c_double), ("executed_flops_per_point", ctypes.c_double),
         ("bytes_per_point", ctypes.c_int32), ("time_block", ctypes.c_int32),
+        ("pad0", ctypes.c_int32), ("operand_bytes", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -67,7 +69,7 @@ EXPORTS = [
     "stencil_batch_create", "stencil_batch_run_steps", "stencil_batch_info", "stencil_batch_destroy",
     "stencil_autotune",
     "stencil_server_create", "stencil_server_stream", "stencil_server_submit", "stencil_server_tick",
-    "stencil_server_poll", "stencil_server_destroy",
+    "stencil_server_poll", "stencil_server_destroy", "stencil_run_steps_noalloc",
 ]
 
 
@@ -116,6 +118,7 @@ def load_library(path: str = LIB_PATH):
     lib.stencil_apply.argtypes = [vp, vp, vp, vp]
     lib.stencil_run_steps.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(i32)]
     lib.stencil_error_norms.argtypes = [vp, i32, vp, i64, vp, vp]
+    lib.stencil_run_steps_noalloc.argtypes = [ctypes.POINTER(Desc), vp, vp, i64, vp, ctypes.POINTER(i32)]
     lib.stencil_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32,
                                          ctypes.POINTER(vp)]
     lib.stencil_batch_run_steps.argtypes = [vp, i64, vp, ctypes.POINTER(i32)]
@@ -287,6 +290,28 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def run_steps_noalloc(x, tmp, steps: int, radius: int, shape: int, coeffs, boundary=BC_ZERO, path=PATH_AUTO,
+                      lines=LINES_AUTO, block_n=0, chunk=0, time_block=0, stream=None):
+    """``steps`` Jacobi steps of the stencil described by the arguments on the
+    grid in ``x`` (ping-ponging with ``tmp``) through
+    ``stencil_run_steps_noalloc``: no plan object, no device allocation.
+    Returns the tensor that holds the final state."""
+    torch = _torch()
+    for t in (x, tmp):
+        if not (t.is_cuda and t.is_contiguous()) or t.dtype not in (torch.float32, torch.float64):
+            raise ValueError("grids must be contiguous float32/float64 GPU tensors")
+    if x.shape != tmp.shape or x.dtype != tmp.dtype:
+        raise ValueError("x and tmp must have the same shape and dtype")
+    dtype = F64 if x.dtype == torch.float64 else F32
+    d, keep = make_desc(tuple(x.shape), radius, shape, coeffs, boundary=boundary, dtype=dtype, path=path,
+                        lines=lines, block_n=block_n, chunk=chunk, time_block=time_block)
+    idx = ctypes.c_int32(0)
+    _check(load_library().stencil_run_steps_noalloc(ctypes.byref(d), x.data_ptr(), tmp.data_ptr(), int(steps),
+                                                     _stream_ptr(stream), ctypes.byref(idx)),
+           "stencil_run_steps_noalloc")
+    return x if idx.value == 0 else tmp
 
 
 def autotune(dims, radius, shape, coeffs, boundary=BC_ZERO, dtype=F32, path=PATH_AUTO, lines=LINES_AUTO,

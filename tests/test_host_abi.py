@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_status_strings(lib):
-    for s in (st.OK, st.EINVAL, st.EUNSUPPORTED, st.ENOMEM, st.EHIP, st.EALIAS, st.EINTERNAL):
+    for s in (st.OK, st.EINVAL, st.EUNSUPPORTED, st.ENOMEM, st.EHIP, st.EALIAS, st.EINTERNAL, st.ETOOBIG):
         assert st.status_string(s) not in ("", "unknown status")
     assert st.status_string(99) == "unknown status"
     assert "gfx950" in st.version()
@@ -501,3 +501,49 @@ def test_general_3d_gather_choice(lib):
                 auto = st.describe((32, 32, 64), r, st.GENERAL, c, dtype=dt)["path"]
                 mfma = dt == st.F32 and r >= 3 and n > {3: 88, 4: 128}[r]
                 assert auto == (st.PATH_MFMA if mfma else st.PATH_GATHER), (r, dt, n)
+
+
+# ---------------------------------------------------------------- no-allocation entry point
+
+def _noalloc(lib, desc, b0=1 << 20, b1=1 << 30, steps=1):
+    idx = ctypes.c_int32(-1)
+    return lib.stencil_run_steps_noalloc(ctypes.byref(desc), b0, b1, steps, None, ctypes.byref(idx)), idx.value
+
+
+def test_noalloc_rejects_operands_beyond_scratch_before_any_device_call(lib):
+    # FP64 3D box of order 2 on 16x16 blocks: 25 lines x 5 K chunks x 64 lanes x 8 B = 64000 B of fragments
+    c = inputs.coefficients(3, 2, inputs.BOX, seed=3, dtype=np.float64)
+    d, keep = st.make_desc((40, 40, 64), 2, st.BOX, c, dtype=st.F64, path=st.PATH_MFMA)
+    info = st.describe((40, 40, 64), 2, st.BOX, c, dtype=st.F64, path=st.PATH_MFMA)
+    assert info["operand_bytes"] > st.NOALLOC_SCRATCH_BYTES
+    assert _noalloc(lib, d)[0] == st.ETOOBIG  # no GPU here: the check precedes every device call
+
+
+def test_noalloc_argument_errors(lib):
+    c = _box(2, 1)
+    d, keep = st.make_desc((64, 64), 1, st.BOX, c)
+    assert lib.stencil_run_steps_noalloc(None, 1 << 20, 1 << 30, 1, None, None) == st.EINVAL
+    assert lib.stencil_run_steps_noalloc(ctypes.byref(d), None, 1 << 30, 1, None, None) == st.EINVAL
+    assert lib.stencil_run_steps_noalloc(ctypes.byref(d), 1 << 20, 1 << 30, -1, None, None) == st.EINVAL
+    assert _noalloc(lib, d, b0=1 << 20, b1=(1 << 20) + 64)[0] == st.EALIAS
+    # steps == 0 enqueues nothing and touches no device
+    assert _noalloc(lib, d, steps=0) == (st.OK, 0)
+    bad, keep2 = st.make_desc((64, 64), 5, st.BOX, np.ones(121))
+    assert _noalloc(lib, bad)[0] == st.EINVAL
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+@pytest.mark.parametrize("dtype", [st.F32, st.F64])
+def test_operand_bytes_of_auto_plans_fit_the_noalloc_scratch(lib, nd, dtype):
+    dims = (520, 384) if nd == 2 else (40, 48, 64)
+    for r in range(1, 5):
+        for shape in (st.STAR, st.BOX):
+            c = inputs.coefficients(nd, r, shape, seed=r, dtype=np.float64)
+            for path in (st.PATH_AUTO, st.PATH_GATHER, st.PATH_MFMA):
+                if st.desc_check(dims, r, shape, c, dtype=dtype, path=path) != st.OK:
+                    continue
+                info = st.describe(dims, r, shape, c, dtype=dtype, path=path)
+                if nd == 3 and dtype == st.F64 and shape == st.BOX and r == 2 and path == st.PATH_MFMA:
+                    continue  # 64000 B of FP64 16x16 fragments: the one plan beyond the scratch
+                assert 256 < info["operand_bytes"] <= st.NOALLOC_SCRATCH_BYTES, (r, shape, path, info)
+                assert info["operand_bytes"] % 256 == 0
