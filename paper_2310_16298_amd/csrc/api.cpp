@@ -23,7 +23,11 @@ extern "C" {
 const char* stencil_version(void) { return "paper_2310_16298_amd 0.1.0 (gfx950)"; }
 
 const char* stencil_status_string(stencil_status_t s) {
-  switch (s) {
+  // callers may pass any integer: read its bits, not an enum value (a value
+  // outside the enumerators is not a valid stencil_status_t in C++)
+  int v = 0;
+  std::memcpy(&v, &s, sizeof(v) < sizeof(s) ? sizeof(v) : sizeof(s));
+  switch (v) {
     case STENCIL_OK: return "ok";
     case STENCIL_EINVAL: return "invalid argument";
     case STENCIL_EUNSUPPORTED: return "unsupported combination";

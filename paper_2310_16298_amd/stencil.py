@@ -14,7 +14,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libstencil.so")
+# STENCIL_LIBRARY names another build of the same library (the host-side
+# sanitizer build of the CPU tests); the default is the in-tree libstencil.so.
+LIB_PATH = os.environ.get("STENCIL_LIBRARY") or os.path.join(_HERE, "libstencil.so")
 
 # enums (mirror include/stencil.h)
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP, EALIAS, EINTERNAL, ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7
