@@ -89,7 +89,9 @@ typedef enum {
                                    and 2D GENERAL
                                    stencils (FP32 grids wider than 64 columns: the line cover or
                                    the nonzero-tap gather, whichever a cost fitted on MI355X
-                                   prefers -- 12290 + 403 n per point for n nonzero taps against
+                                   prefers -- 12290 + 403 n per point for n nonzero taps (n capped
+                                   at the nonzero-tap limit of the GENERAL gather, past which the
+                                   all-tap gather runs at about that cost) against
                                    12910 + 1530 L (2r+4)/12 for L lines), GATHER otherwise; 2D
                                    grids whose column extent is not
                                    a multiple of 4, or at most 64 (stars, the F64 9-point box),
@@ -436,7 +438,8 @@ stencil_status_t stencil_autotune(const stencil_desc_t* desc, const char* cache_
  * mixed-precision runs.  a: device array of n elements of a_dtype
  * (stencil_dtype_t); ref: device FP64 array of n elements.  out: device
  * array of 3 doubles, overwritten with
- *   out[0] = sum (a - ref)^2,  out[1] = sum ref^2,  out[2] = max |a - ref|.
+ *   out[0] = sum (a - ref)^2,  out[1] = sum ref^2,  out[2] = max |a - ref|
+ * (out[2] is +infinity when an element of a or ref is NaN, as out[0] is NaN).
  * Enqueued on `stream`; the sums are accumulated with atomics, so their last
  * bits may vary between calls. */
 stencil_status_t stencil_error_norms(const void* a, int32_t a_dtype, const double* ref, int64_t n,

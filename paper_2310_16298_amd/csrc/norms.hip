@@ -18,7 +18,7 @@ __global__ __launch_bounds__(256) void norms_kernel(const T* __restrict__ a, con
     const double d = (double)a[i] - r;
     d2 += d * d;
     r2 += r * r;
-    mx = fmax(mx, fabs(d));
+    mx = d != d ? INFINITY : fmax(mx, fabs(d));  // a NaN state reads as an infinite error
   }
   s_d2[threadIdx.x] = d2;
   s_r2[threadIdx.x] = r2;

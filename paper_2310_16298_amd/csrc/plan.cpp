@@ -366,6 +366,11 @@ static int general_cover(const std::vector<double>& cg, int R, bool c4, int* row
   return ncov;
 }
 
+// Largest nonzero-tap count of a GENERAL 2D stencil on the nonzero-tap gather
+// (measured on MI355X, 8192^2; FP32 / FP64, orders 1..4): beyond it the
+// all-tap gather is as fast, so that kernel runs every tap instead.
+static const int kSparseMax[2][5] = {{0, 3, 10, 27, 43}, {0, 5, 10, 27, 31}};
+
 // Largest nonzero-tap count of a GENERAL 3D stencil on the nonzero-tap
 // gather; beyond it the all-tap gather is as fast (measured on MI355X,
 // 256^3; FP32 / FP64, orders 1..4).
@@ -427,13 +432,17 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       bool heavy = f32 && (general || (box && R >= 3));
       const bool narrow = d.dims[1] <= 64 && (!box || (!f32 && R == 1));
       if (general && f32 && dma_cols && d.dims[1] > 64) {
-        // GENERAL: the nonzero-tap gather against the line cover.  Time per
-        // point fitted on MI355X (order 4, 8192^2 FP32), in units of 1e-7 us:
-        // 12290 + 403 n for n nonzero taps, 12910 + 1530 L for L lines, the
-        // line term scaled by the band length (2r + 4) / 12 for other orders.
+        // GENERAL: the gather against the line cover.  Time per point fitted
+        // on MI355X (order 4, 8192^2 FP32), in units of 1e-16 s: 12290 + 403 n
+        // for the nonzero-tap gather over n taps, 12910 + 1530 L for L lines,
+        // the line term scaled by the band length (2r + 4) / 12 for other
+        // orders.  Past kSparseMax taps the plan runs the all-tap gather,
+        // whose time per point equals the nonzero-tap kernel's at that count
+        // (the limit is their measured crossover), so n is capped there.
         int rr[9] = {0}, cc[9] = {0};
         const int L = general_cover(cg, R, d.block_n != 16, rr, cc);
-        if (12 * 403 * in.taps < 12 * 620 + 1530 * L * (4 + 2 * R)) heavy = false;
+        const int n_eff = std::min(in.taps, kSparseMax[0][R]);
+        if (12 * 403 * n_eff < 12 * 620 + 1530 * L * (4 + 2 * R)) heavy = false;
       }
       path = dma_cols && !heavy && !narrow ? STENCIL_PATH_GATHER : STENCIL_PATH_MFMA;
     }
@@ -488,9 +497,7 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     } else if (path == STENCIL_PATH_GATHER) {
       rs->family = FAM_GATHER2D;
       // GENERAL: the nonzero-tap gather (Section 3.5: weights left to vector
-      // units) up to the tap count where the all-tap gather catches up
-      // (measured on MI355X, 8192^2; FP32 / FP64, orders 1..4)
-      static const int kSparseMax[2][5] = {{0, 3, 10, 27, 43}, {0, 5, 10, 27, 31}};
+      // units) up to kSparseMax taps, the all-tap gather beyond
       // (grids that cannot take direct-to-LDS windows run every tap anyway)
       const bool dma_shape = d.dims[1] % 4 == 0 && !(d.dtype == STENCIL_F32 && d.dims[1] <= kTile2D);
       const bool sparse = general && dma_shape && in.taps <= kSparseMax[d.dtype == STENCIL_F64 ? 1 : 0][R];

@@ -79,8 +79,8 @@ def test_fullsize_3d_windows(grid3, dtype, shape, r, path):
     """512^3, zero halo, the configuration of the 3D benchmark (stars r = 1..4,
     the 27-point box) and the serving mix's large boxes, on sampled 8^3
     windows including corners and faces."""
-    if dtype == st.F64 and shape == st.BOX and r > 2 and path != st.PATH_GATHER:
-        pytest.skip("FP64 3D boxes beyond r = 2 run on the gather kernel only")
+    if dtype == st.F64 and shape == st.BOX and r > 2 and path == st.PATH_MFMA:
+        pytest.skip("FP64 3D boxes beyond r = 2 have no outer-product kernel (AUTO takes the gather)")
     torch = torch_cuda()
     c = inputs.coefficients(3, r, shape, seed=3100 + 10 * shape + r, dtype=np.float64)
     ce = eff_coeffs(c, dtype)
@@ -117,3 +117,51 @@ def test_fullsize_512_fp64_star(path, tb):
     tol = error_bound(c, 2, 1, st.STAR, st.F64, st.PATH_GATHER, 10, 1.0)
     assert np.abs(got - want).max() <= tol
     plan.close()
+
+
+# ------------------------------------------------- mixed precision, full size
+# The split-precision configurations at their benchmark shapes (zero halo):
+# 2D box r = 2 at 4096^2 and 3D star r = 4 at 384^3, BF16 and FP16 hi/lo
+# operands with FP32 accumulation, on sampled light-cone windows (corners,
+# faces, interior) against the FP64 oracle with the split bound.
+@pytest.mark.parametrize("path", [st.PATH_MFMA_BF16X3, st.PATH_MFMA_F16X3])
+def test_fullsize_mixed_2d_4096(path):
+    torch = torch_cuda()
+    dims, r, steps = (4096, 4096), 2, 4
+    c = inputs.coefficients(2, r, st.BOX, seed=4100, dtype=np.float64)
+    ce = eff_coeffs(c, st.F32)
+    a0 = inputs.grid(dims, seed=401)
+    plan = st.Plan(dims, r, st.BOX, c, boundary=st.BC_ZERO, dtype=st.F32, path=path)
+    assert plan.info["path"] == path
+    x = torch.from_numpy(a0).cuda()
+    res = plan.run_steps(x, torch.empty_like(x), steps)
+    torch.cuda.synchronize()
+    tol = error_bound(ce, 2, r, st.BOX, st.F32, path, steps, 1.0)
+    for lo in [(0, 0), (0, 4080), (4080, 0), (4080, 4080), (0, 2000), (2048, 4080), (1999, 3001)]:
+        want = oracle.window(a0, ce, r, st.BOX, st.BC_ZERO, steps, lo, (16, 16))
+        got = res[lo[0]:lo[0] + 16, lo[1]:lo[1] + 16].cpu().numpy().astype(np.float64)
+        assert np.abs(got - want).max() <= tol, (lo, np.abs(got - want).max(), tol)
+    plan.close()
+
+
+@pytest.mark.parametrize("path", [st.PATH_MFMA_BF16X3, st.PATH_MFMA_F16X3])
+def test_fullsize_mixed_3d_384(path):
+    torch = torch_cuda()
+    dims, r, steps = (384, 384, 384), 4, 3
+    c = inputs.coefficients(3, r, st.STAR, seed=4200, dtype=np.float64)
+    ce = eff_coeffs(c, st.F32)
+    a0 = inputs.grid(dims, seed=402)
+    plan = st.Plan(dims, r, st.STAR, c, boundary=st.BC_ZERO, dtype=st.F32, path=path)
+    assert plan.info["path"] == path
+    x = torch.from_numpy(a0).cuda()
+    res = plan.run_steps(x, torch.empty_like(x), steps)
+    torch.cuda.synchronize()
+    tol = error_bound(ce, 3, r, st.STAR, st.F32, path, steps, 1.0)
+    for lo in [(0, 0, 0), (376, 376, 376), (0, 376, 0), (376, 0, 376), (190, 0, 100), (0, 190, 190),
+               (200, 150, 376), (123, 231, 77)]:
+        want = oracle.window(a0, ce, r, st.STAR, st.BC_ZERO, steps, lo, (8, 8, 8))
+        got = res[lo[0]:lo[0] + 8, lo[1]:lo[1] + 8, lo[2]:lo[2] + 8].cpu().numpy().astype(np.float64)
+        assert np.abs(got - want).max() <= tol, (lo, np.abs(got - want).max(), tol)
+    plan.close()
+    del x, res
+    torch.cuda.empty_cache()

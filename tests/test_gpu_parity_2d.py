@@ -136,13 +136,18 @@ def test_abi_errors_on_device():
     assert res.data_ptr() == x.data_ptr() and float(res[0, 0]) == 3.0
 
 
-def test_auto_path_matches_oracle():
-    c = inputs.coefficients(2, 3, st.BOX, seed=70, dtype=np.float64)
+@pytest.mark.parametrize("dims,r,shape", [((200, 130), 3, st.BOX), ((200, 132), 3, st.BOX), ((256, 512), 4, st.BOX),
+                                           ((96, 300), 2, st.STAR), ((64, 64), 1, st.STAR)])
+def test_auto_path_matches_oracle(dims, r, shape):
+    """AUTO against the oracle, with the bound of the path the plan resolved to."""
+    c = inputs.coefficients(2, r, shape, seed=70, dtype=np.float64)
     ce = eff_coeffs(c, st.F32)
-    a0 = inputs.grid((200, 130), seed=71)
-    got = run_gpu(a0, c, 3, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_AUTO, 4)
-    want = oracle.run(a0, ce, 3, st.BOX, st.BC_PERIODIC, 4)
-    assert np.abs(got - want).max() <= error_bound(ce, 2, 3, st.BOX, st.F32, st.PATH_MFMA_BF16X3, 4, 1.0)
+    a0 = inputs.grid(dims, seed=71)
+    resolved = st.describe(dims, r, shape, c, boundary=st.BC_PERIODIC, dtype=st.F32)["path"]
+    assert resolved in (st.PATH_GATHER, st.PATH_MFMA)
+    got = run_gpu(a0, c, r, shape, st.BC_PERIODIC, st.F32, st.PATH_AUTO, 4)
+    want = oracle.run(a0, ce, r, shape, st.BC_PERIODIC, 4)
+    assert np.abs(got - want).max() <= error_bound(ce, 2, r, shape, st.F32, resolved, 4, 1.0)
 
 
 def test_error_norms_kernel():
@@ -155,6 +160,10 @@ def test_error_norms_kernel():
     assert np.isclose(out[0], (d ** 2).sum(), rtol=1e-12)
     assert np.isclose(out[1], (ref.cpu().numpy() ** 2).sum(), rtol=1e-12)
     assert out[2] == np.abs(d).max()
+    # a NaN in the state (a blown-up run) must show in the max column too
+    a[123, 45] = float("nan")
+    out = st.error_norms(a, ref).cpu().numpy()
+    assert np.isnan(out[0]) and out[2] == np.inf
 
 
 @pytest.mark.parametrize("path,dtype", [(st.PATH_GATHER, st.F32), (st.PATH_MFMA, st.F32),

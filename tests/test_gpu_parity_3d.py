@@ -243,3 +243,60 @@ def test_general_3d_nonzero_tap_gather_shift(r):
             got = plan.run_steps(x, torch.empty_like(x), 1).cpu().numpy()
             assert np.array_equal(got, np.roll(a0, shift=(r - a, r - b, r - c), axis=(0, 1, 2))), (a, b, c)
             plan.close()
+
+
+def _mask_with_taps(r, n, seed):
+    w = 2 * r + 1
+    rng = np.random.default_rng(seed)
+    flat = np.zeros(w ** 3, dtype=bool)
+    flat[rng.choice(w ** 3, size=n, replace=False)] = True
+    return flat.reshape(w, w, w)
+
+
+# The nonzero-tap gather holds taps 0..63 in one lane register and 64..127 in
+# a second: exactly 64, 65 and the maximum 128 taps, direct-to-LDS (k = 64)
+# and staged (k = 70 / 75) windows, both boundaries, FP32 and FP64 (whose
+# order >= 3 form accumulates into the ring directly).
+@pytest.mark.parametrize("r", [3, 4])
+@pytest.mark.parametrize("ntaps", [64, 65, 128])
+@pytest.mark.parametrize("dtype,dims", [(st.F32, (10, 40, 64)), (st.F32, (9, 35, 70)),
+                                        (st.F64, (10, 40, 64)), (st.F64, (6, 33, 75))])
+def test_general_3d_nonzero_tap_counts(r, ntaps, dtype, dims):
+    torch = torch_cuda()
+    ndt = np.float32 if dtype == st.F32 else np.float64
+    a0 = inputs.grid(dims, seed=900 + r, dtype=ndt)
+    mask = _mask_with_taps(r, ntaps, 910 + r + ntaps)
+    rng = np.random.default_rng(920 + r)
+    cg = np.where(mask, rng.uniform(-1.0, 1.0, size=mask.shape), 0.0)
+    cg /= float(np.abs(cg).sum())
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        plan = st.Plan(dims, r, st.GENERAL, cg, boundary=bc, dtype=dtype, path=st.PATH_GATHER)
+        assert plan.info["taps"] == ntaps and plan.info["executed_flops_per_point"] == 2.0 * ntaps
+        x = torch.from_numpy(a0).cuda()
+        got = plan.run_steps(x, torch.empty_like(x), 2).cpu().numpy().astype(np.float64)
+        ce = eff_coeffs(cg, dtype)
+        want = oracle.run(a0.astype(np.float64), ce, r, st.BOX, bc, 2)
+        tol = error_bound(ce, 3, r, st.BOX, dtype, st.PATH_GATHER, 2, np.abs(a0).max())
+        assert np.abs(got - want).max() <= tol, (bc, np.abs(got - want).max(), tol)
+        plan.close()
+
+
+@pytest.mark.parametrize("r", [3, 4])
+@pytest.mark.parametrize("dtype", [st.F32, st.F64])
+def test_general_3d_nonzero_tap_max_integer_bit_exact(r, dtype):
+    """128 nonzero integer taps (the table's limit): bit-exact against the oracle."""
+    torch = torch_cuda()
+    ndt = np.float32 if dtype == st.F32 else np.float64
+    a0 = inputs.int_grid((8, 36, 64), seed=930 + r).astype(ndt)
+    mask = _mask_with_taps(r, 128, 940 + r)
+    rng = np.random.default_rng(950 + r)
+    v = rng.integers(-2, 3, size=mask.shape).astype(np.float64)
+    v[v == 0] = 1.0
+    cg = np.where(mask, v, 0.0)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        plan = st.Plan(a0.shape, r, st.GENERAL, cg, boundary=bc, dtype=dtype, path=st.PATH_GATHER)
+        assert plan.info["executed_flops_per_point"] == 256.0
+        x = torch.from_numpy(a0).cuda()
+        got = plan.run_steps(x, torch.empty_like(x), 1).cpu().numpy().astype(np.float64)
+        assert np.array_equal(got, oracle.run(a0.astype(np.float64), cg, r, st.BOX, bc, 1)), bc
+        plan.close()

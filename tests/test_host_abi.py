@@ -437,8 +437,8 @@ def test_general_gather_choice(lib):
     """GENERAL 2D: the gather path walks the nonzero taps up to a measured count
     per order and dtype (every tap beyond it); AUTO on FP32 direct-to-LDS grids wider
     than 64 columns takes that gather when its fitted cost (12290 + 403 n per
-    point, n nonzero taps) is below the line cover's (12910 + 1530 L (2r+4)/12,
-    L lines), and the cover otherwise."""
+    point, n nonzero taps capped at the measured count) is below the line
+    cover's (12910 + 1530 L (2r+4)/12, L lines), and the cover otherwise."""
     limit = {st.F32: (0, 3, 10, 27, 43), st.F64: (0, 5, 10, 27, 31)}
     for r in (1, 2, 3, 4):
         w = 2 * r + 1
@@ -463,7 +463,8 @@ def test_general_gather_choice(lib):
             rows, cols = st.line_cover(c, r)
             nzc = int((c != 0).any(axis=0).sum())
             L = nzc if rows and 2 * nzc <= 2 * len(cols) + 3 * len(rows) else len(rows) + len(cols)
-            want = st.PATH_GATHER if 12 * 403 * n < 12 * 620 + 1530 * L * (4 + 2 * r) else st.PATH_MFMA
+            n_eff = min(n, limit[st.F32][r])  # past the limit: the all-tap gather, priced at the crossover
+            want = st.PATH_GATHER if 12 * 403 * n_eff < 12 * 620 + 1530 * L * (4 + 2 * r) else st.PATH_MFMA
             assert st.describe((256, 256), r, st.GENERAL, c, dtype=st.F32)["path"] == want, (r, n, L)
             # narrow or ragged grids keep the cover; FP64 the gather
             assert st.describe((64, 64), r, st.GENERAL, c, dtype=st.F32)["path"] == st.PATH_MFMA
@@ -474,6 +475,16 @@ def test_general_gather_choice(lib):
         info = st.describe(dims, 2, st.GENERAL, np.eye(5), path=st.PATH_GATHER, dtype=dt)
         assert info["executed_flops_per_point"] == 2.0 * 25, dims
     assert st.describe((80, 64), 2, st.GENERAL, np.eye(5), path=st.PATH_GATHER, dtype=st.F64)["executed_flops_per_point"] == 10.0
+    # past the tap limit AUTO prices the all-tap gather (which the plan then
+    # runs) at the limit's cost: order 2, diagonal + 6 weights = 11 taps over
+    # 5 lines -> gather, every one of the 25 taps executed
+    c = np.eye(5)
+    c[0, 1:4] = c[4, 1:4] = 0.5
+    assert int((c != 0).sum()) == 11 and len(sum(st.line_cover(c, 2), [])) == 5
+    info = st.describe((256, 256), 2, st.GENERAL, c, dtype=st.F32)
+    assert info["path"] == st.PATH_GATHER and info["executed_flops_per_point"] == 50.0
+    # a full order-2 GENERAL pattern: the all-tap gather (measured 617 vs 604 GSt/s for the box)
+    assert st.describe((256, 256), 2, st.GENERAL, np.ones((5, 5)), dtype=st.F32)["path"] == st.PATH_GATHER
     # the measured order-4 cases: diagonals to the gather, short covers to MFMA
     w = 9
     assert st.describe((8192, 8192), 4, st.GENERAL, np.eye(w), dtype=st.F32)["path"] == st.PATH_GATHER
