@@ -13,11 +13,16 @@ are timed beside it on the same inputs.
 Other configurations (their own JSON line each; not the headline):
     --workload star2d_512   2D five-point star, 512 x 512 FP64, zero halo, 10 steps
     --workload grid3d       3D stars r=1..4 and the 27-point box, 512^3 FP32/FP64, 50 steps
-    --workload mixed        BF16x3 / FP16x3 with an FP64 shadow, drift check every 50 steps
+    --workload mixed        BF16x3 / FP16x3 with an FP64 shadow and the CPU FP64 oracle (whole grid),
+                            drift check every 50 steps
     --workload batch        many small FP64 grids (Table 3 shapes) per batched launch vs one by one
     --workload tune         autotuner sweep: line option x MFMA block x chunk per radius
     --workload serve        serving loop, Poisson arrivals at 0.5 / 0.8 load: p50/p99 latency
     --workload cover        irregular order-4 stencils: minimum line cover vs box and gather
+
+The default line also carries ``configs``: the 512^2 FP64 latency case, the
+512^3 3D stars and 27-point box (FP32 / FP64, AUTO) and the mixed-precision
+pair at 200 steps, a few repetitions each (``--no-configs`` skips them).
 """
 from __future__ import annotations
 
@@ -181,21 +186,29 @@ def workload_star2d_512(args, torch, st, inputs) -> dict:
 def workload_grid3d(args, torch, st, inputs) -> dict:
     """3D stars r = 1..4 and boxes r = 1..4 (27-point box: r = 1) on 512^3,
     FP32 and FP64, zero halo, 50 Jacobi steps: gather vs outer-product paths."""
-    dims, steps = (512, 512, 512), 50
+    dims, steps = (512, 512, 512), args.solve_steps or 50
     a64 = inputs.grid(dims, seed=301, dtype=np.float64)
     stream = torch.cuda.Stream()
-    out = {"metric": "GStencil/s", "workload": "3D 512^3, zero halo, 50 Jacobi steps", "cases": {}}
+    out = {"metric": "GStencil/s", "workload": f"3D 512^3, zero halo, {steps} Jacobi steps", "cases": {}}
     cases = [(st.STAR, r) for r in (1, 2, 3, 4)] + [(st.BOX, r) for r in (1, 2, 3, 4)]
+    want_cases = set(args.cases.split(",")) if args.cases else None
+    want_paths = set(args.paths3d.split(",")) if args.paths3d else None
     for dt, tdt in ((st.F32, np.float32), (st.F64, np.float64)):
-        x0 = torch.from_numpy(a64.astype(tdt)).cuda()
-        paths = [("gather", st.PATH_GATHER), ("mfma", st.PATH_MFMA)]
+        x0 = None
+        paths = [("gather", st.PATH_GATHER), ("mfma", st.PATH_MFMA), ("auto", st.PATH_AUTO)]
         if dt == st.F32:
             paths += [("mfma_f16x3", st.PATH_MFMA_F16X3), ("mfma_bf16x3", st.PATH_MFMA_BF16X3)]
         for shape, r in cases:
             c = inputs.coefficients(3, r, shape, seed=3100 + 10 * shape + r, dtype=np.float64)
             key = f"{'f32' if dt == st.F32 else 'f64'}_{'box' if shape == st.BOX else 'star'}_r{r}"
+            if want_cases is not None and key not in want_cases:
+                continue
+            if x0 is None:
+                x0 = torch.from_numpy(a64.astype(tdt)).cuda()
             out["cases"][key] = {}
             for name, path in paths:
+                if want_paths is not None and name not in want_paths:
+                    continue
                 if shape == st.BOX and r > 1 and path != st.PATH_GATHER and (path != st.PATH_MFMA or
                                                                            (dt == st.F64 and r > 2)):
                     continue  # 3D boxes beyond r = 1: gather and outer products (FP64: r <= 2)
@@ -204,10 +217,11 @@ def workload_grid3d(args, torch, st, inputs) -> dict:
                 g = dims[0] * dims[1] * dims[2] * steps / (np.median(times) * 1e-3) / 1e9
                 bpp = 8 if dt == st.F32 else 16
                 out["cases"][key][name] = {"gstencil_s": round(g, 2), "hbm_frac": round(g * bpp / HBM_PEAK_GBS, 4),
-                                           "ms_per_solve": round(float(np.median(times)), 3)}
+                                           "ms_per_solve": round(float(np.median(times)), 3),
+                                           "resolved_path": st.PATH_NAMES[plan.info["path"]]}
                 print(f"[bench] {key} {name}: {g:.1f} GStencil/s", file=sys.stderr, flush=True)
                 plan.close()
-        del x0
+        x0 = None
         torch.cuda.empty_cache()
     return out
 
@@ -567,69 +581,196 @@ def workload_general3d(args, torch, st, inputs) -> dict:
     return out
 
 
+def _drift_run(torch, st, plan, shadow_plan, x0, sh0, checks, every, oracle_states=None):
+    """Advance the FP32 state and its FP64 shadow `every` steps at a time;
+    at each check the rel-L2 / max-abs of the state against the shadow (GPU)
+    and, when given, against the CPU FP64 oracle's state of that step."""
+    x = x0.clone()
+    tmp = torch.empty_like(x)
+    s64 = sh0.clone()
+    sh_tmp = torch.empty_like(s64)
+    drift = []
+    for k in range(checks):
+        res = plan.run_steps(x, tmp, every)
+        if res.data_ptr() != x.data_ptr():
+            x, tmp = tmp, x
+        r64 = shadow_plan.run_steps(s64, sh_tmp, every)
+        if r64.data_ptr() != s64.data_ptr():
+            s64, sh_tmp = sh_tmp, s64
+        nrm = st.error_norms(x, s64).cpu().numpy()
+        d = {"step": every * (k + 1), "rel_l2": float(np.sqrt(nrm[0] / nrm[1])), "max_abs": float(nrm[2])}
+        if oracle_states is not None:
+            want = oracle_states[k]
+            got = x.cpu().numpy().astype(np.float64)
+            diff = got - want
+            d["rel_l2_vs_cpu_oracle"] = float(np.sqrt((diff * diff).sum() / (want * want).sum()))
+            d["max_abs_vs_cpu_oracle"] = float(np.abs(diff).max())
+            d["shadow_vs_cpu_oracle_max_abs"] = float(np.abs(s64.cpu().numpy() - want).max())
+        drift.append(d)
+    return drift
+
+
+MIXED_SPECS = [("box2d_r2_4096", (4096, 4096), 2, 1, 401, 4100),   # shape 1 = BOX
+               ("star3d_r4_384", (384, 384, 384), 4, 0, 402, 4200)]  # shape 0 = STAR
+
+
 def workload_mixed(args, torch, st, inputs) -> dict:
-    """BF16x3 / FP16x3 outer products with FP32 state for 200 steps; an FP64
-    shadow trajectory (FP64 gather path) on the GPU; rel-L2 and max-abs of the
-    state against it every 50 steps."""
+    """BF16x3 / FP16x3 outer products with FP32 state for 200 steps, beside the
+    FP32 paths; an FP64 shadow trajectory (FP64 gather path) on the GPU and
+    the CPU FP64 oracle on the whole grid; rel-L2 and max-abs of the state
+    against both every 50 steps."""
     import oracle
-    out = {"metric": "GStencil/s and drift vs FP64", "cases": {}}
+    oracle.build(force=False)
+    threads = oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    out = {"metric": "GStencil/s and drift vs FP64 (GPU shadow and CPU oracle, whole grid)", "cases": {},
+           "cpu_oracle_threads": threads}
     stream = torch.cuda.Stream()
-    specs = [("box2d_r2_4096", (4096, 4096), 2, st.BOX, 401, 4100),
-             ("star3d_r4_384", (384, 384, 384), 4, st.STAR, 402, 4200)]
-    for key, dims, r, shape, iseed, cseed in specs:
+    nsteps = args.solve_steps or 200
+    checks = max(1, nsteps // 50)
+    want_cases = set(args.cases.split(",")) if args.cases else None
+    want_paths = set(args.paths3d.split(",")) if args.paths3d else None
+    for key, dims, r, shape, iseed, cseed in MIXED_SPECS:
+        if want_cases is not None and key not in want_cases:
+            continue
         nd = len(dims)
         c = inputs.coefficients(nd, r, shape, seed=cseed, dtype=np.float64)
         c32 = c.astype(np.float32).astype(np.float64)
         a32 = inputs.grid(dims, seed=iseed, dtype=np.float32)
+        states = None
+        out["cases"][key] = {}
+        if not args.no_oracle:
+            # the CPU oracle's states at steps 50, 100, 150, 200 (whole grid, FP64)
+            t0 = time.perf_counter()
+            states, cur = [], a32.astype(np.float64)
+            for k in range(checks):
+                cur = oracle.run(cur, c32, r, shape, st.BC_ZERO, 50)
+                states.append(cur)
+                print(f"[bench] {key}: CPU oracle at step {50 * (k + 1)} ({time.perf_counter() - t0:.0f} s)",
+                      file=sys.stderr, flush=True)
+            out["cases"][key]["cpu_oracle_seconds"] = round(time.perf_counter() - t0, 1)
+            del cur
         x0 = torch.from_numpy(a32).cuda()
         shadow_plan = st.Plan(dims, r, shape, c32, boundary=st.BC_ZERO, dtype=st.F64, path=st.PATH_GATHER)
         sh = x0.double()
-        sh_tmp = torch.empty_like(sh)
-        out["cases"][key] = {}
         for name, path in (("mfma_bf16x3", st.PATH_MFMA_BF16X3), ("mfma_f16x3", st.PATH_MFMA_F16X3),
-                           ("mfma", st.PATH_MFMA), ("gather", st.PATH_GATHER)):
+                           ("mfma", st.PATH_MFMA), ("gather", st.PATH_GATHER), ("auto", st.PATH_AUTO)):
+            if want_paths is not None and name not in want_paths:
+                continue
             plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=st.F32, path=path)
-            times = _time_solve(torch, plan, x0, 200, args.steps, args.warmup, stream)
-            g = float(np.prod(dims)) * 200 / (np.median(times) * 1e-3) / 1e9
-            # drift: state and FP64 shadow advanced 50 steps at a time
-            x = x0.clone()
-            tmp = torch.empty_like(x)
-            s64 = sh.clone()
-            drift = []
-            for k in range(4):
-                res = plan.run_steps(x, tmp, 50)
-                if res.data_ptr() != x.data_ptr():
-                    x, tmp = tmp, x
-                r64 = shadow_plan.run_steps(s64, sh_tmp, 50)
-                if r64.data_ptr() != s64.data_ptr():
-                    s64, sh_tmp = sh_tmp, s64
-                nrm = st.error_norms(x, s64).cpu().numpy()
-                drift.append({"step": 50 * (k + 1), "rel_l2": float(np.sqrt(nrm[0] / nrm[1])),
-                              "max_abs": float(nrm[2])})
-            entry = {"gstencil_s": round(g, 2), "hbm_frac": round(g * 8 / HBM_PEAK_GBS, 4), "drift": drift}
-            if nd == 2:
-                # CPU FP64 oracle on light-cone windows of the final state
-                fin = x.cpu().numpy().astype(np.float64)
-                errs = []
-                for lo in [(0, 0), (2000, 3000)]:
-                    want = oracle.window(a32, c32, r, shape, st.BC_ZERO, 200, lo, (8, 8))
-                    errs.append(float(np.abs(fin[lo[0]:lo[0] + 8, lo[1]:lo[1] + 8] - want).max()))
-                entry["max_abs_vs_cpu_oracle_windows"] = max(errs)
+            times = _time_solve(torch, plan, x0, nsteps, args.steps, args.warmup, stream)
+            g = float(np.prod(dims)) * nsteps / (np.median(times) * 1e-3) / 1e9
+            entry = {"gstencil_s": round(g, 2), "hbm_frac": round(g * 8 / HBM_PEAK_GBS, 4),
+                     "resolved_path": st.PATH_NAMES[plan.info["path"]]}
+            if name != "auto":
+                drift = _drift_run(torch, st, plan, shadow_plan, x0, sh, checks, 50, states)
+                entry["drift"] = drift
+                msg = f"rel_l2 vs shadow {drift[-1]['rel_l2']:.2e}"
+                if states is not None:
+                    msg += (f", vs oracle {drift[-1]['rel_l2_vs_cpu_oracle']:.2e} "
+                            f"(max_abs {drift[-1]['max_abs_vs_cpu_oracle']:.2e})")
+            else:
+                msg = f"path {entry['resolved_path']}"
             out["cases"][key][name] = entry
-            print(f"[bench] {key} {name}: {g:.1f} GStencil/s drift@200 rel_l2={drift[-1]['rel_l2']:.2e}",
-                  file=sys.stderr, flush=True)
+            print(f"[bench] {key} {name}: {g:.1f} GStencil/s; {msg}", file=sys.stderr, flush=True)
             plan.close()
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
+        sh_tmp = torch.empty_like(sh)
         t0.record(stream)
-        shadow_plan.run_steps(sh.clone(), sh_tmp, 200, stream=stream)
+        shadow_plan.run_steps(sh.clone(), sh_tmp, nsteps, stream=stream)
         t1.record(stream)
         torch.cuda.synchronize()
-        out["cases"][key]["fp64_shadow_ms_per_200_steps"] = t0.elapsed_time(t1)
+        out["cases"][key][f"fp64_shadow_ms_per_{nsteps}_steps"] = t0.elapsed_time(t1)
         shadow_plan.close()
-        del x0, sh, sh_tmp
+        del x0, sh, sh_tmp, states
         torch.cuda.empty_cache()
     return out
+
+
+def config_extras(args, torch, st, inputs) -> dict:
+    """The other benchmark configurations in compact form for the default
+    line (a few repetitions each):
+      star2d_512_fp64 -- 2D five-point star, 512^2 FP64, zero halo, 10 steps:
+                         AUTO latency p50/p99 and the CPU oracle's time;
+      grid3d_512      -- 3D stars r = 1..4 and the 27-point box, 512^3 FP32
+                         and FP64, zero halo, 50 steps, AUTO path;
+      mixed_200       -- 2D box r = 2 at 4096^2 and 3D star r = 4 at 384^3,
+                         200 steps, BF16x3 / FP16x3 beside the FP32 paths,
+                         drift against the FP64 GPU shadow at step 200."""
+    import oracle
+    stream = torch.cuda.Stream()
+    ex = {}
+    # config: 512^2 FP64 five-point star
+    dims, steps = (512, 512), 10
+    c = inputs.diffusion_5pt()
+    a0 = inputs.grid(dims, seed=101, dtype=np.float64)
+    x0 = torch.from_numpy(a0).cuda()
+    plan = st.Plan(dims, 1, st.STAR, c, boundary=st.BC_ZERO, dtype=st.F64)
+    times = _time_solve(torch, plan, x0, steps, 50, 5, stream)
+    res = plan.run_steps(x0.clone(), torch.empty_like(x0), steps)
+    torch.cuda.synchronize()
+    oracle.build(force=False)
+    used = oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    t0 = time.perf_counter()
+    want = oracle.run(a0, c, 1, st.STAR, st.BC_ZERO, steps)
+    cpu_s = time.perf_counter() - t0
+    ex["star2d_512_fp64"] = {"path": st.PATH_NAMES[plan.info["path"]], "time_block": plan.info["time_block"],
+                             "p50_us": round(float(np.percentile(times, 50)) * 1e3, 1),
+                             "p99_us": round(float(np.percentile(times, 99)) * 1e3, 1),
+                             "gstencil_s": round(dims[0] * dims[1] * steps / (np.median(times) * 1e-3) / 1e9, 2),
+                             "max_abs_err_vs_oracle": float(np.abs(res.cpu().numpy() - want).max()),
+                             "cpu_oracle_s": round(cpu_s, 4), "cpu_threads": used}
+    plan.close()
+    print(f"[bench] extra star2d_512_fp64: {ex['star2d_512_fp64']}", file=sys.stderr, flush=True)
+    # config: 512^3 3D stars and 27-point box, FP32 and FP64, AUTO
+    dims, steps = (512, 512, 512), 50
+    a64 = inputs.grid(dims, seed=301, dtype=np.float64)
+    g3 = {}
+    for dt, ndt, tag, bpp in ((st.F32, np.float32, "f32", 8), (st.F64, np.float64, "f64", 16)):
+        x0 = torch.from_numpy(a64.astype(ndt)).cuda()
+        for shape, r in [(st.STAR, 1), (st.STAR, 2), (st.STAR, 3), (st.STAR, 4), (st.BOX, 1)]:
+            c = inputs.coefficients(3, r, shape, seed=3100 + 10 * shape + r, dtype=np.float64)
+            plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=dt)
+            times = _time_solve(torch, plan, x0, steps, 3, 1, stream)
+            g = float(np.prod(dims)) * steps / (np.median(times) * 1e-3) / 1e9
+            g3[f"{tag}_{'box' if shape == st.BOX else 'star'}_r{r}"] = {
+                "path": st.PATH_NAMES[plan.info["path"]], "gstencil_s": round(g, 1),
+                "hbm_frac": round(g * bpp / HBM_PEAK_GBS, 4)}
+            plan.close()
+        del x0
+        torch.cuda.empty_cache()
+    del a64
+    ex["grid3d_512"] = g3
+    print(f"[bench] extra grid3d_512: {g3}", file=sys.stderr, flush=True)
+    # config: mixed precision, 200 steps, drift at 200 against the FP64 shadow
+    mx = {}
+    for key, dims, r, shape, iseed, cseed in MIXED_SPECS:
+        nd = len(dims)
+        c = inputs.coefficients(nd, r, shape, seed=cseed, dtype=np.float64)
+        c32 = c.astype(np.float32).astype(np.float64)
+        x0 = torch.from_numpy(inputs.grid(dims, seed=iseed, dtype=np.float32)).cuda()
+        shadow_plan = st.Plan(dims, r, shape, c32, boundary=st.BC_ZERO, dtype=st.F64, path=st.PATH_GATHER)
+        sh = x0.double()
+        mx[key] = {}
+        for name, path in (("mfma_bf16x3", st.PATH_MFMA_BF16X3), ("mfma_f16x3", st.PATH_MFMA_F16X3),
+                           ("mfma", st.PATH_MFMA), ("gather", st.PATH_GATHER), ("auto", st.PATH_AUTO)):
+            plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=st.F32, path=path)
+            times = _time_solve(torch, plan, x0, 200, 3, 1, stream)
+            g = float(np.prod(dims)) * 200 / (np.median(times) * 1e-3) / 1e9
+            e = {"gstencil_s": round(g, 1), "hbm_frac": round(g * 8 / HBM_PEAK_GBS, 4)}
+            if name.startswith("mfma_"):
+                d = _drift_run(torch, st, plan, shadow_plan, x0, sh, 1, 200)[-1]
+                e.update({"rel_l2_200": d["rel_l2"], "max_abs_200": d["max_abs"]})
+            if name == "auto":
+                e["path"] = st.PATH_NAMES[plan.info["path"]]
+            mx[key][name] = e
+            plan.close()
+        shadow_plan.close()
+        del x0, sh
+        torch.cuda.empty_cache()
+    ex["mixed_200"] = mx
+    print(f"[bench] extra mixed_200: {mx}", file=sys.stderr, flush=True)
+    return ex
 
 
 def main() -> int:
@@ -643,6 +784,8 @@ def main() -> int:
     ap.add_argument("--paths", default="gather,mfma,mfma_f16x3,mfma_bf16x3,gather_tb,tuned,auto",
                     help="gather_tb: time-blocked gather (largest time block); tuned: the autotuner's plan")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations' compact results in the default line")
     ap.add_argument("--radii", default="1,2,3,4", help="orders to run (profiling runs use a subset)")
     ap.add_argument("--jacobi-steps", type=int, default=JACOBI_STEPS,
                     help="Jacobi steps per solve (profiling runs only; the benchmark uses 100)")
@@ -653,6 +796,11 @@ def main() -> int:
     ap.add_argument("--serve-arena-gib", type=int, default=64)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="first run N plain device copies of one grid (known bytes) for counter scaling")
+    ap.add_argument("--cases", default="", help="grid3d / mixed: comma-separated case keys (default all)")
+    ap.add_argument("--paths3d", default="", help="grid3d / mixed: comma-separated path names (default all)")
+    ap.add_argument("--solve-steps", type=int, default=0,
+                    help="grid3d / mixed: Jacobi steps per solve (profiling runs only; default 50 / 200)")
+    ap.add_argument("--no-oracle", action="store_true", help="mixed: skip the CPU oracle (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU runs are not part of this build.",
@@ -667,6 +815,16 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     st.load_library()
+    if args.calibrate_copy:
+        # a plain device copy of 2^26 FP32 values (268,435,456 bytes read and written) per repetition:
+        # the reference reading for scaling the FETCH_SIZE / WRITE_SIZE counters of the kernels
+        src = torch.empty(1 << 26, dtype=torch.float32, device="cuda").uniform_(-1.0, 1.0)
+        dst = torch.empty_like(src)
+        for _ in range(args.calibrate_copy):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration: {args.calibrate_copy} copies of {src.numel() * 4} bytes", file=sys.stderr)
+        del src, dst
     if args.workload != "box2d":
         fn = {"star2d_512": workload_star2d_512, "grid3d": workload_grid3d, "mixed": workload_mixed,
               "batch": workload_batch, "tune": workload_tune, "serve": workload_serve,
@@ -697,12 +855,6 @@ def main() -> int:
     coeffs = {r: inputs.coefficients(2, r, inputs.BOX, seed=COEF_SEED0 + r, dtype=np.float64) for r in RADII}
     a0_dev = torch.from_numpy(a0).cuda()
     stream = torch.cuda.Stream()
-    if args.calibrate_copy:
-        dst = torch.empty_like(a0_dev)
-        for _ in range(args.calibrate_copy):
-            dst.copy_(a0_dev)
-        torch.cuda.synchronize()
-        print(f"[bench] calibration: {args.calibrate_copy} copies of {a0_dev.numel() * 4} bytes", file=sys.stderr)
     pts_per_solve = DIMS[0] * DIMS[1] * JACOBI_STEPS
 
     results = {}
@@ -791,6 +943,10 @@ def main() -> int:
         cb = cpu_baseline(coeffs, a0)
         cb.pop("seconds", None)
         line["cpu_baseline"] = cb
+    if not args.no_configs:
+        del a0_dev
+        torch.cuda.empty_cache()
+        line["configs"] = config_extras(args, torch, st, inputs)
     print(json.dumps(line))
     return 0
 
