@@ -137,6 +137,13 @@ typedef struct {
                            2D grids on the GATHER path (AUTO resolves to it); the halo r*T rounded up
                            to a multiple of 4 is at most 12 for F32 and 8 for F64 (r = 1: T <= 12 / 8;
                            r = 2: 6 / 4; r = 3: 4 / 2; r = 4: 3 / 2), else EUNSUPPORTED */
+  int32_t reg_rows;     /* register tile of the 2D FP32 outer products on n = 4 blocks (box stencils,
+                           MFMA path; the i unrolling of Section 4.2): output rows per wave, 8 / 16 / 32
+                           (two, four or eight 4-row accumulator blocks), 0 = library choice (16) */
+  int32_t tile_width;   /* workgroup tile of the same kernel: columns per strip, 256 (four waves side by
+                           side) or 128 (two rows of two waves), 0 = library choice (256).  Non-default
+                           reg_rows / tile_width on any other plan: EUNSUPPORTED; grids whose column
+                           extent is not a multiple of 4 run the tiled kernel, which ignores both */
   const double* coeffs; /* host pointer to (2r+1)^ndim gather coefficients C^g,
                            C order, index o + r for offset o; copied by the call.
                            For an F32 plan they are rounded to float first. */
@@ -161,6 +168,8 @@ typedef struct {
   int32_t pad0;
   int64_t operand_bytes;         /* device bytes of the plan's operands: band fragments, dense C^g
                                     and a 256-byte zero line, each rounded up to 256 bytes */
+  int32_t reg_rows;              /* output rows per wave of the n = 4 2D outer products (0: other kernels) */
+  int32_t tile_width;            /* their workgroup tile width in columns (0: other kernels) */
 } stencil_plan_info_t;
 
 typedef struct stencil_plan_s* stencil_plan_t;
@@ -396,20 +405,25 @@ stencil_status_t stencil_server_destroy(stencil_server_t server);
  *      when desc->lines is AUTO, block edges 4 and 16 for MFMA when
  *      desc->block_n is 0 -- combinations stencil_desc_check rejects are
  *      skipped;
- *   2. 2D grids, path AUTO or GATHER, time_block 0: time blocks T = 2..12
+ *   2. when the winner is a 2D FP32 box on n = 4 MFMA blocks and reg_rows /
+ *      tile_width are 0: register tiles of 8 / 16 / 32 rows per wave x
+ *      workgroup tiles of 128 / 256 columns (the unrolling study of Section
+ *      4.2, Fig. 4);
+ *   3. 2D grids, path AUTO or GATHER, time_block 0: time blocks T = 2..12
  *      (those stencil_desc_check accepts) on the gather path;
- *   3. for the winner (unless time-blocked), chunk lengths 16..1024 rows (2D)
+ *   4. for the winner (unless time-blocked), chunk lengths 16..1024 rows (2D)
  *      or 8..128 planes (3D) when desc->chunk is 0.
  * Fields of desc other than 0 / AUTO are kept fixed.
  * Timing: two scratch grids of desc's size (allocated here, set to zero,
  * freed before returning) on `stream`, which must not be under capture; per
  * candidate one warm-up run and the best of three timed runs of 24..64
  * steps (about 2e8 point-steps).
- * best: receives desc with the chosen path, lines, block_n, chunk and
- *   time_block (coeffs pointer unchanged).  ms_per_step (may be NULL): the
+ * best: receives desc with the chosen path, lines, block_n, chunk,
+ *   time_block, reg_rows and tile_width (coeffs pointer unchanged).  ms_per_step (may be NULL): the
  *   winner's time per step.
  * cache_path (may be NULL): a text file, one line per tuned request
- *   ("<key> -> path=.. lines=.. block_n=.. chunk=.. time_block=.. ms=.."),
+ *   ("<key> -> path=.. lines=.. block_n=.. chunk=.. time_block=.. reg_rows=..
+ *   tile_width=.. ms=.."),
  *   keyed by ndim,
  *   shape, radius, dtype, boundary, dims and the requested knobs (the
  *   coefficient values do not change the timing).  A hit returns the stored
@@ -425,7 +439,7 @@ stencil_status_t stencil_server_destroy(stencil_server_t server);
 #define STENCIL_TUNE_FORCE 2
 
 typedef struct {
-  int32_t path, lines, block_n, chunk, time_block;
+  int32_t path, lines, block_n, chunk, time_block, reg_rows, tile_width;
   int32_t status;       /* stencil_status_t of the candidate */
   double ms_per_step;   /* best timed run; negative if the candidate failed */
 } stencil_tune_result_t;

@@ -148,13 +148,44 @@ __device__ __forceinline__ void dma_block_loop(typename D::elem_t* bufs, const K
   }
 }
 
+// Block loop with one barrier per block, for kernels whose body issues NST
+// store instructions per wave when the block is whole: wait for this wave's
+// loads of window b (the stores of block b - 1, issued after them, may stay
+// in flight), barrier (window b visible; every wave is past block b - 1,
+// whose buffer then takes window b + 1), issue window b + 1, compute and
+// store block b.  body(cur, ib) returns NST when all its stores were issued,
+// else -1 (the next wait then waits for everything).
+template <class D, int BM, int NST, class Body>
+__device__ __forceinline__ void dma_block_loop1(typename D::elem_t* bufs, const KArgs& a, const Strip2D& sp, Body body) {
+  typedef typename D::elem_t T;
+  constexpr int R = D::RAD;
+  const T* __restrict__ in = (const T*)a.in;
+  const T* __restrict__ zeros = (const T*)a.zeros;
+  const bool periodic = a.periodic != 0;
+  const int nb = (int)((sp.i1 - sp.i0 + BM - 1) / BM);
+  D::issue(bufs, in, zeros, a.d0, a.d1, sp.i0 - R, sp.j0, periodic);
+  int pend = 0;
+  for (int bi = 0; bi < nb; ++bi) {
+    const int64_t ib = sp.i0 + (int64_t)bi * BM;
+    T* cur = bufs + (bi & 1) * D::BUF;
+    if (pend == NST) D::template wait_vm<NST>();
+    else D::template wait_vm<0>();
+    lds_barrier();
+    if (bi + 1 < nb) D::issue(bufs + ((bi + 1) & 1) * D::BUF, in, zeros, a.d0, a.d1, ib + BM - R, sp.j0, periodic);
+    pend = body(cur, ib);
+  }
+}
+
 // ---------------------------------------------------------------------------
-// n = 4 block outer products on DMA-fed windows: 256-column strips, 16-row
-// blocks; wave w owns columns 64 w .. 64 w + 63 and all 16 rows (four
-// accumulators of 4 rows, the i unrolling ui = 4).  The input row segment is
-// the MFMA A operand and the coefficient vector the B operand, so block beta
-// of the instruction holds D[i][j] = input column 4 beta + i times the weight
-// for block row j: lane 4 beta + j then owns four consecutive columns of one
+// n = 4 block outer products on DMA-fed windows.  Register tile (the i and j
+// unrolling of Section 4.2): wave w owns 64 columns (lane 4 beta + j of block
+// beta) and 4 UI rows (UI accumulators of 4 rows); the workgroup's four waves
+// are WR rows x (4 / WR) columns of such tiles, so its strip is 256 / WR
+// columns wide and its row block BM = 4 UI WR.  Default UI = 4, WR = 1:
+// 256-column strips of 16-row blocks.  The input row segment is the MFMA A
+// operand and the coefficient vector the B operand, so block beta of the
+// instruction holds D[i][j] = input column 4 beta + i times the weight for
+// block row j: lane 4 beta + j then owns four consecutive columns of one
 // output row and stores them with one 16-byte write.
 //
 // Every block of the instruction uses the same B vector, so one VGPR carries
@@ -164,16 +195,30 @@ __device__ __forceinline__ void dma_block_loop(typename D::elem_t* bufs, const K
 // ---------------------------------------------------------------------------
 constexpr int kDmaTN = 256, kDmaBM = 16;
 
-template <int R, bool BOX>
+// Scheduling pattern of one line: X LDS reads, each followed by its share of
+// the line's NM MFMAs (the group sizes must be constants, hence the recursion).
+template <int X, int NM, int K = 0>
+__device__ __forceinline__ void interleave_reads_mfma() {
+  if constexpr (K < X) {
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                              // one LDS read
+    __builtin_amdgcn_sched_group_barrier(0x008, (K + 1) * NM / X - K * NM / X, 0);  // MFMAs
+    interleave_reads_mfma<X, NM, K + 1>();
+  }
+}
+
+template <int R, bool BOX, int UI = 4, int WR = 1>
 __device__ __forceinline__ void mfma2d_b4_dma_item(const KArgs& a, int item) {
-  constexpr int BM = kDmaBM, TN = kDmaTN, NB = 4 + 2 * R, NL = BOX ? 2 * R + 1 : 1;
+  constexpr int NWC = 4 / WR, TN = 64 * NWC, BM = 4 * UI * WR;
+  constexpr int NB = 4 + 2 * R, NL = BOX ? 2 * R + 1 : 1;
   constexpr int NC = NL * NB, NP = (NC + 3) / 4;  // coefficient vectors, packed registers
+  static_assert(WR == 1 || WR == 2, "one or two rows of wave tiles");
   typedef DmaWindow<float, R, BM, TN, 256> D;
   __shared__ __attribute__((aligned(16))) float bufs[2 * D::BUF];
 
   const int64_t N = a.d1;
   float* __restrict__ out = (float*)a.out;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wc = w % NWC, wr = w / NWC;
   const Strip2D sp = decode_strip(a, item, TN);
 
   // vector c's value for lane l sits at frag[64 c + l] (it depends on l mod 4
@@ -191,34 +236,44 @@ __device__ __forceinline__ void mfma2d_b4_dma_item(const KArgs& a, int item) {
 #pragma unroll
     for (int b = 0; b <= 2 * R; ++b) cw[b] = c[R * (2 * R + 1) + b];
   }
-  const int orow = lane & 3;                            // block row owned by this lane
-  const int64_t gj = sp.j0 + 64 * w + 4 * (lane >> 2);  // first of its four columns
+  const int orow = lane & 3;                             // block row owned by this lane
+  const int64_t gj = sp.j0 + 64 * wc + 4 * (lane >> 2);  // first of its four columns
+  const int row0 = 4 * UI * wr;                          // the wave's first row in the block
 
-  dma_block_loop<D, BM>(bufs, a, sp, [&](const float* cur, int64_t ib) {
-    const float* rowp = cur + D::WCOL0 + 64 * w + lane;
-    floatx4 acc[4];
+  dma_block_loop1<D, BM, UI>(bufs, a, sp, [&](const float* cur, int64_t ib) {
+    const float* rowp = cur + row0 * D::PITCH + D::WCOL0 + 64 * wc + lane;
+    floatx4 acc[UI];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc[s] = floatx4{0, 0, 0, 0};
+    for (int s = 0; s < UI; ++s) acc[s] = floatx4{0, 0, 0, 0};
+    // the window rows of line li + 1 are read while line li's MFMAs run (two
+    // register sets), the reads spread evenly between the MFMAs
+    constexpr int X = 4 * UI + 2 * R, NM = UI * NB;  // rows read and MFMAs per line
+    float hv[2][X];
+#pragma unroll
+    for (int x = 0; x < X; ++x) hv[0][x] = rowp[x * D::PITCH + (BOX ? 0 : R)];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int li = 0; li < NL; ++li) {
-      const int b = BOX ? li : R;
+      if (li + 1 < NL) {
 #pragma unroll
-      for (int x = 0; x < 16 + 2 * R; ++x) {
-        const float hv = rowp[x * D::PITCH + b];
+        for (int x = 0; x < X; ++x) hv[(li + 1) & 1][x] = rowp[x * D::PITCH + li + 1];
+      }
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
+      for (int x = 0; x < X; ++x)
+#pragma unroll
+        for (int s = 0; s < UI; ++s) {
           const int d = x - 4 * s, c = li * NB + d;
           if (d < 0 || d >= NB) continue;
-          acc[s] = mfma4_group(hv, af[c >> 2], acc[s], c & 3);
+          acc[s] = mfma4_group(hv[li & 1][x], af[c >> 2], acc[s], c & 3);
         }
-      }
-      __builtin_amdgcn_sched_barrier(0);  // keep each line's LDS reads next to its MFMAs
+      if (li + 1 < NL) interleave_reads_mfma<X, NM>();
+      __builtin_amdgcn_sched_barrier(0);
     }
     if constexpr (!BOX) {
       // single-weight lines b != r: D[row][col] += C^g[r][b] * H[row + r][col + b]
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const float* rp = cur + (4 * s + orow + R) * D::PITCH + D::WCOL0 + 64 * w + 4 * (lane >> 2);
+      for (int s = 0; s < UI; ++s) {
+        const float* rp = cur + (row0 + 4 * s + orow + R) * D::PITCH + D::WCOL0 + 64 * wc + 4 * (lane >> 2);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float sum = 0.0f;
@@ -233,22 +288,24 @@ __device__ __forceinline__ void mfma2d_b4_dma_item(const KArgs& a, int item) {
     }
     if (gj < N) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int64_t gi = ib + 4 * s + orow;
+      for (int s = 0; s < UI; ++s) {
+        const int64_t gi = ib + row0 + 4 * s + orow;
         if (gi < sp.i1) *reinterpret_cast<float4*>(out + gi * N + gj) = float4{acc[s][0], acc[s][1], acc[s][2], acc[s][3]};
       }
     }
+    // all UI stores issued: the wave's columns lie inside the grid and its rows inside the block
+    return (sp.j0 + 64 * wc + 64 <= N && ib + row0 + 4 * UI <= sp.i1) ? UI : -1;
   });
 }
 
-template <int R, bool BOX>
+template <int R, bool BOX, int UI = 4, int WR = 1>
 __global__ __launch_bounds__(256) void mfma2d_b4_dma_kernel(KArgs a) {
-  mfma2d_b4_dma_item<R, BOX>(a, xcd_remap(blockIdx.x, gridDim.x));
+  mfma2d_b4_dma_item<R, BOX, UI, WR>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-template <int R, bool BOX>
+template <int R, bool BOX, int UI = 4, int WR = 1>
 __global__ __launch_bounds__(256) void mfma2d_b4_dma_batch(BatchArgs b) {
-  for_each_batch_item(b, [&](const KArgs& x, int id) { mfma2d_b4_dma_item<R, BOX>(x, id); });
+  for_each_batch_item(b, [&](const KArgs& x, int id) { mfma2d_b4_dma_item<R, BOX, UI, WR>(x, id); });
 }
 
 // ---------------------------------------------------------------------------

@@ -20,6 +20,7 @@
 #include "dma3d.hpp"
 #include "kernels_2d.hpp"
 #include "kernels_split2d.hpp"
+#include "launch.hpp"
 #include "mfma_traits.hpp"
 
 namespace stencil {
@@ -33,6 +34,42 @@ struct Chunk3D {
 
 // Work items of a 3D grid: (j, k) tiles x i-chunks (set by the plan).
 inline int64_t chunk3d_items(const KArgs& a) { return (int64_t)a.tiles0 * a.tiles1 * a.nchunks; }
+
+// Work items of a single-grid launch of `kernel`.  When the chunk is the
+// library's choice, the kernel keeps at most three workgroups per CU and the
+// plan-time decomposition needs more than one wave of them, the planes are
+// re-cut into the most chunks of equal depth (at least 4r planes) whose items
+// still fit one wave: every (tile, chunk) item then runs at once (no partial
+// last wave), and the items an XCD receives are neighbours in the plane, so
+// the halo rows one reads are in L2 when the next reads them.  Measured on
+// MI355X: FP32 stars of order 4 +8-19 % (384^3, 512^3), FP64 stars of order
+// 4 at 384^3 +60 %; kernels with four or more workgroups per CU ran 2-4 %
+// slower re-cut and keep the plan's chunks.
+inline int64_t balanced_items3d(KArgs& a, const void* kernel, int R, int32_t chunk_req) {
+  const int64_t items = chunk3d_items(a);
+  if (chunk_req > 0) return items;
+  const Residency res = resident_workgroups(kernel);
+  if (res.per_cu <= 0 || res.per_cu > 3) return items;
+  const int64_t slots = (int64_t)res.per_cu * res.cus;
+  const int64_t tiles = (int64_t)a.tiles0 * a.tiles1;
+  if (items <= slots) return items;
+  int64_t nch = slots / tiles;
+  if (nch < 1) nch = 1;
+  int64_t chunk = (a.d0 + nch - 1) / nch;
+  const int64_t minc = 4 * R < a.d0 ? 4 * R : a.d0;
+  if (chunk < minc) chunk = minc;
+  a.chunk = (int32_t)chunk;
+  a.nchunks = (int32_t)((a.d0 + chunk - 1) / chunk);
+  return chunk3d_items(a);
+}
+
+// A 3D kernel (single-grid K, batched B) for its plan's args: items as above.
+template <auto K, auto B>
+inline Kernel kernel3d(KArgs& a, int R, int32_t chunk_req) {
+  Kernel k = kernel_of<K, B>(0);
+  k.items = balanced_items3d(a, k.single_id, R, chunk_req);
+  return k;
+}
 
 __device__ __forceinline__ Chunk3D decode_chunk(const KArgs& a, int id) {
   const int per_plane = a.tiles0 * a.tiles1;
@@ -835,6 +872,169 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
           if constexpr (BOX) acx[2 * R][t] = floatx4{0, 0, 0, 0};
         }
       });
+}
+
+// ---------------------------------------------------------------------------
+// Split-precision star in the hybrid cover of Table 2 (the line assignment of
+// the FP32 n = 4 kernel): on every input plane the two in-plane lines through
+// the centre run as BF16/FP16 hi/lo products on 16x16x32 MFMAs -- the line
+// along k, CLS(r, r, *) (centre included), as D[p][q] += sum_y H[p][y] S[y][q]
+// (A = eight consecutive k values of one row: one 16-byte LDS read), and the
+// line along j, CLS(r, *, r) (centre excluded), as D[p][q] += sum_x T[p][x]
+// H[x][q] with the band T[p][x] = C^g[r][x - p][r] as the A operand and B =
+// eight consecutive j values of one column, read as 16-bit elements (lanes of
+// a row read neighbouring elements: no bank conflicts) -- and the 2r lines
+// CLS(a, *, r), a != r, one weight each, are the vector FMAs of the i arm into
+// the other ring slots.  Each FP32 window is split once into row-major hi/lo
+// planes.  Both lines' products land in the same accumulator layout; their
+// cross terms (hi*lo + lo*hi) are summed apart and folded into the centre
+// plane's slot.
+// ---------------------------------------------------------------------------
+template <int R>
+struct SplitStar3DShape {
+  static constexpr int W = 2 * R + 1;
+  static constexpr int WROWS = kTJ + 2 * R;   // window rows (global j0 - r ..)
+  static constexpr int WCOLS = kTK + 2 * R;   // window columns (global k0 - r ..)
+  static constexpr int PR = kTJ + 16;         // plane rows: the j line's K = 32 reads rows up to 47
+  static constexpr int P = 88;                // 16-bit pitch: the k line's K = 32 reads columns up to 79
+  static_assert((kTK - 32) + 16 + 32 <= P && WCOLS <= P && WROWS <= PR, "plane too small");
+};
+
+template <int KIND, int R, bool DMA>
+__device__ __forceinline__ void split3d_hybrid_item(const KArgs& a, int item) {
+  typedef SplitStar3DShape<R> S;
+  typedef PlaneWalk<float, R, S::WROWS, DMA, true> PW;
+  static_assert(PW::COL0 + R == 4, "tile body at LDS column 4");
+  constexpr int W = S::W;
+  // one LDS object (separate ones make the compiler wait for the plane in
+  // flight before LDS accesses): the plane buffers, then the hi and lo planes
+  constexpr int PLANE = (S::PR * S::P * 2 + 15) / 16 * 4;  // floats per 16-bit plane
+  __shared__ __attribute__((aligned(16))) float bufs[PW::NBUF * PW::BUF + 2 * PLANE];
+  uint16_t* lhi = reinterpret_cast<uint16_t*>(bufs + PW::NBUF * PW::BUF);
+  uint16_t* llo = reinterpret_cast<uint16_t*>(bufs + PW::NBUF * PW::BUF + PLANE);
+
+  const Chunk3D ch = decode_chunk(a, item);
+  const int64_t Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
+  float* __restrict__ out = (float*)a.out;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wj = w >> 1, wk = w & 1;
+  const int g = lane >> 4, q = lane & 15;
+
+  // line 0: along k (B operand S[y][q]); line 1: along j (A operand T[p][x]);
+  // both bands pack as w[8 (l / 16) + e - l % 16] in lane l, element e
+  const u16x8* __restrict__ frag = (const u16x8*)a.frag;
+  const u16x8 kh = frag[0 * 64 + lane], kl = frag[1 * 64 + lane];
+  const u16x8 jh = frag[2 * 64 + lane], jl = frag[3 * 64 + lane];
+  const float cscale = 1.0f / a.out_scale;  // exact power of two
+  float ci[W];                               // i-arm weights C^g[a][r][r], scaled
+  {
+    const float* __restrict__ c = (const float*)a.coef;
+#pragma unroll
+    for (int b = 0; b < W; ++b) ci[b] = c[(b * W + R) * W + R] * cscale;
+  }
+  // padding the MFMAs read with zero weights (columns past the window, rows
+  // past it): keep it finite
+  zero_region<uint16_t, kThreads>(lhi, S::WROWS, S::P - S::WCOLS, S::P, 0, S::WCOLS);
+  zero_region<uint16_t, kThreads>(llo, S::WROWS, S::P - S::WCOLS, S::P, 0, S::WCOLS);
+  zero_region<uint16_t, kThreads>(lhi, S::PR - S::WROWS, S::P, S::P, S::WROWS, 0);
+  zero_region<uint16_t, kThreads>(llo, S::PR - S::WROWS, S::P, S::P, S::WROWS, 0);
+  const float lo_mul = 1.0f / a.lo_scale;
+  const float ls = a.lo_scale, os = a.out_scale;
+
+  floatx4 acc[W][2], acx[2];
+#pragma unroll
+  for (int z = 0; z < W; ++z)
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc[z][t] = floatx4{0, 0, 0, 0};
+  // ring slot z holds output plane i - r + z while input plane i is
+  // scattered; slot 0 is stored after the plane and the ring shifts down
+  PW::walk(
+      bufs, a, ch,
+      [&](const float* win, bool valid) {
+        if (!valid) return;
+        // split the FP32 window into hi/lo planes, two columns per thread and step
+        constexpr int HALF = S::WCOLS / 2;
+        for (int idx = threadIdx.x; idx < S::WROWS * HALF; idx += kThreads) {
+          const int row = idx / HALF, y = 2 * (idx - (idx / HALF) * HALF);
+          const float* src = win + row * PW::PITCH + PW::COL0 + y;
+          uint16_t h0, l0, h1, l1;
+          Split16<KIND>::split(src[0], lo_mul, h0, l0);
+          Split16<KIND>::split(src[1], lo_mul, h1, l1);
+          *reinterpret_cast<uint32_t*>(lhi + row * S::P + y) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+          *reinterpret_cast<uint32_t*>(llo + row * S::P + y) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+        }
+        lds_barrier();
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acx[t] = floatx4{0, 0, 0, 0};
+        // k line: rows r + 16 wj + q, columns 32 wk + 16 t + 8 g ..
+        const uint16_t* pkh = lhi + (R + 16 * wj + q) * S::P + 32 * wk + 8 * g;
+        const uint16_t* pkl = llo + (R + 16 * wj + q) * S::P + 32 * wk + 8 * g;
+        // j line: rows 16 wj + 8 g + e, column r + 32 wk + 16 t + q
+        const uint16_t* pjh = lhi + (16 * wj + 8 * g) * S::P + R + 32 * wk + q;
+        const uint16_t* pjl = llo + (16 * wj + 8 * g) * S::P + R + 32 * wk + q;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const u16x8 ah = *reinterpret_cast<const u16x8*>(pkh + 16 * t);
+          const u16x8 al = *reinterpret_cast<const u16x8*>(pkl + 16 * t);
+          acc[R][t] = Split16<KIND>::mma(ah, kh, acc[R][t]);
+          acx[t] = Split16<KIND>::mma(ah, kl, acx[t]);
+          acx[t] = Split16<KIND>::mma(al, kh, acx[t]);
+          u16x8 bh, bl;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            bh[e] = pjh[e * S::P + 16 * t];
+            bl[e] = pjl[e * S::P + 16 * t];
+          }
+          acc[R][t] = Split16<KIND>::mma(jh, bh, acc[R][t]);
+          acx[t] = Split16<KIND>::mma(jl, bh, acx[t]);
+          acx[t] = Split16<KIND>::mma(jh, bl, acx[t]);
+        }
+        // i arm: this plane's centre values reach output plane i - ap + r
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float* cp = win + (16 * wj + 4 * g + v + R) * PW::PITCH + PW::COL0 + R + 32 * wk + q;
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const float ctr = cp[16 * t];
+#pragma unroll
+            for (int ap = 0; ap < W; ++ap) {
+              if (ap == R) continue;
+              acc[2 * R - ap][t][v] += ci[ap] * ctr;
+            }
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[R][t] += ls * acx[t];
+      },
+      [&](int64_t o, bool live) {
+        if (live) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t gj = ch.j0 + 16 * wj + 4 * g + v;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              const int64_t gk = ch.k0 + 32 * wk + 16 * t + q;
+              if (gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = acc[0][t][v] * os;
+            }
+          }
+        }
+#pragma unroll
+        for (int z = 0; z < 2 * R; ++z)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) acc[z][t] = acc[z + 1][t];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[2 * R][t] = floatx4{0, 0, 0, 0};
+      });
+}
+
+template <int KIND, int R, bool DMA>
+__global__ __launch_bounds__(kThreads) void split3d_hybrid_kernel(KArgs a) {
+  split3d_hybrid_item<KIND, R, DMA>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <int KIND, int R, bool DMA>
+__global__ __launch_bounds__(kThreads) void split3d_hybrid_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { split3d_hybrid_item<KIND, R, DMA>(x, id); });
 }
 
 template <int KIND, int R, bool BOX, bool DMA>

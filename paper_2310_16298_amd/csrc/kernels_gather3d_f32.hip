@@ -6,10 +6,9 @@
 namespace stencil {
 
 template <int R, bool BOX>
-static Kernel pick_gather3d(KArgs& a, int32_t) {
-  const int64_t items = chunk3d_items(a);
-  if (dma3d_ok<float>(a)) return kernel_of<gather3d_kernel<float, R, BOX, true>, gather3d_batch<float, R, BOX, true>>(items);
-  return kernel_of<gather3d_kernel<float, R, BOX, false>, gather3d_batch<float, R, BOX, false>>(items);
+static Kernel pick_gather3d(KArgs& a, int32_t chunk) {
+  if (dma3d_ok<float>(a)) return kernel3d<gather3d_kernel<float, R, BOX, true>, gather3d_batch<float, R, BOX, true>>(a, R, chunk);
+  return kernel3d<gather3d_kernel<float, R, BOX, false>, gather3d_batch<float, R, BOX, false>>(a, R, chunk);
 }
 
 template <bool BOX>

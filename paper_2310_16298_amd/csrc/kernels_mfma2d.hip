@@ -50,7 +50,10 @@ static Picker pick_b4r(int R) {
   return nullptr;
 }
 
-Picker find_mfma2d_b4(int R, bool box) { return box ? pick_b4r<true>(R) : pick_b4r<false>(R); }
+Picker find_mfma2d_b4(int R, bool box, int ui, int wr) {
+  if (box && (ui != 4 || wr != 1)) return find_mfma2d_b4_tiles(R, ui, wr);
+  return box ? pick_b4r<true>(R) : pick_b4r<false>(R);
+}
 
 // Line cover on n = 4 blocks; grids the direct-to-LDS kernels cannot take use
 // the 16x16 cover kernel, whose fragments follow the n = 4 ones in the buffer.

@@ -7,10 +7,9 @@
 namespace stencil {
 
 template <typename T, int R, bool BOX>
-static Kernel pick_mfma3d(KArgs& a, int32_t) {
-  const int64_t items = chunk3d_items(a);
-  if (dma3d_ok<T>(a)) return kernel_of<mfma3d_kernel<T, R, BOX, true>, mfma3d_batch<T, R, BOX, true>>(items);
-  return kernel_of<mfma3d_kernel<T, R, BOX, false>, mfma3d_batch<T, R, BOX, false>>(items);
+static Kernel pick_mfma3d(KArgs& a, int32_t chunk) {
+  if (dma3d_ok<T>(a)) return kernel3d<mfma3d_kernel<T, R, BOX, true>, mfma3d_batch<T, R, BOX, true>>(a, R, chunk);
+  return kernel3d<mfma3d_kernel<T, R, BOX, false>, mfma3d_batch<T, R, BOX, false>>(a, R, chunk);
 }
 
 template <typename T>
@@ -33,17 +32,15 @@ static Picker pick(int R, bool box) {
 
 // n = 4 blocks (FP32): stars r = 1..4 and the 27-point box
 template <int R, bool BOX>
-static Kernel pick_mfma3d_b4(KArgs& a, int32_t) {
-  const int64_t items = chunk3d_items(a);
-  if (dma3d_ok<float>(a)) return kernel_of<mfma3d_b4_kernel<R, BOX, true>, mfma3d_b4_batch<R, BOX, true>>(items);
-  return kernel_of<mfma3d_b4_kernel<R, BOX, false>, mfma3d_b4_batch<R, BOX, false>>(items);
+static Kernel pick_mfma3d_b4(KArgs& a, int32_t chunk) {
+  if (dma3d_ok<float>(a)) return kernel3d<mfma3d_b4_kernel<R, BOX, true>, mfma3d_b4_batch<R, BOX, true>>(a, R, chunk);
+  return kernel3d<mfma3d_b4_kernel<R, BOX, false>, mfma3d_b4_batch<R, BOX, false>>(a, R, chunk);
 }
 
 template <int R>
-static Kernel pick_mfma3d_b4box(KArgs& a, int32_t) {
-  const int64_t items = chunk3d_items(a);
-  if (dma3d_ok<float>(a)) return kernel_of<mfma3d_b4box_kernel<R, true>, mfma3d_b4box_batch<R, true>>(items);
-  return kernel_of<mfma3d_b4box_kernel<R, false>, mfma3d_b4box_batch<R, false>>(items);
+static Kernel pick_mfma3d_b4box(KArgs& a, int32_t chunk) {
+  if (dma3d_ok<float>(a)) return kernel3d<mfma3d_b4box_kernel<R, true>, mfma3d_b4box_batch<R, true>>(a, R, chunk);
+  return kernel3d<mfma3d_b4box_kernel<R, false>, mfma3d_b4box_batch<R, false>>(a, R, chunk);
 }
 
 Picker find_mfma3d_b4(int R, bool box) {

@@ -1,4 +1,5 @@
-// Instantiations of the 3D split-precision kernels.  Box: r = 1 (27 points).
+// Instantiations of the 3D split-precision kernels.  Box: r = 1 (27 points);
+// stars: parallel (k lines on MFMA) and hybrid (j and k lines) covers.
 #include "kernels_3d.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
@@ -6,15 +7,31 @@
 namespace stencil {
 
 template <int KIND, int R, bool BOX>
-static Kernel pick_split3d(KArgs& a, int32_t) {
-  const int64_t items = chunk3d_items(a);
-  if (dma3d_ok<float>(a)) return kernel_of<split3d_kernel<KIND, R, BOX, true>, split3d_batch<KIND, R, BOX, true>>(items);
-  return kernel_of<split3d_kernel<KIND, R, BOX, false>, split3d_batch<KIND, R, BOX, false>>(items);
+static Kernel pick_split3d(KArgs& a, int32_t chunk) {
+  if (dma3d_ok<float>(a)) return kernel3d<split3d_kernel<KIND, R, BOX, true>, split3d_batch<KIND, R, BOX, true>>(a, R, chunk);
+  return kernel3d<split3d_kernel<KIND, R, BOX, false>, split3d_batch<KIND, R, BOX, false>>(a, R, chunk);
+}
+
+// Stars in the hybrid cover: the lines along j and k on MFMA, the i arm on VALU
+template <int KIND, int R>
+static Kernel pick_split3d_hybrid(KArgs& a, int32_t chunk) {
+  if (dma3d_ok<float>(a))
+    return kernel3d<split3d_hybrid_kernel<KIND, R, true>, split3d_hybrid_batch<KIND, R, true>>(a, R, chunk);
+  return kernel3d<split3d_hybrid_kernel<KIND, R, false>, split3d_hybrid_batch<KIND, R, false>>(a, R, chunk);
 }
 
 template <int KIND>
-static Picker pick(int R, bool box) {
+static Picker pick(int R, bool box, bool hybrid) {
   if (box) return R == 1 ? pick_split3d<KIND, 1, true> : nullptr;
+  if (hybrid) {
+    switch (R) {
+      case 1: return pick_split3d_hybrid<KIND, 1>;
+      case 2: return pick_split3d_hybrid<KIND, 2>;
+      case 3: return pick_split3d_hybrid<KIND, 3>;
+      case 4: return pick_split3d_hybrid<KIND, 4>;
+    }
+    return nullptr;
+  }
   switch (R) {
     case 1: return pick_split3d<KIND, 1, false>;
     case 2: return pick_split3d<KIND, 2, false>;
@@ -24,6 +41,8 @@ static Picker pick(int R, bool box) {
   return nullptr;
 }
 
-Picker find_split3d(int kind, int R, bool box) { return kind == 1 ? pick<1>(R, box) : pick<0>(R, box); }
+Picker find_split3d(int kind, int R, bool box, bool hybrid) {
+  return kind == 1 ? pick<1>(R, box, hybrid) : pick<0>(R, box, hybrid);
+}
 
 }  // namespace stencil

@@ -21,12 +21,22 @@ typedef hipError_t (*BatchLaunch)(const BatchArgs& b, unsigned blocks, hipStream
 struct Kernel {
   SingleLaunch launch = nullptr;       // one grid: one workgroup per item
   BatchLaunch launch_batch = nullptr;  // persistent loop over a table of grids
+  const void* single_id = nullptr;     // the single-grid __global__ function: occupancy queries
   const void* batch_id = nullptr;      // the batched __global__ function: grouping and occupancy queries
   int64_t items = 0;                   // work items (workgroup tiles) of the grid
 };
 
 // chunk: requested rows (2D) / planes (3D) per work item, 0 = library choice.
 typedef Kernel (*Picker)(KArgs& a, int32_t chunk);
+
+// Workgroups of 256 threads of `kernel` resident on one CU of the current
+// device at once, and the device's CU count; 0 if the runtime cannot tell.
+// Cached per device and kernel (occupancy.cpp).
+struct Residency {
+  int per_cu = 0;
+  int cus = 0;
+};
+Residency resident_workgroups(const void* kernel);
 
 template <auto K>
 hipError_t launch_single(const KArgs& a, unsigned blocks, hipStream_t s) {
@@ -47,6 +57,7 @@ inline Kernel kernel_of(int64_t items) {
   Kernel k;
   k.launch = launch_single<KS>;
   k.launch_batch = launch_batched<KB>;
+  k.single_id = reinterpret_cast<const void*>(KS);
   k.batch_id = reinterpret_cast<const void*>(KB);
   k.items = items;
   return k;

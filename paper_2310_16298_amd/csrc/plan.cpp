@@ -164,6 +164,8 @@ static int validate(const stencil_desc_t* d) {
   if (d->lines < STENCIL_LINES_AUTO || d->lines > STENCIL_LINES_HYBRID) return STENCIL_EINVAL;
   if (d->block_n != 0 && d->block_n != 4 && d->block_n != 16) return STENCIL_EINVAL;
   if (d->chunk < 0 || d->time_block < 0) return STENCIL_EINVAL;
+  if (d->reg_rows != 0 && d->reg_rows != 8 && d->reg_rows != 16 && d->reg_rows != 32) return STENCIL_EINVAL;
+  if (d->tile_width != 0 && d->tile_width != 128 && d->tile_width != 256) return STENCIL_EINVAL;
   if (d->time_block > 1) {
     if (d->ndim != 2 || (d->path != STENCIL_PATH_AUTO && d->path != STENCIL_PATH_GATHER)) return STENCIL_EUNSUPPORTED;
     if (d->time_block > tb2d_max_steps(d->dtype, d->radius)) return STENCIL_EUNSUPPORTED;
@@ -454,6 +456,10 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     lines = STENCIL_LINES_PARALLEL;
   } else if (lines == STENCIL_LINES_AUTO) {
     if (nd == 2) lines = R == 1 ? STENCIL_LINES_PARALLEL : STENCIL_LINES_ORTHOGONAL;
+    // 3D: the hybrid cover on FP32/FP64 MFMA; the split paths keep the line
+    // along k alone on MFMA (measured on MI355X at 384^3 and 512^3: the hybrid
+    // split kernel ties it at r = 4 and trails it by 6 % at r = 1, its extra
+    // hi/lo products costing more than the vector FMAs they replace)
     else lines = split ? STENCIL_LINES_PARALLEL : STENCIL_LINES_HYBRID;
   }
 
@@ -536,7 +542,16 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       const bool b4_ok = d.dtype == STENCIL_F32 && (rs->variant == VAR_BOX || rs->variant == VAR_STAR_PARALLEL);
       if (d.block_n == 4 && !b4_ok && !cover) return STENCIL_EUNSUPPORTED;
       const bool b4 = b4_ok && d.block_n != 16;
-      rs->pick = b4 ? find_mfma2d_b4(R, box) : find_mfma2d(d.dtype, R, rs->variant);  // cover: set below
+      // register / workgroup tile of the n = 4 box kernel (library choice: 16 rows, 256 columns)
+      const bool tiles_set = (d.reg_rows != 0 && d.reg_rows != 16) || (d.tile_width != 0 && d.tile_width != 256);
+      if (tiles_set && !(b4 && rs->variant == VAR_BOX)) return STENCIL_EUNSUPPORTED;
+      const int ui = d.reg_rows ? d.reg_rows / 4 : 4, wr = d.tile_width == 128 ? 2 : 1;
+      if (b4 && rs->variant == VAR_BOX) {
+        in.reg_rows = 4 * ui;
+        in.tile_width = 256 / wr;
+      }
+      rs->pick = b4 ? find_mfma2d_b4(R, box, rs->variant == VAR_BOX ? ui : 4, rs->variant == VAR_BOX ? wr : 1)
+                    : find_mfma2d(d.dtype, R, rs->variant);  // cover: set below
       std::vector<Line> col, row;
       const int fixed_r[3] = {R, R, 0};
       if (rs->variant == VAR_COVER) {
@@ -642,6 +657,7 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     if (box && R >= 2) chunk = std::max(chunk, std::min<int64_t>(64, d.dims[0] * tiles / 1024));
     if (chunk < 4 * R) chunk = 4 * R;
     if (d.chunk > 0) chunk = d.chunk;
+    rs->chunk_req = d.chunk;  // 0: the kernel's picker may re-cut to one wave of resident workgroups
     if (chunk > d.dims[0]) chunk = d.dims[0];
     const int64_t nch = ceil_div(d.dims[0], chunk);
     if (tiles * nch > (int64_t(1) << 31) - 1 || tiles > (int64_t(1) << 30)) return STENCIL_EUNSUPPORTED;
@@ -722,9 +738,10 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       }
       in.executed_flops_per_point = 2.0 * in.k_rows + 2.0 * in.valu_lines;
     } else {
-      if (!box && lines != STENCIL_LINES_PARALLEL) return STENCIL_EUNSUPPORTED;
+      if (!box && lines != STENCIL_LINES_PARALLEL && lines != STENCIL_LINES_HYBRID) return STENCIL_EUNSUPPORTED;
+      const bool hybrid = !box && lines == STENCIL_LINES_HYBRID;
       rs->family = box ? FAM_SPLIT3D_BOX : FAM_SPLIT3D_STAR;
-      rs->pick = find_split3d(rs->split16, R, box);
+      rs->pick = find_split3d(rs->split16, R, box, hybrid);
       std::vector<Line> row;
       if (box) {
         for (int ap = 0; ap < W; ++ap)
@@ -735,6 +752,14 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
         in.mfma_lines = W * W;
         in.valu_lines = 0;
         in.rank1_per_block = (int64_t)W * W * (2 * R + n);
+      } else if (hybrid) {
+        const int fk[3] = {R, R, 0};
+        row.push_back(line_of(cg, 3, R, 2, fk, false));  // CLS(r, r, *), centre included (B operand)
+        const int fj[3] = {R, 0, R};
+        row.push_back(line_of(cg, 3, R, 1, fj, true));   // CLS(r, *, r), centre excluded (A operand)
+        in.mfma_lines = 2;
+        in.valu_lines = 2 * R;
+        in.rank1_per_block = 2 * (2 * R + n) + (int64_t)2 * R * n;  // Table 2, hybrid
       } else {
         const int fk[3] = {R, R, 0};
         row.push_back(line_of(cg, 3, R, 2, fk, false));  // CLS(r, r, *), centre included
@@ -752,6 +777,8 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   }
   in.path = path;
   in.lines = lines;
+  if (((d.reg_rows != 0 && d.reg_rows != 16) || (d.tile_width != 0 && d.tile_width != 256)) && in.reg_rows == 0)
+    return STENCIL_EUNSUPPORTED;  // the tile knobs belong to the n = 4 2D box kernel
   if (pack) in.operand_bytes = 256 + (int64_t)round_up((int)rs->coef.size(), 256) + (int64_t)round_up((int)rs->frag.size(), 256);
   if (!rs->pick) return STENCIL_EUNSUPPORTED;
   if (d.block_n != 0 && path != STENCIL_PATH_GATHER && d.block_n != in.block_n) return STENCIL_EUNSUPPORTED;

@@ -65,7 +65,8 @@ Picker find_sparse2d(int dtype, int R);
 constexpr int kSparse3DTapMax = 128, kSparse3DCodeIndex = 16, kSparse3DWeightOffset = 1024;
 Picker find_sparse3d(int dtype, int R);
 Picker find_mfma2d(int dtype, int R, int variant);
-Picker find_mfma2d_b4(int R, bool box);
+Picker find_mfma2d_b4(int R, bool box, int ui = 4, int wr = 1);  // ui 4-row blocks per wave, wr rows of waves
+Picker find_mfma2d_b4_tiles(int R, int ui, int wr);  // the box kernel's other register / workgroup tiles
 Picker find_mfma2d_b4c(int R);  // line cover, n = 4 (FP32)
 // Bytes of the n = 4 cover fragments that precede the 16x16 ones.
 inline size_t cover_b4_frag_bytes(int R) { return (size_t)(2 * R + 1) * (4 + 2 * R) * 64 * sizeof(float); }
@@ -73,7 +74,7 @@ Picker find_split2d(int kind, int R, int variant);
 Picker find_gather3d(int dtype, int R, bool box);
 Picker find_mfma3d(int dtype, int R, bool box);
 Picker find_mfma3d_b4(int R, bool box);  // FP32 n = 4 blocks: stars, 27-point box
-Picker find_split3d(int kind, int R, bool box);
+Picker find_split3d(int kind, int R, bool box, bool hybrid);  // hybrid: stars, lines along j and k on MFMA
 Picker find_tb2d(int dtype, int R, bool box);
 int tb2d_max_steps(int dtype, int R);  // largest time_block of the time-blocked kernel
 

@@ -1,6 +1,7 @@
 // Autotuner (declared in stencil.h): measures candidate plans of one
 // descriptor and returns the fastest choice of path, line cover, MFMA block
-// edge and work-item chunk, with an optional text cache of results.
+// edge, register and workgroup tile, time block and work-item chunk, with an
+// optional text cache of results.
 #include <cerrno>
 #include <cstdio>
 #include <cstring>
@@ -15,7 +16,7 @@ using namespace stencil;
 namespace {
 
 struct Candidate {
-  int32_t path, lines, block_n, chunk, time_block;
+  int32_t path, lines, block_n, chunk, time_block, reg_rows, tile_width;
 };
 
 std::string cache_key(const stencil_desc_t& d) {
@@ -30,8 +31,8 @@ std::string cache_key(const stencil_desc_t& d) {
 // different tuning problem.
 std::string request_key(const stencil_desc_t& d, int32_t flags) {
   char buf[128];
-  std::snprintf(buf, sizeof(buf), " req=%d,%d,%d,%d,%d,%d", d.path, d.lines, d.block_n, d.chunk, d.time_block,
-                flags & STENCIL_TUNE_ALLOW_SPLIT);
+  std::snprintf(buf, sizeof(buf), " req=%d,%d,%d,%d,%d,%d,%d,%d", d.path, d.lines, d.block_n, d.chunk, d.time_block,
+                d.reg_rows, d.tile_width, flags & STENCIL_TUNE_ALLOW_SPLIT);
   return buf;
 }
 
@@ -45,8 +46,8 @@ bool cache_lookup(const char* path, const std::string& key, Candidate* c, double
     if (!sep || std::strncmp(line, key.c_str(), key.size()) != 0 || (size_t)(sep - line) != key.size()) continue;
     Candidate t;
     double m = 0.0;
-    if (std::sscanf(sep + 4, "path=%d lines=%d block_n=%d chunk=%d time_block=%d ms=%lf", &t.path, &t.lines,
-                    &t.block_n, &t.chunk, &t.time_block, &m) == 6) {
+    if (std::sscanf(sep + 4, "path=%d lines=%d block_n=%d chunk=%d time_block=%d reg_rows=%d tile_width=%d ms=%lf",
+                    &t.path, &t.lines, &t.block_n, &t.chunk, &t.time_block, &t.reg_rows, &t.tile_width, &m) == 8) {
       *c = t;  // the last entry for a key wins
       *ms = m;
       found = true;
@@ -59,8 +60,8 @@ bool cache_lookup(const char* path, const std::string& key, Candidate* c, double
 void cache_store(const char* path, const std::string& key, const Candidate& c, double ms) {
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s -> path=%d lines=%d block_n=%d chunk=%d time_block=%d ms=%.6f\n", key.c_str(), c.path,
-               c.lines, c.block_n, c.chunk, c.time_block, ms);
+  std::fprintf(f, "%s -> path=%d lines=%d block_n=%d chunk=%d time_block=%d reg_rows=%d tile_width=%d ms=%.6f\n",
+               key.c_str(), c.path, c.lines, c.block_n, c.chunk, c.time_block, c.reg_rows, c.tile_width, ms);
   std::fclose(f);
 }
 
@@ -71,6 +72,8 @@ stencil_desc_t with(const stencil_desc_t& d, const Candidate& c) {
   x.block_n = c.block_n;
   x.chunk = c.chunk;
   x.time_block = c.time_block;
+  x.reg_rows = c.reg_rows;
+  x.tile_width = c.tile_width;
   return x;
 }
 
@@ -155,7 +158,7 @@ stencil_status_t stencil_autotune(const stencil_desc_t* desc, const char* cache_
       if (d.block_n == 0 && p == STENCIL_PATH_MFMA) blocks = {4, 16};
       for (int32_t l : lines)
         for (int32_t b : blocks) {
-          const Candidate c{p, l, b, d.chunk, d.time_block};
+          const Candidate c{p, l, b, d.chunk, d.time_block, d.reg_rows, d.tile_width};
           if (valid(d, c)) first.push_back(c);
         }
     }
@@ -189,6 +192,8 @@ stencil_status_t stencil_autotune(const stencil_desc_t* desc, const char* cache_
         r.block_n = c.block_n;
         r.chunk = c.chunk;
         r.time_block = c.time_block;
+        r.reg_rows = c.reg_rows;
+        r.tile_width = c.tile_width;
         r.ms_per_step = ms;
         r.status = cst;
       }
@@ -209,17 +214,35 @@ stencil_status_t stencil_autotune(const stencil_desc_t* desc, const char* cache_
       if (st != STENCIL_OK) break;
       consider(c);
     }
-    // 2) time blocking (2D gather form) when the request leaves it open
+    // 2) register x workgroup tile of the n = 4 2D box outer products, when
+    //    the winner is that kernel and the request leaves both open
+    if (st == STENCIL_OK && win_ms >= 0.0 && d.reg_rows == 0 && d.tile_width == 0) {
+      Resolved wr;
+      stencil_desc_t wx = with(d, win);
+      if (resolve_plan(&wx, &wr, false) == STENCIL_OK && wr.info.reg_rows != 0) {
+        const Candidate head = win;
+        for (int32_t rows : {8, 16, 32})
+          for (int32_t width : {256, 128}) {
+            if (rows == 16 && width == 256) continue;  // the library's choice, measured above
+            Candidate c = head;
+            c.reg_rows = rows;
+            c.tile_width = width;
+            if (valid(d, c)) consider(c);
+            if (st != STENCIL_OK) break;
+          }
+      }
+    }
+    // 3) time blocking (2D gather form) when the request leaves it open
     if (st == STENCIL_OK && d.ndim == 2 && d.time_block == 0 &&
         (d.path == STENCIL_PATH_AUTO || d.path == STENCIL_PATH_GATHER)) {
       for (int32_t t = 2; t <= 12; ++t) {
-        const Candidate c{STENCIL_PATH_GATHER, STENCIL_LINES_AUTO, 0, 0, t};
+        const Candidate c{STENCIL_PATH_GATHER, STENCIL_LINES_AUTO, 0, 0, t, 0, 0};
         if (!valid(d, c)) continue;
         consider(c);
         if (st != STENCIL_OK) break;
       }
     }
-    // 3) chunk length for the winner (coordinate search; not used by time blocks)
+    // 4) chunk length for the winner (coordinate search; not used by time blocks)
     if (st == STENCIL_OK && win_ms >= 0.0 && d.chunk == 0 && win.time_block <= 1) {
       const int32_t opts2[] = {16, 32, 64, 128, 256, 512, 1024};
       const int32_t opts3[] = {8, 16, 32, 64, 128};

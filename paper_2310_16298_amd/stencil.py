@@ -43,6 +43,7 @@ class Desc(ctypes.Structure):
         ("shape", ctypes.c_int32), ("boundary", ctypes.c_int32), ("dtype", ctypes.c_int32),
         ("path", ctypes.c_int32), ("lines", ctypes.c_int32), ("block_n", ctypes.c_int32),
         ("chunk", ctypes.c_int32), ("time_block", ctypes.c_int32),
+        ("reg_rows", ctypes.c_int32), ("tile_width", ctypes.c_int32),
         ("coeffs", ctypes.POINTER(ctypes.c_double)),
     ]
 
@@ -58,6 +59,7 @@ class PlanInfo(ctypes.Structure):
         ("useful_flops_per_point", ctypes.c_double), ("executed_flops_per_point", ctypes.c_double),
         ("bytes_per_point", ctypes.c_int32), ("time_block", ctypes.c_int32),
         ("pad0", ctypes.c_int32), ("operand_bytes", ctypes.c_int64),
+        ("reg_rows", ctypes.c_int32), ("tile_width", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -90,7 +92,8 @@ TUNE_ALLOW_SPLIT, TUNE_FORCE = 1, 2
 class TuneResult(ctypes.Structure):
     _fields_ = [
         ("path", ctypes.c_int32), ("lines", ctypes.c_int32), ("block_n", ctypes.c_int32), ("chunk", ctypes.c_int32),
-        ("time_block", ctypes.c_int32), ("status", ctypes.c_int32), ("ms_per_step", ctypes.c_double),
+        ("time_block", ctypes.c_int32), ("reg_rows", ctypes.c_int32), ("tile_width", ctypes.c_int32),
+        ("status", ctypes.c_int32), ("ms_per_step", ctypes.c_double),
     ]
 
 _lib = None
@@ -156,7 +159,7 @@ def _check(status: int, where: str):
 
 def make_desc(dims: Sequence[int], radius: int, shape: int, coeffs, boundary: int = BC_ZERO,
               dtype: int = F32, path: int = PATH_AUTO, lines: int = LINES_AUTO, block_n: int = 0,
-              chunk: int = 0, time_block: int = 0):
+              chunk: int = 0, time_block: int = 0, reg_rows: int = 0, tile_width: int = 0):
     """Build a Desc; returns (desc, keepalive) -- keep the array alive while used."""
     c = np.ascontiguousarray(coeffs, dtype=np.float64)
     d = Desc()
@@ -166,6 +169,7 @@ def make_desc(dims: Sequence[int], radius: int, shape: int, coeffs, boundary: in
         d.dims[k] = int(dims[k]) if k < len(dims) else 1
     d.shape, d.boundary, d.dtype, d.path, d.lines = int(shape), int(boundary), int(dtype), int(path), int(lines)
     d.block_n, d.chunk, d.time_block = int(block_n), int(chunk), int(time_block)
+    d.reg_rows, d.tile_width = int(reg_rows), int(tile_width)
     d.coeffs = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return d, c
 
@@ -226,18 +230,19 @@ class Plan:
     """A stencil plan on the current device.
 
     ``Plan(dims, radius, shape, coeffs, boundary, dtype, path, lines, block_n,
-    chunk, time_block)``; grids
+    chunk, time_block, reg_rows, tile_width)``; grids
     are torch tensors on the plan's device, contiguous, of the plan's dims and
     dtype (float32 / float64).
     """
 
     def __init__(self, dims, radius, shape, coeffs, boundary=BC_ZERO, dtype=F32,
-                 path=PATH_AUTO, lines=LINES_AUTO, block_n=0, chunk=0, time_block=0):
+                 path=PATH_AUTO, lines=LINES_AUTO, block_n=0, chunk=0, time_block=0, reg_rows=0, tile_width=0):
         lib = load_library()
         self.dims = tuple(int(v) for v in dims)
         self.dtype = dtype
         d, keep = make_desc(self.dims, radius, shape, coeffs, boundary=boundary, dtype=dtype,
-                            path=path, lines=lines, block_n=block_n, chunk=chunk, time_block=time_block)
+                            path=path, lines=lines, block_n=block_n, chunk=chunk, time_block=time_block,
+                            reg_rows=reg_rows, tile_width=tile_width)
         h = ctypes.c_void_p()
         _check(lib.stencil_plan(ctypes.byref(d), ctypes.byref(h)), "stencil_plan")
         self._h = h
@@ -338,9 +343,10 @@ def autotune(dims, radius, shape, coeffs, boundary=BC_ZERO, dtype=F32, path=PATH
                                 capacity, ctypes.byref(cnt)),
            "stencil_autotune")
     knobs = {"path": best.path, "lines": best.lines, "block_n": best.block_n, "chunk": best.chunk,
-             "time_block": best.time_block}
+             "time_block": best.time_block, "reg_rows": best.reg_rows, "tile_width": best.tile_width}
     rows = [{"path": r.path, "lines": r.lines, "block_n": r.block_n, "chunk": r.chunk, "time_block": r.time_block,
-             "ms_per_step": r.ms_per_step, "status": r.status} for r in res[:min(cnt.value, capacity)]]
+             "reg_rows": r.reg_rows, "tile_width": r.tile_width, "ms_per_step": r.ms_per_step, "status": r.status}
+            for r in res[:min(cnt.value, capacity)]]
     return knobs, ms.value, rows
 
 

@@ -28,7 +28,8 @@ def test_autotune_picks_fastest_and_caches(tmp_path, dims, r, shape, dtype):
     assert all(row["status"] == st.OK and row["ms_per_step"] > 0 for row in rows)
     fastest = min(rows, key=lambda row: row["ms_per_step"])
     assert ms == fastest["ms_per_step"]
-    assert knobs == {k: fastest[k] for k in ("path", "lines", "block_n", "chunk", "time_block")}
+    assert knobs == {k: fastest[k] for k in ("path", "lines", "block_n", "chunk", "time_block", "reg_rows",
+                                             "tile_width")}
     assert knobs["path"] in (st.PATH_GATHER, st.PATH_MFMA)  # no split paths unless allowed
     again, ms2, rows2 = st.autotune(dims, r, shape, c, boundary=st.BC_ZERO, dtype=dtype, cache=cache)
     assert again == knobs and rows2 == [] and abs(ms2 - ms) < 1e-6
@@ -69,3 +70,14 @@ def test_chunk_knob_keeps_results(chunk):
             x = torch.from_numpy(a0).cuda()
             outs.append(plan.run_steps(x, torch.empty_like(x), 3).cpu().numpy())
         assert np.array_equal(outs[0], outs[1])
+
+
+def test_autotune_tries_register_and_workgroup_tiles():
+    """A 2D FP32 box whose winner is the n = 4 outer products: the tuner then
+    measures the other register (rows per wave) x workgroup (columns) tiles."""
+    torch_cuda()
+    c = inputs.coefficients(2, 4, st.BOX, seed=9400, dtype=np.float64)
+    knobs, ms, rows = st.autotune((512, 1024), 4, st.BOX, c, path=st.PATH_MFMA, block_n=4, force=True)
+    tiles = {(row["reg_rows"], row["tile_width"]) for row in rows}
+    assert {(8, 256), (32, 256), (8, 128), (16, 128), (32, 128)} <= tiles
+    assert all(row["status"] == st.OK for row in rows)

@@ -217,3 +217,39 @@ def test_graph_replays_match_eager(path):
         junk.mul_(2.0)
         torch.cuda.synchronize()
     plan.close()
+
+
+# Register tiles (rows per wave: 8, 16, 32) and workgroup tiles (256 / 128
+# columns) of the FP32 box outer products on n = 4 blocks: every variant
+# against the oracle, bit for bit against the default tile (same arithmetic
+# per point), bit-exact on integers, ragged row extents and both boundaries.
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("rows,width", [(8, 256), (32, 256), (8, 128), (16, 128), (32, 128)])
+def test_box_tile_variants(r, rows, width):
+    torch = torch_cuda()
+    c = inputs.coefficients(2, r, st.BOX, seed=1200 + r, dtype=np.float64)
+    ce = eff_coeffs(c, st.F32)
+    for dims in [(150, 260), (67, 516), (256, 128)]:
+        a0 = inputs.grid(dims, seed=1210 + r)
+        for bc in (st.BC_ZERO, st.BC_PERIODIC):
+            x = torch.from_numpy(a0).cuda()
+            ref = st.Plan(dims, r, st.BOX, c, boundary=bc, dtype=st.F32, path=st.PATH_MFMA)
+            var = st.Plan(dims, r, st.BOX, c, boundary=bc, dtype=st.F32, path=st.PATH_MFMA, reg_rows=rows,
+                          tile_width=width)
+            assert (var.info["reg_rows"], var.info["tile_width"]) == (rows, width)
+            want = ref.run_steps(x.clone(), torch.empty_like(x), 3).cpu().numpy()
+            got = var.run_steps(x.clone(), torch.empty_like(x), 3).cpu().numpy()
+            assert np.array_equal(got, want), (dims, bc)
+            exact = oracle.run(a0, ce, r, st.BOX, bc, 3)
+            assert np.abs(got.astype(np.float64) - exact).max() <= error_bound(ce, 2, r, st.BOX, st.F32, st.PATH_MFMA,
+                                                                              3, 1.0)
+            ref.close()
+            var.close()
+    ai = inputs.int_grid((96, 260), seed=1220 + r)
+    ci = inputs.int_coefficients(2, r, st.BOX, seed=1230 + r)
+    x = torch.from_numpy(ai).cuda()
+    var = st.Plan(ai.shape, r, st.BOX, ci, boundary=st.BC_PERIODIC, dtype=st.F32, path=st.PATH_MFMA, reg_rows=rows,
+                  tile_width=width)
+    got = var.run_steps(x, torch.empty_like(x), 1).cpu().numpy().astype(np.float64)
+    assert np.array_equal(got, oracle.run(ai, ci, r, st.BOX, st.BC_PERIODIC, 1))
+    var.close()

@@ -300,3 +300,29 @@ def test_general_3d_nonzero_tap_max_integer_bit_exact(r, dtype):
         got = plan.run_steps(x, torch.empty_like(x), 1).cpu().numpy().astype(np.float64)
         assert np.array_equal(got, oracle.run(a0.astype(np.float64), cg, r, st.BOX, bc, 1)), bc
         plan.close()
+
+
+# Split-precision stars in both covers: PARALLEL (AUTO: the line along k on
+# MFMA, the j and i arms on vector FMAs) and HYBRID (the lines along j and k
+# on MFMA, the i arm on vector FMAs; Table 2), against the oracle with the
+# split bound, bit-exact on integers, synchronous and direct-to-LDS planes.
+@pytest.mark.parametrize("path", [BF, FH])
+@pytest.mark.parametrize("lines", [st.LINES_PARALLEL, st.LINES_HYBRID])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_split_star_line_options(path, lines, r):
+    c = inputs.coefficients(3, r, st.STAR, seed=960 + r, dtype=np.float64)
+    ce = eff_coeffs(c, st.F32)
+    info = st.describe((37, 45, 77), r, st.STAR, c, path=path, lines=lines)
+    assert info["lines"] == lines and info["mfma_lines"] == (2 if lines == st.LINES_HYBRID else 1)
+    for dims in [(37, 45, 77), (21, 45, 132), (9, 33, 64)]:
+        a0 = inputs.grid(dims, seed=970 + r)
+        for bc in (st.BC_ZERO, st.BC_PERIODIC):
+            want = oracle.run(a0, ce, r, st.STAR, bc, 2)
+            got = run_gpu(a0, c, r, st.STAR, bc, st.F32, path, 2, lines=lines)
+            tol = error_bound(ce, 3, r, st.STAR, st.F32, path, 2, np.abs(a0).max())
+            assert np.abs(got - want).max() <= tol, (dims, bc, np.abs(got - want).max(), tol)
+    ci = inputs.int_coefficients(3, r, st.STAR, seed=980 + r)
+    ai = inputs.int_grid((20, 37, 68), seed=990 + r)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        assert np.array_equal(run_gpu(ai, ci, r, st.STAR, bc, st.F32, path, 1, lines=lines),
+                              oracle.run(ai, ci, r, st.STAR, bc, 1))

@@ -341,15 +341,17 @@ def test_autotune_cache_hit_needs_no_device(lib, tmp_path):
     """A cached entry is returned without measuring (the last entry of a key
     wins; other keys and malformed lines are skipped)."""
     cache = tmp_path / "tune.txt"
-    key = "nd=2 shape=1 r=2 dtype=0 bc=1 dims=64,80,1 req=0,0,0,0,0,0"
+    key = "nd=2 shape=1 r=2 dtype=0 bc=1 dims=64,80,1 req=0,0,0,0,0,0,0,0"
     cache.write_text(
         "garbage line\n"
-        f"{key} -> path=2 lines=1 block_n=16 chunk=0 time_block=0 ms=0.250000\n"
-        "nd=2 shape=1 r=2 dtype=0 bc=1 dims=64,81,1 req=0,0,0,0,0,0 -> path=1 lines=0 block_n=0 chunk=0 "
-        "time_block=3 ms=0.1\n"
-        f"{key} -> path=2 lines=1 block_n=4 chunk=32 time_block=0 ms=0.125000\n")
+        f"{key} -> path=2 lines=1 block_n=16 chunk=0 time_block=0 reg_rows=0 tile_width=0 ms=0.250000\n"
+        "nd=2 shape=1 r=2 dtype=0 bc=1 dims=64,81,1 req=0,0,0,0,0,0,0,0 -> path=1 lines=0 block_n=0 chunk=0 "
+        "time_block=3 reg_rows=0 tile_width=0 ms=0.1\n"
+        f"{key} -> path=2 lines=1 block_n=4 chunk=32 time_block=0 ms=0.2\n"  # an older format: skipped
+        f"{key} -> path=2 lines=1 block_n=4 chunk=32 time_block=0 reg_rows=8 tile_width=128 ms=0.125000\n")
     knobs, ms, rows = st.autotune((64, 80), 2, inputs.BOX, _box(2, 2), boundary=st.BC_PERIODIC, cache=str(cache))
-    assert knobs == {"path": st.PATH_MFMA, "lines": st.LINES_PARALLEL, "block_n": 4, "chunk": 32, "time_block": 0}
+    assert knobs == {"path": st.PATH_MFMA, "lines": st.LINES_PARALLEL, "block_n": 4, "chunk": 32, "time_block": 0,
+                     "reg_rows": 8, "tile_width": 128}
     assert ms == 0.125 and rows == []
 
 
@@ -558,3 +560,29 @@ def test_operand_bytes_of_auto_plans_fit_the_noalloc_scratch(lib, nd, dtype):
                     continue  # 64000 B of FP64 16x16 fragments: the one plan beyond the scratch
                 assert 256 < info["operand_bytes"] <= st.NOALLOC_SCRATCH_BYTES, (r, shape, path, info)
                 assert info["operand_bytes"] % 256 == 0
+
+
+# ------------------------------------------------ register and workgroup tiles
+
+def test_tile_knobs(lib):
+    """reg_rows / tile_width select the register tile (rows per wave) and the
+    workgroup tile (columns) of the 2D FP32 box outer products on n = 4 blocks;
+    the plan reports them; other plans reject non-default values."""
+    c = _box(2, 3)
+    info = st.describe((256, 512), 3, inputs.BOX, c, path=st.PATH_MFMA)
+    assert (info["reg_rows"], info["tile_width"]) == (16, 256)
+    for rows in (8, 16, 32):
+        for width in (128, 256):
+            info = st.describe((256, 512), 3, inputs.BOX, c, path=st.PATH_MFMA, reg_rows=rows, tile_width=width)
+            assert (info["reg_rows"], info["tile_width"], info["block_n"]) == (rows, width, 4)
+    assert st.desc_check((256, 512), 3, inputs.BOX, c, reg_rows=12) == st.EINVAL
+    assert st.desc_check((256, 512), 3, inputs.BOX, c, tile_width=64) == st.EINVAL
+    s = inputs.coefficients(2, 3, inputs.STAR, seed=4, dtype=np.float64)
+    for kw in (dict(path=st.PATH_GATHER), dict(path=st.PATH_MFMA, block_n=16), dict(path=st.PATH_MFMA_BF16X3)):
+        assert st.desc_check((256, 512), 3, inputs.BOX, c, reg_rows=8, **kw) == st.EUNSUPPORTED, kw
+    assert st.desc_check((256, 512), 3, inputs.STAR, s, path=st.PATH_MFMA, tile_width=128) == st.EUNSUPPORTED
+    assert st.desc_check((16, 16, 16), 1, inputs.BOX, _box(3, 1), path=st.PATH_MFMA, reg_rows=32) == st.EUNSUPPORTED
+    # the library's choice spelled out is accepted everywhere
+    assert st.desc_check((256, 512), 3, inputs.BOX, c, path=st.PATH_GATHER, reg_rows=16, tile_width=256) == st.OK
+    # gather and 3D plans report no tile
+    assert st.describe((256, 512), 3, inputs.BOX, c, path=st.PATH_GATHER)["reg_rows"] == 0
