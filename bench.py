@@ -19,6 +19,7 @@ Other configurations (their own JSON line each; not the headline):
     --workload tune         autotuner sweep: line option x MFMA block x chunk per radius
     --workload serve        serving loop, Poisson arrivals at 0.5 / 0.8 load: p50/p99 latency
     --workload cover        irregular order-4 stencils: minimum line cover vs box and gather
+    --workload tiles        register x workgroup tiles of the n = 4 box outer products (Fig. 4 on MI355X)
 
 The default line also carries ``configs``: the 512^2 FP64 latency case, the
 512^3 3D stars and 27-point box (FP32 / FP64, AUTO) and the mixed-precision
@@ -614,6 +615,32 @@ MIXED_SPECS = [("box2d_r2_4096", (4096, 4096), 2, 1, 401, 4100),   # shape 1 = B
                ("star3d_r4_384", (384, 384, 384), 4, 0, 402, 4200)]  # shape 0 = STAR
 
 
+def workload_tiles(args, torch, st, inputs) -> dict:
+    """The unrolling study of Section 4.2 (Fig. 4) on MI355X: the FP32 box
+    outer products on n = 4 blocks at 8192^2 (periodic, 50 steps) for every
+    register tile (8 / 16 / 32 output rows per wave: two, four or eight 4-row
+    accumulator blocks, the i unrolling) and workgroup tile (256 columns: four
+    waves side by side; 128: two rows of two waves), r = 1..4."""
+    dims, steps = DIMS, 50
+    stream = torch.cuda.Stream()
+    a0 = torch.from_numpy(inputs.grid(dims, seed=INPUT_SEED, dtype=np.float32)).cuda()
+    out = {"metric": "GStencil/s", "workload": f"2D box r=1..4, {dims[0]}x{dims[1]} FP32, periodic, {steps} steps, "
+           "MFMA path on n = 4 blocks", "cases": {}}
+    for r in RADII:
+        c = inputs.coefficients(2, r, inputs.BOX, seed=COEF_SEED0 + r, dtype=np.float64)
+        res = {}
+        for rows in (8, 16, 32):
+            for width in (256, 128):
+                plan = st.Plan(dims, r, st.BOX, c, boundary=st.BC_PERIODIC, dtype=st.F32, path=st.PATH_MFMA,
+                               reg_rows=rows, tile_width=width)
+                times = _time_solve(torch, plan, a0, steps, args.steps, args.warmup, stream)
+                res[f"{rows}x{width}"] = round(float(dims[0] * dims[1] * steps / (np.median(times) * 1e-3) / 1e9), 1)
+                plan.close()
+        out["cases"][f"r{r}"] = res
+        print(f"[bench] tiles r={r}: {res}", file=sys.stderr, flush=True)
+    return out
+
+
 def workload_mixed(args, torch, st, inputs) -> dict:
     """BF16x3 / FP16x3 outer products with FP32 state for 200 steps, beside the
     FP32 paths; an FP64 shadow trajectory (FP64 gather path) on the GPU and
@@ -789,7 +816,8 @@ def main() -> int:
     ap.add_argument("--radii", default="1,2,3,4", help="orders to run (profiling runs use a subset)")
     ap.add_argument("--jacobi-steps", type=int, default=JACOBI_STEPS,
                     help="Jacobi steps per solve (profiling runs only; the benchmark uses 100)")
-    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch", "tune", "serve", "cover", "cover_sweep", "general3d"])
+    ap.add_argument("--workload", default="box2d", choices=["box2d", "star2d_512", "grid3d", "mixed", "batch", "tune", "serve", "cover", "cover_sweep", "general3d",
+                             "tiles"])
     ap.add_argument("--patterns", default="", help="cover workload: comma-separated pattern names (default all)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per offered load")
     ap.add_argument("--serve-warmup", type=int, default=200)
@@ -829,7 +857,7 @@ def main() -> int:
         fn = {"star2d_512": workload_star2d_512, "grid3d": workload_grid3d, "mixed": workload_mixed,
               "batch": workload_batch, "tune": workload_tune, "serve": workload_serve,
               "cover": workload_cover, "cover_sweep": workload_cover_sweep,
-              "general3d": workload_general3d}[args.workload]
+              "general3d": workload_general3d, "tiles": workload_tiles}[args.workload]
         res = fn(args, torch, st, inputs)
         res.update({"n_gpus": 1, "data": "synthetic"})
         print(json.dumps(res))
