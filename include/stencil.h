@@ -85,8 +85,8 @@ typedef enum { STENCIL_F32 = 0, STENCIL_F64 = 1 } stencil_dtype_t;
 typedef enum {
   STENCIL_PATH_AUTO = 0,        /* library picks, from measurements on MI355X: MFMA for F32 boxes of
                                    order >= 3 (2D and 3D; 3D GENERAL stencils with at most 88 / 128
-                                   nonzero taps at order 3 / 4 take GATHER), 3D stars of order 4
-                                   and 2D GENERAL
+                                   nonzero taps at order 3 / 4 take GATHER), F64 3D stars of order
+                                   4 and 2D GENERAL
                                    stencils (FP32 grids wider than 64 columns: the line cover or
                                    the nonzero-tap gather, whichever a cost fitted on MI355X
                                    prefers -- 12290 + 403 n per point for n nonzero taps (n capped

@@ -421,12 +421,15 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     // FP64 matrix rate equals the FP64 vector rate).  2D extents whose column
     // count is not a multiple of 4 (no direct-to-LDS windows): outer products.
     const bool f32 = d.dtype == STENCIL_F32;
-    if (nd == 3) {  // also the r = 4 stars: the hybrid outer products lead by 4 % (FP32) / 10 % (FP64)
+    if (nd == 3) {
+      // FP64 stars of radius 4 too: the hybrid outer products lead the gather
+      // by 10 % at 384^3 and 512^3.  FP32 stars of radius 4 stay on the gather
+      // kernel (ahead by 4 % at 512^3 and 3 % at 256^3, level at 384^3).
       // GENERAL with few nonzero taps: the nonzero-tap gather beats the box
       // outer products up to 88 (r = 3) / 128 (r = 4) taps (256^3 FP32)
       static const int kSparse3DAuto[5] = {0, 0, 0, 88, 128};
       const bool few = general && in.taps <= kSparse3DAuto[R];
-      path = (f32 && box && R >= 3 && !few) || (!box && R == 4) ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
+      path = (f32 && box && R >= 3 && !few) || (!f32 && !box && R == 4) ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
     } else {
       // grids at most 64 columns wide (the paper's smallest Table 3 shapes):
       // outer products for stars and the FP64 9-point box, measured ahead there
