@@ -52,7 +52,8 @@ COEF_SEED0 = 2100
 # Sources of the 2D kernels timed by the default workload: a counter summary
 # in profiles/traffic.json is used only while these files are unchanged.
 KERNEL_SOURCES_2D = ["device_common.hpp", "stream2d.hpp", "dma2d.hpp", "kernels_2d.hpp", "kernels_split2d.hpp",
-                     "mfma_traits.hpp", "kernels_mfma2d.hip", "kernels_split2d.hip", "kernels_gather2d.hip"]
+                     "mfma_traits.hpp", "kernels_mfma2d.hip", "kernels_split2d.hip", "kernels_gather2d.hip",
+                     "kernels_tb2d.hpp", "kernels_tb2d.hip", "kernels_tb2d_box.hip", "kernels_tb2d_star.hip"]
 
 
 def kernel_source_hash() -> str:
@@ -910,27 +911,44 @@ def main() -> int:
     # dominant kernel: the order with the largest share of the step
     r_dom = max(RADII, key=lambda r: head[r]["ms_per_solve"])
     dom = head[r_dom]
-    launch_ms = dom["ms_per_solve"] / JACOBI_STEPS
     info = dom["info"]
+    # a time-blocked plan advances up to T steps per launch: per launch it
+    # reads and writes the grid once and does the arithmetic of its steps
+    tb = max(1, int(info.get("time_block", 1)))
+    launches = -(-JACOBI_STEPS // tb)
+    launch_ms = dom["ms_per_solve"] / launches
+    steps_per_launch = JACOBI_STEPS / launches
     bytes_per_launch = info["bytes_per_point"] * DIMS[0] * DIMS[1]
     gbs = bytes_per_launch / (launch_ms * 1e-3) / 1e9
-    flops_per_launch = info["useful_flops_per_point"] * DIMS[0] * DIMS[1]
+    flops_per_launch = info["useful_flops_per_point"] * DIMS[0] * DIMS[1] * steps_per_launch
     tflops = flops_per_launch / (launch_ms * 1e-3) / 1e12
-    exec_tflops = info["executed_flops_per_point"] * DIMS[0] * DIMS[1] / (launch_ms * 1e-3) / 1e12
+    exec_tflops = info["executed_flops_per_point"] * DIMS[0] * DIMS[1] * steps_per_launch / (launch_ms * 1e-3) / 1e12
     rpath = dom["resolved_path"]
     mfma_dtype = {"mfma": "f32", "mfma_f16x3": "f16", "mfma_bf16x3": "bf16"}.get(rpath)
-    # bound: HBM unless the executed matrix work at the unit's peak would take longer than the bytes
+    # bound: HBM unless the arithmetic at its unit's peak (matrix cores for the
+    # outer products, FP32 vector ALUs for the gather) would take longer than the bytes
+    t_mem = bytes_per_launch / (HBM_PEAK_GBS * 1e9)
     bound = "hbm"
     if mfma_dtype:
-        t_mem = bytes_per_launch / (HBM_PEAK_GBS * 1e9)
-        t_mfma = info["executed_flops_per_point"] * DIMS[0] * DIMS[1] / (PEAK_TFLOPS[mfma_dtype] * 1e12)
+        t_mfma = exec_tflops * 1e12 * launch_ms * 1e-3 / (PEAK_TFLOPS[mfma_dtype] * 1e12)
         if t_mfma > t_mem:
             bound = "mfma"
+    elif flops_per_launch / (PEAK_TFLOPS["f32"] * 1e12) > t_mem:
+        bound = "alu"
     src_hash = kernel_source_hash()
-    kernel_key = f"{rpath}_box_r{r_dom}_f32_{DIMS[0]}x{DIMS[1]}_periodic"
+    klabel = f"{rpath}_tb{tb}" if tb > 1 else rpath
+    kernel_key = f"{klabel}_box_r{r_dom}_f32_{DIMS[0]}x{DIMS[1]}_periodic"
     traffic = load_traffic(kernel_key, src_hash)
     if bound == "hbm":
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+    elif bound == "alu":
+        # FP32 vector peak 157.3 TFLOP/s = 256 CUs x 4 SIMDs x 2.4 GHz x 64
+        # flop/clock with packed FP32; without packed instructions (never
+        # emitted here) a SIMD retires 16 FMAs a clock: 78.6 TFLOP/s
+        peak = PEAK_TFLOPS["f32"]
+        roof = {"bound": "alu", "achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak,
+                "peak_unpacked": peak / 2, "frac_unpacked": tflops / (peak / 2), "hbm_gbs": gbs,
+                "steps_per_launch": steps_per_launch}
     else:
         peak = PEAK_TFLOPS[mfma_dtype]
         roof = {"bound": "mfma", "achieved": tflops, "peak": peak, "unit": "TFLOP/s", "frac": tflops / peak,
@@ -950,7 +968,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.headline in ("mfma", "gather") else ("f32+" + (mfma_dtype or "f32")),
+        "dtype": "f32+" + mfma_dtype if mfma_dtype in ("bf16", "f16") else "f32",
         "data": "synthetic",
         "config": {"workload": f"2D box stencils r=1..4, {DIMS[0]}x{DIMS[1]} FP32 grid, periodic, "
                                f"{JACOBI_STEPS} Jacobi steps per order (4 solves per bench step)",

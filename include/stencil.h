@@ -131,12 +131,19 @@ typedef struct {
                            other resolved block edge: EUNSUPPORTED; ignored by the GATHER path */
   int32_t chunk;        /* output rows (2D) or i-planes (3D) per workgroup work item: 0 = library
                            choice; rounded up to the kernel's row block and clipped to the extent */
-  int32_t time_block;   /* steps fused per launch (time blocking): 0 or 1 = one step per launch;
-                           T > 1: each launch advances T steps on overlapped tiles held in LDS
-                           (halo r*T), cutting HBM traffic per point-step about T-fold.  Built for
-                           2D grids on the GATHER path (AUTO resolves to it); the halo r*T rounded up
-                           to a multiple of 4 is at most 12 for F32 and 8 for F64 (r = 1: T <= 12 / 8;
-                           r = 2: 6 / 4; r = 3: 4 / 2; r = 4: 3 / 2), else EUNSUPPORTED */
+  int32_t time_block;   /* steps fused per launch (time blocking; the temporal reuse Section 6
+                           leaves to future work): 1 = one step per launch; T > 1: each launch
+                           advances T steps on overlapped tiles held in LDS (halo r*T), cutting HBM
+                           traffic per point-step about T-fold.  Built for 2D grids on the GATHER
+                           path (AUTO resolves to it); the halo r*T rounded up to a multiple of 4 is
+                           at most 12 for F32 and 8 for F64 (r = 1: T <= 12 / 8; r = 2: 6 / 4;
+                           r = 3: 4 / 2; r = 4: 3 / 2), else EUNSUPPORTED.  0 = library choice:
+                           one step per launch, except that path AUTO on F32 2D STAR / BOX grids
+                           wider than 64 columns whose column extent is a multiple of 4, with
+                           lines, block_n, chunk, reg_rows and tile_width all 0, takes the
+                           time-blocked gather with T measured fastest on MI355X (stars 8 / 4 / 4
+                           / 3, boxes 8 / 4 / 4 / 2 for r = 1..4; stencil_plan_info reports it).
+                           stencil_apply is always one step */
   int32_t reg_rows;     /* register tile of the 2D FP32 outer products on n = 4 blocks (box stencils,
                            MFMA path; the i unrolling of Section 4.2): output rows per wave, 8 / 16 / 32
                            (two, four or eight 4-row accumulator blocks), 0 = library choice (16) */
@@ -242,8 +249,9 @@ stencil_status_t stencil_apply(stencil_plan_t plan, const void* in, void* out, v
  * buf[t % 2] and writes buf[(t+1) % 2], starting from the state in buf0
  * (Section 2.2).  *result_index (may be NULL) receives the index of the
  * buffer holding the final state: steps % 2, or for a time-blocked plan
- * (time_block T > 1) the parity of its launch count ceil(steps / T) -- each
- * launch advances up to T steps from one buffer into the other.  steps == 0
+ * (stencil_plan_info's time_block T > 1, asked for or chosen by the library)
+ * the parity of its launch count ceil(steps / T) -- each launch advances up
+ * to T steps from one buffer into the other.  steps == 0
  * enqueues nothing.  Negative steps: EINVAL; overlapping buffers: EALIAS.
  * Launch mode: when 2 <= steps <= 4096 and `stream` is not being captured by
  * the caller, the launches are recorded once into a HIP graph, cached in the
@@ -300,7 +308,9 @@ typedef struct stencil_batch_s* stencil_batch_t;
  * the batch; the plans may be shared between batches.  Errors: EINVAL (null
  * pointers, count < 1, a plan of another device), EALIAS (any two of the
  * 2 x count buffers overlap), EUNSUPPORTED (more than 2^31-1 work items in
- * one group, or a time-blocked plan), ENOMEM, EHIP.  On error *out is NULL. */
+ * one group, or a plan whose descriptor asked for a time block > 1; a time
+ * block the library chose runs one step per launch in the batch, with the
+ * same arithmetic), ENOMEM, EHIP.  On error *out is NULL. */
 stencil_status_t stencil_batch_create(const stencil_plan_t* plans, void* const* buf0, void* const* buf1,
                                       int32_t count, stencil_batch_t* out);
 
@@ -343,7 +353,8 @@ stencil_status_t stencil_batch_destroy(stencil_batch_t batch);
  * request's result equals the result of a plan of the same descriptor run
  * alone (same kernel, same arithmetic).  Not thread-safe: one thread drives a
  * server.  Time-blocked descriptors (time_block > 1) are rejected
- * (EUNSUPPORTED). */
+ * (EUNSUPPORTED); a time block the library chose (time_block 0) is run one
+ * step per launch, with the same arithmetic. */
 typedef struct stencil_server_s* stencil_server_t;
 
 typedef struct {

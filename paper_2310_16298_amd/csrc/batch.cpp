@@ -96,7 +96,9 @@ stencil_status_t stencil_batch_create(const stencil_plan_t* plans, void* const* 
       const stencil_plan_s* p = plans[i];
       if (!p || !buf0[i] || !buf1[i]) return STENCIL_EINVAL;
       if (p->device != device) return STENCIL_EINVAL;
-      if (p->rs.time_block > 1) return STENCIL_EUNSUPPORTED;
+      // an explicit time block is rejected; one the library chose runs one
+      // step per launch here (the plan's picker gives the one-step kernel)
+      if (p->rs.time_block > 1 && !p->rs.tb_auto) return STENCIL_EUNSUPPORTED;
       spans.push_back({(uintptr_t)buf0[i], (uintptr_t)buf0[i] + p->grid_bytes});
       spans.push_back({(uintptr_t)buf1[i], (uintptr_t)buf1[i] + p->grid_bytes});
     }

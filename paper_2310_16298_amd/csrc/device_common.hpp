@@ -49,6 +49,9 @@ __host__ __device__ constexpr int round_up(int v, int m) { return (v + m - 1) / 
 __host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
+// Destination type of the direct-to-LDS loads (global_load_lds).
+typedef __attribute__((address_space(3))) void lds_void_t;
+
 // Workgroup barrier over LDS only: waits for this wave's LDS operations
 // (lgkmcnt(0)) and joins the barrier, leaving vector-memory operations in
 // flight.  __syncthreads() also waits for those (vmcnt(0)) -- the compiler

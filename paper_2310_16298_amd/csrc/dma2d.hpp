@@ -32,8 +32,6 @@
 
 namespace stencil {
 
-typedef __attribute__((address_space(3))) void lds_void_t;
-
 template <typename T, int R, int BM, int TN, int NT>
 struct DmaWindow {
   typedef T elem_t;

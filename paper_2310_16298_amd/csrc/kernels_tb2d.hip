@@ -1,4 +1,6 @@
-// Instantiations of the time-blocked 2D gather kernel.
+// Instantiations of the time-blocked 2D gather kernels.
+#include <type_traits>
+
 #include "kernels_tb2d.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
@@ -6,7 +8,18 @@
 namespace stencil {
 
 template <typename T, int R, bool BOX>
-static Kernel pick_tb2d(KArgs& a, int32_t) {
+static Kernel pick_tb2d(KArgs& a, int32_t chunk) {
+  // a launch of one step (the remainder of a run): the one-step gather
+  if (a.steps <= 1) return find_gather2d(std::is_same<T, double>::value ? STENCIL_F64 : STENCIL_F32, R, BOX)(a, chunk);
+  if constexpr (std::is_same<T, float>::value) {
+    if (tb2d_fast<T>(a) && a.zeros != nullptr) {
+      a.tiles0 = (int32_t)((a.d0 + 63) / 64);
+      a.tiles1 = (int32_t)((a.d1 + 63) / 64);
+      const int64_t items = (int64_t)a.tiles0 * a.tiles1;
+      const Kernel k = BOX ? tb2d_dma_box(R, a.steps, items) : tb2d_dma_star(R, a.steps, items);
+      if (k.launch) return k;
+    }
+  }
   const int64_t items = tb2d_items<T>(a);
   if (tb2d_fast<T>(a)) return kernel_of<tb2d_kernel<T, R, BOX, true>, tb2d_batch<T, R, BOX, true>>(items);
   return kernel_of<tb2d_kernel<T, R, BOX, false>, tb2d_batch<T, R, BOX, false>>(items);

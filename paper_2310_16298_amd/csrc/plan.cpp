@@ -413,6 +413,7 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
   int path = d.path;
   in.time_block = 1;
   if (d.time_block > 1) path = STENCIL_PATH_GATHER;
+  int tb_auto = 0;  // steps per launch the library chose (AUTO), 0 if none
   if (path == STENCIL_PATH_AUTO) {
     // Measured on MI355X: outer products on MFMA where the arithmetic
     // outgrows the memory traffic -- FP32 boxes of radius >= 3 (2D and 3D)
@@ -450,6 +451,19 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
         if (12 * 403 * n_eff < 12 * 620 + 1530 * L * (4 + 2 * R)) heavy = false;
       }
       path = dma_cols && !heavy && !narrow ? STENCIL_PATH_GATHER : STENCIL_PATH_MFMA;
+      // Time blocking: on FP32 grids wider than 64 columns that take
+      // direct-to-LDS windows, the time-blocked gather with the step count
+      // measured fastest on MI355X (8192^2 and 2048^2, periodic) beats every
+      // one-step plan: 8 / 4 / 4 / 3 steps per launch for stars of order
+      // 1..4, 8 / 4 / 4 / 2 for boxes (ahead of the outer products by 2-4 %
+      // at order 3 and 7-10 % at order 4 on 8192^2, by 1.1-1.4x on 2048^2).
+      // Only when every kernel knob is left to the library.
+      static const int kAutoTimeBlock[2][5] = {{0, 8, 4, 4, 3}, {0, 8, 4, 4, 2}};
+      if (f32 && !general && dma_cols && d.dims[1] > 64 && d.time_block == 0 && d.lines == STENCIL_LINES_AUTO &&
+          d.block_n == 0 && d.chunk == 0 && d.reg_rows == 0 && d.tile_width == 0) {
+        path = STENCIL_PATH_GATHER;
+        tb_auto = kAutoTimeBlock[box ? 1 : 0][R];
+      }
     }
   }
   const bool split = path == STENCIL_PATH_MFMA_BF16X3 || path == STENCIL_PATH_MFMA_F16X3;
@@ -494,11 +508,12 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     rs->chunk_req = d.chunk;
     in.tile_rows = kTile2D;
     in.tile_cols = kTile2D;
-    if (path == STENCIL_PATH_GATHER && d.time_block > 1) {
+    if (path == STENCIL_PATH_GATHER && (d.time_block > 1 || tb_auto > 1)) {
       rs->family = FAM_TB2D;
       rs->pick = find_tb2d(d.dtype, R, box);
-      rs->time_block = d.time_block;
-      in.time_block = d.time_block;
+      rs->time_block = d.time_block > 1 ? d.time_block : tb_auto;
+      rs->tb_auto = tb_auto > 1;
+      in.time_block = rs->time_block;
       in.tile_rows = d.dtype == STENCIL_F64 ? 32 : 64;
       in.tile_cols = 64;
       in.executed_flops_per_point = 2.0 * in.taps;

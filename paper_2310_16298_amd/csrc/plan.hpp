@@ -39,6 +39,7 @@ struct Resolved {
   KArgs args{};             // everything but in/out
   int32_t chunk_req = 0;    // requested rows (2D) per work item, 0 = library choice
   int32_t time_block = 1;   // steps per launch
+  bool tb_auto = false;     // time_block chosen by the library (AUTO): batches run such plans one step per launch
   Picker pick = nullptr;
 };
 

@@ -117,20 +117,20 @@ inline stencil_status_t check_device(int device) {
   return dev == device ? STENCIL_OK : STENCIL_EINVAL;
 }
 
-// The resolved plan's args with the two buffers filled in, its kernel picked
-// and the decomposition applied.
-inline Kernel plan_kernel(const Resolved& rs, const void* in, void* out, KArgs* a) {
+// The resolved plan's args with the two buffers and the launch's step count
+// filled in, its kernel picked and the decomposition applied.
+inline Kernel plan_kernel(const Resolved& rs, const void* in, void* out, KArgs* a, int fused = 1) {
   *a = rs.args;
   a->in = in;
   a->out = out;
+  a->steps = fused;
   return rs.pick(*a, rs.chunk_req);
 }
 
 // One launch: one step, or `fused` steps of a time-blocked plan.
 inline stencil_status_t launch_one(const Resolved& rs, const void* in, void* out, hipStream_t s, int fused = 1) {
   KArgs a;
-  const Kernel k = plan_kernel(rs, in, out, &a);
-  a.steps = fused;
+  const Kernel k = plan_kernel(rs, in, out, &a, fused);
   if (!k.launch || k.items < 1 || k.items > (int64_t(1) << 31) - 1) return STENCIL_EINTERNAL;
   return k.launch(a, (unsigned)k.items, s) == hipSuccess ? STENCIL_OK : STENCIL_EHIP;
 }

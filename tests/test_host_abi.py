@@ -394,12 +394,22 @@ def test_auto_path_choice(lib, shape):
     """AUTO: outer products on MFMA for FP32 boxes of radius >= 3 (2D and 3D),
     FP64 3D stars of radius 4 and 2D GENERAL covers, the gather kernel for the rest
     when the column extent allows direct-to-LDS windows (a multiple of 4; 2D),
-    MFMA on other 2D extents."""
+    MFMA on other 2D extents; on FP32 2D direct-to-LDS grids wider than 64
+    columns with no kernel knob set, the time-blocked gather."""
     for r in (1, 2, 3, 4):
         c = inputs.coefficients(2, r, shape, seed=3, dtype=np.float64)
         heavy = shape == inputs.BOX and r >= 3
-        assert st.describe((96, 96), r, shape, c, dtype=st.F32)["path"] == (st.PATH_MFMA if heavy else st.PATH_GATHER)
+        # FP32 direct-to-LDS grids wider than 64 columns: the time-blocked gather
+        info = st.describe((96, 96), r, shape, c, dtype=st.F32)
+        assert info["path"] == st.PATH_GATHER
+        assert info["time_block"] == ({1: 8, 2: 4, 3: 4, 4: 3} if shape == inputs.STAR else {1: 8, 2: 4, 3: 4, 4: 2})[r]
+        # any kernel knob set keeps one step per launch (and the one-step choice)
+        one = st.describe((96, 96), r, shape, c, dtype=st.F32, chunk=64)
+        assert one["time_block"] == 1 and one["path"] == (st.PATH_MFMA if heavy else st.PATH_GATHER)
+        assert st.describe((96, 96), r, shape, c, dtype=st.F32, time_block=1)["time_block"] == 1
+        assert st.describe((96, 96), r, shape, c, dtype=st.F32, path=st.PATH_GATHER)["time_block"] == 1
         assert st.describe((96, 96), r, shape, c, dtype=st.F64)["path"] == st.PATH_GATHER
+        assert st.describe((96, 96), r, shape, c, dtype=st.F64)["time_block"] == 1
         # at most 64 columns: stars and the FP64 9-point box take the outer products
         narrow = shape == inputs.STAR or heavy
         assert st.describe((64, 64), r, shape, c, dtype=st.F32)["path"] == (st.PATH_MFMA if narrow else st.PATH_GATHER)
