@@ -138,11 +138,12 @@ typedef struct {
                            path (AUTO resolves to it); the halo r*T rounded up to a multiple of 4 is
                            at most 12 for F32 and 8 for F64 (r = 1: T <= 12 / 8; r = 2: 6 / 4;
                            r = 3: 4 / 2; r = 4: 3 / 2), else EUNSUPPORTED.  0 = library choice:
-                           one step per launch, except that path AUTO on F32 2D STAR / BOX grids
+                           one step per launch, except that path AUTO on 2D STAR / BOX grids
                            wider than 64 columns whose column extent is a multiple of 4, with
                            lines, block_n, chunk, reg_rows and tile_width all 0, takes the
-                           time-blocked gather with T measured fastest on MI355X (stars 8 / 4 / 4
-                           / 3, boxes 8 / 4 / 4 / 2 for r = 1..4; stencil_plan_info reports it).
+                           time-blocked gather with T measured fastest on MI355X (r = 1..4,
+                           F32 stars 8 / 4 / 4 / 3, boxes 8 / 4 / 4 / 2; F64 stars 8 / 4 / 2 /
+                           2, boxes 8 / 4 / - / -; stencil_plan_info reports it).
                            stencil_apply is always one step */
   int32_t reg_rows;     /* register tile of the 2D FP32 outer products on n = 4 blocks (box stencils,
                            MFMA path; the i unrolling of Section 4.2): output rows per wave, 8 / 16 / 32

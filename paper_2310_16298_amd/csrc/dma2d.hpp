@@ -433,12 +433,29 @@ __device__ __forceinline__ void gather2d_dma_item(const KArgs& a, int item) {
       // LDS columns c4 .. c4 + 11 hold window columns c4 - 4 + r .. c4 + 7 + r
       const V* rp = reinterpret_cast<const V*>(cur + (PR * rg + x) * D::PITCH + c4);
       T vv[12];
+      if constexpr (sizeof(T) == 4 && R < 4) {
+        // FP32 below r = 4: a row uses 4 + 2r of the 12 columns (a star row
+        // off every output row's centre only the middle four), and a partly
+        // used 16-byte vector would be narrowed into 4- or 8-byte reads that
+        // meet a quarter or half of the banks at this 16-byte lane stride;
+        // the empty asm keeps the vector whole
+        const bool full = BOX || (x >= R && x < R + PR);
 #pragma unroll
-      for (int k = 0; k < 12 / VEC; ++k) {
-        const V t = rp[k];
-        const T* pt = reinterpret_cast<const T*>(&t);
+        for (int k = 0; k < 3; ++k) {
+          if (!full && k != 1) continue;
+          floatx4 t4 = reinterpret_cast<const floatx4*>(rp)[k];
+          asm volatile("" : "+v"(t4));
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) vv[k * VEC + e] = pt[e];
+          for (int e = 0; e < 4; ++e) vv[4 * k + e] = t4[e];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 12 / VEC; ++k) {
+          const V t = rp[k];
+          const T* pt = reinterpret_cast<const T*>(&t);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) vv[k * VEC + e] = pt[e];
+        }
       }
 #pragma unroll
       for (int p = 0; p < PR; ++p) {

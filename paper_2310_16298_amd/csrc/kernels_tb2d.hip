@@ -11,14 +11,15 @@ template <typename T, int R, bool BOX>
 static Kernel pick_tb2d(KArgs& a, int32_t chunk) {
   // a launch of one step (the remainder of a run): the one-step gather
   if (a.steps <= 1) return find_gather2d(std::is_same<T, double>::value ? STENCIL_F64 : STENCIL_F32, R, BOX)(a, chunk);
-  if constexpr (std::is_same<T, float>::value) {
-    if (tb2d_fast<T>(a) && a.zeros != nullptr) {
-      a.tiles0 = (int32_t)((a.d0 + 63) / 64);
-      a.tiles1 = (int32_t)((a.d1 + 63) / 64);
-      const int64_t items = (int64_t)a.tiles0 * a.tiles1;
-      const Kernel k = BOX ? tb2d_dma_box(R, a.steps, items) : tb2d_dma_star(R, a.steps, items);
-      if (k.launch) return k;
-    }
+  if (tb2d_fast<T>(a) && a.zeros != nullptr) {
+    constexpr int TM = tb2d_dma_rows<T>();
+    a.tiles0 = (int32_t)((a.d0 + TM - 1) / TM);
+    a.tiles1 = (int32_t)((a.d1 + 63) / 64);
+    const int64_t items = (int64_t)a.tiles0 * a.tiles1;
+    Kernel k;
+    if constexpr (std::is_same<T, float>::value) k = BOX ? tb2d_dma_box(R, a.steps, items) : tb2d_dma_star(R, a.steps, items);
+    else k = tb2d_dma_f64(BOX, R, a.steps, items);
+    if (k.launch) return k;
   }
   const int64_t items = tb2d_items<T>(a);
   if (tb2d_fast<T>(a)) return kernel_of<tb2d_kernel<T, R, BOX, true>, tb2d_batch<T, R, BOX, true>>(items);

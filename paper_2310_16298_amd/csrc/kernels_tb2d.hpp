@@ -199,52 +199,60 @@ __global__ __launch_bounds__(256) void tb2d_batch(BatchArgs b) {
 }
 
 // ---------------------------------------------------------------------------
-// FP32 form with the step count TS fixed at compile time, for grids that take
+// Form with the step count TS fixed at compile time, for grids that take
 // direct-to-LDS windows (column extent a multiple of 4, 16-byte aligned
 // buffers, a zero line).  The window is sized for TS: halo HW =
-// round_up(r TS, 4), so a 64 x 64 tile at r TS <= 4 holds 72 x 80 floats
+// round_up(r TS, 4), so a 64 x 64 FP32 tile at r TS <= 4 holds 72 x 80 floats
 // (23 KiB) and six workgroups share a CU, against two for the general form,
-// which sizes its two buffers for the largest halo.  The window is copied
-// from global memory straight into LDS (global_load_lds_dwordx4, no
-// registers; lines outside a zero-halo grid and the 4-column margins read
-// the zero line) and the steps update it in place: each thread computes its
-// 2 x 4 blocks of a step into registers, a barrier, then writes them back.
-// Every loop bound is a constant once TS is.
+// which sizes its two buffers for the largest halo (FP64: 32 x 64 tiles).
+// The window is copied from global memory straight into LDS
+// (global_load_lds_dwordx4, no registers; lines outside a zero-halo grid and
+// the 4-column margins read the zero line) and the steps update it in place:
+// each thread computes its 2 x 4 blocks of a step into registers, a barrier,
+// then writes them back.  Every loop bound is a constant once TS is.
 // ---------------------------------------------------------------------------
-template <int R, int TS>
+template <typename T, int R, int TS>
 struct TbDmaShape {
-  static constexpr int TM = 64, TN = 64;
+  static constexpr int TM = sizeof(T) == 4 ? 64 : 32, TN = 64;
+  static constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte line
   static constexpr int HW = round_up(R * TS, 4);
   static constexpr int WM = TM + 2 * HW, WN = TN + 2 * HW;
-  static constexpr int P = WN + 8;              // LDS row: window columns -4 .. WN + 3
-  static constexpr int LPR = P / 4;             // 16-byte lines per LDS row
+  static constexpr int P = WN + 8;                 // LDS row: window columns -4 .. WN + 3
+  static constexpr int LPR = P / VEC;              // 16-byte lines per LDS row
+  static constexpr int MARGIN = 4 / VEC;           // lines of the 4-column margins
   static constexpr int NI = (WM * LPR + 63) / 64;  // load instructions (1 KiB each)
   static constexpr int NPW = (NI + 3) / 4;         // per wave, at most
-  // floats: the loaded lines (whole instructions) and one row past the
+  // elements: the loaded lines (whole instructions) and one row past the
   // window, which the last 2-row block of a step reads
-  static constexpr int BUF = NI * 64 * 4 > (WM + 1) * P ? NI * 64 * 4 : (WM + 1) * P;
+  static constexpr int BUF = NI * 64 * VEC > (WM + 1) * P ? NI * 64 * VEC : (WM + 1) * P;
   // 2 x 4 blocks of the first (largest) step, and per thread
   static constexpr int NBLK1 = ((WM - 2 * R + 1) / 2) * ((WN - R + 3) / 4 - R / 4);
   static constexpr int NBPT = (NBLK1 + 255) / 256;
-  static_assert(HW <= 12, "halo within the general form's limit");
+  static_assert(HW <= TbShape<T>::HMAX, "halo within the general form's limit");
 };
 
-template <int R, bool BOX, int TS>
+template <typename T> struct TbVec;
+template <> struct TbVec<float> { typedef floatx4 type; };
+template <> struct TbVec<double> { typedef double __attribute__((ext_vector_type(2))) type; };
+
+template <typename T, int R, bool BOX, int TS>
 __device__ __forceinline__ void tb2d_dma_item(const KArgs& a, int item) {
-  typedef TbDmaShape<R, TS> S;
-  constexpr int W = 2 * R + 1;
-  __shared__ __attribute__((aligned(16))) float buf[S::BUF];
+  typedef TbDmaShape<T, R, TS> S;
+  typedef typename TbVec<T>::type V;
+  constexpr int W = 2 * R + 1, VEC = S::VEC;
+  __shared__ __attribute__((aligned(16))) T buf[S::BUF];
 
   const int ti = item / a.tiles1, tj = item - (item / a.tiles1) * a.tiles1;
   const int64_t M = a.d0, N = a.d1;
   const int64_t i0 = (int64_t)ti * S::TM - S::HW, j0 = (int64_t)tj * S::TN - S::HW;  // window origin
   const bool periodic = a.periodic != 0;
-  const float* __restrict__ in = (const float*)a.in;
-  const float* __restrict__ zeros = (const float*)a.zeros;
-  float* __restrict__ out = (float*)a.out;
-  // the weights a step uses: scalar registers up to 49 of them (star, boxes to
-  // r = 3); the 81 of the r = 4 box go to vector registers
-  typedef typename std::conditional<(BOX ? W * W : 2 * W - 1) <= 49, ConstPtr<float>, const float*>::type CoefPtr;
+  const T* __restrict__ in = (const T*)a.in;
+  const T* __restrict__ zeros = (const T*)a.zeros;
+  T* __restrict__ out = (T*)a.out;
+  // the weights a step uses: scalar registers up to 49 FP32 / 25 FP64 of
+  // them; more (the r = 4 FP32 box, FP64 boxes from r = 3) go to vector registers
+  constexpr int NW = BOX ? W * W : 2 * W - 1;
+  typedef typename std::conditional<NW <= (sizeof(T) == 4 ? 49 : 25), ConstPtr<T>, const T*>::type CoefPtr;
   const CoefPtr c = (CoefPtr)a.coef;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
 
@@ -254,14 +262,14 @@ __device__ __forceinline__ void tb2d_dma_item(const KArgs& a, int item) {
     const int inst = k * 4 + w;
     if (inst >= S::NI) break;  // wave-uniform
     const int line = inst * 64 + lane;
-    const float* src = zeros;
+    const T* src = zeros;
     const int row = line / S::LPR, lc = line - (line / S::LPR) * S::LPR;
-    if (row < S::WM && lc > 0 && lc < S::LPR - 1) {
+    if (row < S::WM && lc >= S::MARGIN && lc < S::LPR - S::MARGIN) {
       const int64_t g = map_index(i0 + row, M, periodic);
-      const int64_t cc = map_index(j0 - 4 + 4 * lc, N, periodic);
+      const int64_t cc = map_index(j0 - 4 + VEC * lc, N, periodic);
       if (g >= 0 && cc >= 0) src = in + g * N + cc;
     }
-    __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t*)(buf + inst * 256), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)src, (lds_void_t*)(buf + inst * 64 * VEC), 16, 0, 0);
   }
   __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wave's lines are in LDS
   __syncthreads();
@@ -272,7 +280,7 @@ __device__ __forceinline__ void tb2d_dma_item(const KArgs& a, int item) {
     const int lo = R * (s + 1);
     const int sg0 = lo / 4, nseg = (S::WN - lo + 3) / 4 - sg0;
     const int nblk = ((S::WM - 2 * lo + 1) / 2) * nseg;
-    float res[S::NBPT][2][4];
+    T res[S::NBPT][2][4];
 #pragma unroll
     for (int q = 0; q < S::NBPT; ++q) {
       const int idx = tid + 256 * q;
@@ -282,30 +290,27 @@ __device__ __forceinline__ void tb2d_dma_item(const KArgs& a, int item) {
 #pragma unroll
       for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) res[q][p][e] = 0.0f;
+        for (int e = 0; e < 4; ++e) res[q][p][e] = T(0);
 #pragma unroll
       for (int dx = 0; dx < 2 + 2 * R; ++dx) {
-        // window row x - r + dx, LDS columns 4 sg .. 4 sg + 11, read as three
-        // whole 16-byte vectors.  Below r = 4 a row uses only 4 + 2r of the 12
-        // columns, and the compiler would narrow a partly used vector into
-        // 4- or 8-byte reads, which at this 16-byte lane stride meet only 16
-        // or 32 of the 64 banks; the empty asm keeps every lane of the vector
-        // live (at the cost of a wait for it, which r = 4, using all 12, is
-        // spared)
-        const floatx4* rp = reinterpret_cast<const floatx4*>(buf + (x - R + dx) * S::P + 4 * sg);
-        // a star row other than the two output rows' own uses the centre
-        // column only: the middle vector
+        // window row x - r + dx, LDS columns 4 sg .. 4 sg + 11 (window
+        // columns 4 sg - 4 .. 4 sg + 7), read as whole 16-byte vectors.  A row
+        // uses columns 4 - r .. 7 + r of the 12 (a star row other than the two
+        // output rows' own: 4 .. 7 only); vectors outside are skipped, and
+        // the compiler would narrow a partly used one into 4- or 8-byte reads
+        // that meet a fraction of the banks at this lane stride, so the empty
+        // asm keeps it whole (at the cost of a wait for it)
+        const V* rp = reinterpret_cast<const V*>(buf + (x - R + dx) * S::P + 4 * sg);
         const bool full = BOX || dx == R || dx == R + 1;
-        float v[12];
+        T v[12];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          if (!full && k != 1) continue;
-          floatx4 t4 = rp[k];
-          if constexpr (R < 4) asm volatile("" : "+v"(t4));
-          v[4 * k] = t4[0];
-          v[4 * k + 1] = t4[1];
-          v[4 * k + 2] = t4[2];
-          v[4 * k + 3] = t4[3];
+        for (int k = 0; k < 12 / VEC; ++k) {
+          const int lo_e = full ? 4 - R : 4, hi_e = full ? 7 + R : 7;  // columns used
+          if (VEC * k + VEC - 1 < lo_e || VEC * k > hi_e) continue;
+          V t4 = rp[k];
+          if (VEC * k < lo_e || VEC * k + VEC - 1 > hi_e) asm volatile("" : "+v"(t4));
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) v[VEC * k + e] = t4[e];
         }
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
@@ -314,7 +319,7 @@ __device__ __forceinline__ void tb2d_dma_item(const KArgs& a, int item) {
 #pragma unroll
           for (int b = 0; b < W; ++b) {
             if (!BOX && aa != R && b != R) continue;
-            const float wgt = c[aa * W + b];
+            const T wgt = c[aa * W + b];
 #pragma unroll
             for (int e = 0; e < 4; ++e) res[q][p][e] += wgt * v[4 - R + e + b];
           }
@@ -337,11 +342,17 @@ __device__ __forceinline__ void tb2d_dma_item(const KArgs& a, int item) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int64_t gj = j0 + 4 * sg + e;
-            if (!row_in || gj < 0 || gj >= N) res[q][p][e] = 0.0f;
+            if (!row_in || gj < 0 || gj >= N) res[q][p][e] = T(0);
           }
         }
-        *reinterpret_cast<float4*>(buf + (x + p) * S::P + 4 + 4 * sg) =
-            float4{res[q][p][0], res[q][p][1], res[q][p][2], res[q][p][3]};
+        V* dv = reinterpret_cast<V*>(buf + (x + p) * S::P + 4 + 4 * sg);
+#pragma unroll
+        for (int k = 0; k < 4 / VEC; ++k) {
+          V t4;
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) t4[e] = res[q][p][VEC * k + e];
+          dv[k] = t4;
+        }
       }
     }
     __syncthreads();
@@ -355,44 +366,49 @@ __device__ __forceinline__ void tb2d_dma_item(const KArgs& a, int item) {
     const int x = idx / TSEG, sg = idx - (idx / TSEG) * TSEG;
     const int64_t gi = (int64_t)ti * S::TM + x, gj = (int64_t)tj * S::TN + 4 * sg;
     if (gi >= M || gj >= N) continue;
-    *reinterpret_cast<float4*>(out + gi * N + gj) =
-        *reinterpret_cast<const float4*>(buf + (S::HW + x) * S::P + 4 + S::HW + 4 * sg);
+    const V* sv = reinterpret_cast<const V*>(buf + (S::HW + x) * S::P + 4 + S::HW + 4 * sg);
+    V* dv = reinterpret_cast<V*>(out + gi * N + gj);
+#pragma unroll
+    for (int e = 0; e < 4 / VEC; ++e) dv[e] = sv[e];
   }
 }
 
-template <int R, bool BOX, int TS>
+template <typename T, int R, bool BOX, int TS>
 __global__ __launch_bounds__(256) void tb2d_dma_kernel(KArgs a) {
-  tb2d_dma_item<R, BOX, TS>(a, xcd_remap(blockIdx.x, gridDim.x));
+  tb2d_dma_item<T, R, BOX, TS>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-template <int R, bool BOX, int TS>
+template <typename T, int R, bool BOX, int TS>
 __global__ __launch_bounds__(256) void tb2d_dma_batch(BatchArgs b) {
-  for_each_batch_item(b, [&](const KArgs& x, int id) { tb2d_dma_item<R, BOX, TS>(x, id); });
+  for_each_batch_item(b, [&](const KArgs& x, int id) { tb2d_dma_item<T, R, BOX, TS>(x, id); });
 }
 
-// The FP32 direct-to-LDS kernel for order R and `steps` steps (2 <= steps,
-// halo within the limit), empty if not built; the two shapes are
-// instantiated in separate translation units.
+// The direct-to-LDS kernel for order R and `steps` steps (2 <= steps, halo
+// within the limit), empty if not built, with its tile rows; FP32 boxes,
+// FP32 stars and FP64 are instantiated in separate translation units.
 Kernel tb2d_dma_box(int R, int steps, int64_t items);
 Kernel tb2d_dma_star(int R, int steps, int64_t items);
+Kernel tb2d_dma_f64(bool box, int R, int steps, int64_t items);
+template <typename T>
+constexpr int tb2d_dma_rows() { return TbDmaShape<T, 1, 2>::TM; }
 
-template <int R, bool BOX, int TS>
+template <typename T, int R, bool BOX, int TS>
 Kernel tb2d_dma_of(int steps, int64_t items) {
-  if constexpr (round_up(R * TS, 4) > TbShape<float>::HMAX) {
+  if constexpr (round_up(R * TS, 4) > TbShape<T>::HMAX) {
     return Kernel{};
   } else {
-    if (steps == TS) return kernel_of<tb2d_dma_kernel<R, BOX, TS>, tb2d_dma_batch<R, BOX, TS>>(items);
-    return tb2d_dma_of<R, BOX, TS + 1>(steps, items);
+    if (steps == TS) return kernel_of<tb2d_dma_kernel<T, R, BOX, TS>, tb2d_dma_batch<T, R, BOX, TS>>(items);
+    return tb2d_dma_of<T, R, BOX, TS + 1>(steps, items);
   }
 }
 
-template <bool BOX>
+template <typename T, bool BOX>
 Kernel tb2d_dma_pick(int R, int steps, int64_t items) {
   switch (R) {
-    case 1: return tb2d_dma_of<1, BOX, 2>(steps, items);
-    case 2: return tb2d_dma_of<2, BOX, 2>(steps, items);
-    case 3: return tb2d_dma_of<3, BOX, 2>(steps, items);
-    case 4: return tb2d_dma_of<4, BOX, 2>(steps, items);
+    case 1: return tb2d_dma_of<T, 1, BOX, 2>(steps, items);
+    case 2: return tb2d_dma_of<T, 2, BOX, 2>(steps, items);
+    case 3: return tb2d_dma_of<T, 3, BOX, 2>(steps, items);
+    case 4: return tb2d_dma_of<T, 4, BOX, 2>(steps, items);
   }
   return Kernel{};
 }

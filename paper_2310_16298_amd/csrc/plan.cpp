@@ -451,18 +451,24 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
         if (12 * 403 * n_eff < 12 * 620 + 1530 * L * (4 + 2 * R)) heavy = false;
       }
       path = dma_cols && !heavy && !narrow ? STENCIL_PATH_GATHER : STENCIL_PATH_MFMA;
-      // Time blocking: on FP32 grids wider than 64 columns that take
-      // direct-to-LDS windows, the time-blocked gather with the step count
-      // measured fastest on MI355X (8192^2 and 2048^2, periodic) beats every
-      // one-step plan: 8 / 4 / 4 / 3 steps per launch for stars of order
-      // 1..4, 8 / 4 / 4 / 2 for boxes (ahead of the outer products by 2-4 %
-      // at order 3 and 7-10 % at order 4 on 8192^2, by 1.1-1.4x on 2048^2).
-      // Only when every kernel knob is left to the library.
-      static const int kAutoTimeBlock[2][5] = {{0, 8, 4, 4, 3}, {0, 8, 4, 4, 2}};
-      if (f32 && !general && dma_cols && d.dims[1] > 64 && d.time_block == 0 && d.lines == STENCIL_LINES_AUTO &&
+      // Time blocking: on grids wider than 64 columns that take direct-to-LDS
+      // windows, the time-blocked gather with the step count measured fastest
+      // on MI355X (512^2, 2048^2 and 8192^2, periodic) beats every one-step
+      // plan.  FP32: 8 / 4 / 4 / 3 steps per launch for stars of order 1..4,
+      // 8 / 4 / 4 / 2 for boxes (ahead of the outer products by 2-4 % at
+      // order 3 and 7-10 % at order 4 on 8192^2, by 1.1-1.4x on 2048^2).
+      // FP64: stars 8 / 4 / 2 / 2, boxes 8 / 4 and none from order 3 (their
+      // 49 / 81 weights take 98 / 162 vector registers there).  Only when
+      // every kernel knob is left to the library.
+      static const int kAutoTimeBlock[2][2][5] = {{{0, 8, 4, 4, 3}, {0, 8, 4, 4, 2}},   // F32 star, box
+                                                  {{0, 8, 4, 2, 2}, {0, 8, 4, 0, 0}}};  // F64 star, box
+      if (!general && dma_cols && d.dims[1] > 64 && d.time_block == 0 && d.lines == STENCIL_LINES_AUTO &&
           d.block_n == 0 && d.chunk == 0 && d.reg_rows == 0 && d.tile_width == 0) {
-        path = STENCIL_PATH_GATHER;
-        tb_auto = kAutoTimeBlock[box ? 1 : 0][R];
+        const int t = kAutoTimeBlock[f32 ? 0 : 1][box ? 1 : 0][R];
+        if (t > 1) {
+          path = STENCIL_PATH_GATHER;
+          tb_auto = t;
+        }
       }
     }
   }

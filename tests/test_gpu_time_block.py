@@ -55,17 +55,18 @@ def test_time_block_parity(dtype, shape, r, bc, dims):
         _case(dims, r, shape, bc, dtype, tb, 2 * tb + 1, seed=1000 + 10 * r + bc)
 
 
+@pytest.mark.parametrize("dtype", [st.F32, st.F64])
 @pytest.mark.parametrize("r", [1, 2, 3, 4])
 @pytest.mark.parametrize("shape", [st.BOX, st.STAR])
-def test_time_block_every_step_count_f32(r, shape):
-    """FP32 grids whose column extent takes direct-to-LDS windows run one
-    kernel per step count: every time block from 2 to the largest, in runs
-    whose last launch fuses T - 1 steps (2T - 1 steps) or one step (T + 1;
-    the one-step gather)."""
-    for tb in range(2, TMAX[(st.F32, r)] + 1):
+def test_time_block_every_step_count(dtype, r, shape):
+    """Grids whose column extent takes direct-to-LDS windows run one kernel
+    per step count: every time block from 2 to the largest, in runs whose
+    last launch fuses T - 1 steps (2T - 1 steps) or one step (T + 1; the
+    one-step gather)."""
+    for tb in range(2, TMAX[(dtype, r)] + 1):
         for bc in (st.BC_ZERO, st.BC_PERIODIC):
             for steps in (2 * tb - 1, tb + 1):
-                _case((70, 132), r, shape, bc, st.F32, tb, steps, seed=1050 + 10 * r + tb)
+                _case((70, 132), r, shape, bc, dtype, tb, steps, seed=1050 + 10 * r + tb)
 
 
 @pytest.mark.parametrize("dims", [(1, 1), (5, 3), (3, 70), (70, 2), (9, 9), (1, 4), (5, 8), (70, 4), (3, 68)])
