@@ -137,14 +137,18 @@ typedef struct {
                            traffic per point-step about T-fold.  Built for 2D grids on the GATHER
                            path (AUTO resolves to it); the halo r*T rounded up to a multiple of 4 is
                            at most 12 for F32 and 8 for F64 (r = 1: T <= 12 / 8; r = 2: 6 / 4;
-                           r = 3: 4 / 2; r = 4: 3 / 2), else EUNSUPPORTED.  0 = library choice:
+                           r = 3: 4 / 2; r = 4: 3 / 2), and for 3D r = 1 STAR / BOX grids whose
+                           last extent is a multiple of 4 (T = 2; its launches need 16-byte
+                           aligned buffers, else stencil_run_steps returns EINVAL); else
+                           EUNSUPPORTED.  0 = library choice:
                            one step per launch, except that path AUTO on 2D STAR / BOX grids
                            wider than 64 columns whose column extent is a multiple of 4, with
                            lines, block_n, chunk, reg_rows and tile_width all 0, takes the
                            time-blocked gather with T measured fastest on MI355X (r = 1..4,
                            F32 stars 8 / 4 / 4 / 3, boxes 8 / 4 / 4 / 2; F64 stars 8 / 4 / 2 /
-                           2, boxes 8 / 4 / - / -; stencil_plan_info reports it).
-                           stencil_apply is always one step */
+                           2, boxes 8 / 4 / - / -), and AUTO on 3D r = 1 STAR / BOX grids of at most
+                           64^3 points (F32 stars: 128^3) whose last extent is a multiple of 4 takes
+                           T = 2 (stencil_plan_info reports it).  stencil_apply is always one step */
   int32_t reg_rows;     /* register tile of the 2D FP32 outer products on n = 4 blocks (box stencils,
                            MFMA path; the i unrolling of Section 4.2): output rows per wave, 8 / 16 / 32
                            (two, four or eight 4-row accumulator blocks), 0 = library choice (16) */
@@ -421,7 +425,7 @@ stencil_status_t stencil_server_destroy(stencil_server_t server);
  *      tile_width are 0: register tiles of 8 / 16 / 32 rows per wave x
  *      workgroup tiles of 128 / 256 columns (the unrolling study of Section
  *      4.2, Fig. 4);
- *   3. 2D grids, path AUTO or GATHER, time_block 0: time blocks T = 2..12
+ *   3. path AUTO or GATHER, time_block 0: time blocks T = 2..12 (3D: T = 2)
  *      (those stencil_desc_check accepts) on the gather path;
  *   4. for the winner (unless time-blocked), chunk lengths 16..1024 rows (2D)
  *      or 8..128 planes (3D) when desc->chunk is 0.

@@ -167,8 +167,14 @@ static int validate(const stencil_desc_t* d) {
   if (d->reg_rows != 0 && d->reg_rows != 8 && d->reg_rows != 16 && d->reg_rows != 32) return STENCIL_EINVAL;
   if (d->tile_width != 0 && d->tile_width != 128 && d->tile_width != 256) return STENCIL_EINVAL;
   if (d->time_block > 1) {
-    if (d->ndim != 2 || (d->path != STENCIL_PATH_AUTO && d->path != STENCIL_PATH_GATHER)) return STENCIL_EUNSUPPORTED;
-    if (d->time_block > tb2d_max_steps(d->dtype, d->radius)) return STENCIL_EUNSUPPORTED;
+    if (d->path != STENCIL_PATH_AUTO && d->path != STENCIL_PATH_GATHER) return STENCIL_EUNSUPPORTED;
+    if (d->ndim == 3) {
+      // 3D: the 7-point star and the 27-point box, two steps, direct-to-LDS lines
+      if (d->radius != 1 || d->shape == STENCIL_GENERAL || d->time_block > 2 || d->dims[2] % 4 != 0)
+        return STENCIL_EUNSUPPORTED;
+    } else if (d->time_block > tb2d_max_steps(d->dtype, d->radius)) {
+      return STENCIL_EUNSUPPORTED;
+    }
   }
   int64_t total = 1;
   for (int k = 0; k < d->ndim; ++k) {
@@ -431,6 +437,19 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       static const int kSparse3DAuto[5] = {0, 0, 0, 88, 128};
       const bool few = general && in.taps <= kSparse3DAuto[R];
       path = (f32 && box && R >= 3 && !few) || (!f32 && !box && R == 4) ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
+      // Time blocking: the 7-point star and the 27-point box, two steps per
+      // launch, on k extents that take direct-to-LDS lines, when every knob
+      // is left open, on grids small enough for the halved launch count to
+      // pay (measured on MI355X, zero halo: at 64^3 and below 1.14-1.6x the
+      // one-step gather, FP32 star 1.2x at 128^3; from 256^3 on the window's
+      // halo work and re-reads make it tie or lose)
+      const int64_t pts3 = d.dims[0] * d.dims[1] * d.dims[2];
+      const bool small3 = pts3 <= (int64_t(1) << 18) || (f32 && !box && pts3 <= (int64_t(1) << 21));
+      if (small3 && R == 1 && !general && d.dims[2] % 4 == 0 && d.time_block == 0 &&
+          d.lines == STENCIL_LINES_AUTO && d.block_n == 0 && d.chunk == 0) {
+        path = STENCIL_PATH_GATHER;
+        tb_auto = 2;
+      }
     } else {
       // grids at most 64 columns wide (the paper's smallest Table 3 shapes):
       // outer products for stars and the FP64 9-point box, measured ahead there
@@ -691,7 +710,16 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     a.nchunks = (int32_t)nch;
     in.tile_rows = kTJ;
     in.tile_cols = kTK;
-    if (path == STENCIL_PATH_GATHER) {
+    const int tb3 = d.time_block > 1 ? d.time_block : tb_auto;
+    if (path == STENCIL_PATH_GATHER && tb3 > 1) {
+      rs->family = FAM_TB3D;
+      rs->pick = find_tb3d(d.dtype, R, box);
+      rs->time_block = tb3;
+      rs->tb_auto = d.time_block <= 1;
+      in.time_block = tb3;
+      in.executed_flops_per_point = 2.0 * in.taps;
+      lines = STENCIL_LINES_AUTO;
+    } else if (path == STENCIL_PATH_GATHER) {
       rs->family = FAM_GATHER3D;
       // GENERAL: the nonzero-tap gather up to the tap count where the all-tap
       // gather catches up (measured on MI355X; FP32 / FP64, orders 1..4)

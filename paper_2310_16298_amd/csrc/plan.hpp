@@ -23,7 +23,8 @@ enum Family {
   FAM_MFMA3D_BOX = 5,
   FAM_SPLIT3D_STAR = 6,
   FAM_SPLIT3D_BOX = 7,
-  FAM_TB2D = 8         // time-blocked gather
+  FAM_TB2D = 8,        // time-blocked gather
+  FAM_TB3D = 9         // time-blocked 3D gather (r = 1)
 };
 
 // Everything the plan resolves on the host.
@@ -77,6 +78,7 @@ Picker find_mfma3d(int dtype, int R, bool box);
 Picker find_mfma3d_b4(int R, bool box);  // FP32 n = 4 blocks: stars, 27-point box
 Picker find_split3d(int kind, int R, bool box, bool hybrid);  // hybrid: stars, lines along j and k on MFMA
 Picker find_tb2d(int dtype, int R, bool box);
+Picker find_tb3d(int dtype, int R, bool box);  // r = 1, two steps per launch
 int tb2d_max_steps(int dtype, int R);  // largest time_block of the time-blocked kernel
 
 hipError_t launch_error_norms(const void* a, int a_dtype, const double* ref, int64_t n, double* out,

@@ -232,10 +232,9 @@ stencil_status_t stencil_autotune(const stencil_desc_t* desc, const char* cache_
           }
       }
     }
-    // 3) time blocking (2D gather form) when the request leaves it open
-    if (st == STENCIL_OK && d.ndim == 2 && d.time_block == 0 &&
-        (d.path == STENCIL_PATH_AUTO || d.path == STENCIL_PATH_GATHER)) {
-      for (int32_t t = 2; t <= 12; ++t) {
+    // 3) time blocking (gather form; 3D: two steps) when the request leaves it open
+    if (st == STENCIL_OK && d.time_block == 0 && (d.path == STENCIL_PATH_AUTO || d.path == STENCIL_PATH_GATHER)) {
+      for (int32_t t = 2; t <= (d.ndim == 3 ? 2 : 12); ++t) {
         const Candidate c{STENCIL_PATH_GATHER, STENCIL_LINES_AUTO, 0, 0, t, 0, 0};
         if (!valid(d, c)) continue;
         consider(c);

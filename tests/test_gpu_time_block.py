@@ -118,3 +118,63 @@ def test_batch_rejects_time_blocked_plan():
     with pytest.raises(st.StencilError) as e:
         st.Batch([plan], [x], [y])
     assert e.value.status == st.EUNSUPPORTED
+
+
+# ------------------------------------------------------------------- 3D
+def _run3(a0, c, shape, bc, dtype, tb, steps):
+    torch = torch_cuda()
+    plan = st.Plan(a0.shape, 1, shape, c, boundary=bc, dtype=dtype, path=st.PATH_GATHER, time_block=tb)
+    assert plan.info["time_block"] == max(tb, 1)
+    x = torch.from_numpy(a0).cuda()
+    y = torch.empty_like(x)
+    res = plan.run_steps(x, y, steps)
+    torch.cuda.synchronize()
+    launches = -(-steps // max(tb, 1))
+    assert (res is x) == (launches % 2 == 0)
+    out = res.cpu().numpy()
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("dtype", [st.F32, st.F64])
+@pytest.mark.parametrize("shape", [st.BOX, st.STAR])
+@pytest.mark.parametrize("bc", [st.BC_ZERO, st.BC_PERIODIC])
+@pytest.mark.parametrize("dims", [(19, 35, 68), (8, 16, 64), (5, 3, 4), (1, 1, 4), (33, 17, 132), (9, 40, 32)])
+def test_time_block_3d_parity(dtype, shape, bc, dims):
+    """3D order-1 time blocks (two steps per launch): against the oracle, and
+    bit for bit against one step per launch (the same per-point tap order),
+    on runs with a last launch of two steps and of one."""
+    c = inputs.coefficients(3, 1, shape, seed=1500 + len(dims), dtype=np.float64)
+    ce = eff_coeffs(c, dtype)
+    a0 = inputs.grid(dims, seed=1501, dtype=np.float32 if dtype == st.F32 else np.float64)
+    for steps in (2, 5):
+        got = _run3(a0, c, shape, bc, dtype, 2, steps)
+        assert np.array_equal(got, _run3(a0, c, shape, bc, dtype, 1, steps))
+        want = oracle.run(a0, ce, 1, shape, bc, steps)
+        tol = error_bound(ce, 3, 1, shape, dtype, st.PATH_GATHER, steps, np.abs(a0).max())
+        err = np.abs(got.astype(np.float64) - want).max()
+        assert err <= tol, f"max err {err:.3e} > bound {tol:.3e}"
+
+
+@pytest.mark.parametrize("dtype", [st.F32, st.F64])
+def test_time_block_3d_integer_bit_exact(dtype):
+    for shape in (st.BOX, st.STAR):
+        c = inputs.int_coefficients(3, 1, shape, seed=1600)
+        a0 = inputs.int_grid((21, 37, 72), seed=1601, dtype=np.float32 if dtype == st.F32 else np.float64)
+        for bc in (st.BC_ZERO, st.BC_PERIODIC):
+            assert np.array_equal(_run3(a0, c, shape, bc, dtype, 2, 4).astype(np.float64),
+                                  oracle.run(a0, c, 1, shape, bc, 4))
+
+
+def test_time_block_3d_misaligned_buffer_rejected():
+    torch = torch_cuda()
+    c = inputs.coefficients(3, 1, st.STAR, seed=1700, dtype=np.float64)
+    plan = st.Plan((8, 8, 8), 1, st.STAR, c, path=st.PATH_GATHER, time_block=2)
+    base = torch.zeros(8 * 8 * 8 + 1, device="cuda")
+    x = base[1:].view(8, 8, 8)  # 4-byte offset
+    y = torch.zeros(8, 8, 8, device="cuda")
+    with pytest.raises(st.StencilError) as e:
+        plan.run_steps(x, y, 2)
+    assert e.value.status == st.EINVAL
+    torch.cuda.synchronize()
+    plan.close()

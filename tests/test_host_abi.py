@@ -139,8 +139,9 @@ def test_tuning_fields(lib):
 
 @pytest.mark.parametrize("r,f32max,f64max", [(1, 12, 8), (2, 6, 4), (3, 4, 2), (4, 3, 2)])
 def test_time_block_limits(lib, r, f32max, f64max):
-    """Time blocks: 2D gather form only; the halo r*T rounded up to 4 fits
-    the kernel's LDS window (12 for FP32, 8 for FP64)."""
+    """Time blocks: 2D gather form, the halo r*T rounded up to 4 within the
+    kernel's LDS window (12 for FP32, 8 for FP64); 3D: order 1 star and box,
+    two steps, last extent a multiple of 4."""
     c = _box(2, r)
     for dt, tmax in ((st.F32, f32max), (st.F64, f64max)):
         assert st.desc_check((100, 100), r, inputs.BOX, c, dtype=dt, time_block=tmax) == st.OK
@@ -148,7 +149,26 @@ def test_time_block_limits(lib, r, f32max, f64max):
         info = st.describe((100, 100), r, inputs.BOX, c, dtype=dt, time_block=tmax)
         assert info["time_block"] == tmax and info["path"] == st.PATH_GATHER
     assert st.desc_check((100, 100), r, inputs.BOX, c, path=st.PATH_MFMA, time_block=2) == st.EUNSUPPORTED
-    assert st.desc_check((20, 20, 20), r, inputs.BOX, _box(3, r), time_block=2) == st.EUNSUPPORTED
+    for dt in (st.F32, st.F64):
+        for shape, c3 in ((inputs.BOX, _box(3, r)), (inputs.STAR, inputs.coefficients(3, r, inputs.STAR, seed=1))):
+            want3 = st.OK if r == 1 else st.EUNSUPPORTED
+            assert st.desc_check((20, 20, 20), r, shape, c3, dtype=dt, time_block=2) == want3
+            assert st.desc_check((20, 20, 20), r, shape, c3, dtype=dt, time_block=3) == st.EUNSUPPORTED
+            assert st.desc_check((20, 20, 18), r, shape, c3, dtype=dt, time_block=2) == st.EUNSUPPORTED
+            assert st.desc_check((20, 20, 20), r, shape, c3, dtype=dt, path=st.PATH_MFMA, time_block=2) == st.EUNSUPPORTED
+            if r == 1:
+                info3 = st.describe((20, 20, 20), r, shape, c3, dtype=dt, time_block=2)
+                assert info3["time_block"] == 2 and info3["path"] == st.PATH_GATHER
+                # AUTO: two steps per launch on small grids only
+                assert st.describe((64, 64, 64), r, shape, c3, dtype=dt)["time_block"] == 2
+                assert st.describe((64, 64, 62), r, shape, c3, dtype=dt)["time_block"] == 1
+                small128 = dt == st.F32 and shape == inputs.STAR
+                assert st.describe((128, 128, 128), r, shape, c3, dtype=dt)["time_block"] == (2 if small128 else 1)
+                assert st.describe((256, 256, 256), r, shape, c3, dtype=dt)["time_block"] == 1
+                assert st.describe((64, 64, 64), r, shape, c3, dtype=dt, chunk=8)["time_block"] == 1
+        g3 = _box(3, r)
+        g3[0, 0, 0] = 0.0
+        assert st.desc_check((20, 20, 20), r, st.GENERAL, g3, dtype=dt, time_block=2) == st.EUNSUPPORTED
     assert st.describe((100, 100), r, inputs.BOX, c, time_block=1)["time_block"] == 1
 
 
