@@ -220,7 +220,8 @@ def workload_grid3d(args, torch, st, inputs) -> dict:
                 bpp = 8 if dt == st.F32 else 16
                 out["cases"][key][name] = {"gstencil_s": round(g, 2), "hbm_frac": round(g * bpp / HBM_PEAK_GBS, 4),
                                            "ms_per_solve": round(float(np.median(times)), 3),
-                                           "resolved_path": st.PATH_NAMES[plan.info["path"]]}
+                                           "resolved_path": st.PATH_NAMES[plan.info["path"]],
+                                           "time_block": plan.info["time_block"]}
                 print(f"[bench] {key} {name}: {g:.1f} GStencil/s", file=sys.stderr, flush=True)
                 plan.close()
         x0 = None
@@ -688,7 +689,7 @@ def workload_mixed(args, torch, st, inputs) -> dict:
             times = _time_solve(torch, plan, x0, nsteps, args.steps, args.warmup, stream)
             g = float(np.prod(dims)) * nsteps / (np.median(times) * 1e-3) / 1e9
             entry = {"gstencil_s": round(g, 2), "hbm_frac": round(g * 8 / HBM_PEAK_GBS, 4),
-                     "resolved_path": st.PATH_NAMES[plan.info["path"]]}
+                     "resolved_path": st.PATH_NAMES[plan.info["path"]], "time_block": plan.info["time_block"]}
             if name != "auto":
                 drift = _drift_run(torch, st, plan, shadow_plan, x0, sh, checks, 50, states)
                 entry["drift"] = drift

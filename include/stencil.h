@@ -405,6 +405,19 @@ stencil_status_t stencil_server_tick(stencil_server_t server, stencil_server_sta
  * receives the number written.  Non-blocking. */
 stencil_status_t stencil_server_poll(stencil_server_t server, int64_t* ids, int32_t capacity, int32_t* count);
 
+/* Withdraw request `id` (a caller's time-out, a client gone).  A request
+ * still queued leaves at once: the server never touched its buffers.  A
+ * resident one gets no further launch and its output buffer is never
+ * written; its arena block is free for later admissions (which are enqueued
+ * behind the work already on the server's stream), and that already
+ * enqueued work may still read its input until the server's stream passes
+ * this point (synchronise stencil_server_stream before reusing the input).
+ * A cancelled request is never reported by stencil_server_poll; the other
+ * requests' results are unchanged.  Errors: EINVAL (null server, an id that
+ * was never submitted, has finished -- its completion was enqueued -- or was
+ * cancelled already). */
+stencil_status_t stencil_server_cancel(stencil_server_t server, int64_t id);
+
 /* Wait for the server's stream and release everything (NULL accepted);
  * requests not yet finished are dropped. */
 stencil_status_t stencil_server_destroy(stencil_server_t server);

@@ -524,6 +524,32 @@ stencil_status_t stencil_server_tick(stencil_server_t s, stencil_server_stats_t*
   }
 }
 
+stencil_status_t stencil_server_cancel(stencil_server_t s, int64_t id) {
+  if (!s || id < 1) return STENCIL_EINVAL;
+  try {
+    // still queued: nothing of it reached the device
+    for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+      if ((*it)->id != id) continue;
+      delete *it;
+      s->queue.erase(it);
+      return STENCIL_OK;
+    }
+    // resident: no further launch or copy is enqueued for it; work already
+    // enqueued on the server's stream still reads its arena block, and any
+    // later use of the block (a new admission) is enqueued behind that work
+    for (auto it = s->active.begin(); it != s->active.end(); ++it) {
+      if ((*it)->id != id) continue;
+      s->arena.release((*it)->arena_off);
+      delete *it;
+      s->active.erase(it);
+      return STENCIL_OK;
+    }
+    return STENCIL_EINVAL;  // unknown, finished or already cancelled
+  } catch (...) {
+    return STENCIL_EINTERNAL;
+  }
+}
+
 stencil_status_t stencil_server_poll(stencil_server_t s, int64_t* ids, int32_t capacity, int32_t* count) {
   if (!s || !count || capacity < 0 || (capacity > 0 && !ids)) return STENCIL_EINVAL;
   try {

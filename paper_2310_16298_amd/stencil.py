@@ -73,7 +73,7 @@ EXPORTS = [
     "stencil_batch_create", "stencil_batch_run_steps", "stencil_batch_info", "stencil_batch_destroy",
     "stencil_autotune",
     "stencil_server_create", "stencil_server_stream", "stencil_server_submit", "stencil_server_tick",
-    "stencil_server_poll", "stencil_server_destroy", "stencil_run_steps_noalloc",
+    "stencil_server_poll", "stencil_server_destroy", "stencil_run_steps_noalloc", "stencil_server_cancel",
 ]
 
 
@@ -135,6 +135,7 @@ def load_library(path: str = LIB_PATH):
     lib.stencil_server_tick.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.stencil_server_poll.argtypes = [vp, ctypes.POINTER(i64), i32, ctypes.POINTER(i32)]
     lib.stencil_server_destroy.argtypes = [vp]
+    lib.stencil_server_cancel.argtypes = [vp, i64]
     lib.stencil_autotune.argtypes = [ctypes.POINTER(Desc), ctypes.c_char_p, i32, ctypes.POINTER(Desc),
                                      ctypes.POINTER(ctypes.c_double), vp, ctypes.POINTER(TuneResult), i32,
                                      ctypes.POINTER(i32)]
@@ -415,6 +416,7 @@ class Server:
         self._h = h
         self._lib = lib
         self._live = {}
+        self._cancelled = []  # tensors of cancelled requests, kept until close()
         sp = ctypes.c_void_p()
         _check(lib.stencil_server_stream(h, ctypes.byref(sp)), "stencil_server_stream")
         self.stream_handle = sp.value
@@ -444,6 +446,15 @@ class Server:
         _check(self._lib.stencil_server_tick(self._h, ctypes.byref(stats)), "stencil_server_tick")
         return {name: getattr(stats, name) for name, _ in ServerStats._fields_}
 
+    def cancel(self, rid: int):
+        """Withdraw a queued or resident request (``stencil_server_cancel``);
+        its tensors are released here once the server's stream has passed
+        the work already enqueued for it."""
+        _check(self._lib.stencil_server_cancel(self._h, int(rid)), "stencil_server_cancel")
+        entry = self._live.pop(rid, None)
+        if entry is not None:
+            self._cancelled.append(entry)
+
     def poll(self, capacity: int = 4096):
         ids = (ctypes.c_int64 * capacity)()
         cnt = ctypes.c_int32(0)
@@ -458,6 +469,7 @@ class Server:
             self._lib.stencil_server_destroy(self._h)
             self._h = ctypes.c_void_p()
             self._live.clear()
+            self._cancelled.clear()
 
     def __del__(self):
         try:

@@ -125,3 +125,54 @@ def test_server_rejects():
     d, keep = st.make_desc((64, 64), 1, st.BOX, c, time_block=2)
     assert srv._lib.stencil_server_submit(srv._h, d, x.data_ptr(), big.data_ptr(), 1, None) == st.EUNSUPPORTED
     srv.close()
+
+
+def test_server_cancel_isolates_the_rest():
+    """Requests withdrawn while queued or resident are never reported and
+    never write their outputs; every other request still equals its run
+    alone bit for bit, and the arena empties."""
+    torch = torch_cuda()
+    picks = [0, 2, 5, 7, 11, 12, 13, 14]  # mixed 2D / 3D, FP32 / FP64, short and long runs
+    data = {k: _inputs(k, SPECS[k]) for k in picks}
+    srv = st.Server(96 << 20, max_active=3)
+    ids, outs = {}, {}
+    for k in picks:
+        dims, r, shape, bc, dt, path, steps = SPECS[k]
+        c, a0 = data[k]
+        x = torch.from_numpy(a0).cuda()
+        out = torch.full_like(x, 7.0)  # sentinel: a cancelled request's output stays untouched
+        torch.cuda.synchronize()
+        ids[srv.submit(x, out, steps, r, shape, c, boundary=bc, path=path)] = k
+        outs[k] = out
+    rids = list(ids)
+    cancelled = {rids[7]}  # still queued behind max_active = 3
+    srv.cancel(rids[7])
+    srv.tick()
+    st_ = srv.tick()
+    assert st_["active"] >= 1
+    srv.cancel(rids[5])  # the 64^2 request of 137 steps: resident or queued by now
+    cancelled.add(rids[5])
+    with pytest.raises(st.StencilError) as e:
+        srv.cancel(rids[5])
+    assert e.value.status == st.EINVAL
+    with pytest.raises(st.StencilError) as e:
+        srv.cancel(10_000)
+    assert e.value.status == st.EINVAL
+    done, ticks = set(), 0
+    while len(done) < len(rids) - len(cancelled):
+        stats = srv.tick()
+        ticks += 1
+        for rid in srv.poll():
+            assert rid not in cancelled and rid not in done
+            done.add(rid)
+        assert ticks < 10000
+    torch.cuda.synchronize()
+    assert stats["arena_in_use"] == 0 and stats["active"] == 0 and stats["queued"] == 0
+    for rid, k in ids.items():
+        got = outs[k].cpu().numpy()
+        if rid in cancelled:
+            assert np.all(got == 7.0), f"cancelled request {k} wrote its output"
+        else:
+            c, a0 = data[k]
+            assert np.array_equal(got, _alone(torch, SPECS[k], c, a0)), f"request {k} {SPECS[k]}"
+    srv.close()

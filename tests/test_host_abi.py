@@ -119,6 +119,7 @@ def test_null_arguments(lib):
     assert lib.stencil_server_tick(None, None) == st.EINVAL
     cnt = ctypes.c_int32(0)
     assert lib.stencil_server_poll(None, None, 0, ctypes.byref(cnt)) == st.EINVAL
+    assert lib.stencil_server_cancel(None, 1) == st.EINVAL
     assert lib.stencil_server_destroy(None) == st.OK
 
 
