@@ -65,6 +65,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def hbm_frac(gstencil_s: float, bytes_per_point: int, time_block: int = 1) -> float:
+    """Algorithmic HBM bytes per second over the 8 TB/s peak: a launch reads and
+    writes the grid once and advances time_block steps."""
+    return round(gstencil_s * bytes_per_point / max(1, int(time_block)) / HBM_PEAK_GBS, 4)
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -218,7 +224,8 @@ def workload_grid3d(args, torch, st, inputs) -> dict:
                 times = _time_solve(torch, plan, x0, steps, args.steps, args.warmup, stream)
                 g = dims[0] * dims[1] * dims[2] * steps / (np.median(times) * 1e-3) / 1e9
                 bpp = 8 if dt == st.F32 else 16
-                out["cases"][key][name] = {"gstencil_s": round(g, 2), "hbm_frac": round(g * bpp / HBM_PEAK_GBS, 4),
+                out["cases"][key][name] = {"gstencil_s": round(g, 2),
+                                           "hbm_frac": hbm_frac(g, bpp, plan.info["time_block"]),
                                            "ms_per_solve": round(float(np.median(times)), 3),
                                            "resolved_path": st.PATH_NAMES[plan.info["path"]],
                                            "time_block": plan.info["time_block"]}
@@ -688,7 +695,7 @@ def workload_mixed(args, torch, st, inputs) -> dict:
             plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=st.F32, path=path)
             times = _time_solve(torch, plan, x0, nsteps, args.steps, args.warmup, stream)
             g = float(np.prod(dims)) * nsteps / (np.median(times) * 1e-3) / 1e9
-            entry = {"gstencil_s": round(g, 2), "hbm_frac": round(g * 8 / HBM_PEAK_GBS, 4),
+            entry = {"gstencil_s": round(g, 2), "hbm_frac": hbm_frac(g, 8, plan.info["time_block"]),
                      "resolved_path": st.PATH_NAMES[plan.info["path"]], "time_block": plan.info["time_block"]}
             if name != "auto":
                 drift = _drift_run(torch, st, plan, shadow_plan, x0, sh, checks, 50, states)
@@ -762,9 +769,10 @@ def config_extras(args, torch, st, inputs) -> dict:
             plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=dt)
             times = _time_solve(torch, plan, x0, steps, 3, 1, stream)
             g = float(np.prod(dims)) * steps / (np.median(times) * 1e-3) / 1e9
+            tb = plan.info["time_block"]
             g3[f"{tag}_{'box' if shape == st.BOX else 'star'}_r{r}"] = {
-                "path": st.PATH_NAMES[plan.info["path"]], "gstencil_s": round(g, 1),
-                "hbm_frac": round(g * bpp / HBM_PEAK_GBS, 4)}
+                "path": st.PATH_NAMES[plan.info["path"]], "time_block": tb, "gstencil_s": round(g, 1),
+                "hbm_frac": hbm_frac(g, bpp, tb)}
             plan.close()
         del x0
         torch.cuda.empty_cache()
@@ -786,12 +794,13 @@ def config_extras(args, torch, st, inputs) -> dict:
             plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=st.F32, path=path)
             times = _time_solve(torch, plan, x0, 200, 3, 1, stream)
             g = float(np.prod(dims)) * 200 / (np.median(times) * 1e-3) / 1e9
-            e = {"gstencil_s": round(g, 1), "hbm_frac": round(g * 8 / HBM_PEAK_GBS, 4)}
+            e = {"gstencil_s": round(g, 1), "hbm_frac": hbm_frac(g, 8, plan.info["time_block"])}
             if name.startswith("mfma_"):
                 d = _drift_run(torch, st, plan, shadow_plan, x0, sh, 1, 200)[-1]
                 e.update({"rel_l2_200": d["rel_l2"], "max_abs_200": d["max_abs"]})
             if name == "auto":
                 e["path"] = st.PATH_NAMES[plan.info["path"]]
+                e["time_block"] = plan.info["time_block"]
             mx[key][name] = e
             plan.close()
         shadow_plan.close()
@@ -980,7 +989,7 @@ def main() -> int:
     line["per_order"] = {name: {str(r): {"gstencil_s": round(v["gstencil_s"], 2), "p50_ms": round(v["p50_ms"], 3),
                                          "p99_ms": round(v["p99_ms"], 3), "path": v["resolved_path"],
                                          "time_block": v["info"]["time_block"],
-                                         "hbm_frac": round(v["gstencil_s"] * 8 / HBM_PEAK_GBS, 4)}
+                                         "hbm_frac": hbm_frac(v["gstencil_s"], 8, v["info"]["time_block"])}
                                  for r, v in res.items()} for name, res in results.items()}
     if "gather" in results:
         line["vs_gather"] = {name: {str(r): round(res[r]["gstencil_s"] / results["gather"][r]["gstencil_s"], 3)

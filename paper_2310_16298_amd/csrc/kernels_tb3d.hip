@@ -1,4 +1,7 @@
-// Instantiations of the time-blocked 3D gather kernel (r = 1, two steps).
+// Instantiations of the time-blocked 3D gather kernels (two steps per launch):
+// the streaming form for FP32 stars of order 1 and 2 and the 27-point box on
+// planes of at least 32 (j, k) tiles, the whole-window form for order 1
+// otherwise (FP64 always).
 #include <type_traits>
 
 #include "kernels_tb3d.hpp"
@@ -6,21 +9,36 @@
 
 namespace stencil {
 
-template <typename T, bool BOX>
+template <typename T, int R, bool BOX>
 static Kernel pick_tb3d(KArgs& a, int32_t chunk) {
   const int dtype = std::is_same<T, double>::value ? STENCIL_F64 : STENCIL_F32;
   // a launch of one step (the remainder of a run): the one-step gather
-  if (a.steps <= 1) return find_gather3d(dtype, 1, BOX)(a, chunk);
+  if (a.steps <= 1) return find_gather3d(dtype, R, BOX)(a, chunk);
   if (!tb3d_ok(a) || a.steps != 2) return Kernel{};
-  int64_t ti, tj, tk;
-  tb3d_tiles<T, 1, 2>(a.d0, a.d1, a.d2, &ti, &tj, &tk);
-  return kernel_of<tb3d_dma_kernel<T, 1, BOX, 2>, tb3d_dma_batch<T, 1, BOX, 2>>(ti * tj * tk);
+  if constexpr (std::is_same<T, float>::value) {
+    // the streaming form wants planes of at least 32 (j, k) tiles: fewer
+    // leave its chunks too shallow for their 4r warm-up planes (measured on
+    // MI355X: 128^3 and 64^3 lose to the whole-window form at order 1)
+    if (R == 2 || tb3d_plane_tiles(a) >= 32)
+      return kernel3d<tb3d_stream_kernel<T, R, BOX>, tb3d_stream_batch<T, R, BOX>>(a, R, chunk);
+  }
+  if constexpr (R == 1) {
+    int64_t ti, tj, tk;
+    tb3d_tiles<T, R, 2>(a.d0, a.d1, a.d2, &ti, &tj, &tk);
+    return kernel_of<tb3d_dma_kernel<T, R, BOX, 2>, tb3d_dma_batch<T, R, BOX, 2>>(ti * tj * tk);
+  }
+  return Kernel{};
+}
+
+bool tb3d_built(int dtype, int R, bool box) {
+  return R == 1 || (dtype == STENCIL_F32 && R == 2 && !box);
 }
 
 Picker find_tb3d(int dtype, int R, bool box) {
-  if (R != 1) return nullptr;
-  if (dtype == STENCIL_F64) return box ? pick_tb3d<double, true> : pick_tb3d<double, false>;
-  return box ? pick_tb3d<float, true> : pick_tb3d<float, false>;
+  if (!tb3d_built(dtype, R, box)) return nullptr;
+  if (dtype == STENCIL_F64) return box ? pick_tb3d<double, 1, true> : pick_tb3d<double, 1, false>;
+  if (R == 2) return pick_tb3d<float, 2, false>;
+  return box ? pick_tb3d<float, 1, true> : pick_tb3d<float, 1, false>;
 }
 
 }  // namespace stencil

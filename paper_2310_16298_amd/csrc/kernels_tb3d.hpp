@@ -27,6 +27,7 @@
 #include <type_traits>
 
 #include "device_common.hpp"
+#include "kernels_3d.hpp"
 #include "launch.hpp"
 
 namespace stencil {
@@ -61,6 +62,11 @@ template <> struct Tb3Vec<double> { typedef double __attribute__((ext_vector_typ
 inline bool tb3d_ok(const KArgs& a) {
   return a.d2 % 4 == 0 && (reinterpret_cast<uintptr_t>(a.in) & 15) == 0 &&
          (reinterpret_cast<uintptr_t>(a.out) & 15) == 0 && a.zeros != nullptr;
+}
+
+// (j, k) tiles of a plane in the one-step 3D decomposition (kTJ x kTK).
+inline int64_t tb3d_plane_tiles(const KArgs& a) {
+  return ((a.d1 + kTJ - 1) / kTJ) * ((a.d2 + kTK - 1) / kTK);
 }
 
 // Tiles of a launch along i, j, k.
@@ -276,6 +282,264 @@ __global__ __launch_bounds__(256) void tb3d_dma_kernel(KArgs a) {
 template <typename T, int R, bool BOX, int TS>
 __global__ __launch_bounds__(256) void tb3d_dma_batch(BatchArgs b) {
   for_each_batch_item(b, [&](const KArgs& x, int id) { tb3d_dma_item<T, R, BOX, TS>(x, id); });
+}
+
+
+// ---------------------------------------------------------------------------
+// Streaming form (two steps): the work item of the one-step 3D kernels -- a
+// kTJ x kTK tile of the (j, k) plane and a chunk of output planes -- with a
+// plane ring per time level.  The walk reads input planes ib - 2r ..
+// iend + 2r - 1 once each: the window of a plane (rows j0 - 2r .., columns
+// k0 - 4 .. k0 + kTK + 3) is copied straight into LDS (double-buffered) and
+// scattered into a ring of 2r+1 level-1 planes in registers covering the
+// tile plus an r halo (rows j0 - r .., columns k0 - 4 .. k0 + kTK + 3).  When
+// level-1 plane p is complete it goes to an LDS plane (zero outside a
+// zero-halo grid) and is scattered into the ring of level-2 planes (the
+// tile), whose complete plane p - r is stored.  Only the r-row and 4-column
+// halos of the (j, k) window are read twice; along i nothing is, apart from
+// the 4r planes at the ends of a chunk.  Both levels sum their taps in the
+// order of the one-step kernel (its ring scatter), so the result equals two
+// one-step launches bit for bit.  Built for FP32 stars of order 1 and 2 and
+// the 27-point box.
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool BOX>
+struct Tb3Stream {
+  static constexpr int W = 2 * R + 1, VEC = 16 / (int)sizeof(T);
+  static constexpr int ROWS0 = kTJ + 4 * R;                     // input window rows: global j0 - 2r ..
+  typedef DmaPlane<T, 2 * R, ROWS0, kTK, 256> D;                // columns k0 - 4 .. k0 + kTK + 3
+  static constexpr int P0 = D::PITCH;
+  static constexpr int PAD = 4;                                 // elements before the window (16 bytes)
+  // a 12-wide read of the first column block starts 4 elements before a row,
+  // one of the last ends 4 past it
+  static constexpr int BUF0 = round_up(PAD + cmax(D::BUF, ROWS0 * P0) + 4, 4);
+  static constexpr int ROWS1 = kTJ + 2 * R;                     // level-1 rows: global j0 - r ..
+  static constexpr int SEG1 = (kTK + 8) / 4;                    // level-1 column blocks: k0 - 4 ..
+  static constexpr int P1 = kTK + 16;                           // level-1 row: global columns k0 - 8 ..
+  static constexpr int BUF1 = ROWS1 * P1;
+  static constexpr int NBLK1 = ROWS1 / 2 * SEG1;
+  static constexpr int NB1 = (NBLK1 + 255) / 256;               // level-1 blocks per thread
+  static_assert(kTJ / 2 * (kTK / 4) == 256, "one level-2 block per thread");
+  static_assert(2 * R <= 4, "halo within the window's 4 columns");
+};
+
+template <typename T, int R, bool BOX>
+__device__ __forceinline__ void tb3d_stream_item(const KArgs& a, int item) {
+  typedef Tb3Stream<T, R, BOX> S;
+  typedef typename S::D D;
+  typedef typename Tb3Vec<T>::type V;
+  constexpr int W = S::W, VEC = S::VEC;
+  __shared__ __attribute__((aligned(16))) T lds[2 * S::BUF0 + S::BUF1];
+
+  const Chunk3D ch = decode_chunk(a, item);
+  const int64_t Ni = a.d0, Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
+  const bool periodic = a.periodic != 0;
+  const T* __restrict__ in = (const T*)a.in;
+  const T* __restrict__ zeros = (const T*)a.zeros;
+  T* __restrict__ out = (T*)a.out;
+  const ConstPtr<T> c = (ConstPtr<T>)a.coef;  // 27 weights at most: scalar loads
+  const int tid = threadIdx.x;
+  T* const l1 = lds + 2 * S::BUF0;
+
+  // pads and the level-1 plane start at zero (cells no DMA line writes)
+  for (int e = tid; e < 2 * S::BUF0 + S::BUF1; e += 256) lds[e] = T(0);
+  __syncthreads();
+
+  // ring1[n]: the level-1 ring of this thread's block n; ring2: its level-2 block
+  T ring1[S::NB1][W][2][4], ring2[W][2][4];
+#pragma unroll
+  for (int z = 0; z < W; ++z) {
+#pragma unroll
+    for (int n = 0; n < S::NB1; ++n)
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ring1[n][z][p][e] = T(0);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ring2[z][p][e] = T(0);
+  }
+
+  // 12 values from LDS (whole 16-byte vectors; `lo_e .. hi_e`: the ones used,
+  // a partly used vector kept whole so the compiler does not narrow it)
+  auto read12 = [&](const T* src, int lo_e, int hi_e, T v[12]) {
+    const V* rp = reinterpret_cast<const V*>(src);
+#pragma unroll
+    for (int q = 0; q < 12 / VEC; ++q) {
+      if (VEC * q + VEC - 1 < lo_e || VEC * q > hi_e) continue;
+      V t4 = rp[q];
+      if (VEC * q < lo_e || VEC * q + VEC - 1 > hi_e) asm volatile("" : "+v"(t4));
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) v[VEC * q + e] = t4[e];
+    }
+  };
+  // Scatter one plane from LDS into a ring (the one-step kernel's order):
+  // `src` = LDS row of the block's first row minus r, at the first of 12
+  // columns (the block's columns are 4 .. 7 of them).
+  auto scatter = [&](const T* src, int pitch, T ring[W][2][4]) {
+    if constexpr (BOX) {
+#pragma unroll
+      for (int x = 0; x < 2 + 2 * R; ++x) {
+        T v[12];
+        read12(src + x * pitch, 4 - R, 7 + R, v);
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const int bb = x - p;
+          if (bb < 0 || bb > 2 * R) continue;
+#pragma unroll
+          for (int ap = 0; ap < W; ++ap)
+#pragma unroll
+            for (int cc = 0; cc < W; ++cc) {
+              const T wgt = c[(ap * W + bb) * W + cc];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) ring[2 * R - ap][p][e] += wgt * v[4 - R + e + cc];
+            }
+        }
+      }
+    } else {
+      // j arm (centre included) into the centre plane's slot r
+#pragma unroll
+      for (int x = 0; x < 2 + 2 * R; ++x) {
+        T v[12];
+        read12(src + x * pitch, 4, 7, v);
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const int bb = x - p;
+          if (bb < 0 || bb > 2 * R) continue;
+          const T wgt = c[(R * W + bb) * W + R];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) ring[R][p][e] += wgt * v[4 + e];
+        }
+      }
+      // k arm (centre excluded) and i arm from the block's own rows
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        T v[12];
+        read12(src + (p + R) * pitch, 4 - R, 7 + R, v);
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) {
+          if (cc == R) continue;
+          const T wgt = c[(R * W + R) * W + cc];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) ring[R][p][e] += wgt * v[4 - R + e + cc];
+        }
+#pragma unroll
+        for (int ap = 0; ap < W; ++ap) {
+          if (ap == R) continue;
+          const T wgt = c[(ap * W + R) * W + R];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) ring[2 * R - ap][p][e] += wgt * v[4 + e];
+        }
+      }
+    }
+  };
+  auto shift = [&](T ring[W][2][4]) {
+#pragma unroll
+    for (int z = 0; z < 2 * R; ++z)
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ring[z][p][e] = ring[z + 1][p][e];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ring[2 * R][p][e] = T(0);
+  };
+
+  typename D::Lines lines;
+  D::prepare(lines, Nj, Nk, ch.j0 - 2 * R, ch.k0, periodic);
+  const int nu = (int)(ch.iend - ch.ib) + 4 * R;
+  {
+    const int64_t g0 = map_index(ch.ib - 2 * R, Ni, periodic);
+    D::issue(lds + S::PAD, g0 >= 0 ? in + g0 * plane : nullptr, zeros, lines);
+  }
+  const int rp2 = tid >> 4, q2 = tid & 15;  // level-2 block: rows j0 + 2 rp2 .., columns k0 + 4 q2 ..
+  for (int u = 0; u < nu; ++u) {
+    T* const win = lds + (u & 1) * S::BUF0 + S::PAD;
+    if (u + 1 < nu) {
+      const int64_t g1 = map_index(ch.ib - 2 * R + u + 1, Ni, periodic);
+      D::issue(lds + ((u + 1) & 1) * S::BUF0 + S::PAD, g1 >= 0 ? in + g1 * plane : nullptr, zeros, lines);
+      D::template wait_vm<D::NPW>();
+    } else {
+      D::template wait_vm<0>();
+    }
+    lds_barrier();  // window u in LDS; the level-2 reads of the last level-1 plane are done
+    // level 1: block (rp, s) = rows j0 - r + 2 rp .., columns k0 - 4 + 4 s ..
+#pragma unroll
+    for (int n = 0; n < S::NB1; ++n) {
+      const int b = tid + 256 * n;
+      if (b >= S::NBLK1) break;
+      const int rp = b / S::SEG1, s = b - (b / S::SEG1) * S::SEG1;
+      scatter(win + 2 * rp * S::P0 + 4 * s - 4, S::P0, ring1[n]);
+    }
+    // level-1 plane ib - 3r + u is complete once its 2r+1 input planes were walked
+    const int64_t p1 = ch.ib - 3 * R + u;
+    const bool have1 = u >= 2 * R;
+    if (have1) {
+      const int64_t gp1 = p1;
+      const bool plane_in = periodic || (gp1 >= 0 && gp1 < Ni);
+#pragma unroll
+      for (int n = 0; n < S::NB1; ++n) {
+        const int b = tid + 256 * n;
+        if (b >= S::NBLK1) break;
+        const int rp = b / S::SEG1, s = b - (b / S::SEG1) * S::SEG1;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          T val[4];
+          const int64_t gj = ch.j0 - R + 2 * rp + p;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t gk = ch.k0 - 4 + 4 * s + e;
+            const bool inside = periodic || (plane_in && gj >= 0 && gj < Nj && gk >= 0 && gk < Nk);
+            val[e] = inside ? ring1[n][0][p][e] : T(0);
+          }
+          V* dv = reinterpret_cast<V*>(l1 + (2 * rp + p) * S::P1 + 4 + 4 * s);
+#pragma unroll
+          for (int m = 0; m < 4 / VEC; ++m) {
+            V t4;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) t4[e] = val[VEC * m + e];
+            dv[m] = t4;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < S::NB1; ++n) shift(ring1[n]);
+    lds_barrier();  // level-1 plane p1 visible
+    if (have1) {
+      scatter(l1 + 2 * rp2 * S::P1 + 4 + 4 * q2, S::P1, ring2);
+      // level-2 plane p1 - r = ib + u - 4r is complete
+      if (u >= 4 * R) {
+        const int64_t o = ch.ib + u - 4 * R;
+        const int64_t gk = ch.k0 + 4 * q2;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const int64_t gj = ch.j0 + 2 * rp2 + p;
+          if (gj >= Nj || gk >= Nk) continue;  // Nk % 4 == 0: a 4-column block lies inside the row
+          V* dst = reinterpret_cast<V*>(out + o * plane + gj * Nk + gk);
+#pragma unroll
+          for (int m = 0; m < 4 / VEC; ++m) {
+            V t4;
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) t4[e] = ring2[0][p][VEC * m + e];
+            dst[m] = t4;
+          }
+        }
+      }
+      shift(ring2);
+    }
+  }
+}
+
+template <typename T, int R, bool BOX>
+__global__ __launch_bounds__(256) void tb3d_stream_kernel(KArgs a) {
+  tb3d_stream_item<T, R, BOX>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int R, bool BOX>
+__global__ __launch_bounds__(256) void tb3d_stream_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int id) { tb3d_stream_item<T, R, BOX>(x, id); });
 }
 
 }  // namespace stencil

@@ -169,8 +169,10 @@ static int validate(const stencil_desc_t* d) {
   if (d->time_block > 1) {
     if (d->path != STENCIL_PATH_AUTO && d->path != STENCIL_PATH_GATHER) return STENCIL_EUNSUPPORTED;
     if (d->ndim == 3) {
-      // 3D: the 7-point star and the 27-point box, two steps, direct-to-LDS lines
-      if (d->radius != 1 || d->shape == STENCIL_GENERAL || d->time_block > 2 || d->dims[2] % 4 != 0)
+      // 3D: two steps, direct-to-LDS lines; FP32 stars of order 1 and 2 and the
+      // 27-point box, FP64 order 1
+      if (d->shape == STENCIL_GENERAL || !tb3d_built(d->dtype, d->radius, d->shape == STENCIL_BOX) ||
+          d->time_block > 2 || d->dims[2] % 4 != 0)
         return STENCIL_EUNSUPPORTED;
     } else if (d->time_block > tb2d_max_steps(d->dtype, d->radius)) {
       return STENCIL_EUNSUPPORTED;
@@ -437,15 +439,20 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       static const int kSparse3DAuto[5] = {0, 0, 0, 88, 128};
       const bool few = general && in.taps <= kSparse3DAuto[R];
       path = (f32 && box && R >= 3 && !few) || (!f32 && !box && R == 4) ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
-      // Time blocking: the 7-point star and the 27-point box, two steps per
-      // launch, on k extents that take direct-to-LDS lines, when every knob
-      // is left open, on grids small enough for the halved launch count to
-      // pay (measured on MI355X, zero halo: at 64^3 and below 1.14-1.6x the
-      // one-step gather, FP32 star 1.2x at 128^3; from 256^3 on the window's
-      // halo work and re-reads make it tie or lose)
+      // Time blocking, two steps per launch, on k extents that take
+      // direct-to-LDS lines, when every knob is left open; measured on MI355X
+      // (zero halo) against the one-step gather: the whole-window form on
+      // small grids (order 1 at 64^3 and below: 1.14-1.6x; FP32 stars 1.2x
+      // at 128^3), the FP32 streaming form on planes of many (j, k) tiles
+      // (7-point star from 32 tiles: 1.15x at 256^3, 1.45x at 384^3, 1.49x at
+      // 512^3; order-2 star from 64: 1.22x at 384^3, 1.15x at 512^3, losing at
+      // 256^3; 27-point box from 96: 1.07x at 512^3, level at 384^3)
       const int64_t pts3 = d.dims[0] * d.dims[1] * d.dims[2];
-      const bool small3 = pts3 <= (int64_t(1) << 18) || (f32 && !box && pts3 <= (int64_t(1) << 21));
-      if (small3 && R == 1 && !general && d.dims[2] % 4 == 0 && d.time_block == 0 &&
+      const int64_t tiles3 = ceil_div(d.dims[1], kTJ) * ceil_div(d.dims[2], kTK);
+      const bool small3 = R == 1 && (pts3 <= (int64_t(1) << 18) || (f32 && !box && pts3 <= (int64_t(1) << 21)));
+      const int64_t stream_tiles = !box ? (R == 1 ? 32 : R == 2 ? 64 : 0) : (R == 1 ? 96 : 0);
+      const bool stream3 = f32 && stream_tiles > 0 && tiles3 >= stream_tiles;
+      if ((small3 || stream3) && !general && d.dims[2] % 4 == 0 && d.time_block == 0 &&
           d.lines == STENCIL_LINES_AUTO && d.block_n == 0 && d.chunk == 0) {
         path = STENCIL_PATH_GATHER;
         tb_auto = 2;

@@ -121,9 +121,9 @@ def test_batch_rejects_time_blocked_plan():
 
 
 # ------------------------------------------------------------------- 3D
-def _run3(a0, c, shape, bc, dtype, tb, steps):
+def _run3(a0, c, shape, bc, dtype, tb, steps, r=1):
     torch = torch_cuda()
-    plan = st.Plan(a0.shape, 1, shape, c, boundary=bc, dtype=dtype, path=st.PATH_GATHER, time_block=tb)
+    plan = st.Plan(a0.shape, r, shape, c, boundary=bc, dtype=dtype, path=st.PATH_GATHER, time_block=tb)
     assert plan.info["time_block"] == max(tb, 1)
     x = torch.from_numpy(a0).cuda()
     y = torch.empty_like(x)
@@ -136,34 +136,39 @@ def _run3(a0, c, shape, bc, dtype, tb, steps):
     return out
 
 
-@pytest.mark.parametrize("dtype", [st.F32, st.F64])
-@pytest.mark.parametrize("shape", [st.BOX, st.STAR])
+TB3 = [(st.F32, st.STAR, 1), (st.F32, st.BOX, 1), (st.F32, st.STAR, 2), (st.F64, st.STAR, 1), (st.F64, st.BOX, 1)]
+
+
+@pytest.mark.parametrize("dtype,shape,r", TB3)
 @pytest.mark.parametrize("bc", [st.BC_ZERO, st.BC_PERIODIC])
-@pytest.mark.parametrize("dims", [(19, 35, 68), (8, 16, 64), (5, 3, 4), (1, 1, 4), (33, 17, 132), (9, 40, 32)])
-def test_time_block_3d_parity(dtype, shape, bc, dims):
-    """3D order-1 time blocks (two steps per launch): against the oracle, and
-    bit for bit against one step per launch (the same per-point tap order),
-    on runs with a last launch of two steps and of one."""
-    c = inputs.coefficients(3, 1, shape, seed=1500 + len(dims), dtype=np.float64)
+@pytest.mark.parametrize("dims", [(19, 35, 68), (8, 16, 64), (5, 3, 4), (1, 1, 4), (33, 17, 132), (9, 40, 32),
+                                  (70, 66, 136), (9, 256, 260), (40, 130, 512)])
+def test_time_block_3d_parity(dtype, shape, r, bc, dims):
+    """3D time blocks (two steps per launch; FP32 streaming plane rings on
+    planes of 32 or more (j, k) tiles -- the last two extents here -- and at
+    order 2, whole windows otherwise): against the oracle, and bit for bit
+    against one step per launch (the same per-point tap order), on runs with
+    a last launch of two steps and of one, over several tiles and chunks with
+    ragged tails."""
+    c = inputs.coefficients(3, r, shape, seed=1500 + len(dims) + r, dtype=np.float64)
     ce = eff_coeffs(c, dtype)
     a0 = inputs.grid(dims, seed=1501, dtype=np.float32 if dtype == st.F32 else np.float64)
     for steps in (2, 5):
-        got = _run3(a0, c, shape, bc, dtype, 2, steps)
-        assert np.array_equal(got, _run3(a0, c, shape, bc, dtype, 1, steps))
-        want = oracle.run(a0, ce, 1, shape, bc, steps)
-        tol = error_bound(ce, 3, 1, shape, dtype, st.PATH_GATHER, steps, np.abs(a0).max())
+        got = _run3(a0, c, shape, bc, dtype, 2, steps, r)
+        assert np.array_equal(got, _run3(a0, c, shape, bc, dtype, 1, steps, r))
+        want = oracle.run(a0, ce, r, shape, bc, steps)
+        tol = error_bound(ce, 3, r, shape, dtype, st.PATH_GATHER, steps, np.abs(a0).max())
         err = np.abs(got.astype(np.float64) - want).max()
         assert err <= tol, f"max err {err:.3e} > bound {tol:.3e}"
 
 
-@pytest.mark.parametrize("dtype", [st.F32, st.F64])
-def test_time_block_3d_integer_bit_exact(dtype):
-    for shape in (st.BOX, st.STAR):
-        c = inputs.int_coefficients(3, 1, shape, seed=1600)
-        a0 = inputs.int_grid((21, 37, 72), seed=1601, dtype=np.float32 if dtype == st.F32 else np.float64)
-        for bc in (st.BC_ZERO, st.BC_PERIODIC):
-            assert np.array_equal(_run3(a0, c, shape, bc, dtype, 2, 4).astype(np.float64),
-                                  oracle.run(a0, c, 1, shape, bc, 4))
+@pytest.mark.parametrize("dtype,shape,r", TB3)
+def test_time_block_3d_integer_bit_exact(dtype, shape, r):
+    c = inputs.int_coefficients(3, r, shape, seed=1600 + r)
+    a0 = inputs.int_grid((21, 37, 72), seed=1601, dtype=np.float32 if dtype == st.F32 else np.float64)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        assert np.array_equal(_run3(a0, c, shape, bc, dtype, 2, 4, r).astype(np.float64),
+                              oracle.run(a0, c, r, shape, bc, 4))
 
 
 def test_time_block_3d_misaligned_buffer_rejected():

@@ -152,21 +152,28 @@ def test_time_block_limits(lib, r, f32max, f64max):
     assert st.desc_check((100, 100), r, inputs.BOX, c, path=st.PATH_MFMA, time_block=2) == st.EUNSUPPORTED
     for dt in (st.F32, st.F64):
         for shape, c3 in ((inputs.BOX, _box(3, r)), (inputs.STAR, inputs.coefficients(3, r, inputs.STAR, seed=1))):
-            want3 = st.OK if r == 1 else st.EUNSUPPORTED
+            built3 = r == 1 or (r == 2 and dt == st.F32 and shape == inputs.STAR)
+            want3 = st.OK if built3 else st.EUNSUPPORTED
             assert st.desc_check((20, 20, 20), r, shape, c3, dtype=dt, time_block=2) == want3
             assert st.desc_check((20, 20, 20), r, shape, c3, dtype=dt, time_block=3) == st.EUNSUPPORTED
             assert st.desc_check((20, 20, 18), r, shape, c3, dtype=dt, time_block=2) == st.EUNSUPPORTED
             assert st.desc_check((20, 20, 20), r, shape, c3, dtype=dt, path=st.PATH_MFMA, time_block=2) == st.EUNSUPPORTED
-            if r == 1:
+            if built3:
                 info3 = st.describe((20, 20, 20), r, shape, c3, dtype=dt, time_block=2)
                 assert info3["time_block"] == 2 and info3["path"] == st.PATH_GATHER
-                # AUTO: two steps per launch on small grids only
-                assert st.describe((64, 64, 64), r, shape, c3, dtype=dt)["time_block"] == 2
-                assert st.describe((64, 64, 62), r, shape, c3, dtype=dt)["time_block"] == 1
-                small128 = dt == st.F32 and shape == inputs.STAR
-                assert st.describe((128, 128, 128), r, shape, c3, dtype=dt)["time_block"] == (2 if small128 else 1)
-                assert st.describe((256, 256, 256), r, shape, c3, dtype=dt)["time_block"] == 1
-                assert st.describe((64, 64, 64), r, shape, c3, dtype=dt, chunk=8)["time_block"] == 1
+            # AUTO: two steps per launch on small grids (order 1) and, FP32, on
+            # planes of many (j, k) tiles (32 x 64 each)
+            f32star1 = dt == st.F32 and shape == inputs.STAR and r == 1
+            f32star2 = dt == st.F32 and shape == inputs.STAR and r == 2
+            stream96 = dt == st.F32 and (r == 1 or f32star2)
+            assert st.describe((64, 64, 64), r, shape, c3, dtype=dt)["time_block"] == (2 if r == 1 else 1)
+            assert st.describe((64, 64, 62), r, shape, c3, dtype=dt)["time_block"] == 1
+            assert st.describe((128, 128, 128), r, shape, c3, dtype=dt)["time_block"] == (2 if f32star1 else 1)
+            assert st.describe((256, 256, 256), r, shape, c3, dtype=dt)["time_block"] == (2 if f32star1 else 1)
+            assert st.describe((8, 512, 384), r, shape, c3, dtype=dt)["time_block"] == (2 if stream96 else 1)
+            assert st.describe((8, 512, 320), r, shape, c3, dtype=dt)["time_block"] == (2 if f32star1 or f32star2 else 1)
+            assert st.describe((8, 384, 320), r, shape, c3, dtype=dt)["time_block"] == (2 if f32star1 else 1)
+            assert st.describe((64, 64, 64), r, shape, c3, dtype=dt, chunk=8)["time_block"] == 1
         g3 = _box(3, r)
         g3[0, 0, 0] = 0.0
         assert st.desc_check((20, 20, 20), r, st.GENERAL, g3, dtype=dt, time_block=2) == st.EUNSUPPORTED
