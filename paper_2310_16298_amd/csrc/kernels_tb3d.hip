@@ -1,7 +1,7 @@
 // Instantiations of the time-blocked 3D gather kernels (two steps per launch):
-// the streaming form for FP32 stars of order 1 and 2 and the 27-point box on
-// planes of at least 32 (j, k) tiles, the whole-window form for order 1
-// otherwise (FP64 always).
+// the streaming form for stars of order 1 (FP32 also 2) and the 27-point box
+// on planes of at least 32 (j, k) tiles, the whole-window form for order 1
+// otherwise.
 #include <type_traits>
 
 #include "kernels_tb3d.hpp"
@@ -15,13 +15,11 @@ static Kernel pick_tb3d(KArgs& a, int32_t chunk) {
   // a launch of one step (the remainder of a run): the one-step gather
   if (a.steps <= 1) return find_gather3d(dtype, R, BOX)(a, chunk);
   if (!tb3d_ok(a) || a.steps != 2) return Kernel{};
-  if constexpr (std::is_same<T, float>::value) {
-    // the streaming form wants planes of at least 32 (j, k) tiles: fewer
-    // leave its chunks too shallow for their 4r warm-up planes (measured on
-    // MI355X: 128^3 and 64^3 lose to the whole-window form at order 1)
-    if (R == 2 || tb3d_plane_tiles(a) >= 32)
-      return kernel3d<tb3d_stream_kernel<T, R, BOX>, tb3d_stream_batch<T, R, BOX>>(a, R, chunk);
-  }
+  // the streaming form wants planes of at least 32 (j, k) tiles: fewer
+  // leave its chunks too shallow for their 4r warm-up planes (measured on
+  // MI355X: 128^3 and 64^3 lose to the whole-window form at order 1)
+  if (R == 2 || tb3d_plane_tiles(a) >= 32)
+    return kernel3d<tb3d_stream_kernel<T, R, BOX>, tb3d_stream_batch<T, R, BOX>>(a, R, chunk);
   if constexpr (R == 1) {
     int64_t ti, tj, tk;
     tb3d_tiles<T, R, 2>(a.d0, a.d1, a.d2, &ti, &tj, &tk);

@@ -165,14 +165,16 @@ def test_time_block_limits(lib, r, f32max, f64max):
             # planes of many (j, k) tiles (32 x 64 each)
             f32star1 = dt == st.F32 and shape == inputs.STAR and r == 1
             f32star2 = dt == st.F32 and shape == inputs.STAR and r == 2
-            stream96 = dt == st.F32 and (r == 1 or f32star2)
+            star1 = shape == inputs.STAR and r == 1
+            stream96 = r == 1 or f32star2
+            stream64 = star1 or f32star2 or (dt == st.F64 and r == 1)
             assert st.describe((64, 64, 64), r, shape, c3, dtype=dt)["time_block"] == (2 if r == 1 else 1)
             assert st.describe((64, 64, 62), r, shape, c3, dtype=dt)["time_block"] == 1
             assert st.describe((128, 128, 128), r, shape, c3, dtype=dt)["time_block"] == (2 if f32star1 else 1)
-            assert st.describe((256, 256, 256), r, shape, c3, dtype=dt)["time_block"] == (2 if f32star1 else 1)
+            assert st.describe((256, 256, 256), r, shape, c3, dtype=dt)["time_block"] == (2 if star1 else 1)
             assert st.describe((8, 512, 384), r, shape, c3, dtype=dt)["time_block"] == (2 if stream96 else 1)
-            assert st.describe((8, 512, 320), r, shape, c3, dtype=dt)["time_block"] == (2 if f32star1 or f32star2 else 1)
-            assert st.describe((8, 384, 320), r, shape, c3, dtype=dt)["time_block"] == (2 if f32star1 else 1)
+            assert st.describe((8, 512, 320), r, shape, c3, dtype=dt)["time_block"] == (2 if stream64 else 1)
+            assert st.describe((8, 384, 320), r, shape, c3, dtype=dt)["time_block"] == (2 if star1 else 1)
             assert st.describe((64, 64, 64), r, shape, c3, dtype=dt, chunk=8)["time_block"] == 1
         g3 = _box(3, r)
         g3[0, 0, 0] = 0.0
