@@ -319,7 +319,8 @@ def workload_batch(args, torch, st, inputs) -> dict:
 
 
 def workload_tune(args, torch, st, inputs) -> dict:
-    """The autotuner over line option x MFMA block x chunk, per radius: 2D
+    """The autotuner over line option x MFMA block x register/workgroup tile x
+    time block x chunk, per radius: 2D
     box/star r = 1..4 at 8192^2 FP32 (periodic), 3D star r = 1..4 and the
     27-point box at 512^3 FP32 (zero halo), 2D box/star r = 1..3 at 512^2 FP64
     (zero halo): every measured candidate and the winner."""
@@ -338,14 +339,41 @@ def workload_tune(args, torch, st, inputs) -> dict:
         out["cases"][key] = {
             "winner": {"path": st.PATH_NAMES[knobs["path"]], "lines": names[knobs["lines"]],
                        "block_n": knobs["block_n"], "chunk": knobs["chunk"], "time_block": knobs["time_block"],
+                       "reg_rows": knobs["reg_rows"], "tile_width": knobs["tile_width"],
                        "ms_per_step": round(ms, 5), "gstencil_s": round(pts / (ms * 1e-3) / 1e9, 2)},
             "candidates": [{"path": st.PATH_NAMES[row["path"]], "lines": names[row["lines"]],
                             "block_n": row["block_n"], "chunk": row["chunk"], "time_block": row["time_block"],
+                            "reg_rows": row["reg_rows"], "tile_width": row["tile_width"],
                             "gstencil_s": round(pts / (row["ms_per_step"] * 1e-3) / 1e9, 2)} for row in rows]}
         w = out["cases"][key]["winner"]
         print(f"[bench] tune {key}: {w['path']} lines={w['lines']} n={w['block_n']} chunk={w['chunk']} "
               f"T={w['time_block']} {w['gstencil_s']} GStencil/s ({len(rows)} candidates)", file=sys.stderr, flush=True)
+    out["data_sensitivity"] = data_sensitivity(args, torch, st, inputs)
     return out
+
+
+def data_sensitivity(args, torch, st, inputs) -> dict:
+    """Why the tuner times candidates on seeded data: GStencil/s of a 100-step
+    solve (8192^2 FP32 box, periodic) from a zeroed grid and from the seeded
+    headline grid, for the MFMA outer products, the one-step gather and the
+    library's time block, r = 1..4 (median of --steps runs)."""
+    stream = torch.cuda.Stream()
+    seeded = torch.from_numpy(inputs.grid(DIMS, seed=INPUT_SEED, dtype=np.float32)).cuda()
+    zero = torch.zeros_like(seeded)
+    res = {}
+    for r in RADII:
+        c = inputs.coefficients(2, r, inputs.BOX, seed=COEF_SEED0 + r, dtype=np.float64)
+        row = {}
+        for name, knobs in (("mfma", {"path": st.PATH_MFMA}), ("gather", {"path": st.PATH_GATHER}),
+                            ("auto", {})):
+            plan = st.Plan(DIMS, r, st.BOX, c, boundary=st.BC_PERIODIC, dtype=st.F32, **knobs)
+            for label, x0 in (("zero", zero), ("seeded", seeded)):
+                times = _time_solve(torch, plan, x0, JACOBI_STEPS, max(args.steps, 3), 1, stream)
+                row[f"{name}_{label}"] = round(float(DIMS[0] * DIMS[1] * JACOBI_STEPS / (np.median(times) * 1e-3) / 1e9), 1)
+            plan.close()
+        res[f"box_r{r}"] = row
+        print(f"[bench] data sensitivity r={r}: {row}", file=sys.stderr, flush=True)
+    return res
 
 
 def _serve_requests(n, st):

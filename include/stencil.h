@@ -443,10 +443,12 @@ stencil_status_t stencil_server_destroy(stencil_server_t server);
  *   4. for the winner (unless time-blocked), chunk lengths 16..1024 rows (2D)
  *      or 8..128 planes (3D) when desc->chunk is 0.
  * Fields of desc other than 0 / AUTO are kept fixed.
- * Timing: two scratch grids of desc's size (allocated here, set to zero,
- * freed before returning) on `stream`, which must not be under capture; per
- * candidate one warm-up run and the best of three timed runs of 24..64
- * steps (about 2e8 point-steps).
+ * Timing: two scratch grids of desc's size (allocated here, freed before
+ * returning) on `stream`, which must not be under capture; per candidate one
+ * warm-up run and the best of three timed runs of 24..64 steps (about 2e8
+ * point-steps), each run from the same seeded state of values in [-1, 1)
+ * (refilled before the run, outside the timed region: zero operands let the
+ * matrix cores and vector ALUs hold a higher clock than real data does).
  * best: receives desc with the chosen path, lines, block_n, chunk,
  *   time_block, reg_rows and tile_width (coeffs pointer unchanged).  ms_per_step (may be NULL): the
  *   winner's time per step.

@@ -84,5 +84,7 @@ int tb2d_max_steps(int dtype, int R);  // largest time_block of the time-blocked
 
 hipError_t launch_error_norms(const void* a, int a_dtype, const double* ref, int64_t n, double* out,
                               hipStream_t s);
+// n values of dtype spread over [-1, 1), a fixed function of (seed, index)
+hipError_t launch_trial_fill(void* p, int dtype, int64_t n, uint64_t seed, hipStream_t s);
 
 }  // namespace stencil
