@@ -193,7 +193,8 @@ def workload_star2d_512(args, torch, st, inputs) -> dict:
 
 def workload_grid3d(args, torch, st, inputs) -> dict:
     """3D stars r = 1..4 and boxes r = 1..4 (27-point box: r = 1) on 512^3,
-    FP32 and FP64, zero halo, 50 Jacobi steps: gather vs outer-product paths."""
+    FP32 and FP64, zero halo, 50 Jacobi steps: gather vs outer-product paths,
+    the two-step time block (`gather_tb2`, where it is built) and AUTO."""
     dims, steps = (512, 512, 512), args.solve_steps or 50
     a64 = inputs.grid(dims, seed=301, dtype=np.float64)
     stream = torch.cuda.Stream()
@@ -203,9 +204,10 @@ def workload_grid3d(args, torch, st, inputs) -> dict:
     want_paths = set(args.paths3d.split(",")) if args.paths3d else None
     for dt, tdt in ((st.F32, np.float32), (st.F64, np.float64)):
         x0 = None
-        paths = [("gather", st.PATH_GATHER), ("mfma", st.PATH_MFMA), ("auto", st.PATH_AUTO)]
+        paths = [("gather", st.PATH_GATHER, 0), ("gather_tb2", st.PATH_GATHER, 2), ("mfma", st.PATH_MFMA, 0),
+                 ("auto", st.PATH_AUTO, 0)]
         if dt == st.F32:
-            paths += [("mfma_f16x3", st.PATH_MFMA_F16X3), ("mfma_bf16x3", st.PATH_MFMA_BF16X3)]
+            paths += [("mfma_f16x3", st.PATH_MFMA_F16X3, 0), ("mfma_bf16x3", st.PATH_MFMA_BF16X3, 0)]
         for shape, r in cases:
             c = inputs.coefficients(3, r, shape, seed=3100 + 10 * shape + r, dtype=np.float64)
             key = f"{'f32' if dt == st.F32 else 'f64'}_{'box' if shape == st.BOX else 'star'}_r{r}"
@@ -214,13 +216,16 @@ def workload_grid3d(args, torch, st, inputs) -> dict:
             if x0 is None:
                 x0 = torch.from_numpy(a64.astype(tdt)).cuda()
             out["cases"][key] = {}
-            for name, path in paths:
+            for name, path, tb in paths:
                 if want_paths is not None and name not in want_paths:
                     continue
                 if shape == st.BOX and r > 1 and path != st.PATH_GATHER and (path != st.PATH_MFMA or
                                                                            (dt == st.F64 and r > 2)):
                     continue  # 3D boxes beyond r = 1: gather and outer products (FP64: r <= 2)
-                plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=dt, path=path)
+                if tb and st.desc_check(dims, r, shape, c, boundary=st.BC_ZERO, dtype=dt, path=path,
+                                        time_block=tb) != st.OK:
+                    continue  # no time-blocked kernel for this stencil
+                plan = st.Plan(dims, r, shape, c, boundary=st.BC_ZERO, dtype=dt, path=path, time_block=tb)
                 times = _time_solve(torch, plan, x0, steps, args.steps, args.warmup, stream)
                 g = dims[0] * dims[1] * dims[2] * steps / (np.median(times) * 1e-3) / 1e9
                 bpp = 8 if dt == st.F32 else 16

@@ -137,8 +137,9 @@ typedef struct {
                            traffic per point-step about T-fold.  Built for 2D grids on the GATHER
                            path (AUTO resolves to it); the halo r*T rounded up to a multiple of 4 is
                            at most 12 for F32 and 8 for F64 (r = 1: T <= 12 / 8; r = 2: 6 / 4;
-                           r = 3: 4 / 2; r = 4: 3 / 2), and for 3D r = 1 STAR / BOX grids whose
-                           last extent is a multiple of 4 (T = 2; its launches need 16-byte
+                           r = 3: 4 / 2; r = 4: 3 / 2), and for 3D r = 1 STAR / BOX grids and
+                           F32 STAR grids of r = 2..4 whose last extent is a multiple of 4
+                           (T = 2; its launches need 16-byte
                            aligned buffers, else stencil_run_steps returns EINVAL); else
                            EUNSUPPORTED.  0 = library choice:
                            one step per launch, except that path AUTO on 2D STAR / BOX grids

@@ -18,23 +18,24 @@ namespace stencil {
 
 typedef __attribute__((address_space(3))) void lds_void3_t;
 
-template <typename T, int R, int ROWS, int TK, int NT>
+template <typename T, int R, int ROWS, int TK, int NT, int M = 4>
 struct DmaPlane {
   static constexpr int VEC = 16 / (int)sizeof(T);
-  static constexpr int PITCH = TK + 8;           // elements per LDS row: columns k0-4 .. k0+TK+3
+  static constexpr int PITCH = TK + 2 * M;       // elements per LDS row: columns k0-M .. k0+TK+M-1
   static constexpr int LPR = PITCH / VEC;        // 16-byte lines per row
-  static constexpr int COL0 = 4 - R;             // LDS column of window column 0 (global k0 - r)
+  static constexpr int COL0 = M - R;             // LDS column of window column 0 (global k0 - r)
   static constexpr int LINES = ROWS * LPR;
   static constexpr int NWAVES = NT / 64;
   static constexpr int NPW = ((LINES + 63) / 64 + NWAVES - 1) / NWAVES;
   static constexpr int BUF = NPW * NWAVES * 64 * VEC;   // elements per buffer, incl. slack
-  static_assert(R <= 4, "window covers at most 4 halo columns");
+  static_assert(R <= M, "window covers at most M halo columns");
+  static_assert(M % VEC == 0, "16-byte lines start on a line boundary");
   static_assert(NPW < 64, "vmcnt range");
 
   // Per-lane source offsets (elements from the plane's start) of the lines
   // this lane loads, -1 for a zero line.  They are the same for every plane
   // of a work item, so they are computed once: window rows (global j)
-  // grow0 .. grow0 + ROWS - 1, columns k0 - 4 .., under the boundary rule.
+  // grow0 .. grow0 + ROWS - 1, columns k0 - M .., under the boundary rule.
   struct Lines {
     int64_t off[NPW];
   };
@@ -49,7 +50,7 @@ struct DmaPlane {
       if (line < LINES) {
         const int row = line / LPR, lc = line - (line / LPR) * LPR;
         const int64_t g = map_index(grow0 + row, Nj, periodic);
-        const int64_t c = map_index(k0 - 4 + VEC * lc, Nk, periodic);
+        const int64_t c = map_index(k0 - M + VEC * lc, Nk, periodic);
         if (g >= 0 && c >= 0) L.off[k] = g * Nk + c;
       }
     }

@@ -1,5 +1,5 @@
 // Instantiations of the time-blocked 3D gather kernels (two steps per launch):
-// the streaming form for stars of order 1 (FP32 also 2) and the 27-point box
+// the streaming form for stars of order 1 (FP32 up to 4) and the 27-point box
 // on planes of at least 32 (j, k) tiles, the whole-window form for order 1
 // otherwise.
 #include <type_traits>
@@ -18,7 +18,7 @@ static Kernel pick_tb3d(KArgs& a, int32_t chunk) {
   // the streaming form wants planes of at least 32 (j, k) tiles: fewer
   // leave its chunks too shallow for their 4r warm-up planes (measured on
   // MI355X: 128^3 and 64^3 lose to the whole-window form at order 1)
-  if (R == 2 || tb3d_plane_tiles(a) >= 32)
+  if (R >= 2 || tb3d_plane_tiles(a) >= 32)
     return kernel3d<tb3d_stream_kernel<T, R, BOX>, tb3d_stream_batch<T, R, BOX>>(a, R, chunk);
   if constexpr (R == 1) {
     int64_t ti, tj, tk;
@@ -29,13 +29,15 @@ static Kernel pick_tb3d(KArgs& a, int32_t chunk) {
 }
 
 bool tb3d_built(int dtype, int R, bool box) {
-  return R == 1 || (dtype == STENCIL_F32 && R == 2 && !box);
+  return R == 1 || (dtype == STENCIL_F32 && R <= 4 && !box);
 }
 
 Picker find_tb3d(int dtype, int R, bool box) {
   if (!tb3d_built(dtype, R, box)) return nullptr;
   if (dtype == STENCIL_F64) return box ? pick_tb3d<double, 1, true> : pick_tb3d<double, 1, false>;
   if (R == 2) return pick_tb3d<float, 2, false>;
+  if (R == 3) return pick_tb3d<float, 3, false>;
+  if (R == 4) return pick_tb3d<float, 4, false>;
   return box ? pick_tb3d<float, 1, true> : pick_tb3d<float, 1, false>;
 }
 

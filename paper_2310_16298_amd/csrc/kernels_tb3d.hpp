@@ -290,28 +290,35 @@ __global__ __launch_bounds__(256) void tb3d_dma_batch(BatchArgs b) {
 // kTJ x kTK tile of the (j, k) plane and a chunk of output planes -- with a
 // plane ring per time level.  The walk reads input planes ib - 2r ..
 // iend + 2r - 1 once each: the window of a plane (rows j0 - 2r .., columns
-// k0 - 4 .. k0 + kTK + 3) is copied straight into LDS (double-buffered) and
-// scattered into a ring of 2r+1 level-1 planes in registers covering the
-// tile plus an r halo (rows j0 - r .., columns k0 - 4 .. k0 + kTK + 3).  When
-// level-1 plane p is complete it goes to an LDS plane (zero outside a
-// zero-halo grid) and is scattered into the ring of level-2 planes (the
-// tile), whose complete plane p - r is stored.  Only the r-row and 4-column
-// halos of the (j, k) window are read twice; along i nothing is, apart from
-// the 4r planes at the ends of a chunk.  Both levels sum their taps in the
-// order of the one-step kernel (its ring scatter), so the result equals two
-// one-step launches bit for bit.  Built for FP32 stars of order 1 and 2 and
-// the 27-point box.
+// k0 - M .. k0 + kTK + M - 1, M = 4 up to order 2 and 8 beyond) is copied
+// straight into LDS (double-buffered) and scattered into a ring of 2r+1
+// level-1 planes in registers covering the tile plus an r halo (rows
+// j0 - r .., columns k0 - 4 .. k0 + kTK + 3).  When level-1 plane p is
+// complete it goes to an LDS plane (zero outside a zero-halo grid) and is
+// scattered into the ring of level-2 planes (the tile), whose complete plane
+// p - r is stored.  Only the 2r-row and M-column halos of the (j, k) window
+// are read twice; along i nothing is, apart from the 4r planes at the ends of
+// a chunk.  Both levels sum their taps in the order of the one-step kernel
+// (its ring scatter), so the result equals two one-step launches bit for bit.
+// Built for FP32 stars of order 1 to 4, the FP32 27-point box and FP64
+// order 1.
 // ---------------------------------------------------------------------------
 template <typename T, int R, bool BOX>
 struct Tb3Stream {
   static constexpr int W = 2 * R + 1, VEC = 16 / (int)sizeof(T);
   static constexpr int ROWS0 = kTJ + 4 * R;                     // input window rows: global j0 - 2r ..
-  typedef DmaPlane<T, 2 * R, ROWS0, kTK, 256> D;                // columns k0 - 4 .. k0 + kTK + 3
+  // window columns k0 - M .. k0 + kTK + M - 1: level 1 reaches 2r columns
+  // past the tile, within a 4-column margin up to order 2, an 8-column one beyond
+  static constexpr int M = 2 * R <= 4 ? 4 : 8;
+  typedef DmaPlane<T, 2 * R, ROWS0, kTK, 256, M> D;
   static constexpr int P0 = D::PITCH;
   static constexpr int PAD = 4;                                 // elements before the window (16 bytes)
-  // a 12-wide read of the first column block starts 4 elements before a row,
-  // one of the last ends 4 past it
+  // with M = 4 a 12-wide read of the first column block starts 4 elements
+  // before a row, one of the last ends 4 past it
   static constexpr int BUF0 = round_up(PAD + cmax(D::BUF, ROWS0 * P0) + 4, 4);
+  // LDS column (in a window row) where level-1 block s's 12-wide read starts,
+  // minus 4 s: global column k0 - 8 + 4 s
+  static constexpr int SRC0 = M - 8;
   static constexpr int ROWS1 = kTJ + 2 * R;                     // level-1 rows: global j0 - r ..
   static constexpr int SEG1 = (kTK + 8) / 4;                    // level-1 column blocks: k0 - 4 ..
   static constexpr int P1 = kTK + 16;                           // level-1 row: global columns k0 - 8 ..
@@ -319,7 +326,7 @@ struct Tb3Stream {
   static constexpr int NBLK1 = ROWS1 / 2 * SEG1;
   static constexpr int NB1 = (NBLK1 + 255) / 256;               // level-1 blocks per thread
   static_assert(kTJ / 2 * (kTK / 4) == 256, "one level-2 block per thread");
-  static_assert(2 * R <= 4, "halo within the window's 4 columns");
+  static_assert(R <= 4, "level-1 blocks k0 - 4 .. cover the level-2 reach");
 };
 
 template <typename T, int R, bool BOX>
@@ -470,7 +477,7 @@ __device__ __forceinline__ void tb3d_stream_item(const KArgs& a, int item) {
       const int b = tid + 256 * n;
       if (b >= S::NBLK1) break;
       const int rp = b / S::SEG1, s = b - (b / S::SEG1) * S::SEG1;
-      scatter(win + 2 * rp * S::P0 + 4 * s - 4, S::P0, ring1[n]);
+      scatter(win + 2 * rp * S::P0 + 4 * s + S::SRC0, S::P0, ring1[n]);
     }
     // level-1 plane ib - 3r + u is complete once its 2r+1 input planes were walked
     const int64_t p1 = ch.ib - 3 * R + u;

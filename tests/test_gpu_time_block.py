@@ -136,7 +136,8 @@ def _run3(a0, c, shape, bc, dtype, tb, steps, r=1):
     return out
 
 
-TB3 = [(st.F32, st.STAR, 1), (st.F32, st.BOX, 1), (st.F32, st.STAR, 2), (st.F64, st.STAR, 1), (st.F64, st.BOX, 1)]
+TB3 = [(st.F32, st.STAR, 1), (st.F32, st.BOX, 1), (st.F32, st.STAR, 2), (st.F32, st.STAR, 3), (st.F32, st.STAR, 4),
+       (st.F64, st.STAR, 1), (st.F64, st.BOX, 1)]
 
 
 @pytest.mark.parametrize("dtype,shape,r", TB3)
@@ -144,9 +145,10 @@ TB3 = [(st.F32, st.STAR, 1), (st.F32, st.BOX, 1), (st.F32, st.STAR, 2), (st.F64,
 @pytest.mark.parametrize("dims", [(19, 35, 68), (8, 16, 64), (5, 3, 4), (1, 1, 4), (33, 17, 132), (9, 40, 32),
                                   (70, 66, 136), (9, 256, 260), (40, 130, 512)])
 def test_time_block_3d_parity(dtype, shape, r, bc, dims):
-    """3D time blocks (two steps per launch; FP32 streaming plane rings on
-    planes of 32 or more (j, k) tiles -- the last two extents here -- and at
-    order 2, whole windows otherwise): against the oracle, and bit for bit
+    """3D time blocks (two steps per launch; streaming plane rings on planes
+    of 32 or more (j, k) tiles -- the last two extents here -- and for FP32
+    stars of order 2 to 4 (8-column window margins beyond order 2), whole
+    windows otherwise): against the oracle, and bit for bit
     against one step per launch (the same per-point tap order), on runs with
     a last launch of two steps and of one, over several tiles and chunks with
     ragged tails."""
