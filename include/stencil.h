@@ -147,9 +147,12 @@ typedef struct {
                            lines, block_n, chunk, reg_rows and tile_width all 0, takes the
                            time-blocked gather with T measured fastest on MI355X (r = 1..4,
                            F32 stars 8 / 4 / 4 / 3, boxes 8 / 4 / 4 / 2; F64 stars 8 / 4 / 2 /
-                           2, boxes 8 / 4 / - / -), and AUTO on 3D r = 1 STAR / BOX grids of at most
-                           64^3 points (F32 stars: 128^3) whose last extent is a multiple of 4 takes
-                           T = 2 (stencil_plan_info reports it).  stencil_apply is always one step */
+                           2, boxes 8 / 4 / - / -), and AUTO on 3D grids whose last extent is a
+                           multiple of 4 takes T = 2 for r = 1 STAR / BOX grids of at most 64^3
+                           points (F32 stars: 128^3) and for planes of many 32 x 64 (j, k) tiles:
+                           at least 32 (r = 1 STARs), 48 (F32 r = 2 STAR), 64 (F64 r = 1 BOX) or
+                           96 (F32 r = 1 BOX) (stencil_plan_info reports it).  stencil_apply is
+                           always one step */
   int32_t reg_rows;     /* register tile of the 2D FP32 outer products on n = 4 blocks (box stencils,
                            MFMA path; the i unrolling of Section 4.2): output rows per wave, 8 / 16 / 32
                            (two, four or eight 4-row accumulator blocks), 0 = library choice (16) */

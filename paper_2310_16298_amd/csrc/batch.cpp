@@ -146,7 +146,8 @@ stencil_status_t stencil_batch_create(const stencil_plan_t* plans, void* const* 
     size_t table_entries = 0;
     for (Group& g : b->groups) {
       int occ = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, g.k.batch_id, 256, 0) != hipSuccess || occ < 1) occ = 1;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, g.k.batch_id, g.k.threads, 0) != hipSuccess || occ < 1)
+        occ = 1;
       const int64_t cap = (int64_t)occ * cus;
       g.blocks = (unsigned)std::min<int64_t>(g.total, cap);
       table_entries += g.grids.size();

@@ -44,13 +44,17 @@ inline int64_t chunk3d_items(const KArgs& a) { return (int64_t)a.tiles0 * a.tile
 // the halo rows one reads are in L2 when the next reads them.  Measured on
 // MI355X: FP32 stars of order 4 +8-19 % (384^3, 512^3), FP64 stars of order
 // 4 at 384^3 +60 %; kernels with four or more workgroups per CU ran 2-4 %
-// slower re-cut and keep the plan's chunks.
-inline int64_t balanced_items3d(KArgs& a, const void* kernel, int R, int32_t chunk_req) {
+// slower re-cut and keep the plan's chunks.  cap_per_cu > 0 counts at most
+// that many workgroups per CU (a kernel that runs slower with more of them
+// resident: its items are re-cut to fill the CUs evenly at the cap).
+inline int64_t balanced_items3d(KArgs& a, const void* kernel, int R, int32_t chunk_req, int threads = 256,
+                                int cap_per_cu = 0) {
   const int64_t items = chunk3d_items(a);
   if (chunk_req > 0) return items;
-  const Residency res = resident_workgroups(kernel);
-  if (res.per_cu <= 0 || res.per_cu > 3) return items;
-  const int64_t slots = (int64_t)res.per_cu * res.cus;
+  const Residency res = resident_workgroups(kernel, threads);
+  const int per_cu = cap_per_cu > 0 && res.per_cu > cap_per_cu ? cap_per_cu : res.per_cu;
+  if (per_cu <= 0 || per_cu > 3) return items;
+  const int64_t slots = (int64_t)per_cu * res.cus;
   const int64_t tiles = (int64_t)a.tiles0 * a.tiles1;
   if (items <= slots) return items;
   int64_t nch = slots / tiles;
@@ -64,10 +68,10 @@ inline int64_t balanced_items3d(KArgs& a, const void* kernel, int R, int32_t chu
 }
 
 // A 3D kernel (single-grid K, batched B) for its plan's args: items as above.
-template <auto K, auto B>
-inline Kernel kernel3d(KArgs& a, int R, int32_t chunk_req) {
-  Kernel k = kernel_of<K, B>(0);
-  k.items = balanced_items3d(a, k.single_id, R, chunk_req);
+template <auto K, auto B, int NT = 256>
+inline Kernel kernel3d(KArgs& a, int R, int32_t chunk_req, int cap_per_cu = 0) {
+  Kernel k = kernel_of<K, B, NT>(0);
+  k.items = balanced_items3d(a, k.single_id, R, chunk_req, NT, cap_per_cu);
   return k;
 }
 

@@ -18,8 +18,14 @@ static Kernel pick_tb3d(KArgs& a, int32_t chunk) {
   // the streaming form wants planes of at least 32 (j, k) tiles: fewer
   // leave its chunks too shallow for their 4r warm-up planes (measured on
   // MI355X: 128^3 and 64^3 lose to the whole-window form at order 1)
+  // The 5- and 6-wave workgroups of the FP32 stars of order 1-2 run at most
+  // two per CU: with a third resident on some CUs (576 items of 72 tiles at
+  // 384^3) those CUs set the launch time (MI355X: 573 GStencil/s at 384^3
+  // against 1056 at 512^3, where 512 items fill every CU with two).
+  typedef Tb3Stream<T, R, BOX> S;
   if (R >= 2 || tb3d_plane_tiles(a) >= 32)
-    return kernel3d<tb3d_stream_kernel<T, R, BOX>, tb3d_stream_batch<T, R, BOX>>(a, R, chunk);
+    return kernel3d<tb3d_stream_kernel<T, R, BOX>, tb3d_stream_batch<T, R, BOX>, S::NT>(a, R, chunk,
+                                                                                        S::SPREAD ? 2 : 0);
   if constexpr (R == 1) {
     int64_t ti, tj, tk;
     tb3d_tiles<T, R, 2>(a.d0, a.d1, a.d2, &ti, &tj, &tk);

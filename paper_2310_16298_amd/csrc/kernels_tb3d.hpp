@@ -310,7 +310,19 @@ struct Tb3Stream {
   // window columns k0 - M .. k0 + kTK + M - 1: level 1 reaches 2r columns
   // past the tile, within a 4-column margin up to order 2, an 8-column one beyond
   static constexpr int M = 2 * R <= 4 ? 4 : 8;
-  typedef DmaPlane<T, 2 * R, ROWS0, kTK, 256, M> D;
+  static constexpr int ROWS1 = kTJ + 2 * R;                     // level-1 rows: global j0 - r ..
+  static constexpr int SEG1 = (kTK + 8) / 4;                    // level-1 column blocks: k0 - 4 ..
+  static constexpr int NBLK1 = ROWS1 / 2 * SEG1;
+  // Workgroup size.  The level-1 pass has 306-360 blocks: with 256 threads
+  // one or two waves run a second pass while the others wait at the plane's
+  // barrier.  FP32 stars of order 1-2 take one block per thread (5 / 6 waves,
+  // the waves past the fourth sit out level 2; 512^3 on MI355X: 1053 vs 938
+  // and 784 vs 683 GStencil/s); the 27-point box, FP64 and orders 3-4 ran
+  // slower that way (587 vs 635, FP64 star 468 vs 591, order 3 406 vs 537)
+  // and keep 256 threads.
+  static constexpr bool SPREAD = sizeof(T) == 4 && !BOX && R <= 2;
+  static constexpr int NT = SPREAD ? round_up(NBLK1, 64) : 256;
+  typedef DmaPlane<T, 2 * R, ROWS0, kTK, NT, M> D;
   static constexpr int P0 = D::PITCH;
   static constexpr int PAD = 4;                                 // elements before the window (16 bytes)
   // with M = 4 a 12-wide read of the first column block starts 4 elements
@@ -319,13 +331,11 @@ struct Tb3Stream {
   // LDS column (in a window row) where level-1 block s's 12-wide read starts,
   // minus 4 s: global column k0 - 8 + 4 s
   static constexpr int SRC0 = M - 8;
-  static constexpr int ROWS1 = kTJ + 2 * R;                     // level-1 rows: global j0 - r ..
-  static constexpr int SEG1 = (kTK + 8) / 4;                    // level-1 column blocks: k0 - 4 ..
   static constexpr int P1 = kTK + 16;                           // level-1 row: global columns k0 - 8 ..
   static constexpr int BUF1 = ROWS1 * P1;
-  static constexpr int NBLK1 = ROWS1 / 2 * SEG1;
-  static constexpr int NB1 = (NBLK1 + 255) / 256;               // level-1 blocks per thread
-  static_assert(kTJ / 2 * (kTK / 4) == 256, "one level-2 block per thread");
+  static constexpr int NB1 = (NBLK1 + NT - 1) / NT;             // level-1 blocks per thread
+  static_assert(kTJ / 2 * (kTK / 4) == 256, "one level-2 block per thread of the first four waves");
+  static_assert(NT <= 1024 && NT % 64 == 0, "workgroup of whole waves");
   static_assert(R <= 4, "level-1 blocks k0 - 4 .. cover the level-2 reach");
 };
 
@@ -348,7 +358,7 @@ __device__ __forceinline__ void tb3d_stream_item(const KArgs& a, int item) {
   T* const l1 = lds + 2 * S::BUF0;
 
   // pads and the level-1 plane start at zero (cells no DMA line writes)
-  for (int e = tid; e < 2 * S::BUF0 + S::BUF1; e += 256) lds[e] = T(0);
+  for (int e = tid; e < 2 * S::BUF0 + S::BUF1; e += S::NT) lds[e] = T(0);
   __syncthreads();
 
   // ring1[n]: the level-1 ring of this thread's block n; ring2: its level-2 block
@@ -474,7 +484,7 @@ __device__ __forceinline__ void tb3d_stream_item(const KArgs& a, int item) {
     // level 1: block (rp, s) = rows j0 - r + 2 rp .., columns k0 - 4 + 4 s ..
 #pragma unroll
     for (int n = 0; n < S::NB1; ++n) {
-      const int b = tid + 256 * n;
+      const int b = tid + S::NT * n;
       if (b >= S::NBLK1) break;
       const int rp = b / S::SEG1, s = b - (b / S::SEG1) * S::SEG1;
       scatter(win + 2 * rp * S::P0 + 4 * s + S::SRC0, S::P0, ring1[n]);
@@ -487,7 +497,7 @@ __device__ __forceinline__ void tb3d_stream_item(const KArgs& a, int item) {
       const bool plane_in = periodic || (gp1 >= 0 && gp1 < Ni);
 #pragma unroll
       for (int n = 0; n < S::NB1; ++n) {
-        const int b = tid + 256 * n;
+        const int b = tid + S::NT * n;
         if (b >= S::NBLK1) break;
         const int rp = b / S::SEG1, s = b - (b / S::SEG1) * S::SEG1;
 #pragma unroll
@@ -514,7 +524,7 @@ __device__ __forceinline__ void tb3d_stream_item(const KArgs& a, int item) {
 #pragma unroll
     for (int n = 0; n < S::NB1; ++n) shift(ring1[n]);
     lds_barrier();  // level-1 plane p1 visible
-    if (have1) {
+    if (have1 && tid < 256) {  // level 2: the first four waves
       scatter(l1 + 2 * rp2 * S::P1 + 4 + 4 * q2, S::P1, ring2);
       // level-2 plane p1 - r = ib + u - 4r is complete
       if (u >= 4 * R) {
@@ -540,12 +550,12 @@ __device__ __forceinline__ void tb3d_stream_item(const KArgs& a, int item) {
 }
 
 template <typename T, int R, bool BOX>
-__global__ __launch_bounds__(256) void tb3d_stream_kernel(KArgs a) {
+__global__ __launch_bounds__((Tb3Stream<T, R, BOX>::NT)) void tb3d_stream_kernel(KArgs a) {
   tb3d_stream_item<T, R, BOX>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 template <typename T, int R, bool BOX>
-__global__ __launch_bounds__(256) void tb3d_stream_batch(BatchArgs b) {
+__global__ __launch_bounds__((Tb3Stream<T, R, BOX>::NT)) void tb3d_stream_batch(BatchArgs b) {
   for_each_batch_item(b, [&](const KArgs& x, int id) { tb3d_stream_item<T, R, BOX>(x, id); });
 }
 

@@ -7,7 +7,7 @@
 
 namespace stencil {
 
-Residency resident_workgroups(const void* kernel) {
+Residency resident_workgroups(const void* kernel, int threads) {
   static std::mutex mu;
   static std::map<std::pair<int, const void*>, Residency> cache;
   int dev = -1;
@@ -18,7 +18,7 @@ Residency resident_workgroups(const void* kernel) {
   if (it != cache.end()) return it->second;
   int occ = 0, cus = 0;
   Residency r;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 256, 0) == hipSuccess &&
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, threads, 0) == hipSuccess &&
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && occ > 0 && cus > 0) {
     r.per_cu = occ;
     r.cus = cus;

@@ -444,16 +444,16 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       // (zero halo) against the one-step gather: the whole-window form on
       // small grids (order 1 at 64^3 and below: 1.14-1.6x; FP32 stars 1.2x
       // at 128^3), the FP32 streaming form on planes of many (j, k) tiles
-      // (FP32 7-point star from 32 tiles: 1.15x at 256^3, 1.45x at 384^3,
-      // 1.49x at 512^3; order-2 star from 64: 1.22x at 384^3, 1.15x at 512^3,
-      // losing at 256^3; 27-point box from 96: 1.07x at 512^3, level at
-      // 384^3.  FP64 7-point star from 32: 1.31x / 2.2x / 1.63x at 256^3 /
-      // 384^3 / 512^3; 27-point box from 64: 1.54x at 384^3, 1.10x at 512^3,
-      // losing at 256^3)
+      // (FP32 7-point star from 32 tiles: 1.3x at 256^3, 1.8x at 320^3,
+      // 1.86x at 384^3, 1.68x at 512^3; order-2 star from 48: 1.27x at
+      // 320^3, 1.40x at 384^3, 1.32x at 512^3, losing at 256^3; 27-point box
+      // from 96: 1.07x at 512^3, level at 384^3.  FP64 7-point star from 32:
+      // 1.30x / 2.1x / 2.2x / 1.61x at 256^3 / 320^3 / 384^3 / 512^3;
+      // 27-point box from 64: 1.54x at 384^3, 1.10x at 512^3, losing at 256^3)
       const int64_t pts3 = d.dims[0] * d.dims[1] * d.dims[2];
       const int64_t tiles3 = ceil_div(d.dims[1], kTJ) * ceil_div(d.dims[2], kTK);
       const bool small3 = R == 1 && (pts3 <= (int64_t(1) << 18) || (f32 && !box && pts3 <= (int64_t(1) << 21)));
-      const int64_t stream_tiles = f32 ? (!box ? (R == 1 ? 32 : R == 2 ? 64 : 0) : (R == 1 ? 96 : 0))
+      const int64_t stream_tiles = f32 ? (!box ? (R == 1 ? 32 : R == 2 ? 48 : 0) : (R == 1 ? 96 : 0))
                                        : (R == 1 ? (box ? 64 : 32) : 0);
       const bool stream3 = stream_tiles > 0 && tiles3 >= stream_tiles;
       if ((small3 || stream3) && !general && d.dims[2] % 4 == 0 && d.time_block == 0 &&

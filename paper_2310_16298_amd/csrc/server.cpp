@@ -301,7 +301,8 @@ stencil_status_t rebuild_tables(stencil_server_s* s) {
     G.launches = most;
     if (G.total > (int64_t(1) << 31) - 1) return STENCIL_EUNSUPPORTED;
     int occ = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, G.k.batch_id, 256, 0) != hipSuccess || occ < 1) occ = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, G.k.batch_id, G.k.threads, 0) != hipSuccess || occ < 1)
+      occ = 1;
     G.blocks = (unsigned)std::min<int64_t>(G.total, (int64_t)occ * s->cus);
   }
   if (e && hipMemcpyAsync(s->d_tables[k], h, (size_t)e * sizeof(BatchGrid), hipMemcpyHostToDevice, s->stream) !=
