@@ -53,18 +53,29 @@ inline int64_t balanced_items3d(KArgs& a, const void* kernel, int R, int32_t chu
   if (chunk_req > 0) return items;
   const Residency res = resident_workgroups(kernel, threads);
   const int per_cu = cap_per_cu > 0 && res.per_cu > cap_per_cu ? cap_per_cu : res.per_cu;
-  if (per_cu <= 0 || per_cu > 3) return items;
-  const int64_t slots = (int64_t)per_cu * res.cus;
+  if (per_cu <= 0 || res.cus <= 0) return items;
   const int64_t tiles = (int64_t)a.tiles0 * a.tiles1;
-  if (items <= slots) return items;
-  int64_t nch = slots / tiles;
-  if (nch < 1) nch = 1;
-  int64_t chunk = (a.d0 + nch - 1) / nch;
-  const int64_t minc = 4 * R < a.d0 ? 4 * R : a.d0;
-  if (chunk < minc) chunk = minc;
-  a.chunk = (int32_t)chunk;
-  a.nchunks = (int32_t)((a.d0 + chunk - 1) / chunk);
-  return chunk3d_items(a);
+  auto recut = [&](int64_t nch) {
+    if (nch < 1) nch = 1;
+    int64_t chunk = (a.d0 + nch - 1) / nch;
+    const int64_t minc = 4 * R < a.d0 ? 4 * R : a.d0;
+    if (chunk < minc) chunk = minc;
+    a.chunk = (int32_t)chunk;
+    a.nchunks = (int32_t)((a.d0 + chunk - 1) / chunk);
+    return chunk3d_items(a);
+  };
+  const int64_t slots = (int64_t)per_cu * res.cus;
+  if (per_cu <= 3 && items > slots) return recut(slots / tiles);
+  // Even fill: the plan rounds its chunk count up from an item target, which
+  // on extents that are not powers of two leaves some CUs one workgroup more
+  // than the rest (FP64 7-point star at 384^3: 576 items, 2.25 per CU, the
+  // CUs with three setting the launch time).  Round the items per CU to the
+  // nearest whole number and re-cut the planes into at most that many.
+  if (items >= res.cus) {
+    const int64_t target = (items + res.cus / 2) / res.cus * res.cus;
+    if (items > target && target / tiles >= 1) return recut(target / tiles);
+  }
+  return items;
 }
 
 // A 3D kernel (single-grid K, batched B) for its plan's args: items as above.
