@@ -84,19 +84,23 @@ def cpu_model() -> str:
 
 def time_path(st, torch, knobs, radius, a0_dev, coeffs, reps, warmup, stream):
     """Per-rep wall times (ms, HIP events on the launch stream) of one
-    100-step solve; knobs: Plan keyword arguments (path, time_block, ...)."""
+    100-step solve from the seeded grid (restored before each solve, outside
+    the timed region); knobs: Plan keyword arguments (path, time_block, ...)."""
     plan = st.Plan(DIMS, radius, st.BOX, coeffs, boundary=st.BC_PERIODIC, dtype=st.F32, **knobs)
     x = a0_dev.clone()
     tmp = torch.empty_like(x)
     with torch.cuda.stream(stream):
         for _ in range(warmup):
+            x.copy_(a0_dev)
             plan.run_steps(x, tmp, JACOBI_STEPS, stream=stream)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for s, e in evs:
-        s.record(stream)
-        plan.run_steps(x, tmp, JACOBI_STEPS, stream=stream)
-        e.record(stream)
+    with torch.cuda.stream(stream):
+        for s, e in evs:
+            x.copy_(a0_dev)
+            s.record(stream)
+            plan.run_steps(x, tmp, JACOBI_STEPS, stream=stream)
+            e.record(stream)
     torch.cuda.synchronize()
     times = [s.elapsed_time(e) for s, e in evs]
     info = plan.info
@@ -140,16 +144,22 @@ def load_traffic(kernel_key: str, src_hash: str):
 
 
 def _time_solve(torch, plan, x0, steps, reps, warmup, stream):
+    """Wall times (ms) of `steps`-step solves, each from x0 (restored on the
+    launch stream before the start event)."""
     x = x0.clone()
     tmp = torch.empty_like(x)
-    for _ in range(warmup):
-        plan.run_steps(x, tmp, steps, stream=stream)
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            x.copy_(x0)
+            plan.run_steps(x, tmp, steps, stream=stream)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for s0, e0 in evs:
-        s0.record(stream)
-        plan.run_steps(x, tmp, steps, stream=stream)
-        e0.record(stream)
+    with torch.cuda.stream(stream):
+        for s0, e0 in evs:
+            x.copy_(x0)
+            s0.record(stream)
+            plan.run_steps(x, tmp, steps, stream=stream)
+            e0.record(stream)
     torch.cuda.synchronize()
     return [a.elapsed_time(b) for a, b in evs]
 
