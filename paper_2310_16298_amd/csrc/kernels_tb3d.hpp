@@ -315,12 +315,12 @@ struct Tb3Stream {
   static constexpr int NBLK1 = ROWS1 / 2 * SEG1;
   // Workgroup size.  The level-1 pass has 306-360 blocks: with 256 threads
   // one or two waves run a second pass while the others wait at the plane's
-  // barrier.  FP32 stars of order 1-2 take one block per thread (5 / 6 waves,
-  // the waves past the fourth sit out level 2; 512^3 on MI355X: 1053 vs 938
-  // and 784 vs 683 GStencil/s); the 27-point box, FP64 and orders 3-4 ran
-  // slower that way (587 vs 635, FP64 star 468 vs 591, order 3 406 vs 537)
-  // and keep 256 threads.
-  static constexpr bool SPREAD = sizeof(T) == 4 && !BOX && R <= 2;
+  // barrier.  FP32 stars of order 1-2 and the FP32 27-point box take one
+  // block per thread (5 / 6 waves, the waves past the fourth sit out level 2;
+  // at most two workgroups per CU; 512^3 on MI355X: 1053 vs 938, 784 vs 683
+  // and 627 vs 612 GStencil/s, 384^3 box 560 vs 522); FP64 (463 vs 581 at
+  // 512^3) and orders 3-4 (406 vs 537) ran slower that way and keep 256.
+  static constexpr bool SPREAD = sizeof(T) == 4 && (R == 1 || (!BOX && R == 2));
   static constexpr int NT = SPREAD ? round_up(NBLK1, 64) : 256;
   typedef DmaPlane<T, 2 * R, ROWS0, kTK, NT, M> D;
   static constexpr int P0 = D::PITCH;
