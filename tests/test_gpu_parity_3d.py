@@ -326,3 +326,26 @@ def test_split_star_line_options(path, lines, r):
     for bc in (st.BC_ZERO, st.BC_PERIODIC):
         assert np.array_equal(run_gpu(ai, ci, r, st.STAR, bc, st.F32, path, 1, lines=lines),
                               oracle.run(ai, ci, r, st.STAR, bc, 1))
+
+
+@pytest.mark.parametrize("dtype,shape,r,path", [
+    (st.F64, st.STAR, 1, st.PATH_GATHER), (st.F64, st.BOX, 1, st.PATH_GATHER), (st.F64, st.STAR, 4, st.PATH_MFMA),
+    (st.F32, st.STAR, 2, st.PATH_GATHER), (st.F32, st.STAR, 3, st.PATH_GATHER), (st.F32, st.BOX, 1, st.PATH_GATHER)])
+@pytest.mark.parametrize("dims", [(96, 320, 320), (40, 384, 388)])
+def test_whole_number_items_per_cu(dtype, shape, r, path, dims):
+    """Planes of 50 / 84 (j, k) tiles, where the library's chunks leave a
+    fraction of a work item per CU and the launch re-cuts the planes to a
+    whole number per CU: against the oracle, and bit for bit against a
+    requested chunk (never re-cut; a point's taps are summed in the same order
+    whatever the chunking)."""
+    c = inputs.coefficients(3, r, shape, seed=2600 + r, dtype=np.float64)
+    ce = eff_coeffs(c, dtype)
+    a0 = inputs.grid(dims, seed=2601, dtype=np.float32 if dtype == st.F32 else np.float64)
+    steps = 3
+    got = run_gpu(a0, c, r, shape, st.BC_ZERO, dtype, path, steps, time_block=1)
+    fixed = run_gpu(a0, c, r, shape, st.BC_ZERO, dtype, path, steps, time_block=1, chunk=8)
+    assert np.array_equal(got, fixed)
+    want = oracle.run(a0, ce, r, shape, st.BC_ZERO, steps)
+    tol = error_bound(ce, 3, r, shape, dtype, path, steps, np.abs(a0).max())
+    err = np.abs(got - want).max()
+    assert err <= tol, f"max err {err:.3e} > bound {tol:.3e}"

@@ -173,6 +173,26 @@ def test_time_block_3d_integer_bit_exact(dtype, shape, r):
                               oracle.run(a0, c, r, shape, bc, 4))
 
 
+@pytest.mark.parametrize("shape,r", [(st.STAR, 1), (st.STAR, 2), (st.BOX, 1)])
+@pytest.mark.parametrize("dims", [(64, 384, 384), (48, 320, 324)])
+def test_time_block_3d_stream_two_per_cu(shape, r, dims):
+    """FP32 streaming plans whose workgroups hold one level-1 block per thread
+    and run at most two per CU, on planes of 72 / 60 (j, k) tiles where the
+    launch re-cuts the chunks: bit for bit against one step per launch and
+    within the oracle's bound, on runs ending in a two-step and a one-step
+    launch."""
+    c = inputs.coefficients(3, r, shape, seed=2700 + r, dtype=np.float64)
+    ce = eff_coeffs(c, st.F32)
+    a0 = inputs.grid(dims, seed=2701, dtype=np.float32)
+    for steps in (4, 3):
+        got = _run3(a0, c, shape, st.BC_ZERO, st.F32, 2, steps, r)
+        assert np.array_equal(got, _run3(a0, c, shape, st.BC_ZERO, st.F32, 1, steps, r))
+        want = oracle.run(a0, ce, r, shape, st.BC_ZERO, steps)
+        tol = error_bound(ce, 3, r, shape, st.F32, st.PATH_GATHER, steps, np.abs(a0).max())
+        err = np.abs(got.astype(np.float64) - want).max()
+        assert err <= tol, f"max err {err:.3e} > bound {tol:.3e}"
+
+
 def test_time_block_3d_misaligned_buffer_rejected():
     torch = torch_cuda()
     c = inputs.coefficients(3, 1, st.STAR, seed=1700, dtype=np.float64)
