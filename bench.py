@@ -861,8 +861,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5, help="timed bench steps (one step = 4 solves x 100 Jacobi steps)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--headline", default="auto",
-                    choices=["auto", "mfma", "gather", "mfma_f16x3", "mfma_bf16x3", "gather_tb", "tuned"])
-    ap.add_argument("--paths", default="gather,mfma,mfma_f16x3,mfma_bf16x3,gather_tb,tuned,auto",
+                    choices=["auto", "mfma", "gather", "mfma_f16x3", "mfma_bf16x3", "gather_tb", "mfma_tb2", "tuned"])
+    ap.add_argument("--paths", default="gather,mfma,mfma_f16x3,mfma_bf16x3,gather_tb,mfma_tb2,tuned,auto",
                     help="gather_tb: time-blocked gather (largest time block); tuned: the autotuner's plan")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-configs", action="store_true",
@@ -923,6 +923,8 @@ def main() -> int:
     def knobs_for(name, r):
         if name == "gather_tb":
             return {"path": st.PATH_GATHER, "time_block": tb_max[r]}
+        if name == "mfma_tb2":
+            return {"path": st.PATH_MFMA, "time_block": 2}
         if name == "tuned":
             kn, _, _ = st.autotune(DIMS, r, st.BOX, coeffs[r], boundary=st.BC_PERIODIC, dtype=st.F32)
             return kn

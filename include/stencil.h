@@ -135,7 +135,11 @@ typedef struct {
                            leaves to future work): 1 = one step per launch; T > 1: each launch
                            advances T steps on overlapped tiles held in LDS (halo r*T), cutting HBM
                            traffic per point-step about T-fold.  Built for 2D grids on the GATHER
-                           path (AUTO resolves to it); the halo r*T rounded up to a multiple of 4 is
+                           path (AUTO resolves to it), and T = 2 on the MFMA path for F32 BOX grids
+                           whose column extent is a multiple of 4 with block_n, reg_rows and
+                           tile_width left at 0 / 4 / 16 / 256 (n = 4 outer products at both levels;
+                           its launches need 16-byte aligned buffers, else stencil_run_steps returns
+                           EINVAL); on the GATHER path the halo r*T rounded up to a multiple of 4 is
                            at most 12 for F32 and 8 for F64 (r = 1: T <= 12 / 8; r = 2: 6 / 4;
                            r = 3: 4 / 2; r = 4: 3 / 2), and for 3D r = 1 STAR / BOX grids and
                            F32 STAR grids of r = 2..4 whose last extent is a multiple of 4

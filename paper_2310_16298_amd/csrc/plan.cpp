@@ -167,7 +167,13 @@ static int validate(const stencil_desc_t* d) {
   if (d->reg_rows != 0 && d->reg_rows != 8 && d->reg_rows != 16 && d->reg_rows != 32) return STENCIL_EINVAL;
   if (d->tile_width != 0 && d->tile_width != 128 && d->tile_width != 256) return STENCIL_EINVAL;
   if (d->time_block > 1) {
-    if (d->path != STENCIL_PATH_AUTO && d->path != STENCIL_PATH_GATHER) return STENCIL_EUNSUPPORTED;
+    // outer products: FP32 2D boxes on n = 4 blocks (library tiles), two
+    // steps, column extent a multiple of 4
+    const bool mfma_tb = d->path == STENCIL_PATH_MFMA && d->ndim == 2 && d->shape == STENCIL_BOX &&
+                         d->dtype == STENCIL_F32 && d->time_block == 2 && d->dims[1] % 4 == 0 &&
+                         d->block_n != 16 && (d->reg_rows == 0 || d->reg_rows == 16) &&
+                         (d->tile_width == 0 || d->tile_width == 256);
+    if (d->path != STENCIL_PATH_AUTO && d->path != STENCIL_PATH_GATHER && !mfma_tb) return STENCIL_EUNSUPPORTED;
     if (d->ndim == 3) {
       // 3D: two steps, direct-to-LDS lines; FP32 stars of order 1 and 2 and the
       // 27-point box, FP64 order 1
@@ -420,7 +426,7 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
 
   int path = d.path;
   in.time_block = 1;
-  if (d.time_block > 1) path = STENCIL_PATH_GATHER;
+  if (d.time_block > 1 && path != STENCIL_PATH_MFMA) path = STENCIL_PATH_GATHER;
   int tb_auto = 0;  // steps per launch the library chose (AUTO), 0 if none
   if (path == STENCIL_PATH_AUTO) {
     // Measured on MI355X: outer products on MFMA where the arithmetic
@@ -606,6 +612,13 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       }
       rs->pick = b4 ? find_mfma2d_b4(R, box, rs->variant == VAR_BOX ? ui : 4, rs->variant == VAR_BOX ? wr : 1)
                     : find_mfma2d(d.dtype, R, rs->variant);  // cover: set below
+      if (d.time_block > 1) {
+        // two steps per launch (validated above: FP32 box, n = 4, library tiles)
+        if (!(b4 && rs->variant == VAR_BOX && ui == 4 && wr == 1)) return STENCIL_EUNSUPPORTED;
+        rs->pick = find_tbm2d(R);
+        rs->time_block = 2;
+        in.time_block = 2;
+      }
       std::vector<Line> col, row;
       const int fixed_r[3] = {R, R, 0};
       if (rs->variant == VAR_COVER) {

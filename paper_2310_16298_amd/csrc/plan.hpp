@@ -79,6 +79,7 @@ Picker find_mfma3d_b4(int R, bool box);  // FP32 n = 4 blocks: stars, 27-point b
 Picker find_split3d(int kind, int R, bool box, bool hybrid);  // hybrid: stars, lines along j and k on MFMA
 Picker find_tb2d(int dtype, int R, bool box);
 Picker find_tb3d(int dtype, int R, bool box);  // two steps per launch
+Picker find_tbm2d(int R);  // FP32 2D box outer products, two steps per launch
 bool tb3d_built(int dtype, int R, bool box);    // F32: stars r <= 2, the 27-point box; F64: r = 1
 int tb2d_max_steps(int dtype, int R);  // largest time_block of the time-blocked kernel
 

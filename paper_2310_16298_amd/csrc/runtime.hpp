@@ -131,8 +131,8 @@ inline Kernel plan_kernel(const Resolved& rs, const void* in, void* out, KArgs* 
 inline stencil_status_t launch_one(const Resolved& rs, const void* in, void* out, hipStream_t s, int fused = 1) {
   KArgs a;
   const Kernel k = plan_kernel(rs, in, out, &a, fused);
-  // a time-blocked 3D launch needs 16-byte aligned buffers
-  if (!k.launch && rs.family == FAM_TB3D) return STENCIL_EINVAL;
+  // a time-blocked 3D or outer-product launch needs 16-byte aligned buffers
+  if (!k.launch && (rs.family == FAM_TB3D || (rs.family == FAM_MFMA2D && rs.time_block > 1))) return STENCIL_EINVAL;
   if (!k.launch || k.items < 1 || k.items > (int64_t(1) << 31) - 1) return STENCIL_EINTERNAL;
   return k.launch(a, (unsigned)k.items, s) == hipSuccess ? STENCIL_OK : STENCIL_EHIP;
 }

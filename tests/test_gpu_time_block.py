@@ -193,6 +193,62 @@ def test_time_block_3d_stream_two_per_cu(shape, r, dims):
         assert err <= tol, f"max err {err:.3e} > bound {tol:.3e}"
 
 
+def _run_mfma(a0, c, bc, tb, steps, r):
+    torch = torch_cuda()
+    plan = st.Plan(a0.shape, r, st.BOX, c, boundary=bc, dtype=st.F32, path=st.PATH_MFMA, time_block=tb)
+    assert plan.info["time_block"] == max(tb, 1) and plan.info["path"] == st.PATH_MFMA
+    x = torch.from_numpy(a0).cuda()
+    y = torch.empty_like(x)
+    res = plan.run_steps(x, y, steps)
+    torch.cuda.synchronize()
+    out = res.cpu().numpy()
+    plan.close()
+    return out
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("bc", [st.BC_ZERO, st.BC_PERIODIC])
+@pytest.mark.parametrize("dims", [(37, 20), (70, 252), (45, 500), (130, 744), (300, 1000), (1, 8), (5, 4)])
+def test_mfma_time_block_2d(r, bc, dims):
+    """Two steps per launch on the FP32 box outer products (n = 4 blocks):
+    bit for bit against one step per launch on the same kernels, and within
+    the oracle's bound, on runs ending in a two-step and a one-step launch;
+    extents below, at and across the 248-column strips and the 16-row blocks,
+    and degenerate ones."""
+    c = inputs.coefficients(2, r, st.BOX, seed=2800 + r, dtype=np.float64)
+    ce = eff_coeffs(c, st.F32)
+    a0 = inputs.grid(dims, seed=2801, dtype=np.float32)
+    for steps in (2, 5):
+        got = _run_mfma(a0, c, bc, 2, steps, r)
+        assert np.array_equal(got, _run_mfma(a0, c, bc, 1, steps, r))
+        want = oracle.run(a0, ce, r, st.BOX, bc, steps)
+        tol = error_bound(ce, 2, r, st.BOX, st.F32, st.PATH_MFMA, steps, np.abs(a0).max())
+        err = np.abs(got.astype(np.float64) - want).max()
+        assert err <= tol, f"max err {err:.3e} > bound {tol:.3e}"
+
+
+@pytest.mark.parametrize("r", [2, 4])
+def test_mfma_time_block_2d_integer_bit_exact(r):
+    c = inputs.int_coefficients(2, r, st.BOX, seed=2900 + r)
+    a0 = inputs.int_grid((83, 520), seed=2901, dtype=np.float32)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        assert np.array_equal(_run_mfma(a0, c, bc, 2, 3, r).astype(np.float64), oracle.run(a0, c, r, st.BOX, bc, 3))
+
+
+def test_mfma_time_block_2d_misaligned_buffer_rejected():
+    torch = torch_cuda()
+    c = inputs.coefficients(2, 2, st.BOX, seed=3000, dtype=np.float64)
+    plan = st.Plan((16, 16), 2, st.BOX, c, path=st.PATH_MFMA, time_block=2)
+    base = torch.zeros(16 * 16 + 1, device="cuda")
+    x = base[1:].view(16, 16)  # 4-byte offset
+    y = torch.zeros(16, 16, device="cuda")
+    with pytest.raises(st.StencilError) as e:
+        plan.run_steps(x, y, 2)
+    assert e.value.status == st.EINVAL
+    torch.cuda.synchronize()
+    plan.close()
+
+
 def test_time_block_3d_misaligned_buffer_rejected():
     torch = torch_cuda()
     c = inputs.coefficients(3, 1, st.STAR, seed=1700, dtype=np.float64)

@@ -149,7 +149,18 @@ def test_time_block_limits(lib, r, f32max, f64max):
         assert st.desc_check((100, 100), r, inputs.BOX, c, dtype=dt, time_block=tmax + 1) == st.EUNSUPPORTED
         info = st.describe((100, 100), r, inputs.BOX, c, dtype=dt, time_block=tmax)
         assert info["time_block"] == tmax and info["path"] == st.PATH_GATHER
-    assert st.desc_check((100, 100), r, inputs.BOX, c, path=st.PATH_MFMA, time_block=2) == st.EUNSUPPORTED
+    # outer products: FP32 2D boxes, two steps, column extent a multiple of 4, library tiles
+    assert st.desc_check((100, 100), r, inputs.BOX, c, path=st.PATH_MFMA, time_block=2) == st.OK
+    info = st.describe((100, 100), r, inputs.BOX, c, path=st.PATH_MFMA, time_block=2)
+    assert info["time_block"] == 2 and info["path"] == st.PATH_MFMA
+    for kw in ({"time_block": 3}, {"time_block": 2, "dtype": st.F64}, {"time_block": 2, "block_n": 16},
+               {"time_block": 2, "reg_rows": 8}, {"time_block": 2, "tile_width": 128}):
+        assert st.desc_check((100, 100), r, inputs.BOX, c, path=st.PATH_MFMA, **kw) == st.EUNSUPPORTED
+    assert st.desc_check((100, 98), r, inputs.BOX, c, path=st.PATH_MFMA, time_block=2) == st.EUNSUPPORTED
+    cs = inputs.coefficients(2, r, inputs.STAR, seed=1, dtype=np.float64)
+    assert st.desc_check((100, 100), r, inputs.STAR, cs, path=st.PATH_MFMA, time_block=2) == st.EUNSUPPORTED
+    for sp in (st.PATH_MFMA_BF16X3, st.PATH_MFMA_F16X3):
+        assert st.desc_check((100, 100), r, inputs.BOX, c, path=sp, time_block=2) == st.EUNSUPPORTED
     for dt in (st.F32, st.F64):
         for shape, c3 in ((inputs.BOX, _box(3, r)), (inputs.STAR, inputs.coefficients(3, r, inputs.STAR, seed=1))):
             built3 = r == 1 or (dt == st.F32 and shape == inputs.STAR)
