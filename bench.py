@@ -177,7 +177,7 @@ def workload_star2d_512(args, torch, st, inputs) -> dict:
            "2D 5-point star r=1, 512x512 FP64, zero halo, 10 Jacobi steps, seed 101", "paths": {}}
     for name, knobs in (("gather", {"path": st.PATH_GATHER}), ("mfma", {"path": st.PATH_MFMA}),
                         ("gather_tb5", {"path": st.PATH_GATHER, "time_block": 5}),
-                        ("gather_tb8", {"path": st.PATH_GATHER, "time_block": 8})):
+                        ("gather_tb8", {"path": st.PATH_GATHER, "time_block": 8}), ("auto", {})):
         plan = st.Plan(dims, 1, st.STAR, c, boundary=st.BC_ZERO, dtype=st.F64, **knobs)
         times = _time_solve(torch, plan, x0, steps, max(args.steps, 20), args.warmup, stream)
         res = plan.run_steps(x0.clone(), torch.empty_like(x0), steps)

@@ -266,13 +266,15 @@ stencil_status_t stencil_apply(stencil_plan_t plan, const void* in, void* out, v
  * the parity of its launch count ceil(steps / T) -- each launch advances up
  * to T steps from one buffer into the other.  steps == 0
  * enqueues nothing.  Negative steps: EINVAL; overlapping buffers: EALIAS.
- * Launch mode: when 2 <= steps <= 4096 and `stream` is not being captured by
- * the caller, the launches are recorded once into a HIP graph, cached in the
- * plan per (buf0, buf1, steps) (four entries, least recently used replaced),
- * and replayed with one graph launch; the first call for a key instantiates
- * the graph (host-side work, no device synchronisation).  While the caller is
- * capturing `stream`, or with the environment variable STENCIL_NO_GRAPH=1,
- * the kernels are enqueued one by one. */
+ * Launch mode: a run of at most 4 launches is enqueued kernel by kernel (a
+ * graph replay costs more than that many direct launches).  Longer runs with
+ * steps <= 4096, when `stream` is not being captured by the caller, are
+ * recorded once into a HIP graph, cached in the plan per (buf0, buf1, steps)
+ * (four entries, least recently used replaced), and replayed with one graph
+ * launch; the first call for a key instantiates the graph (host-side work,
+ * no device synchronisation).  While the caller is capturing `stream`, or
+ * with the environment variable STENCIL_NO_GRAPH=1, the kernels are enqueued
+ * one by one. */
 stencil_status_t stencil_run_steps(stencil_plan_t plan, void* buf0, void* buf1, int64_t steps,
                                    void* stream, int32_t* result_index);
 
