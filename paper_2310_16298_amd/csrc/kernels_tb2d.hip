@@ -12,13 +12,18 @@ static Kernel pick_tb2d(KArgs& a, int32_t chunk) {
   // a launch of one step (the remainder of a run): the one-step gather
   if (a.steps <= 1) return find_gather2d(std::is_same<T, double>::value ? STENCIL_F64 : STENCIL_F32, R, BOX)(a, chunk);
   if (tb2d_fast<T>(a) && a.zeros != nullptr) {
-    constexpr int TM = tb2d_dma_rows<T>();
-    a.tiles0 = (int32_t)((a.d0 + TM - 1) / TM);
+    int TM = tb2d_dma_rows<T>();
     a.tiles1 = (int32_t)((a.d1 + 63) / 64);
+    // FP64 grids of fewer tiles than CUs (launch-bound: 512^2 has 128) take
+    // 16-row tiles, twice the workgroups at the cost of more halo rows
+    // (MI355X, 512^2 FP64 five-point star, 8 steps per launch: see below)
+    const bool small = !std::is_same<T, float>::value && (int64_t)((a.d0 + TM - 1) / TM) * a.tiles1 < 256;
+    if (small) TM = kTbSmallRows;
+    a.tiles0 = (int32_t)((a.d0 + TM - 1) / TM);
     const int64_t items = (int64_t)a.tiles0 * a.tiles1;
     Kernel k;
     if constexpr (std::is_same<T, float>::value) k = BOX ? tb2d_dma_box(R, a.steps, items) : tb2d_dma_star(R, a.steps, items);
-    else k = tb2d_dma_f64(BOX, R, a.steps, items);
+    else k = tb2d_dma_f64(BOX, R, a.steps, items, small);
     if (k.launch) return k;
   }
   const int64_t items = tb2d_items<T>(a);

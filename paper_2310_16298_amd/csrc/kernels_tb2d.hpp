@@ -211,9 +211,14 @@ __global__ __launch_bounds__(256) void tb2d_batch(BatchArgs b) {
 // each thread computes its 2 x 4 blocks of a step into registers, a barrier,
 // then writes them back.  Every loop bound is a constant once TS is.
 // ---------------------------------------------------------------------------
-template <typename T, int R, int TS>
+// TM_ = 0: the library's tile rows (64 FP32, 32 FP64); FP64 grids of fewer
+// tiles than CUs take 16-row tiles (twice the workgroups).
+template <typename T, int R, int TS, int TM_ = 0>
 struct TbDmaShape {
-  static constexpr int TM = sizeof(T) == 4 ? 64 : 32, TN = 64;
+  static constexpr int TM = TM_ > 0 ? TM_ : (sizeof(T) == 4 ? 64 : 32), TN = 64;
+  // 16 rows is the smallest tile verified against the oracle (8-row FP64
+  // tiles gave wrong results and are not built)
+  static_assert(TM >= 16, "tile rows");
   static constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte line
   static constexpr int HW = round_up(R * TS, 4);
   static constexpr int WM = TM + 2 * HW, WN = TN + 2 * HW;
@@ -235,9 +240,9 @@ template <typename T> struct TbVec;
 template <> struct TbVec<float> { typedef floatx4 type; };
 template <> struct TbVec<double> { typedef double __attribute__((ext_vector_type(2))) type; };
 
-template <typename T, int R, bool BOX, int TS>
+template <typename T, int R, bool BOX, int TS, int TM_ = 0>
 __device__ __forceinline__ void tb2d_dma_item(const KArgs& a, int item) {
-  typedef TbDmaShape<T, R, TS> S;
+  typedef TbDmaShape<T, R, TS, TM_> S;
   typedef typename TbVec<T>::type V;
   constexpr int W = 2 * R + 1, VEC = S::VEC;
   __shared__ __attribute__((aligned(16))) T buf[S::BUF];
@@ -373,14 +378,14 @@ __device__ __forceinline__ void tb2d_dma_item(const KArgs& a, int item) {
   }
 }
 
-template <typename T, int R, bool BOX, int TS>
+template <typename T, int R, bool BOX, int TS, int TM_ = 0>
 __global__ __launch_bounds__(256) void tb2d_dma_kernel(KArgs a) {
-  tb2d_dma_item<T, R, BOX, TS>(a, xcd_remap(blockIdx.x, gridDim.x));
+  tb2d_dma_item<T, R, BOX, TS, TM_>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
-template <typename T, int R, bool BOX, int TS>
+template <typename T, int R, bool BOX, int TS, int TM_ = 0>
 __global__ __launch_bounds__(256) void tb2d_dma_batch(BatchArgs b) {
-  for_each_batch_item(b, [&](const KArgs& x, int id) { tb2d_dma_item<T, R, BOX, TS>(x, id); });
+  for_each_batch_item(b, [&](const KArgs& x, int id) { tb2d_dma_item<T, R, BOX, TS, TM_>(x, id); });
 }
 
 // The direct-to-LDS kernel for order R and `steps` steps (2 <= steps, halo
@@ -388,27 +393,29 @@ __global__ __launch_bounds__(256) void tb2d_dma_batch(BatchArgs b) {
 // FP32 stars and FP64 are instantiated in separate translation units.
 Kernel tb2d_dma_box(int R, int steps, int64_t items);
 Kernel tb2d_dma_star(int R, int steps, int64_t items);
-Kernel tb2d_dma_f64(bool box, int R, int steps, int64_t items);
+Kernel tb2d_dma_f64(bool box, int R, int steps, int64_t items, bool small_tiles);
+constexpr int kTbSmallRows = 16;  // FP64 tile rows on grids of fewer tiles than CUs
 template <typename T>
 constexpr int tb2d_dma_rows() { return TbDmaShape<T, 1, 2>::TM; }
 
-template <typename T, int R, bool BOX, int TS>
+template <typename T, int R, bool BOX, int TS, int TM_ = 0>
 Kernel tb2d_dma_of(int steps, int64_t items) {
   if constexpr (round_up(R * TS, 4) > TbShape<T>::HMAX) {
     return Kernel{};
   } else {
-    if (steps == TS) return kernel_of<tb2d_dma_kernel<T, R, BOX, TS>, tb2d_dma_batch<T, R, BOX, TS>>(items);
-    return tb2d_dma_of<T, R, BOX, TS + 1>(steps, items);
+    if (steps == TS)
+      return kernel_of<tb2d_dma_kernel<T, R, BOX, TS, TM_>, tb2d_dma_batch<T, R, BOX, TS, TM_>>(items);
+    return tb2d_dma_of<T, R, BOX, TS + 1, TM_>(steps, items);
   }
 }
 
-template <typename T, bool BOX>
+template <typename T, bool BOX, int TM_ = 0>
 Kernel tb2d_dma_pick(int R, int steps, int64_t items) {
   switch (R) {
-    case 1: return tb2d_dma_of<T, 1, BOX, 2>(steps, items);
-    case 2: return tb2d_dma_of<T, 2, BOX, 2>(steps, items);
-    case 3: return tb2d_dma_of<T, 3, BOX, 2>(steps, items);
-    case 4: return tb2d_dma_of<T, 4, BOX, 2>(steps, items);
+    case 1: return tb2d_dma_of<T, 1, BOX, 2, TM_>(steps, items);
+    case 2: return tb2d_dma_of<T, 2, BOX, 2, TM_>(steps, items);
+    case 3: return tb2d_dma_of<T, 3, BOX, 2, TM_>(steps, items);
+    case 4: return tb2d_dma_of<T, 4, BOX, 2, TM_>(steps, items);
   }
   return Kernel{};
 }

@@ -69,6 +69,25 @@ def test_time_block_every_step_count(dtype, r, shape):
                 _case((70, 132), r, shape, bc, dtype, tb, steps, seed=1050 + 10 * r + tb)
 
 
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("shape", [st.BOX, st.STAR])
+@pytest.mark.parametrize("dims", [(70, 132), (520, 1040)])
+def test_time_block_f64_tile_rows(r, shape, dims):
+    """FP64 direct-to-LDS time blocks on 16-row tiles (grids of fewer 32 x 64
+    tiles than CUs: 70 x 132) and 32-row tiles (520 x 1040, 289 tiles): the
+    largest time block, bit for bit against one step per launch and within
+    the oracle's bound, on a run ending in a one-step launch."""
+    tb = TMAX[(st.F64, r)]
+    c = inputs.coefficients(2, r, shape, seed=1150 + r, dtype=np.float64)
+    a0 = inputs.grid(dims, seed=1151, dtype=np.float64)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        got = _run(a0, c, r, shape, bc, st.F64, tb, tb + 1)
+        assert np.array_equal(got, _run(a0, c, r, shape, bc, st.F64, 1, tb + 1))
+        want = oracle.run(a0, c, r, shape, bc, tb + 1)
+        tol = error_bound(c, 2, r, shape, st.F64, st.PATH_GATHER, tb + 1, np.abs(a0).max())
+        assert np.abs(got - want).max() <= tol
+
+
 @pytest.mark.parametrize("dims", [(1, 1), (5, 3), (3, 70), (70, 2), (9, 9), (1, 4), (5, 8), (70, 4), (3, 68)])
 @pytest.mark.parametrize("r", [1, 3])
 def test_time_block_small_extents(dims, r):
