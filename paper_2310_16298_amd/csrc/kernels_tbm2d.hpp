@@ -44,7 +44,7 @@ struct TbmShape {
   static_assert(TN - kTbmStride == 8, "each strip drops one 4-column group at either edge");
 };
 
-// acc[s] (rows row0 + 4 s .., lane's four columns) += the outer products of
+// acc[s] (rows row0 + 4 s .., lane's four columns) = the outer products of
 // a window-layout buffer `src` (row 0 = the block's first row minus r,
 // LDS column D::WCOL0 + c = strip column c - r), the one-step kernel's
 // order: lines li = 0 .. 2r, rows x, accumulator blocks s.
