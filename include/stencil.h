@@ -311,9 +311,19 @@ stencil_status_t stencil_run_steps_noalloc(const stencil_desc_t* desc, void* buf
  * idle one at a time.  Grids whose plans resolve to the same kernel form a
  * group; a group's launch is persistent -- at most (resident workgroups per
  * CU) x (CUs) workgroups loop over the (grid, tile) work items of all its
- * grids.  The groups of a step run concurrently on streams forked from the
- * caller's stream and joined back into it; multi-step runs are replayed from a
- * captured HIP graph under the same rule as stencil_run_steps. */
+ * grids.  Grids whose plans the library time-blocked (stencil_plan_info's
+ * time_block T > 1 with the descriptor's time_block 0) advance up to T steps
+ * per launch, on kernels picked for a grid among many: 2D FP64 grids keep
+ * tiles of full height (32 rows) however small, and 3D grids too small for
+ * the streaming form (whose own plans take the whole-window form) run one
+ * step per launch.  Grids sharing the T-step kernel form a class, whose run of
+ * `steps` steps is the fewest launches of at most T steps (as even as
+ * possible) whose count has the parity of `steps`, each launch size its own
+ * group (one step: the plans' one-step kernel).  Plain groups (steps
+ * launches each) and classes run concurrently on streams forked from the
+ * caller's stream and joined back into it; multi-step runs are replayed from
+ * a captured HIP graph.  Every grid ends in its buffer steps % 2, with the
+ * result of its plan's stencil_run_steps bit for bit. */
 typedef struct stencil_batch_s* stencil_batch_t;
 
 /* Create a batch on the current device.  plans[i] (device = current device)
@@ -323,9 +333,10 @@ typedef struct stencil_batch_s* stencil_batch_t;
  * the batch; the plans may be shared between batches.  Errors: EINVAL (null
  * pointers, count < 1, a plan of another device), EALIAS (any two of the
  * 2 x count buffers overlap), EUNSUPPORTED (more than 2^31-1 work items in
- * one group, or a plan whose descriptor asked for a time block > 1; a time
- * block the library chose runs one step per launch in the batch, with the
- * same arithmetic), ENOMEM, EHIP.  On error *out is NULL. */
+ * one group, or a plan whose descriptor asked for a time block > 1), ENOMEM,
+ * EHIP.  A library-chosen time block whose buffers do not take the
+ * time-blocked kernels (alignment) runs one step per launch.  On error *out
+ * is NULL. */
 stencil_status_t stencil_batch_create(const stencil_plan_t* plans, void* const* buf0, void* const* buf1,
                                       int32_t count, stencil_batch_t* out);
 
@@ -336,8 +347,9 @@ stencil_status_t stencil_batch_create(const stencil_plan_t* plans, void* const* 
 stencil_status_t stencil_batch_run_steps(stencil_batch_t batch, int64_t steps, void* stream,
                                          int32_t* result_index);
 
-/* Number of kernel groups, total work items and persistent workgroups per
- * step of a batch (any pointer may be NULL). */
+/* Number of kernel groups (a time-blocked class counts one per launch size),
+ * and total work items and persistent workgroups over all groups (any pointer
+ * may be NULL). */
 stencil_status_t stencil_batch_info(stencil_batch_t batch, int32_t* groups, int64_t* items, int64_t* blocks);
 
 /* Release a batch (NULL accepted); enqueued work must have completed. */

@@ -9,7 +9,12 @@
 
 namespace stencil {
 
-template <typename T, int R, bool BOX>
+// MANY: the grid is one of many in a batched launch.  The whole-window form
+// recomputes a halo of every window to give a small grid alone enough
+// workgroups; among many grids, whose items fill the chip anyway, that work
+// only costs (MI355X, FP64 batches of 8^3 to 64^3 grids, order 1: 1.3-3.2x
+// behind the one-step gather), so such grids get no two-step kernel there.
+template <typename T, int R, bool BOX, bool MANY = false>
 static Kernel pick_tb3d(KArgs& a, int32_t chunk) {
   const int dtype = std::is_same<T, double>::value ? STENCIL_F64 : STENCIL_F32;
   // a launch of one step (the remainder of a run): the one-step gather
@@ -26,7 +31,7 @@ static Kernel pick_tb3d(KArgs& a, int32_t chunk) {
   if (R >= 2 || tb3d_plane_tiles(a) >= 32)
     return kernel3d<tb3d_stream_kernel<T, R, BOX>, tb3d_stream_batch<T, R, BOX>, S::NT>(a, R, chunk,
                                                                                         S::SPREAD ? 2 : 0);
-  if constexpr (R == 1) {
+  if constexpr (R == 1 && !MANY) {
     int64_t ti, tj, tk;
     tb3d_tiles<T, R, 2>(a.d0, a.d1, a.d2, &ti, &tj, &tk);
     return kernel_of<tb3d_dma_kernel<T, R, BOX, 2>, tb3d_dma_batch<T, R, BOX, 2>>(ti * tj * tk);
@@ -38,13 +43,17 @@ bool tb3d_built(int dtype, int R, bool box) {
   return R == 1 || (dtype == STENCIL_F32 && R <= 4 && !box);
 }
 
-Picker find_tb3d(int dtype, int R, bool box) {
+template <bool MANY>
+static Picker find(int dtype, int R, bool box) {
   if (!tb3d_built(dtype, R, box)) return nullptr;
-  if (dtype == STENCIL_F64) return box ? pick_tb3d<double, 1, true> : pick_tb3d<double, 1, false>;
-  if (R == 2) return pick_tb3d<float, 2, false>;
-  if (R == 3) return pick_tb3d<float, 3, false>;
-  if (R == 4) return pick_tb3d<float, 4, false>;
-  return box ? pick_tb3d<float, 1, true> : pick_tb3d<float, 1, false>;
+  if (dtype == STENCIL_F64) return box ? pick_tb3d<double, 1, true, MANY> : pick_tb3d<double, 1, false, MANY>;
+  if (R == 2) return pick_tb3d<float, 2, false, MANY>;
+  if (R == 3) return pick_tb3d<float, 3, false, MANY>;
+  if (R == 4) return pick_tb3d<float, 4, false, MANY>;
+  return box ? pick_tb3d<float, 1, true, MANY> : pick_tb3d<float, 1, false, MANY>;
 }
+
+Picker find_tb3d(int dtype, int R, bool box) { return find<false>(dtype, R, box); }
+Picker find_tb3d_batch(int dtype, int R, bool box) { return find<true>(dtype, R, box); }
 
 }  // namespace stencil

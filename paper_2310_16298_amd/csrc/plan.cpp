@@ -553,6 +553,7 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     if (path == STENCIL_PATH_GATHER && (d.time_block > 1 || tb_auto > 1)) {
       rs->family = FAM_TB2D;
       rs->pick = find_tb2d(d.dtype, R, box);
+      rs->pick_batch = find_tb2d_batch(d.dtype, R, box);
       rs->time_block = d.time_block > 1 ? d.time_block : tb_auto;
       rs->tb_auto = tb_auto > 1;
       in.time_block = rs->time_block;
@@ -738,6 +739,7 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     if (path == STENCIL_PATH_GATHER && tb3 > 1) {
       rs->family = FAM_TB3D;
       rs->pick = find_tb3d(d.dtype, R, box);
+      rs->pick_batch = find_tb3d_batch(d.dtype, R, box);
       rs->time_block = tb3;
       rs->tb_auto = d.time_block <= 1;
       in.time_block = tb3;

@@ -40,8 +40,13 @@ struct Resolved {
   KArgs args{};             // everything but in/out
   int32_t chunk_req = 0;    // requested rows (2D) per work item, 0 = library choice
   int32_t time_block = 1;   // steps per launch
-  bool tb_auto = false;     // time_block chosen by the library (AUTO): batches run such plans one step per launch
+  bool tb_auto = false;     // time_block chosen by the library (AUTO): batches may time-block such plans
   Picker pick = nullptr;
+  // The kernel of a time-blocked launch when the grid is one of many in a
+  // batched launch (nullptr: pick).  A grid's own pick is sized for the grid
+  // alone, where a small grid leaves most CUs idle; among many grids the
+  // chip is full, and forms that buy occupancy with redundant work lose.
+  Picker pick_batch = nullptr;
 };
 
 // Validate + resolve + pack (no device calls).  Returns a stencil status.
@@ -78,9 +83,11 @@ Picker find_mfma3d(int dtype, int R, bool box);
 Picker find_mfma3d_b4(int R, bool box);  // FP32 n = 4 blocks: stars, 27-point box
 Picker find_split3d(int kind, int R, bool box, bool hybrid);  // hybrid: stars, lines along j and k on MFMA
 Picker find_tb2d(int dtype, int R, bool box);
+Picker find_tb2d_batch(int dtype, int R, bool box);  // among many grids: FP64 tiles of full height
 Picker find_tb3d(int dtype, int R, bool box);  // two steps per launch
+Picker find_tb3d_batch(int dtype, int R, bool box);  // among many grids: the streaming form or none
 Picker find_tbm2d(int R);  // FP32 2D box outer products, two steps per launch
-bool tb3d_built(int dtype, int R, bool box);    // F32: stars r <= 2, the 27-point box; F64: r = 1
+bool tb3d_built(int dtype, int R, bool box);    // F32: stars r <= 4, the 27-point box; F64: r = 1
 int tb2d_max_steps(int dtype, int R);  // largest time_block of the time-blocked kernel
 
 hipError_t launch_error_norms(const void* a, int a_dtype, const double* ref, int64_t n, double* out,

@@ -118,13 +118,15 @@ inline stencil_status_t check_device(int device) {
 }
 
 // The resolved plan's args with the two buffers and the launch's step count
-// filled in, its kernel picked and the decomposition applied.
-inline Kernel plan_kernel(const Resolved& rs, const void* in, void* out, KArgs* a, int fused = 1) {
+// filled in, its kernel picked (by `pick`, else the plan's own picker) and the
+// decomposition applied.
+inline Kernel plan_kernel(const Resolved& rs, const void* in, void* out, KArgs* a, int fused = 1,
+                          Picker pick = nullptr) {
   *a = rs.args;
   a->in = in;
   a->out = out;
   a->steps = fused;
-  return rs.pick(*a, rs.chunk_req);
+  return (pick ? pick : rs.pick)(*a, rs.chunk_req);
 }
 
 // One launch: one step, or `fused` steps of a time-blocked plan.

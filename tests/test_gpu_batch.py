@@ -156,3 +156,65 @@ def test_batch_general_nonzero_tap_gather():
         tol = error_bound(ce, a0.ndim, r, st.BOX, dt, st.PATH_GATHER, 3, np.abs(a0).max())
         assert np.abs(got.astype(np.float64) - want).max() <= tol
     batch.close()
+
+
+# Plans the library time-blocks (AUTO on 2D grids wider than 64 columns with a
+# column extent that is a multiple of 4, 3D order-1 grids of at most 64^3
+# points or planes of many tiles), with plain ones beside them.
+TB_MIXED = [
+    ((200, 136), 1, st.BOX, st.BC_PERIODIC, st.F32, st.PATH_AUTO),
+    ((150, 260), 2, st.STAR, st.BC_ZERO, st.F32, st.PATH_AUTO),
+    ((96, 132), 3, st.BOX, st.BC_ZERO, st.F32, st.PATH_AUTO),
+    ((120, 200), 4, st.STAR, st.BC_PERIODIC, st.F32, st.PATH_AUTO),
+    ((130, 136), 1, st.STAR, st.BC_ZERO, st.F64, st.PATH_AUTO),
+    ((520, 1040), 1, st.BOX, st.BC_PERIODIC, st.F64, st.PATH_AUTO),
+    ((100, 100), 2, st.BOX, st.BC_ZERO, st.F64, st.PATH_AUTO),
+    ((16, 24, 32), 1, st.STAR, st.BC_ZERO, st.F32, st.PATH_AUTO),
+    ((8, 256, 260), 1, st.STAR, st.BC_PERIODIC, st.F32, st.PATH_AUTO),
+    ((20, 30, 64), 1, st.BOX, st.BC_ZERO, st.F64, st.PATH_AUTO),
+    ((77, 45), 2, st.BOX, st.BC_ZERO, st.F32, st.PATH_MFMA),
+    ((64, 64), 1, st.BOX, st.BC_ZERO, st.F64, st.PATH_GATHER),
+    ((90, 62), 2, st.STAR, st.BC_PERIODIC, st.F32, st.PATH_AUTO),
+]
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 7, 10, 17])
+def test_time_blocked_batch_equals_alone(steps):
+    """Grids whose plans the library time-blocked advance up to T steps per
+    batched launch (a schedule whose launch count has the parity of the step
+    count); every grid ends in buffer steps % 2, bit for bit equal to its
+    plan's own run_steps, and within the oracle's bound."""
+    torch = torch_cuda()
+    ms = [_member(torch, spec, 7500 + 10 * k) for k, spec in enumerate(TB_MIXED)]
+    assert sum(m[0].info["time_block"] > 1 for m in ms) >= 9
+    batch = st.Batch([m[0] for m in ms], [m[3] for m in ms], [m[4] for m in ms])
+    idx = batch.run_steps(steps)
+    torch.cuda.synchronize()
+    assert idx == steps % 2
+    for k, (plan, c, a0, x, y) in enumerate(ms):
+        got = (x if idx == 0 else y).cpu().numpy()
+        assert np.array_equal(got, _alone(torch, plan, a0, steps)), f"member {k} {TB_MIXED[k]}"
+    for k in (0, 5, 8):
+        plan, c, a0, x, y = ms[k]
+        dims, r, shape, bc, dt, path = TB_MIXED[k]
+        got = (x if idx == 0 else y).cpu().numpy().astype(np.float64)
+        ce = eff_coeffs(c, dt)
+        want = oracle.run(a0.astype(np.float64), ce, r, shape, bc, steps)
+        tol = error_bound(ce, len(dims), r, shape, dt, st.PATH_GATHER, steps, np.abs(a0).max())
+        assert np.abs(got - want).max() <= tol
+    batch.close()
+
+
+def test_time_blocked_batch_repeated_runs():
+    """Graph replays of a batch with time-blocked classes continue the
+    trajectory: three runs of 6 steps (T = 8: two launches of 3; T = 2: four
+    launches, 2 + 2 + 1 + 1) equal one of 18."""
+    torch = torch_cuda()
+    ms = [_member(torch, spec, 7600 + 10 * k) for k, spec in enumerate(TB_MIXED[:7])]
+    batch = st.Batch([m[0] for m in ms], [m[3] for m in ms], [m[4] for m in ms])
+    for _ in range(3):
+        assert batch.run_steps(6) == 0
+    torch.cuda.synchronize()
+    for plan, c, a0, x, y in ms:
+        assert np.array_equal(x.cpu().numpy(), _alone(torch, plan, a0, 18))
+    batch.close()
