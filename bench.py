@@ -229,9 +229,9 @@ def workload_grid3d(args, torch, st, inputs) -> dict:
             for name, path, tb in paths:
                 if want_paths is not None and name not in want_paths:
                     continue
-                if shape == st.BOX and r > 1 and path != st.PATH_GATHER and (path != st.PATH_MFMA or
-                                                                           (dt == st.F64 and r > 2)):
-                    continue  # 3D boxes beyond r = 1: gather and outer products (FP64: r <= 2)
+                if shape == st.BOX and r > 1 and (path == st.PATH_AUTO or
+                                                  (path == st.PATH_MFMA and dt == st.F64 and r > 2)):
+                    continue  # 3D boxes beyond r = 1: gather, outer products (FP64: r <= 2), split products
                 if tb and st.desc_check(dims, r, shape, c, boundary=st.BC_ZERO, dtype=dt, path=path,
                                         time_block=tb) != st.OK:
                     continue  # no time-blocked kernel for this stencil

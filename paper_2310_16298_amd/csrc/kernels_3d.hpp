@@ -722,7 +722,17 @@ __global__ __launch_bounds__(kThreads) void mfma3d_b4box_batch(BatchArgs b) {
 // the plane order of Algorithm 1.  Lines run along k: CLS(a, b, *) adds
 // D[p][q] += sum_y H[p + b][y] * S_{a,b}[y][q], S_{a,b}[y][q] = C^g[a][b][y - q],
 // to output plane i - a + r (window rows shifted by b as the A operand).
-// Box (27-point, r = 1): all (2r+1)^2 lines on MFMA.  Star: the k line
+// Box: all (2r+1)^2 lines on MFMA; at r = 1 their 27 x 2 band fragments
+// stay in registers.  From r = 2 (25 to 81 lines) they come from an LDS
+// table: lane (g, q) of line (a, b) holds S_{a,b}[8 g + e][q] = C^g[a][b][d + e]
+// (e = 0..7, d = 8 g - q), which is zero unless d lies in -7 .. 2r, so a line
+// has only 2r + 8 distinct nonzero fragments per hi / lo part.  The parts'
+// blocks follow each other, a zero fragment before each and after the last,
+// and a lane reads entry clamp(d + 8, 0, 2r + 9) of every block (the last is
+// the next block's zero): one lane address, the blocks at immediate
+// offsets.  The A operand (window rows shifted by b) is read once per b and
+// feeds the lines of all 2r + 1 planes a; the reads of a line go out two
+// lines ahead of its products.  Star: the k line
 // CLS(r, r, *) on MFMA; the other 4r lines hold one weight each and are vector
 // FMAs on the FP32 window (j arm on the centre plane, i arm into the other
 // ring slots), pre-multiplied by the plan's coefficient scale.  Each staged
@@ -738,17 +748,44 @@ struct Split3DShape {
   static_assert((kTK - 32) + 16 + 32 <= P && WEND <= P, "pitch too small");
 };
 
+// Issue order of the box lines' LDS reads and MFMAs (line n = plane a =
+// n mod W, row shift b = n / W): the reads of line n + 2 (its two band
+// fragments, and the four A operands of its b when it opens one) go out
+// ahead of the six products of line n, so the products of two lines cover
+// the LDS latency of every read.
+template <int W>
+constexpr int split_box_reads(int n) { return n >= W * W ? 0 : 2 + (n % W == 0 ? 4 : 0); }
+
+template <int W, int N = 0>
+__device__ __forceinline__ void split_box_schedule() {
+  constexpr int L = W * W, P = 2;
+  if constexpr (N == 0) __builtin_amdgcn_sched_group_barrier(0x100, split_box_reads<W>(0) + split_box_reads<W>(1), 0);
+  if constexpr (N < L) {
+    if constexpr (N + P < L) __builtin_amdgcn_sched_group_barrier(0x100, split_box_reads<W>(N + P), 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);
+    split_box_schedule<W, N + 1>();
+  }
+}
+
 template <int KIND, int R, bool BOX, bool DMA>
 __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
   typedef Split3DShape<R, BOX> S;
   typedef PlaneWalk<float, R, S::WROWS, DMA> PW;
   constexpr int W = S::W;
   // one LDS object (separate ones make the compiler wait for the plane in
-  // flight before LDS accesses): the plane buffers, then the hi and lo planes
+  // flight before LDS accesses): the plane buffers, then the hi and lo
+  // planes, then (box, r >= 2) the band fragment table
+  constexpr bool TABLE = BOX && R >= 2;
+  constexpr int ND = 2 * R + 8;                                 // nonzero fragments of a line, d = -7 .. 2r
+  constexpr int NB = ND + 1;                                    // stride of a line's part: zero, d = -7 .. 2r
+  static_assert(ND <= 16, "a fragment's source lane is 16 + 15 - (d + 7)");
   constexpr int PLANE = (S::WROWS * S::P * 2 + 15) / 16 * 4;  // floats per 16-bit plane
-  __shared__ __attribute__((aligned(16))) float bufs[PW::NBUF * PW::BUF + 2 * PLANE];
+  constexpr int TAB0 = round_up(PW::NBUF * PW::BUF + 2 * PLANE, 4);
+  constexpr int NTAB = TABLE ? S::NL * 2 * NB + 1 : 0;         // fragments, a zero one last
+  __shared__ __attribute__((aligned(16))) float bufs[TAB0 + 4 * NTAB];
   uint16_t* lhi = reinterpret_cast<uint16_t*>(bufs + PW::NBUF * PW::BUF);
   uint16_t* llo = reinterpret_cast<uint16_t*>(bufs + PW::NBUF * PW::BUF + PLANE);
+  u16x8* tab = reinterpret_cast<u16x8*>(bufs + TAB0);
 
   const Chunk3D ch = decode_chunk(a, item);
   const int64_t Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
@@ -758,11 +795,27 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
   const int g = lane >> 4, q = lane & 15;
 
   const u16x8* __restrict__ frag = (const u16x8*)a.frag;
-  u16x8 bh[S::NL], bl[S::NL];
+  constexpr int NLR = TABLE ? 1 : S::NL;  // lines whose fragments sit in registers
+  u16x8 bh[NLR], bl[NLR];
+  // table: fragment (line l, part h, d) at (2 l + h) NB + d + 8, copied from
+  // lane 16 + 8 - d of the packed fragments (g = 1, q = 8 - d); the entries
+  // at multiples of NB are zero
+  const u16x8* tlane = tab;
+  if constexpr (TABLE) {
+    for (int e = threadIdx.x; e < NTAB; e += kThreads) {
+      u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+      const int lh = e / NB, i = e - lh * NB;
+      if (i != 0) v = frag[lh * 64 + 32 - i];
+      tab[e] = v;
+    }
+    const int di = 8 * g - q + 8;
+    tlane = tab + (di < 0 ? 0 : di > NB ? NB : di);
+  } else {
 #pragma unroll
-  for (int l = 0; l < S::NL; ++l) {
-    bh[l] = frag[(l * 2 + 0) * 64 + lane];
-    bl[l] = frag[(l * 2 + 1) * 64 + lane];
+    for (int l = 0; l < S::NL; ++l) {
+      bh[l] = frag[(l * 2 + 0) * 64 + lane];
+      bl[l] = frag[(l * 2 + 1) * 64 + lane];
+    }
   }
   const float cscale = 1.0f / a.out_scale;  // exact power of two
   float cj[W], ci[W];                        // star: j-arm and i-arm weights, scaled
@@ -810,24 +863,53 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
           *reinterpret_cast<uint32_t*>(llo + row * S::P + y) = (uint32_t)l0 | ((uint32_t)l1 << 16);
         }
         lds_barrier();
-#pragma unroll
-        for (int ap = 0; ap < W; ++ap) {
-          if (!BOX && ap != R) continue;
-          const int slot = 2 * R - ap;
+        if constexpr (TABLE) {
+          // per accumulator the products come in the order of the loop below
+          // (b ascending; hi*lo before lo*hi)
 #pragma unroll
           for (int b = 0; b < W; ++b) {
-            if (!BOX && b != R) continue;
-            const int l = BOX ? ap * W + b : 0;
             const uint16_t* ph = lhi + (16 * wj + b + q) * S::P + 32 * wk + 8 * g;
             const uint16_t* pl = llo + (16 * wj + b + q) * S::P + 32 * wk + 8 * g;
+            u16x8 ah[2], al[2];
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-              const u16x8 ah = *reinterpret_cast<const u16x8*>(ph + 16 * t);
-              const u16x8 al = *reinterpret_cast<const u16x8*>(pl + 16 * t);
-              const int xs = BOX ? slot : 0;
-              acc[slot][t] = Split16<KIND>::mma(ah, bh[l], acc[slot][t]);
-              acx[xs][t] = Split16<KIND>::mma(ah, bl[l], acx[xs][t]);
-              acx[xs][t] = Split16<KIND>::mma(al, bh[l], acx[xs][t]);
+              ah[t] = *reinterpret_cast<const u16x8*>(ph + 16 * t);
+              al[t] = *reinterpret_cast<const u16x8*>(pl + 16 * t);
+            }
+#pragma unroll
+            for (int ap = 0; ap < W; ++ap) {
+              const int slot = 2 * R - ap, l = ap * W + b;
+              const u16x8 vh = tlane[2 * l * NB], vl = tlane[(2 * l + 1) * NB];
+#pragma unroll
+              for (int t = 0; t < 2; ++t) {
+                acc[slot][t] = Split16<KIND>::mma(ah[t], vh, acc[slot][t]);
+                acx[slot][t] = Split16<KIND>::mma(ah[t], vl, acx[slot][t]);
+                acx[slot][t] = Split16<KIND>::mma(al[t], vh, acx[slot][t]);
+              }
+            }
+          }
+          split_box_schedule<W>();
+          __builtin_amdgcn_sched_barrier(0);
+        } else {
+#pragma unroll
+          for (int ap = 0; ap < W; ++ap) {
+            if (!BOX && ap != R) continue;
+            const int slot = 2 * R - ap;
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
+              if (!BOX && b != R) continue;
+              const int l = BOX ? ap * W + b : 0;
+              const uint16_t* ph = lhi + (16 * wj + b + q) * S::P + 32 * wk + 8 * g;
+              const uint16_t* pl = llo + (16 * wj + b + q) * S::P + 32 * wk + 8 * g;
+#pragma unroll
+              for (int t = 0; t < 2; ++t) {
+                const u16x8 ah = *reinterpret_cast<const u16x8*>(ph + 16 * t);
+                const u16x8 al = *reinterpret_cast<const u16x8*>(pl + 16 * t);
+                const int xs = BOX ? slot : 0;
+                acc[slot][t] = Split16<KIND>::mma(ah, bh[l], acc[slot][t]);
+                acx[xs][t] = Split16<KIND>::mma(ah, bl[l], acx[xs][t]);
+                acx[xs][t] = Split16<KIND>::mma(al, bh[l], acx[xs][t]);
+              }
             }
           }
         }
@@ -1052,13 +1134,18 @@ __global__ __launch_bounds__(kThreads) void split3d_hybrid_batch(BatchArgs b) {
   for_each_batch_item(b, [&](const KArgs& x, int id) { split3d_hybrid_item<KIND, R, DMA>(x, id); });
 }
 
+// Boxes of order 3: registers for two waves per SIMD (order 2 fits them
+// anyway; at order 4 the LDS holds one workgroup per CU)
+template <int R, bool BOX>
+constexpr int split3d_waves() { return BOX && R == 3 ? 2 : 1; }
+
 template <int KIND, int R, bool BOX, bool DMA>
-__global__ __launch_bounds__(kThreads) void split3d_kernel(KArgs a) {
+__global__ __launch_bounds__(kThreads, (split3d_waves<R, BOX>())) void split3d_kernel(KArgs a) {
   split3d_item<KIND, R, BOX, DMA>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 template <int KIND, int R, bool BOX, bool DMA>
-__global__ __launch_bounds__(kThreads) void split3d_batch(BatchArgs b) {
+__global__ __launch_bounds__(kThreads, (split3d_waves<R, BOX>())) void split3d_batch(BatchArgs b) {
   for_each_batch_item(b, [&](const KArgs& x, int id) { split3d_item<KIND, R, BOX, DMA>(x, id); });
 }
 

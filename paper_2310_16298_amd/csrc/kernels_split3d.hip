@@ -1,5 +1,5 @@
-// Instantiations of the 3D split-precision kernels.  Box: r = 1 (27 points);
-// stars: parallel (k lines on MFMA) and hybrid (j and k lines) covers.
+// Instantiations of the 3D split-precision kernels.  Boxes r = 1..4; stars:
+// parallel (k lines on MFMA) and hybrid (j and k lines) covers.
 #include "kernels_3d.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
@@ -22,7 +22,15 @@ static Kernel pick_split3d_hybrid(KArgs& a, int32_t chunk) {
 
 template <int KIND>
 static Picker pick(int R, bool box, bool hybrid) {
-  if (box) return R == 1 ? pick_split3d<KIND, 1, true> : nullptr;
+  if (box) {
+    switch (R) {
+      case 1: return pick_split3d<KIND, 1, true>;
+      case 2: return pick_split3d<KIND, 2, true>;
+      case 3: return pick_split3d<KIND, 3, true>;
+      case 4: return pick_split3d<KIND, 4, true>;
+    }
+    return nullptr;
+  }
   if (hybrid) {
     switch (R) {
       case 1: return pick_split3d_hybrid<KIND, 1>;

@@ -99,6 +99,31 @@ def test_fullsize_3d_windows(grid3, dtype, shape, r, path):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("path", [st.PATH_MFMA_BF16X3, st.PATH_MFMA_F16X3])
+@pytest.mark.parametrize("r", [2, 3, 4])
+def test_fullsize_3d_split_box(grid3, path, r):
+    """FP32 3D boxes of order 2-4 on the split-precision outer products
+    (band fragments from the LDS table) at 512^3, zero halo, on the sampled
+    8^3 windows against the FP64 oracle with the split bound."""
+    torch = torch_cuda()
+    c = inputs.coefficients(3, r, st.BOX, seed=3100 + 10 * st.BOX + r, dtype=np.float64)
+    ce = eff_coeffs(c, st.F32)
+    a0 = grid3.astype(np.float32)
+    plan = st.Plan(DIMS3, r, st.BOX, c, boundary=st.BC_ZERO, dtype=st.F32, path=path)
+    assert plan.info["path"] == path and plan.info["mfma_lines"] == (2 * r + 1) ** 2
+    x = torch.from_numpy(a0).cuda()
+    res = plan.run_steps(x, torch.empty_like(x), STEPS3)
+    torch.cuda.synchronize()
+    tol = error_bound(ce, 3, r, st.BOX, st.F32, path, STEPS3, 1.0)
+    for lo in WINDOWS3:
+        want = oracle.window(a0, ce, r, st.BOX, st.BC_ZERO, STEPS3, lo, (8, 8, 8))
+        got = res[lo[0]:lo[0] + 8, lo[1]:lo[1] + 8, lo[2]:lo[2] + 8].cpu().numpy().astype(np.float64)
+        assert np.abs(got - want).max() <= tol, (lo, np.abs(got - want).max(), tol)
+    plan.close()
+    del x, res
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("path,tb", [(st.PATH_AUTO, 0), (st.PATH_GATHER, 0), (st.PATH_MFMA, 0),
                                      (st.PATH_GATHER, 5), (st.PATH_GATHER, 8)])
 def test_fullsize_512_fp64_star(path, tb):

@@ -29,8 +29,7 @@ def combos():
                 out.append((st.PATH_MFMA, dt, st.BOX, r))
         for p in (BF, FH):
             out.append((p, st.F32, st.STAR, r))
-            if r == 1:
-                out.append((p, st.F32, st.BOX, r))
+            out.append((p, st.F32, st.BOX, r))
     return out
 
 

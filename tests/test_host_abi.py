@@ -639,3 +639,17 @@ def test_tile_knobs(lib):
     assert st.desc_check((256, 512), 3, inputs.BOX, c, path=st.PATH_GATHER, reg_rows=16, tile_width=256) == st.OK
     # gather and 3D plans report no tile
     assert st.describe((256, 512), 3, inputs.BOX, c, path=st.PATH_GATHER)["reg_rows"] == 0
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_split_3d_boxes_resolve(r):
+    """FP32 3D boxes of every order take the split-precision products: all
+    (2r+1)^2 lines along k on 16x16x32 MFMAs (K = 32 per line), three
+    products (hi*hi, hi*lo, lo*hi) each; FP64 has no split path."""
+    w = 2 * r + 1
+    for path in (st.PATH_MFMA_BF16X3, st.PATH_MFMA_F16X3):
+        info = st.describe((16, 16, 16), r, inputs.BOX, _box(3, r), path=path)
+        assert info["path"] == path and info["mfma_lines"] == w * w and info["valu_lines"] == 0
+        assert info["k_rows"] == 32 * w * w
+        assert info["executed_flops_per_point"] == 3.0 * 2.0 * 32 * w * w
+        assert st.desc_check((16, 16, 16), r, inputs.BOX, _box(3, r), dtype=st.F64, path=path) == st.EUNSUPPORTED
