@@ -744,7 +744,10 @@ struct Split3DShape {
   static constexpr int NL = BOX ? W * W : 1;
   static constexpr int WROWS = kTJ + 2 * R;
   static constexpr int WEND = kTK + 2 * R;
-  static constexpr int P = 88;  // 16-bit pitch: multiple of 8, covers columns read by K = 32
+  // 16-bit pitch: multiple of 8, covers the columns read by K = 32; 88
+  // spreads a read's 16 rows over all LDS banks, 80 leaves the order-4 box
+  // (with its fragment table) under half the LDS: two workgroups per CU
+  static constexpr int P = BOX && R == 4 ? 80 : 88;
   static_assert((kTK - 32) + 16 + 32 <= P && WEND <= P, "pitch too small");
 };
 
@@ -1134,18 +1137,18 @@ __global__ __launch_bounds__(kThreads) void split3d_hybrid_batch(BatchArgs b) {
   for_each_batch_item(b, [&](const KArgs& x, int id) { split3d_hybrid_item<KIND, R, DMA>(x, id); });
 }
 
-// Boxes of order 3: registers for two waves per SIMD (order 2 fits them
-// anyway; at order 4 the LDS holds one workgroup per CU)
-template <int R, bool BOX>
-constexpr int split3d_waves() { return BOX && R == 3 ? 2 : 1; }
+// Boxes of order 3 and 4 (direct-to-LDS planes): registers for two waves
+// per SIMD (order 2 fits them anyway)
+template <int R, bool BOX, bool DMA>
+constexpr int split3d_waves() { return BOX && (R == 3 || (R == 4 && DMA)) ? 2 : 1; }
 
 template <int KIND, int R, bool BOX, bool DMA>
-__global__ __launch_bounds__(kThreads, (split3d_waves<R, BOX>())) void split3d_kernel(KArgs a) {
+__global__ __launch_bounds__(kThreads, (split3d_waves<R, BOX, DMA>())) void split3d_kernel(KArgs a) {
   split3d_item<KIND, R, BOX, DMA>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 template <int KIND, int R, bool BOX, bool DMA>
-__global__ __launch_bounds__(kThreads, (split3d_waves<R, BOX>())) void split3d_batch(BatchArgs b) {
+__global__ __launch_bounds__(kThreads, (split3d_waves<R, BOX, DMA>())) void split3d_batch(BatchArgs b) {
   for_each_batch_item(b, [&](const KArgs& x, int id) { split3d_item<KIND, R, BOX, DMA>(x, id); });
 }
 
