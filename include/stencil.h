@@ -99,7 +99,8 @@ typedef enum {
                                    stencil_plan_info reports the choice */
   STENCIL_PATH_GATHER = 1,      /* gather-form vector kernel, Eq. (1) */
   STENCIL_PATH_MFMA = 2,        /* outer-product form on MFMA in the grid dtype (FP32 or FP64) */
-  STENCIL_PATH_MFMA_BF16X3 = 3, /* outer-product form, BF16 hi/lo split operands (3 products), FP32 accumulate; F32 grids */
+  STENCIL_PATH_MFMA_BF16X3 = 3, /* outer-product form, BF16 hi/lo split operands (3 products), FP32 accumulate; F32 grids
+                                  (2D stars and boxes, 3D stars and boxes r = 1..4) */
   STENCIL_PATH_MFMA_F16X3 = 4   /* outer-product form, FP16 hi/lo split operands (3 products), FP32 accumulate; F32 grids */
 } stencil_path_t;
 
