@@ -16,6 +16,9 @@
 // that do not allow 16-byte lines) each plane is staged synchronously.
 #pragma once
 
+#include <type_traits>
+#include <utility>
+
 #include "device_common.hpp"
 #include "dma3d.hpp"
 #include "kernels_2d.hpp"
@@ -160,6 +163,60 @@ struct PlaneWalk {
       finish(ch.ib + u - 2 * R, u >= 2 * R);
       if constexpr (DMA) lds_barrier();
     }
+  }
+
+  // As walk, with the loop over planes unrolled by W: body(win, valid, ph)
+  // and finish(o, live, ph) receive ph = u mod W as a std::integral_constant,
+  // so a caller can keep its ring of 2r+1 output planes in place and rotate
+  // the slot it names (slot z of plane u in register (z + ph) mod W) instead
+  // of moving every accumulator down one slot after each plane.
+  template <class Body, class Finish>
+  static __device__ __forceinline__ void walk_phased(T* bufs, const KArgs& a, const Chunk3D& ch, Body body,
+                                                     Finish finish) {
+    const int64_t Ni = a.d0, Nj = a.d1, Nk = a.d2, plane = Nj * Nk;
+    const bool periodic = a.periodic != 0;
+    const T* __restrict__ in = (const T*)a.in;
+    const T* __restrict__ zeros = (const T*)a.zeros;
+    const int nu = (int)(ch.iend - ch.ib) + 2 * R;
+    typename D::Lines lines;
+    if constexpr (DMA) {
+      D::prepare(lines, Nj, Nk, ch.j0 - R, ch.k0, periodic);
+      const int64_t g0 = map_index(ch.ib - R, Ni, periodic);
+      D::issue(bufs, g0 >= 0 ? in + g0 * plane : nullptr, zeros, lines);
+    } else {
+      zero_region<T, kThreads>(bufs, LROWS, PITCH, PITCH, 0, 0);
+    }
+    auto step = [&](int u, auto ph) __attribute__((always_inline)) {
+      const int64_t gi = map_index(ch.ib - R + u, Ni, periodic);
+      const T* win;
+      if constexpr (DMA) {
+        win = bufs + (u & 1) * BUF;
+        if (u + 1 < nu) {
+          const int64_t g1 = map_index(ch.ib - R + u + 1, Ni, periodic);
+          D::issue(bufs + ((u + 1) & 1) * BUF, g1 >= 0 ? in + g1 * plane : nullptr, zeros, lines);
+          D::template wait_vm<D::NPW>();
+        } else {
+          D::template wait_vm<0>();
+        }
+        lds_barrier();
+      } else {
+        win = bufs;
+        __syncthreads();
+        if (gi >= 0)
+          stage_window<T, R, kTJ + 2 * R, kTK, PITCH, kThreads, COL0>(bufs, in + gi * plane, Nj, Nk, ch.j0 - R,
+                                                                     ch.k0, periodic);
+        __syncthreads();
+      }
+      body(win, gi >= 0, ph);
+      finish(ch.ib + u - 2 * R, u >= 2 * R, ph);
+      if constexpr (DMA) lds_barrier();
+    };
+    for (int u0 = 0; u0 < nu; u0 += W) phases(step, u0, nu, std::make_integer_sequence<int, W>{});
+  }
+
+  template <class Step, int... P>
+  static __device__ __forceinline__ void phases(Step& step, int u0, int nu, std::integer_sequence<int, P...>) {
+    ((u0 + P < nu ? step(u0 + P, std::integral_constant<int, P>{}) : void()), ...);
   }
 };
 
@@ -849,10 +906,14 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
 #pragma unroll
     for (int t = 0; t < 2; ++t) acx[z][t] = floatx4{0, 0, 0, 0};
   // ring slot z holds output plane i - r + z while input plane i is
-  // scattered; slot 0 is stored after the plane and the ring shifts down
-  PW::walk(
-      bufs, a, ch,
-      [&](const float* win, bool valid) {
+  // scattered; slot 0 is stored after the plane.  Stars and the 27-point box
+  // rotate the ring: at plane phase PH (input plane u, PH = u mod W) slot z
+  // sits in register set (z + PH) mod W, and the stored set is cleared for
+  // the next plane's top slot.  The table boxes (order >= 2: up to 486 MFMAs
+  // per plane) keep one copy of the plane code and shift the ring down.
+  constexpr bool ROT = !TABLE;
+  auto body = [&](const float* win, bool valid, auto phase) __attribute__((always_inline)) {
+        constexpr int PH = ROT ? decltype(phase)::value : 0;
         if (!valid) return;
         // split the FP32 window into hi/lo planes
         constexpr int HALF = S::WEND / 2;
@@ -881,7 +942,7 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
             }
 #pragma unroll
             for (int ap = 0; ap < W; ++ap) {
-              const int slot = 2 * R - ap, l = ap * W + b;
+              const int slot = (2 * R - ap + PH) % W, l = ap * W + b;
               const u16x8 vh = tlane[2 * l * NB], vl = tlane[(2 * l + 1) * NB];
 #pragma unroll
               for (int t = 0; t < 2; ++t) {
@@ -897,7 +958,7 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
 #pragma unroll
           for (int ap = 0; ap < W; ++ap) {
             if (!BOX && ap != R) continue;
-            const int slot = 2 * R - ap;
+            const int slot = (2 * R - ap + PH) % W;
 #pragma unroll
             for (int b = 0; b < W; ++b) {
               if (!BOX && b != R) continue;
@@ -919,7 +980,7 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
         if constexpr (!BOX) {
 #pragma unroll
           for (int t = 0; t < 2; ++t) {
-            acc[R][t] += ls * acx[0][t];
+            acc[(R + PH) % W][t] += ls * acx[0][t];
             acx[0][t] = floatx4{0, 0, 0, 0};
           }
         }
@@ -935,18 +996,19 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
                 if (b == R) continue;
                 sj += cj[b] * cp[b * PW::PITCH + 16 * t];
               }
-              acc[R][t][v] += sj;
+              acc[(R + PH) % W][t][v] += sj;
               const float ctr = cp[R * PW::PITCH + 16 * t];
 #pragma unroll
               for (int ap = 0; ap < W; ++ap) {
                 if (ap == R) continue;
-                acc[2 * R - ap][t][v] += ci[ap] * ctr;
+                acc[(2 * R - ap + PH) % W][t][v] += ci[ap] * ctr;
               }
             }
           }
         }
-      },
-      [&](int64_t o, bool live) {
+  };
+  auto finish = [&](int64_t o, bool live, auto phase) __attribute__((always_inline)) {
+        constexpr int Z0 = ROT ? decltype(phase)::value : 0;  // register set of slot 0
         if (live) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
@@ -954,24 +1016,34 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
               const int64_t gk = ch.k0 + 32 * wk + 16 * t + q;
-              const float v0 = BOX ? acc[0][t][v] + ls * acx[0][t][v] : acc[0][t][v];
+              const float v0 = BOX ? acc[Z0][t][v] + ls * acx[Z0][t][v] : acc[Z0][t][v];
               if (gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = v0 * os;
             }
           }
         }
+        if constexpr (!ROT) {
 #pragma unroll
-        for (int z = 0; z < 2 * R; ++z)
+          for (int z = 0; z < 2 * R; ++z)
 #pragma unroll
-          for (int t = 0; t < 2; ++t) {
-            acc[z][t] = acc[z + 1][t];
-            if constexpr (BOX) acx[z][t] = acx[z + 1][t];
-          }
+            for (int t = 0; t < 2; ++t) {
+              acc[z][t] = acc[z + 1][t];
+              if constexpr (BOX) acx[z][t] = acx[z + 1][t];
+            }
+        }
+        constexpr int ZT = ROT ? Z0 : 2 * R;  // the next plane's top slot
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          acc[2 * R][t] = floatx4{0, 0, 0, 0};
-          if constexpr (BOX) acx[2 * R][t] = floatx4{0, 0, 0, 0};
+          acc[ZT][t] = floatx4{0, 0, 0, 0};
+          if constexpr (BOX) acx[ZT][t] = floatx4{0, 0, 0, 0};
         }
-      });
+  };
+  if constexpr (ROT) {
+    PW::walk_phased(bufs, a, ch, body, finish);
+  } else {
+    PW::walk(
+        bufs, a, ch, [&](const float* win, bool valid) { body(win, valid, std::integral_constant<int, 0>{}); },
+        [&](int64_t o, bool live) { finish(o, live, std::integral_constant<int, 0>{}); });
+  }
 }
 
 // ---------------------------------------------------------------------------
