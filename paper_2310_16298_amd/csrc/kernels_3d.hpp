@@ -1119,10 +1119,13 @@ __device__ __forceinline__ void split3d_hybrid_item(const KArgs& a, int item) {
 #pragma unroll
     for (int t = 0; t < 2; ++t) acc[z][t] = floatx4{0, 0, 0, 0};
   // ring slot z holds output plane i - r + z while input plane i is
-  // scattered; slot 0 is stored after the plane and the ring shifts down
-  PW::walk(
+  // scattered, in register set (z + PH) mod W at plane phase PH (the ring
+  // rotates: slot 0 is stored after the plane and its set cleared for the
+  // next plane's top slot)
+  PW::walk_phased(
       bufs, a, ch,
-      [&](const float* win, bool valid) {
+      [&](const float* win, bool valid, auto phase) __attribute__((always_inline)) {
+        constexpr int PH = decltype(phase)::value;
         if (!valid) return;
         // split the FP32 window into hi/lo planes, two columns per thread and step
         constexpr int HALF = S::WCOLS / 2;
@@ -1148,7 +1151,7 @@ __device__ __forceinline__ void split3d_hybrid_item(const KArgs& a, int item) {
         for (int t = 0; t < 2; ++t) {
           const u16x8 ah = *reinterpret_cast<const u16x8*>(pkh + 16 * t);
           const u16x8 al = *reinterpret_cast<const u16x8*>(pkl + 16 * t);
-          acc[R][t] = Split16<KIND>::mma(ah, kh, acc[R][t]);
+          acc[(R + PH) % W][t] = Split16<KIND>::mma(ah, kh, acc[(R + PH) % W][t]);
           acx[t] = Split16<KIND>::mma(ah, kl, acx[t]);
           acx[t] = Split16<KIND>::mma(al, kh, acx[t]);
           u16x8 bh, bl;
@@ -1157,7 +1160,7 @@ __device__ __forceinline__ void split3d_hybrid_item(const KArgs& a, int item) {
             bh[e] = pjh[e * S::P + 16 * t];
             bl[e] = pjl[e * S::P + 16 * t];
           }
-          acc[R][t] = Split16<KIND>::mma(jh, bh, acc[R][t]);
+          acc[(R + PH) % W][t] = Split16<KIND>::mma(jh, bh, acc[(R + PH) % W][t]);
           acx[t] = Split16<KIND>::mma(jl, bh, acx[t]);
           acx[t] = Split16<KIND>::mma(jh, bl, acx[t]);
         }
@@ -1171,14 +1174,15 @@ __device__ __forceinline__ void split3d_hybrid_item(const KArgs& a, int item) {
 #pragma unroll
             for (int ap = 0; ap < W; ++ap) {
               if (ap == R) continue;
-              acc[2 * R - ap][t][v] += ci[ap] * ctr;
+              acc[(2 * R - ap + PH) % W][t][v] += ci[ap] * ctr;
             }
           }
         }
 #pragma unroll
-        for (int t = 0; t < 2; ++t) acc[R][t] += ls * acx[t];
+        for (int t = 0; t < 2; ++t) acc[(R + PH) % W][t] += ls * acx[t];
       },
-      [&](int64_t o, bool live) {
+      [&](int64_t o, bool live, auto phase) __attribute__((always_inline)) {
+        constexpr int Z0 = decltype(phase)::value;  // register set of slot 0
         if (live) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
@@ -1186,16 +1190,12 @@ __device__ __forceinline__ void split3d_hybrid_item(const KArgs& a, int item) {
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
               const int64_t gk = ch.k0 + 32 * wk + 16 * t + q;
-              if (gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = acc[0][t][v] * os;
+              if (gj < Nj && gk < Nk) out[o * plane + gj * Nk + gk] = acc[Z0][t][v] * os;
             }
           }
         }
 #pragma unroll
-        for (int z = 0; z < 2 * R; ++z)
-#pragma unroll
-          for (int t = 0; t < 2; ++t) acc[z][t] = acc[z + 1][t];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) acc[2 * R][t] = floatx4{0, 0, 0, 0};
+        for (int t = 0; t < 2; ++t) acc[Z0][t] = floatx4{0, 0, 0, 0};
       });
 }
 
