@@ -266,9 +266,13 @@ __device__ __forceinline__ void gather3d_item(const KArgs& a, int item) {
     }
   };
 
-  PW::walk(
-      bufs, a, ch,
-      [&](const T* win, bool valid) {
+  // Stars and the 27-point box rotate the ring: at plane phase PH (input
+  // plane u, PH = u mod W) slot z sits in register set (z + PH) mod W, and
+  // the stored set is cleared for the next plane's top slot.  Larger boxes
+  // (up to 5832 FMAs per plane) keep one copy of the plane code and shift.
+  constexpr bool ROT = !BOX || R == 1;
+  auto body = [&](const T* win, bool valid, auto phase) __attribute__((always_inline)) {
+        constexpr int PH = ROT ? decltype(phase)::value : 0;
         if (!valid) return;  // a zero-halo plane adds nothing
         if constexpr (BOX) {
 #pragma unroll
@@ -285,7 +289,7 @@ __device__ __forceinline__ void gather3d_item(const KArgs& a, int item) {
                 for (int cc = 0; cc < W; ++cc) {
                   const T w = c[(ap * W + bb) * W + cc];
 #pragma unroll
-                  for (int e = 0; e < 4; ++e) ring[2 * R - ap][p][e] += w * v[4 - R + e + cc];
+                  for (int e = 0; e < 4; ++e) ring[(2 * R - ap + PH) % W][p][e] += w * v[4 - R + e + cc];
                 }
             }
           }
@@ -308,7 +312,7 @@ __device__ __forceinline__ void gather3d_item(const KArgs& a, int item) {
               if (bb < 0 || bb > 2 * R) continue;
               const T w = c[(R * W + bb) * W + R];
 #pragma unroll
-              for (int e = 0; e < 4; ++e) ring[R][p][e] += w * v[e];
+              for (int e = 0; e < 4; ++e) ring[(R + PH) % W][p][e] += w * v[e];
             }
           }
           // k arm (centre excluded) and i arm from the block's own rows
@@ -321,19 +325,20 @@ __device__ __forceinline__ void gather3d_item(const KArgs& a, int item) {
               if (cc == R) continue;
               const T w = c[(R * W + R) * W + cc];
 #pragma unroll
-              for (int e = 0; e < 4; ++e) ring[R][p][e] += w * v[4 - R + e + cc];
+              for (int e = 0; e < 4; ++e) ring[(R + PH) % W][p][e] += w * v[4 - R + e + cc];
             }
 #pragma unroll
             for (int ap = 0; ap < W; ++ap) {
               if (ap == R) continue;
               const T w = c[(ap * W + R) * W + R];
 #pragma unroll
-              for (int e = 0; e < 4; ++e) ring[2 * R - ap][p][e] += w * v[4 + e];
+              for (int e = 0; e < 4; ++e) ring[(2 * R - ap + PH) % W][p][e] += w * v[4 + e];
             }
           }
         }
-      },
-      [&](int64_t o, bool live) {
+  };
+  auto finish = [&](int64_t o, bool live, auto phase) __attribute__((always_inline)) {
+        constexpr int Z0 = ROT ? decltype(phase)::value : 0;  // register set of slot 0
         const int64_t gk = ch.k0 + 4 * q4;
         if (live) {
 #pragma unroll
@@ -350,27 +355,37 @@ __device__ __forceinline__ void gather3d_item(const KArgs& a, int item) {
                 V t;
                 T* pt = reinterpret_cast<T*>(&t);
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) pt[e] = ring[0][p][k * VEC + e];
+                for (int e = 0; e < VEC; ++e) pt[e] = ring[Z0][p][k * VEC + e];
                 reinterpret_cast<V*>(dst)[k] = t;
               }
             } else {
 #pragma unroll
               for (int e = 0; e < 4; ++e)
-                if (gk + e < Nk) dst[e] = ring[0][p][e];
+                if (gk + e < Nk) dst[e] = ring[Z0][p][e];
             }
           }
         }
+        if constexpr (!ROT) {
 #pragma unroll
-        for (int z = 0; z < 2 * R; ++z)
+          for (int z = 0; z < 2 * R; ++z)
 #pragma unroll
-          for (int p = 0; p < 2; ++p)
+            for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) ring[z][p][e] = ring[z + 1][p][e];
+              for (int e = 0; e < 4; ++e) ring[z][p][e] = ring[z + 1][p][e];
+        }
+        constexpr int ZT = ROT ? Z0 : 2 * R;  // the next plane's top slot
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
-          for (int e = 0; e < 4; ++e) ring[2 * R][p][e] = T(0);
-      });
+          for (int e = 0; e < 4; ++e) ring[ZT][p][e] = T(0);
+  };
+  if constexpr (ROT) {
+    PW::walk_phased(bufs, a, ch, body, finish);
+  } else {
+    PW::walk(
+        bufs, a, ch, [&](const T* win, bool valid) { body(win, valid, std::integral_constant<int, 0>{}); },
+        [&](int64_t o, bool live) { finish(o, live, std::integral_constant<int, 0>{}); });
+  }
 }
 
 template <typename T, int R, bool BOX, bool DMA>
