@@ -437,14 +437,15 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
     // count is not a multiple of 4 (no direct-to-LDS windows): outer products.
     const bool f32 = d.dtype == STENCIL_F32;
     if (nd == 3) {
-      // FP64 stars of radius 4 too: the hybrid outer products lead the gather
-      // by 10 % at 384^3 and 512^3.  FP32 stars of radius 4 stay on the gather
-      // kernel (ahead by 4 % at 512^3 and 3 % at 256^3, level at 384^3).
+      // Stars of radius 4 stay on the gather kernel: FP32 ahead by 4 % at
+      // 512^3 and 3 % at 256^3, level at 384^3; FP64 (its rotating ring holds
+      // two waves per SIMD) ahead by 17 % at 256^3, level at 512^3, 3 % behind
+      // the hybrid outer products at 384^3.
       // GENERAL with few nonzero taps: the nonzero-tap gather beats the box
       // outer products up to 88 (r = 3) / 128 (r = 4) taps (256^3 FP32)
       static const int kSparse3DAuto[5] = {0, 0, 0, 88, 128};
       const bool few = general && in.taps <= kSparse3DAuto[R];
-      path = (f32 && box && R >= 3 && !few) || (!f32 && !box && R == 4) ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
+      path = f32 && box && R >= 3 && !few ? STENCIL_PATH_MFMA : STENCIL_PATH_GATHER;
       // Time blocking, two steps per launch, on k extents that take
       // direct-to-LDS lines, when every knob is left open; measured on MI355X
       // (zero halo) against the one-step gather: the whole-window form on
