@@ -930,10 +930,12 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
   auto body = [&](const float* win, bool valid, auto phase) __attribute__((always_inline)) {
         constexpr int PH = ROT ? decltype(phase)::value : 0;
         if (!valid) return;
-        // split the FP32 window into hi/lo planes
+        // split the FP32 window into hi/lo planes: every row for a box, the
+        // rows r .. r + TJ - 1 that the star's k line reads
         constexpr int HALF = S::WEND / 2;
-        for (int idx = threadIdx.x; idx < S::WROWS * HALF; idx += kThreads) {
-          const int row = idx / HALF, y = 2 * (idx - (idx / HALF) * HALF);
+        constexpr int SROW0 = BOX ? 0 : R, SROWS = BOX ? S::WROWS : kTJ;
+        for (int idx = threadIdx.x; idx < SROWS * HALF; idx += kThreads) {
+          const int row = SROW0 + idx / HALF, y = 2 * (idx - (idx / HALF) * HALF);
           const float* src = win + row * PW::PITCH + PW::COL0 + y;
           uint16_t h0, l0, h1, l1;
           Split16<KIND>::split(src[0], lo_mul, h0, l0);
