@@ -855,7 +855,12 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
   constexpr int NB = ND + 1;                                    // stride of a line's part: zero, d = -7 .. 2r
   static_assert(ND <= 16, "a fragment's source lane is 16 + 15 - (d + 7)");
   constexpr int PLANE = (S::WROWS * S::P * 2 + 15) / 16 * 4;  // floats per 16-bit plane
-  constexpr int TAB0 = round_up(PW::NBUF * PW::BUF + 2 * PLANE, 4);
+  // stars from order 2 split their k line's A operand in registers (order 1:
+  // 588 vs 554 GStencil/s at 512^3 with the LDS planes, order 4: 439 vs 455
+  // at 384^3 without them)
+  constexpr bool REGA = !BOX && R >= 2;
+  constexpr int NPLANE = REGA ? 0 : 2;  // hi/lo planes
+  constexpr int TAB0 = round_up(PW::NBUF * PW::BUF + NPLANE * PLANE, 4);
   constexpr int NTAB = TABLE ? S::NL * 2 * NB + 1 : 0;         // fragments, a zero one last
   __shared__ __attribute__((aligned(16))) float bufs[TAB0 + 4 * NTAB];
   uint16_t* lhi = reinterpret_cast<uint16_t*>(bufs + PW::NBUF * PW::BUF);
@@ -902,8 +907,10 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
       ci[b] = c[(b * W + R) * W + R] * cscale;
     }
   }
-  zero_region<uint16_t, kThreads>(lhi, S::WROWS, S::P - S::WEND, S::P, 0, S::WEND);
-  zero_region<uint16_t, kThreads>(llo, S::WROWS, S::P - S::WEND, S::P, 0, S::WEND);
+  if constexpr (!REGA) {
+    zero_region<uint16_t, kThreads>(lhi, S::WROWS, S::P - S::WEND, S::P, 0, S::WEND);
+    zero_region<uint16_t, kThreads>(llo, S::WROWS, S::P - S::WEND, S::P, 0, S::WEND);
+  }
   const float lo_mul = 1.0f / a.lo_scale;
   const float ls = a.lo_scale, os = a.out_scale;
 
@@ -930,20 +937,22 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
   auto body = [&](const float* win, bool valid, auto phase) __attribute__((always_inline)) {
         constexpr int PH = ROT ? decltype(phase)::value : 0;
         if (!valid) return;
-        // split the FP32 window into hi/lo planes: every row for a box, the
-        // rows r .. r + TJ - 1 that the star's k line reads
-        constexpr int HALF = S::WEND / 2;
-        constexpr int SROW0 = BOX ? 0 : R, SROWS = BOX ? S::WROWS : kTJ;
-        for (int idx = threadIdx.x; idx < SROWS * HALF; idx += kThreads) {
-          const int row = SROW0 + idx / HALF, y = 2 * (idx - (idx / HALF) * HALF);
-          const float* src = win + row * PW::PITCH + PW::COL0 + y;
-          uint16_t h0, l0, h1, l1;
-          Split16<KIND>::split(src[0], lo_mul, h0, l0);
-          Split16<KIND>::split(src[1], lo_mul, h1, l1);
-          *reinterpret_cast<uint32_t*>(lhi + row * S::P + y) = (uint32_t)h0 | ((uint32_t)h1 << 16);
-          *reinterpret_cast<uint32_t*>(llo + row * S::P + y) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+        if constexpr (!REGA) {
+          // split the FP32 window into hi/lo planes, read by every wave (a
+          // star's k line reads the rows r .. r + TJ - 1)
+          constexpr int HALF = S::WEND / 2;
+          constexpr int SROW0 = BOX ? 0 : R, SROWS = BOX ? S::WROWS : kTJ;
+          for (int idx = threadIdx.x; idx < SROWS * HALF; idx += kThreads) {
+            const int row = SROW0 + idx / HALF, y = 2 * (idx - (idx / HALF) * HALF);
+            const float* src = win + row * PW::PITCH + PW::COL0 + y;
+            uint16_t h0, l0, h1, l1;
+            Split16<KIND>::split(src[0], lo_mul, h0, l0);
+            Split16<KIND>::split(src[1], lo_mul, h1, l1);
+            *reinterpret_cast<uint32_t*>(lhi + row * S::P + y) = (uint32_t)h0 | ((uint32_t)h1 << 16);
+            *reinterpret_cast<uint32_t*>(llo + row * S::P + y) = (uint32_t)l0 | ((uint32_t)l1 << 16);
+          }
+          lds_barrier();
         }
-        lds_barrier();
         if constexpr (TABLE) {
           // per accumulator the products come in the order of the loop below
           // (b ascending; hi*lo before lo*hi)
@@ -971,6 +980,30 @@ __device__ __forceinline__ void split3d_item(const KArgs& a, int item) {
           }
           split_box_schedule<W>();
           __builtin_amdgcn_sched_barrier(0);
+        } else if constexpr (REGA) {
+          // the k line's A operand straight from the FP32 window: lane (g, q)
+          // takes row 16 wj + r + q, window columns 32 wk + 16 t + 8 g .. + 7
+          // (zero from the window's end on, where the band is zero too), and
+          // splits them in registers -- the same values the box path stages
+          // in LDS, without the planes and their barrier
+          const int slot = (R + PH) % W;
+          const float* arow = win + (16 * wj + R + q) * PW::PITCH + PW::COL0 + 32 * wk + 8 * g;
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            u16x8 ah, al;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const int y = 32 * wk + 16 * t + 8 * g + e;
+              const float x = y < S::WEND ? arow[16 * t + e] : 0.0f;
+              uint16_t h, l;
+              Split16<KIND>::split(x, lo_mul, h, l);
+              ah[e] = h;
+              al[e] = l;
+            }
+            acc[slot][t] = Split16<KIND>::mma(ah, bh[0], acc[slot][t]);
+            acx[0][t] = Split16<KIND>::mma(ah, bl[0], acx[0][t]);
+            acx[0][t] = Split16<KIND>::mma(al, bh[0], acx[0][t]);
+          }
         } else {
 #pragma unroll
           for (int ap = 0; ap < W; ++ap) {
