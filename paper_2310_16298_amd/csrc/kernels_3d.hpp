@@ -399,6 +399,89 @@ __global__ __launch_bounds__(kThreads) void gather3d_batch(BatchArgs b) {
 }
 
 // ---------------------------------------------------------------------------
+// Whole-grid gather for small 3D grids (the paper's Table 3 sizes, 8^3 and
+// up): one workgroup stages the grid with its r halo (zero or wrapped) in
+// LDS and computes every point as Eq. (1), one point per thread and pass.
+// The tiled kernels give such a grid 32 x 64 (j, k) tiles of which an 8 x 8
+// plane fills one lane in 32; a batch of many small grids then keeps every
+// lane of every workgroup busy instead.  VOL: LDS elements (16 or 64 KiB).
+// ---------------------------------------------------------------------------
+template <typename T, int VOL>
+__host__ __device__ constexpr bool whole3d_fits(int64_t Ni, int64_t Nj, int64_t Nk, int R) {
+  return (Ni + 2 * R) * (Nj + 2 * R) * (Nk + 2 * R) <= VOL;
+}
+
+template <typename T, int R, bool BOX, int VOL>
+__device__ __forceinline__ void gather3d_whole_item(const KArgs& a) {
+  constexpr int W = 2 * R + 1;
+  __shared__ T g[VOL];
+  const int Ni = (int)a.d0, Nj = (int)a.d1, Nk = (int)a.d2;
+  const int PJ = Nj + 2 * R, PK = Nk + 2 * R, PP = PJ * PK;
+  const bool periodic = a.periodic != 0;
+  const T* __restrict__ in = (const T*)a.in;
+  T* __restrict__ out = (T*)a.out;
+  const ConstPtr<T> c = (ConstPtr<T>)a.coef;  // uniform reads: scalar loads
+  const int vol = (Ni + 2 * R) * PP;
+  for (int e = threadIdx.x; e < vol; e += kThreads) {
+    const int i = e / PP, rem = e - i * PP, j = rem / PK, k = rem - j * PK;
+    const int64_t gi = map_index(i - R, Ni, periodic), gj = map_index(j - R, Nj, periodic),
+                  gk = map_index(k - R, Nk, periodic);
+    g[e] = (gi >= 0 && gj >= 0 && gk >= 0) ? in[(gi * Nj + gj) * Nk + gk] : T(0);
+  }
+  __syncthreads();
+  const int plane = Nj * Nk, n = Ni * plane;
+  for (int p = threadIdx.x; p < n; p += kThreads) {
+    const int i = p / plane, rem = p - i * plane, j = rem / Nk, k = rem - j * Nk;
+    const T* base = g + i * PP + j * PK + k;  // padded (i, j, k) = neighbourhood corner
+    // the tiled kernel's order per point (input planes ascending; a star's
+    // centre plane: the j arm with the centre, then the k arm), so a grid
+    // gives the same bits on either kernel and under the time-blocked ones
+    T sum = T(0);
+#pragma unroll
+    for (int x = 0; x < W; ++x) {
+      if constexpr (BOX) {
+#pragma unroll
+        for (int y = 0; y < W; ++y)
+#pragma unroll
+          for (int z = 0; z < W; ++z) sum += c[(x * W + y) * W + z] * base[x * PP + y * PK + z];
+      } else if (x != R) {
+        sum += c[(x * W + R) * W + R] * base[x * PP + R * PK + R];
+      } else {
+#pragma unroll
+        for (int y = 0; y < W; ++y) sum += c[(R * W + y) * W + R] * base[R * PP + y * PK + R];
+#pragma unroll
+        for (int z = 0; z < W; ++z)
+          if (z != R) sum += c[(R * W + R) * W + z] * base[R * PP + R * PK + z];
+      }
+    }
+    out[p] = sum;
+  }
+}
+
+template <typename T, int R, bool BOX, int VOL>
+__global__ __launch_bounds__(kThreads) void gather3d_whole_kernel(KArgs a) {
+  gather3d_whole_item<T, R, BOX, VOL>(a);
+}
+
+template <typename T, int R, bool BOX, int VOL>
+__global__ __launch_bounds__(kThreads) void gather3d_whole_batch(BatchArgs b) {
+  for_each_batch_item(b, [&](const KArgs& x, int) { gather3d_whole_item<T, R, BOX, VOL>(x); });
+}
+
+// The whole-grid kernel for a grid that fits 16 or 64 KiB of LDS with its
+// halo and leaves the chunk to the library, else none.
+template <typename T, int R, bool BOX>
+inline Kernel whole3d_kernel(const KArgs& a, int32_t chunk) {
+  constexpr int SMALL = 16384 / (int)sizeof(T), LARGE = 65536 / (int)sizeof(T);
+  if (chunk != 0) return Kernel{};
+  if (whole3d_fits<T, SMALL>(a.d0, a.d1, a.d2, R))
+    return kernel_of<gather3d_whole_kernel<T, R, BOX, SMALL>, gather3d_whole_batch<T, R, BOX, SMALL>>(1);
+  if (whole3d_fits<T, LARGE>(a.d0, a.d1, a.d2, R))
+    return kernel_of<gather3d_whole_kernel<T, R, BOX, LARGE>, gather3d_whole_batch<T, R, BOX, LARGE>>(1);
+  return Kernel{};
+}
+
+// ---------------------------------------------------------------------------
 // Outer-product form on MFMA (FP32 / FP64).  Waves form a 2 x 2 grid over the
 // 32 x 64 tile; each wave owns two 16 x 16 blocks (16 j-rows x 32 k-columns)
 // in each of the 2r+1 ring slots.

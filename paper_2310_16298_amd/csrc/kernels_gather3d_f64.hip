@@ -7,6 +7,8 @@ namespace stencil {
 
 template <int R, bool BOX>
 static Kernel pick_gather3d(KArgs& a, int32_t chunk) {
+  const Kernel whole = whole3d_kernel<double, R, BOX>(a, chunk);  // small grids
+  if (whole.launch) return whole;
   if (dma3d_ok<double>(a)) return kernel3d<gather3d_kernel<double, R, BOX, true>, gather3d_batch<double, R, BOX, true>>(a, R, chunk);
   return kernel3d<gather3d_kernel<double, R, BOX, false>, gather3d_batch<double, R, BOX, false>>(a, R, chunk);
 }
