@@ -404,11 +404,20 @@ __global__ __launch_bounds__(kThreads) void gather3d_batch(BatchArgs b) {
 // LDS and computes every point as Eq. (1), one point per thread and pass.
 // The tiled kernels give such a grid 32 x 64 (j, k) tiles of which an 8 x 8
 // plane fills one lane in 32; a batch of many small grids then keeps every
-// lane of every workgroup busy instead.  VOL: LDS elements (16 or 64 KiB).
+// lane of every workgroup busy instead.  VOL: LDS elements (16, 32 or 64 KiB).
 // ---------------------------------------------------------------------------
 template <typename T, int VOL>
 __host__ __device__ constexpr bool whole3d_fits(int64_t Ni, int64_t Nj, int64_t Nk, int R) {
   return (Ni + 2 * R) * (Nj + 2 * R) * (Nk + 2 * R) <= VOL;
+}
+
+// e / d for 0 <= e < 2^20 and 0 < d: a float estimate from the reciprocal,
+// corrected by one either way (cheaper than the integer division sequence)
+__device__ __forceinline__ int div_small(int e, int d, float rd) {
+  int q = (int)((float)e * rd);
+  if (q * d > e) --q;
+  else if ((q + 1) * d <= e) ++q;
+  return q;
 }
 
 template <typename T, int R, bool BOX, int VOL>
@@ -422,16 +431,18 @@ __device__ __forceinline__ void gather3d_whole_item(const KArgs& a) {
   T* __restrict__ out = (T*)a.out;
   const ConstPtr<T> c = (ConstPtr<T>)a.coef;  // uniform reads: scalar loads
   const int vol = (Ni + 2 * R) * PP;
+  const float rPP = 1.0f / (float)PP, rPK = 1.0f / (float)PK;
   for (int e = threadIdx.x; e < vol; e += kThreads) {
-    const int i = e / PP, rem = e - i * PP, j = rem / PK, k = rem - j * PK;
+    const int i = div_small(e, PP, rPP), rem = e - i * PP, j = div_small(rem, PK, rPK), k = rem - j * PK;
     const int64_t gi = map_index(i - R, Ni, periodic), gj = map_index(j - R, Nj, periodic),
                   gk = map_index(k - R, Nk, periodic);
     g[e] = (gi >= 0 && gj >= 0 && gk >= 0) ? in[(gi * Nj + gj) * Nk + gk] : T(0);
   }
   __syncthreads();
   const int plane = Nj * Nk, n = Ni * plane;
+  const float rplane = 1.0f / (float)plane, rNk = 1.0f / (float)Nk;
   for (int p = threadIdx.x; p < n; p += kThreads) {
-    const int i = p / plane, rem = p - i * plane, j = rem / Nk, k = rem - j * Nk;
+    const int i = div_small(p, plane, rplane), rem = p - i * plane, j = div_small(rem, Nk, rNk), k = rem - j * Nk;
     const T* base = g + i * PP + j * PK + k;  // padded (i, j, k) = neighbourhood corner
     // the tiled kernel's order per point (input planes ascending; a star's
     // centre plane: the j arm with the centre, then the k arm), so a grid
@@ -468,14 +479,17 @@ __global__ __launch_bounds__(kThreads) void gather3d_whole_batch(BatchArgs b) {
   for_each_batch_item(b, [&](const KArgs& x, int) { gather3d_whole_item<T, R, BOX, VOL>(x); });
 }
 
-// The whole-grid kernel for a grid that fits 16 or 64 KiB of LDS with its
-// halo and leaves the chunk to the library, else none.
+// The whole-grid kernel for a grid that fits 16, 32 or 64 KiB of LDS with
+// its halo (the smallest: more workgroups per CU) and leaves the chunk to
+// the library, else none.
 template <typename T, int R, bool BOX>
 inline Kernel whole3d_kernel(const KArgs& a, int32_t chunk) {
-  constexpr int SMALL = 16384 / (int)sizeof(T), LARGE = 65536 / (int)sizeof(T);
+  constexpr int SMALL = 16384 / (int)sizeof(T), MEDIUM = 32768 / (int)sizeof(T), LARGE = 65536 / (int)sizeof(T);
   if (chunk != 0) return Kernel{};
   if (whole3d_fits<T, SMALL>(a.d0, a.d1, a.d2, R))
     return kernel_of<gather3d_whole_kernel<T, R, BOX, SMALL>, gather3d_whole_batch<T, R, BOX, SMALL>>(1);
+  if (whole3d_fits<T, MEDIUM>(a.d0, a.d1, a.d2, R))
+    return kernel_of<gather3d_whole_kernel<T, R, BOX, MEDIUM>, gather3d_whole_batch<T, R, BOX, MEDIUM>>(1);
   if (whole3d_fits<T, LARGE>(a.d0, a.d1, a.d2, R))
     return kernel_of<gather3d_whole_kernel<T, R, BOX, LARGE>, gather3d_whole_batch<T, R, BOX, LARGE>>(1);
   return Kernel{};
