@@ -348,3 +348,23 @@ def test_whole_number_items_per_cu(dtype, shape, r, path, dims):
     tol = error_bound(ce, 3, r, shape, dtype, path, steps, np.abs(a0).max())
     err = np.abs(got - want).max()
     assert err <= tol, f"max err {err:.3e} > bound {tol:.3e}"
+
+
+@pytest.mark.parametrize("dtype", [st.F32, st.F64])
+@pytest.mark.parametrize("shape", [st.STAR, st.BOX])
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("dims", [(8, 8, 8), (12, 16, 20), (5, 7, 3)])
+def test_small_grid_whole_kernel_matches_tiled(dtype, shape, r, dims):
+    """Grids that fit the LDS with their halo run the whole-grid gather (the
+    library's chunk); a requested chunk keeps the tiled kernel.  Both sum a
+    point's taps in the same order: bit for bit equal, and within the bound
+    of the oracle, for both boundaries."""
+    c = inputs.coefficients(3, r, shape, seed=2700 + r, dtype=np.float64)
+    ce = eff_coeffs(c, dtype)
+    a0 = inputs.grid(dims, seed=2701, dtype=np.float32 if dtype == st.F32 else np.float64)
+    for bc in (st.BC_ZERO, st.BC_PERIODIC):
+        whole = run_gpu(a0, c, r, shape, bc, dtype, st.PATH_GATHER, 3, time_block=1)
+        tiled = run_gpu(a0, c, r, shape, bc, dtype, st.PATH_GATHER, 3, time_block=1, chunk=4)
+        assert np.array_equal(whole, tiled), bc
+        want = oracle.run(a0.astype(np.float64), ce, r, shape, bc, 3)
+        assert np.abs(whole - want).max() <= error_bound(ce, 3, r, shape, dtype, st.PATH_GATHER, 3, np.abs(a0).max())
