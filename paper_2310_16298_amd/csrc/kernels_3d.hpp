@@ -432,11 +432,25 @@ __device__ __forceinline__ void gather3d_whole_item(const KArgs& a) {
   const ConstPtr<T> c = (ConstPtr<T>)a.coef;  // uniform reads: scalar loads
   const int vol = (Ni + 2 * R) * PP;
   const float rPP = 1.0f / (float)PP, rPK = 1.0f / (float)PK;
-  for (int e = threadIdx.x; e < vol; e += kThreads) {
-    const int i = div_small(e, PP, rPP), rem = e - i * PP, j = div_small(rem, PK, rPK), k = rem - j * PK;
-    const int64_t gi = map_index(i - R, Ni, periodic), gj = map_index(j - R, Nj, periodic),
-                  gk = map_index(k - R, Nk, periodic);
-    g[e] = (gi >= 0 && gj >= 0 && gk >= 0) ? in[(gi * Nj + gj) * Nk + gk] : T(0);
+  // several loads in flight per thread before their LDS stores (one memory
+  // round trip per UNR elements, not per element); four in the 16 KiB class
+  constexpr int UNR = VOL * (int)sizeof(T) <= 16384 ? 4 : 8;
+  for (int e0 = threadIdx.x; e0 < vol; e0 += UNR * kThreads) {
+    T v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int e = e0 + u * kThreads;
+      v[u] = T(0);
+      if (e < vol) {
+        const int i = div_small(e, PP, rPP), rem = e - i * PP, j = div_small(rem, PK, rPK), k = rem - j * PK;
+        const int64_t gi = map_index(i - R, Ni, periodic), gj = map_index(j - R, Nj, periodic),
+                      gk = map_index(k - R, Nk, periodic);
+        if (gi >= 0 && gj >= 0 && gk >= 0) v[u] = in[(gi * Nj + gj) * Nk + gk];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+      if (e0 + u * kThreads < vol) g[e0 + u * kThreads] = v[u];
   }
   __syncthreads();
   const int plane = Nj * Nk, n = Ni * plane;
