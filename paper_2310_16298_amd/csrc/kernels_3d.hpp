@@ -404,7 +404,7 @@ __global__ __launch_bounds__(kThreads) void gather3d_batch(BatchArgs b) {
 // LDS and computes every point as Eq. (1), one point per thread and pass.
 // The tiled kernels give such a grid 32 x 64 (j, k) tiles of which an 8 x 8
 // plane fills one lane in 32; a batch of many small grids then keeps every
-// lane of every workgroup busy instead.  VOL: LDS elements (16, 32 or 64 KiB).
+// lane of every workgroup busy instead.  VOL: LDS elements (16 to 128 KiB).
 // ---------------------------------------------------------------------------
 template <typename T, int VOL>
 __host__ __device__ constexpr bool whole3d_fits(int64_t Ni, int64_t Nj, int64_t Nk, int R) {
@@ -493,12 +493,13 @@ __global__ __launch_bounds__(kThreads) void gather3d_whole_batch(BatchArgs b) {
   for_each_batch_item(b, [&](const KArgs& x, int) { gather3d_whole_item<T, R, BOX, VOL>(x); });
 }
 
-// The whole-grid kernel for a grid that fits 16, 32 or 64 KiB of LDS with
-// its halo (the smallest: more workgroups per CU) and leaves the chunk to
-// the library, else none.
+// The whole-grid kernel for a grid that fits 16, 32, 64 or 128 KiB of LDS
+// with its halo (the smallest: more workgroups per CU) and leaves the chunk
+// to the library, else none.
 template <typename T, int R, bool BOX>
 inline Kernel whole3d_kernel(const KArgs& a, int32_t chunk) {
-  constexpr int SMALL = 16384 / (int)sizeof(T), MEDIUM = 32768 / (int)sizeof(T), LARGE = 65536 / (int)sizeof(T);
+  constexpr int SMALL = 16384 / (int)sizeof(T), MEDIUM = 32768 / (int)sizeof(T), LARGE = 65536 / (int)sizeof(T),
+                HUGE = 131072 / (int)sizeof(T);
   if (chunk != 0) return Kernel{};
   if (whole3d_fits<T, SMALL>(a.d0, a.d1, a.d2, R))
     return kernel_of<gather3d_whole_kernel<T, R, BOX, SMALL>, gather3d_whole_batch<T, R, BOX, SMALL>>(1);
@@ -506,6 +507,10 @@ inline Kernel whole3d_kernel(const KArgs& a, int32_t chunk) {
     return kernel_of<gather3d_whole_kernel<T, R, BOX, MEDIUM>, gather3d_whole_batch<T, R, BOX, MEDIUM>>(1);
   if (whole3d_fits<T, LARGE>(a.d0, a.d1, a.d2, R))
     return kernel_of<gather3d_whole_kernel<T, R, BOX, LARGE>, gather3d_whole_batch<T, R, BOX, LARGE>>(1);
+  // 128 KiB (one workgroup per CU) only for grids of at most 16^3 points:
+  // larger ones keep the tiled kernel's parallelism when launched alone
+  if (a.d0 * a.d1 * a.d2 <= 4096 && whole3d_fits<T, HUGE>(a.d0, a.d1, a.d2, R))
+    return kernel_of<gather3d_whole_kernel<T, R, BOX, HUGE>, gather3d_whole_batch<T, R, BOX, HUGE>>(1);
   return Kernel{};
 }
 
