@@ -131,7 +131,10 @@ typedef struct {
                            instructions (F64, 2D orthogonal stars, 3D boxes up to order 2); any
                            other resolved block edge: EUNSUPPORTED; ignored by the GATHER path */
   int32_t chunk;        /* output rows (2D) or i-planes (3D) per workgroup work item: 0 = library
-                           choice; rounded up to the kernel's row block and clipped to the extent */
+                           choice (on the 3D GATHER path a grid that fits the LDS with its halo,
+                           8^3 or 16^3 say, is then one work item computed whole by one
+                           workgroup); rounded up to the kernel's row block and clipped to the
+                           extent */
   int32_t time_block;   /* steps fused per launch (time blocking; the temporal reuse Section 6
                            leaves to future work): 1 = one step per launch; T > 1: each launch
                            advances T steps on overlapped tiles held in LDS (halo r*T), cutting HBM
