@@ -453,11 +453,22 @@ def test_auto_path_choice(lib, shape):
         info64 = st.describe((96, 96), r, shape, c, dtype=st.F64)
         assert info64["path"] == st.PATH_GATHER
         assert info64["time_block"] == ({1: 8, 2: 4, 3: 2, 4: 2} if shape == inputs.STAR else {1: 8, 2: 4, 3: 1, 4: 1})[r]
-        # at most 64 columns: stars and the FP64 9-point box take the outer products
+        # 64 columns: the time-blocked gather where the table has a step
+        # count (the FP32 box of order 4 keeps the outer products)
+        d32 = st.describe((64, 64), r, shape, c, dtype=st.F32)
+        if shape == inputs.BOX and r == 4:
+            assert d32["path"] == st.PATH_MFMA and d32["time_block"] == 1
+        else:
+            assert d32["path"] == st.PATH_GATHER
+            assert d32["time_block"] == ({1: 8, 2: 4, 3: 4, 4: 3} if shape == inputs.STAR else {1: 8, 2: 4, 3: 4})[r]
+        d64 = st.describe((64, 64), r, shape, c, dtype=st.F64)
+        t64 = ({1: 8, 2: 4, 3: 2, 4: 2} if shape == inputs.STAR else {1: 8, 2: 4, 3: 1, 4: 1})[r]
+        assert d64["time_block"] == t64 and d64["path"] == st.PATH_GATHER
+        # narrower: stars and the FP64 9-point box take the outer products
         narrow = shape == inputs.STAR or heavy
-        assert st.describe((64, 64), r, shape, c, dtype=st.F32)["path"] == (st.PATH_MFMA if narrow else st.PATH_GATHER)
+        assert st.describe((60, 60), r, shape, c, dtype=st.F32)["path"] == (st.PATH_MFMA if narrow else st.PATH_GATHER)
         narrow64 = shape == inputs.STAR or r == 1
-        assert st.describe((64, 64), r, shape, c, dtype=st.F64)["path"] == (st.PATH_MFMA if narrow64 else st.PATH_GATHER)
+        assert st.describe((60, 60), r, shape, c, dtype=st.F64)["path"] == (st.PATH_MFMA if narrow64 else st.PATH_GATHER)
         for dt in (st.F32, st.F64):
             assert st.describe((64, 66), r, shape, c, dtype=dt)["path"] == st.PATH_MFMA
         g = c.copy()
