@@ -488,13 +488,13 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
         if (12 * 403 * n_eff < 12 * 620 + 1530 * L * (4 + 2 * R)) heavy = false;
       }
       path = dma_cols && !heavy && !narrow ? STENCIL_PATH_GATHER : STENCIL_PATH_MFMA;
-      // Time blocking: on grids of at least 64 columns that take direct-to-LDS
-      // windows, the time-blocked gather with the step count measured fastest
-      // on MI355X (512^2, 2048^2 and 8192^2, periodic) beats every one-step
-      // plan.  On 64 x 64 grids (10 steps, alone) it takes 24-45 us against
-      // 49-78 us for the best one-step plan, and batches of them run 1.8-2.2x
-      // faster, except the FP32 box of order 4 (73 vs 69 us for the outer
-      // products, which it keeps at 64 columns).  FP32: 8 / 4 / 4 / 3 steps per launch for stars of order 1..4,
+      // Time blocking: on grids that take direct-to-LDS windows, the
+      // time-blocked gather with the step count measured fastest on MI355X
+      // (512^2, 2048^2 and 8192^2, periodic) beats every one-step plan.  On
+      // narrow grids too (10 steps, alone: 32^2, 48^2, 32 x 128 and 64^2 take
+      // 24-60 us against 50-108 us for the best one-step plan; batches of 64^2
+      // grids run 1.6-2.1x faster), except the FP32 box of order 4, which
+      // keeps the outer products up to 64 columns (69 vs 73-76 us).  FP32: 8 / 4 / 4 / 3 steps per launch for stars of order 1..4,
       // 8 / 4 / 4 / 2 for boxes (ahead of the outer products by 2-4 % at
       // order 3 and 7-10 % at order 4 on 8192^2, by 1.1-1.4x on 2048^2).
       // FP64: stars 8 / 4 / 2 / 2, boxes 8 / 4 and none from order 3 (their
@@ -502,7 +502,7 @@ int resolve_plan(const stencil_desc_t* desc, Resolved* rs, bool pack) {
       // every kernel knob is left to the library.
       static const int kAutoTimeBlock[2][2][5] = {{{0, 8, 4, 4, 3}, {0, 8, 4, 4, 2}},   // F32 star, box
                                                   {{0, 8, 4, 2, 2}, {0, 8, 4, 0, 0}}};  // F64 star, box
-      const bool tb_cols = d.dims[1] > 64 || (d.dims[1] == 64 && !(f32 && box && R == 4));
+      const bool tb_cols = d.dims[1] > 64 || !(f32 && box && R == 4);
       if (!general && dma_cols && tb_cols && d.time_block == 0 && d.lines == STENCIL_LINES_AUTO &&
           d.block_n == 0 && d.chunk == 0 && d.reg_rows == 0 && d.tile_width == 0) {
         const int t = kAutoTimeBlock[f32 ? 0 : 1][box ? 1 : 0][R];

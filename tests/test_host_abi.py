@@ -464,11 +464,17 @@ def test_auto_path_choice(lib, shape):
         d64 = st.describe((64, 64), r, shape, c, dtype=st.F64)
         t64 = ({1: 8, 2: 4, 3: 2, 4: 2} if shape == inputs.STAR else {1: 8, 2: 4, 3: 1, 4: 1})[r]
         assert d64["time_block"] == t64 and d64["path"] == st.PATH_GATHER
-        # narrower: stars and the FP64 9-point box take the outer products
+        # narrower grids are time-blocked as well (the same table) ...
+        assert st.describe((60, 60), r, shape, c, dtype=st.F32)["time_block"] == d32["time_block"]
+        assert st.describe((60, 60), r, shape, c, dtype=st.F64)["time_block"] == t64
+        # ... and one step per launch (a knob set): stars and the FP64 9-point
+        # box take the outer products up to 64 columns
         narrow = shape == inputs.STAR or heavy
-        assert st.describe((60, 60), r, shape, c, dtype=st.F32)["path"] == (st.PATH_MFMA if narrow else st.PATH_GATHER)
+        one32 = st.describe((60, 60), r, shape, c, dtype=st.F32, chunk=16)
+        assert one32["path"] == (st.PATH_MFMA if narrow else st.PATH_GATHER) and one32["time_block"] == 1
         narrow64 = shape == inputs.STAR or r == 1
-        assert st.describe((60, 60), r, shape, c, dtype=st.F64)["path"] == (st.PATH_MFMA if narrow64 else st.PATH_GATHER)
+        one64 = st.describe((60, 60), r, shape, c, dtype=st.F64, chunk=16)
+        assert one64["path"] == (st.PATH_MFMA if narrow64 else st.PATH_GATHER) and one64["time_block"] == 1
         for dt in (st.F32, st.F64):
             assert st.describe((64, 66), r, shape, c, dtype=dt)["path"] == st.PATH_MFMA
         g = c.copy()
