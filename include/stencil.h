@@ -151,8 +151,8 @@ typedef struct {
                            aligned buffers, else stencil_run_steps returns EINVAL); else
                            EUNSUPPORTED.  0 = library choice:
                            one step per launch, except that path AUTO on 2D STAR / BOX grids
-                           of at least 64 columns (the F32 order-4 box: more than 64) whose
-                           column extent is a multiple of 4, with
+                           whose column extent is a multiple of 4 (the F32 order-4 box: and
+                           more than 64), with
                            lines, block_n, chunk, reg_rows and tile_width all 0, takes the
                            time-blocked gather with T measured fastest on MI355X (r = 1..4,
                            F32 stars 8 / 4 / 4 / 3, boxes 8 / 4 / 4 / 2; F64 stars 8 / 4 / 2 /
