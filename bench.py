@@ -891,7 +891,7 @@ def main() -> int:
     ap.add_argument("--no-oracle", action="store_true", help="mixed: skip the CPU oracle (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU runs are not part of this build.",
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library runs each plan on one device and bench.py does not launch ranks.",
               file=sys.stderr)
         return 2
 
